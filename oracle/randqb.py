@@ -1,0 +1,349 @@
+"""Plain float64 oracle for randQB_EI and randQB_FP (test infrastructure only).
+
+Written from Yu, Gu, Li, arXiv 1606.09402:
+
+* Theorem 1 / eq. (5): for orthonormal Q and B = Q^T A,
+  ||A - QB||_F^2 = ||A||_F^2 - ||B||_F^2, so E = ||A||^2 - sum ||B_i||^2 tracks the
+  squared error without forming the residual (Algorithm 1, Theorem 2).
+* Section 3.1, steps 7a-8e: the indicator may be decremented row by row; at the
+  first row j where E < eps^2 the rows after j of B_i (columns of Q_i) are dropped.
+* Algorithm 2 (randQB_EI): Q_i = orth(A Omega_i - Q (B Omega_i)), re-orthogonalise
+  Q_i = orth(Q_i - Q (Q^T Q_i)), B_i = Q_i^T A.
+* Algorithm 3 with steps 9a-9c, i.e. Algorithm 4 with power parameter P = 0
+  (randQB_FP): G = A Omega, H = A^T G once; per block
+  Y_i = G_J - Q (B Omega_J); [Q_i, R_i] = qr(Y_i);
+  [Q_i, R~_i] = qr(Q_i - Q (Q^T Q_i)); R_i = R~_i R_i;
+  B_i = R_i^{-T} (H_J^T - Y_i^T Q B - Omega_J^T B^T B)   (eq. (23)).
+* Section 5.4: the tolerance is relative, ||A - QB||_F < tol ||A||_F, and the
+  SVD-optimal rank is the smallest k whose tail sum of sigma_j^2 meets it.
+
+Readings where the paper is silent or inconsistent (each one is listed in the
+design notes of the repository):
+
+* stop test is E < eps^2 with eps^2 = tol*tol*||A||^2 (strict, as in Algorithms 1
+  and 2; Algorithm 4 writes sqrt(E) < eps which is NaN for negative E);
+* orth and qr both mean the Q factor of a thin QR with diag(R) >= 0;
+* EI and FP draw Omega from one counter-indexed matrix: EI's Omega_i is FP's
+  Omega(:, J) for the same global columns J;
+* l~ (chunk width) defaults to min(50 b, l_max) (Section 5.4); when a chunk is
+  used up without convergence the next l~ columns of Omega are drawn and G, H
+  recomputed (the restart described after Algorithm 4), keeping Q, B and E;
+* exhaustion guard: before row j of a block is accepted, R_i(j,j) must exceed
+  2^-40 ||G_J(:,j)||_2, otherwise the method stops before row j (the numerical
+  rank of A has been reached and R_i^{-T} would divide by round-off);
+* A = 0 returns rank 0; E < eps^2 before the first block (tol > 1) returns rank 0.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.linalg
+import scipy.sparse as sp
+
+from . import rng
+
+# status codes (same meaning as the C ABI)
+QB_OK = 0
+QB_NOT_CONVERGED = 1
+QB_WARN_TOL_FLOOR = 2
+QB_ERR_ARG = -1
+QB_ERR_NONFINITE = -2
+
+EXHAUST_REL = 2.0 ** -40
+UNIT_ROUNDOFF = 2.0 ** -53
+
+
+def tol_floor(u: float = UNIT_ROUNDOFF, delta: float = 0.01) -> float:
+    """Theorem 3: E is accurate to relative delta only if eps > sqrt(4u/delta) ||A||_F."""
+    return float(np.sqrt(4.0 * u / delta))
+
+
+def sumsq(A) -> float:
+    """||A||_F^2 as a sum of squares of the entries (not a norm squared), accumulated
+    in x87 extended precision, then rounded to binary64 (Section 3.3)."""
+    if sp.issparse(A):
+        vals = np.asarray(A.data, dtype=np.float64).ravel()
+        return float(np.sum(np.square(vals.astype(np.longdouble))))
+    A = np.asarray(A)
+    total = np.longdouble(0.0)
+    rows_per = max(1, (1 << 22) // max(1, A.shape[1]))
+    for r0 in range(0, A.shape[0], rows_per):
+        blk = A[r0:r0 + rows_per].astype(np.longdouble)
+        total += np.sum(blk * blk)
+    return float(total)
+
+
+def qr_pos(X: np.ndarray):
+    """Thin Householder QR (LAPACK) with the signs fixed so that diag(R) >= 0."""
+    Q, R = np.linalg.qr(X, mode="reduced")
+    d = np.sign(np.diag(R))
+    d[d == 0] = 1.0
+    return Q * d[None, :], R * d[:, None]
+
+
+def omega(seed: int, n: int, col0: int, cols: int, batch: int = 0) -> np.ndarray:
+    """Columns [col0, col0+cols) of the n-row Gaussian test matrix (stream 0)."""
+    return rng.gaussian_matrix(seed, n, cols, 0, col0, stream=0, batch=batch)
+
+
+def block_b(H_J, Y, Qk, Bk, W, R):
+    """Eq. (23): B_i = R^{-T} (H_J^T - (Y^T Q) B - W^T B), W = B Omega_J."""
+    S = H_J.T - (Y.T @ Qk) @ Bk - W.T @ Bk
+    return scipy.linalg.solve_triangular(R, S, trans="T", lower=False)
+
+
+def row_sumsq(Bi: np.ndarray) -> np.ndarray:
+    return np.einsum("ij,ij->i", Bi, Bi)
+
+
+class _Grow:
+    """Growable column (Q) / row (B) storage."""
+
+    def __init__(self, m, n):
+        self.Q = np.empty((m, 0))
+        self.B = np.empty((0, n))
+        self.k = 0
+
+    def append(self, Qi, Bi):
+        self.Q = np.concatenate([self.Q, Qi], axis=1)
+        self.B = np.concatenate([self.B, Bi], axis=0)
+        self.k = self.Q.shape[1]
+
+
+@dataclass
+class QBResult:
+    Q: np.ndarray
+    B: np.ndarray
+    rank: int
+    E: float
+    normA2: float
+    status: int
+    passes: int = 0
+    blocks: int = 0
+    chunks: int = 0
+    exhausted: int = 0
+    E_trace: list = field(default_factory=list)   # E after every block (Theorem 2)
+    R_diag: list = field(default_factory=list)    # diag(R_i) per block
+
+
+def _check(A, tol_rel, b, l_max):
+    m, n = A.shape
+    if l_max is None:
+        l_max = min(m, n)
+    if not (1 <= b) or l_max < 0 or l_max > min(m, n) or not (tol_rel >= 0):
+        raise ValueError("bad argument")
+    return m, n, int(l_max)
+
+
+def _scan_rows(Bi, R, gnorm, E, eps2, row_by_row):
+    """Steps 7a-8e (or Algorithm 1 steps 7-8 when row_by_row is False) plus the
+    exhaustion guard.  Returns (rows kept, new E, stop flag, exhausted flag)."""
+    bw = Bi.shape[0]
+    r = row_sumsq(Bi)
+    if row_by_row:
+        for j in range(bw):
+            if not (R[j, j] > EXHAUST_REL * gnorm[j]):
+                return j, E, True, True
+            E = E - r[j]
+            if E < eps2:
+                return j + 1, E, True, False
+        return bw, E, False, False
+    for j in range(bw):
+        if not (R[j, j] > EXHAUST_REL * gnorm[j]):
+            return j, E - float(np.sum(r[:j])), True, True
+    E = E - float(np.sum(r))
+    return bw, E, E < eps2, False
+
+
+def _finish(st, E, normA2, status_tol, exhausted, l_max, k, eps2, **kw):
+    converged = E < eps2
+    if converged:
+        status = status_tol
+    else:
+        status = QB_NOT_CONVERGED
+    return QBResult(Q=st.Q, B=st.B, rank=st.k, E=E, normA2=normA2, status=status,
+                    exhausted=int(exhausted), **kw)
+
+
+def randqb_fp(A, tol_rel: float, b: int, seed: int, l_max=None, l_tilde: int = 0,
+              row_by_row: bool = True) -> QBResult:
+    """randQB_FP for the fixed-precision problem (Algorithm 4 with P = 0)."""
+    m, n, l_max = _check(A, tol_rel, b, l_max)
+    if l_tilde == 0:
+        l_tilde = min(50 * b, l_max)
+    if l_tilde <= 0 or (l_tilde % b != 0 and l_tilde != l_max):
+        raise ValueError("l_tilde must be a multiple of b")
+    normA2 = sumsq(A)
+    if not np.isfinite(normA2):
+        return QBResult(np.empty((m, 0)), np.empty((0, n)), 0, normA2, normA2, QB_ERR_NONFINITE)
+    eps2 = tol_rel * tol_rel * normA2
+    status_tol = QB_WARN_TOL_FLOOR if tol_rel < tol_floor() else QB_OK
+    st = _Grow(m, n)
+    E = normA2
+    if normA2 == 0.0 or E < eps2:
+        return QBResult(st.Q, st.B, 0, E, normA2, status_tol)
+    passes = blocks = chunks = 0
+    exhausted = False
+    trace, rdiag = [], []
+    chunk_lo = chunk_hi = 0
+    Om = G = H = Gnorm = None
+    while st.k < l_max:
+        k = st.k
+        if k == chunk_hi:                       # draw the next chunk of Omega
+            chunk_lo = k
+            chunk_hi = min(k + l_tilde, l_max)
+            Om = omega(seed, n, chunk_lo, chunk_hi - chunk_lo)
+            G = A @ Om
+            H = A.T @ G
+            G = np.asarray(G)
+            H = np.asarray(H)
+            Gnorm = np.sqrt(np.einsum("ij,ij->j", G, G))
+            passes += 2
+            chunks += 1
+        bw = min(b, chunk_hi - k)
+        J = slice(k - chunk_lo, k - chunk_lo + bw)
+        Om_J, G_J, H_J = Om[:, J], G[:, J], H[:, J]
+        W = st.B @ Om_J                              # B Omega_i
+        Y = G_J - st.Q @ W                           # step 11 of Algorithm 4
+        Qi, R = qr_pos(Y)                            # step 12
+        Qi, Rt = qr_pos(Qi - st.Q @ (st.Q.T @ Qi))   # step 13 (re-orthogonalisation)
+        R = Rt @ R                                   # step 14
+        Bi = block_b(H_J, Y, st.Q, st.B, W, R)       # step 15, eq. (23)
+        blocks += 1
+        keep, E, stop, exh = _scan_rows(Bi, R, Gnorm[J], E, eps2, row_by_row)
+        st.append(Qi[:, :keep], Bi[:keep])
+        trace.append(E)
+        rdiag.append(np.diag(R).copy())
+        if stop:
+            exhausted = exh
+            break
+    return _finish(st, E, normA2, status_tol, exhausted, l_max, st.k, eps2, passes=passes,
+                   blocks=blocks, chunks=chunks, E_trace=trace, R_diag=rdiag)
+
+
+def randqb_ei(A, tol_rel: float, b: int, seed: int, l_max=None,
+              row_by_row: bool = True) -> QBResult:
+    """randQB_EI (Algorithm 2) with the row-by-row indicator of steps 7a-8e."""
+    m, n, l_max = _check(A, tol_rel, b, l_max)
+    normA2 = sumsq(A)
+    if not np.isfinite(normA2):
+        return QBResult(np.empty((m, 0)), np.empty((0, n)), 0, normA2, normA2, QB_ERR_NONFINITE)
+    eps2 = tol_rel * tol_rel * normA2
+    status_tol = QB_WARN_TOL_FLOOR if tol_rel < tol_floor() else QB_OK
+    st = _Grow(m, n)
+    E = normA2
+    if normA2 == 0.0 or E < eps2:
+        return QBResult(st.Q, st.B, 0, E, normA2, status_tol)
+    passes = blocks = 0
+    exhausted = False
+    trace, rdiag = [], []
+    while st.k < l_max:
+        k = st.k
+        bw = min(b, l_max - k)
+        Om_i = omega(seed, n, k, bw)                 # step 4
+        G_i = np.asarray(A @ Om_i)                   # a pass over A
+        gnorm = np.sqrt(np.einsum("ij,ij->j", G_i, G_i))
+        Y = G_i - st.Q @ (st.B @ Om_i)               # step 5
+        Qi, R = qr_pos(Y)
+        Qi, Rt = qr_pos(Qi - st.Q @ (st.Q.T @ Qi))   # step 6
+        R = Rt @ R
+        Bi = np.asarray((A.T @ Qi).T)                # step 7, a pass over A
+        passes += 2
+        blocks += 1
+        keep, E, stop, exh = _scan_rows(Bi, R, gnorm, E, eps2, row_by_row)
+        st.append(Qi[:, :keep], Bi[:keep])
+        trace.append(E)
+        rdiag.append(np.diag(R).copy())
+        if stop:
+            exhausted = exh
+            break
+    return _finish(st, E, normA2, status_tol, exhausted, l_max, st.k, eps2, passes=passes,
+                   blocks=blocks, chunks=0, E_trace=trace, R_diag=rdiag)
+
+
+def randqb_fixed(A, Om: np.ndarray):
+    """Basic randQB (Figure 1(a)) without oversampling: Q = qf(A Omega), B = Q^T A."""
+    Q, _ = qr_pos(np.asarray(A @ Om))
+    return Q, np.asarray((A.T @ Q).T)
+
+
+def randqb_fp_fixed(A, Om: np.ndarray, b: int, reorth: bool = True):
+    """Fixed-rank randQB_FP: Algorithm 3, with steps 9a-9c when reorth is True.
+    The rank is Om.shape[1]; the last block may be narrower than b."""
+    A = np.asarray(A)
+    m, n = A.shape
+    G = A @ Om
+    H = A.T @ G
+    Q = np.empty((m, 0))
+    B = np.empty((0, n))
+    l = Om.shape[1]
+    for lo in range(0, l, b):
+        J = slice(lo, min(l, lo + b))
+        W = B @ Om[:, J]
+        Y = G[:, J] - Q @ W
+        Qi, R = qr_pos(Y)
+        if reorth:
+            Qi, Rt = qr_pos(Qi - Q @ (Q.T @ Qi))
+            R = Rt @ R
+            Bi = block_b(H[:, J], Y, Q, B, W, R)
+        else:   # Algorithm 3 step 9: B_i = R_i^{-T} (H_J^T - Omega_J^T B^T B)
+            Bi = scipy.linalg.solve_triangular(R, H[:, J].T - W.T @ B, trans="T", lower=False)
+        Q = np.concatenate([Q, Qi], axis=1)
+        B = np.concatenate([B, Bi], axis=0)
+    return Q, B
+
+
+def jacobi_svd(A: np.ndarray, tol: float = 1e-15, max_sweeps: int = 60):
+    """One-sided Jacobi SVD (Hestenes): rotate column pairs of A until mutually
+    orthogonal; singular values are the final column norms (descending)."""
+    U = np.array(A, dtype=np.float64, copy=True)
+    n = U.shape[1]
+    for _ in range(max_sweeps):
+        rotated = False
+        for p in range(n - 1):
+            for q in range(p + 1, n):
+                a = float(U[:, p] @ U[:, p])
+                c_ = float(U[:, q] @ U[:, q])
+                g = float(U[:, p] @ U[:, q])
+                if abs(g) <= tol * np.sqrt(a * c_) or g == 0.0:
+                    continue
+                rotated = True
+                zeta = (c_ - a) / (2.0 * g)
+                t = np.copysign(1.0, zeta) / (abs(zeta) + np.sqrt(1.0 + zeta * zeta))
+                cs = 1.0 / np.sqrt(1.0 + t * t)
+                sn = cs * t
+                up = U[:, p].copy()
+                U[:, p] = cs * up - sn * U[:, q]
+                U[:, q] = sn * up + cs * U[:, q]
+        if not rotated:
+            break
+    s = np.sqrt(np.einsum("ij,ij->j", U, U))
+    return np.sort(s)[::-1]
+
+
+def svd_optimal_rank(sigma: np.ndarray, tol_rel: float) -> int:
+    """Smallest k with sum_{j>k} sigma_j^2 < tol^2 sum_j sigma_j^2 (Section 5.4)."""
+    s2 = np.sort(np.asarray(sigma, dtype=np.float64) ** 2)[::-1]
+    total = float(np.sum(s2.astype(np.longdouble)))
+    # tail[k] = sum_{j >= k} s2[j] (0-based), accumulated smallest first
+    tail = np.cumsum(s2[::-1].astype(np.longdouble))[::-1]
+    tail = np.append(tail, np.longdouble(0.0))
+    thr = np.longdouble(tol_rel) ** 2 * np.longdouble(total)
+    for k in range(len(s2) + 1):
+        if tail[k] < thr:
+            return k
+    return len(s2)
+
+
+def orth_loss_inf(Q: np.ndarray) -> float:
+    """||Q^T Q - I||_inf (max absolute row sum), the loss-of-orthogonality measure of Fig. 2."""
+    M = Q.T @ Q - np.eye(Q.shape[1])
+    return float(np.max(np.sum(np.abs(M), axis=1))) if M.size else 0.0
+
+
+def residual_sq(A, Q, B) -> float:
+    """Directly computed ||A - QB||_F^2 (for checking E; never used by the method)."""
+    A = A.toarray() if sp.issparse(A) else np.asarray(A)
+    Rm = A - Q @ B
+    return float(np.sum(Rm * Rm))
