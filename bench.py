@@ -1,0 +1,177 @@
+"""Benchmark: QB time-to-tolerance of randQB_FP on one MI355X.
+
+Workload (synthetic, seeded): dense FP64 A = U diag(sigma) V^T + noise, 20000 x 15000,
+sigma_j = exp(-j/150) on 3000 Haar columns, iid N(0, (1e-8)^2) noise, block size b = 64,
+relative Frobenius tolerance 1e-3, l~ = 50 b (the paper's Section 5.4 rule).  One step
+is one full call of the library's randQB_FP (||A||^2, Omega, G = A Omega, H = A^T G,
+block loop to the tolerance) with A already resident in HBM; randQB_EI is timed beside
+it on the same matrix.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Prints one JSON line.  value = median time-to-tolerance in seconds (lower is better).
+roofline: the dominant kernel (the larger of the two FP64 MFMA sketch GEMMs, G = A Omega
+or H = A^T G) -- algorithmic flops 2 m n l~ per launch over its average launch time,
+measured with HIP events recorded by the library on the stream the GEMM runs on;
+MI355X FP64 matrix peak 78.6 TFLOP/s.  cpu_baseline: the FP64 oracle (NumPy/OpenBLAS)
+on the same workload, run once on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ei", action="store_true")
+    ap.add_argument("--l-tilde", type=int, default=0, help="chunk width (0: paper rule 50 b)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
+              "multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1606_09402_amd as qb
+    import workloads as W
+
+    wl = W.C2
+    seed = W.SEED_OMEGA | 2
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    A = wl.make(device=dev)
+    torch.cuda.synchronize()
+    print(f"# generated {wl.name} on the GPU in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    m, n = A.shape
+    l_max = min(m, n)
+    Qs = torch.empty((l_max, m), dtype=torch.float64, device=dev)
+    Bs = torch.empty((l_max, n), dtype=torch.float64, device=dev)
+    need = max(qb.qb_workspace_bytes(qb.QB_ALGO_FP, False, m, n, 0, wl.tol, wl.b, l_max, args.l_tilde),
+               qb.qb_workspace_bytes(qb.QB_ALGO_EI, False, m, n, 0, wl.tol, wl.b, l_max))
+    ws = torch.empty(need, dtype=torch.uint8, device=dev)
+
+    def fp():
+        return qb.qb_fp_dense(A, wl.tol, wl.b, seed, l_max=l_max, l_tilde=args.l_tilde,
+                              Q_store=Qs, B_store=Bs, ws=ws)
+
+    def ei():
+        return qb.qb_ei_dense(A, wl.tol, wl.b, seed, l_max=l_max, Q_store=Qs, B_store=Bs, ws=ws)
+
+    for i in range(args.warmup):
+        r = fp()
+        print(f"# warmup {i}: rank {r.rank} E {r.E:.4e} {r.ms[5]:.1f} ms", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    times, results = [], []
+    t_all = time.perf_counter()
+    for i in range(args.steps):
+        t = time.perf_counter()
+        r = fp()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+        results.append(r)
+        print(f"# step {i}: {times[-1] * 1e3:.2f} ms rank {r.rank}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_all
+    r = results[-1]
+    med = statistics.median(times)
+
+    # dominant kernel: per-launch flops / per-launch device time (HIP events in the library)
+    w_chunks = [min(r.Q_store.shape[0], 50 * wl.b if args.l_tilde == 0 else args.l_tilde)]
+    g_ms = statistics.median(x.ms[2] for x in results) / max(1, r.chunks)
+    h_ms = statistics.median(x.ms[3] for x in results) / max(1, r.chunks)
+    flops_per_launch = r.gemm_flops[0] / max(1, r.chunks)
+    dom_ms, dom_name = (h_ms, "gemm_f64 H=A^T G") if h_ms >= g_ms else (g_ms, "gemm_f64 G=A Omega")
+    achieved = flops_per_launch / (dom_ms * 1e-3) / 1e12
+
+    # accuracy of the returned factorisation (verification, not timed)
+    Q = r.Q
+    Bm = r.B
+    res2 = float(torch.linalg.matrix_norm(A - Q @ Bm) ** 2)
+    true_rel = (res2 / r.normA2) ** 0.5
+
+    out = {
+        "metric": "QB time-to-tol (s)",
+        "value": round(med, 6),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "m": m, "n": n, "b": wl.b, "tol": wl.tol,
+                   "l_tilde": args.l_tilde or 50 * wl.b, "algo": "randQB_FP", "power": 0},
+        "rank": r.rank,
+        "E_rel": (max(r.E, 0.0) / r.normA2) ** 0.5,
+        "true_rel_err": true_rel,
+        "passes": r.passes,
+        "blocks": r.blocks,
+        "phase_ms": {"normA2": r.ms[0], "omega": r.ms[1], "G": r.ms[2], "H": r.ms[3],
+                     "block_loop": r.ms[4], "total": r.ms[5]},
+        "sketch_tflops": (r.gemm_flops[0] + r.gemm_flops[1]) / ((r.ms[2] + r.ms[3]) * 1e-3) / 1e12,
+        "roofline": {"bound": "mfma", "kernel": dom_name, "achieved": round(achieved, 3),
+                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None},
+    }
+    if not args.no_ei:
+        ei()
+        torch.cuda.synchronize()
+        et = []
+        for _ in range(max(1, min(args.steps, 3))):
+            t = time.perf_counter()
+            re_ = ei()
+            torch.cuda.synchronize()
+            et.append(time.perf_counter() - t)
+        out["ei"] = {"time_to_tol_s": round(statistics.median(et), 6), "rank": re_.rank,
+                     "passes": re_.passes, "blocks": re_.blocks,
+                     "phase_ms": {"A_Omega_i": re_.ms[2], "At_Q_i": re_.ms[3], "total": re_.ms[5]}}
+        print(f"# ei: {statistics.median(et) * 1e3:.1f} ms rank {re_.rank} passes {re_.passes}",
+              file=sys.stderr, flush=True)
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(A, wl, seed)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(A, wl, seed):
+    """The FP64 oracle's randQB_FP on the same matrix, once, on the host cores."""
+    import numpy as np
+
+    from oracle import randqb as R
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count() or 1
+    An = A.cpu().numpy()
+    print("# cpu baseline: oracle randQB_FP on the full workload ...", file=sys.stderr, flush=True)
+    t = time.perf_counter()
+    ora = R.randqb_fp(An, wl.tol, wl.b, seed)
+    dt = time.perf_counter() - t
+    print(f"# cpu baseline: {dt:.1f} s rank {ora.rank}", file=sys.stderr, flush=True)
+    return {"value": round(dt, 3), "unit": "s", "cores": threads, "kind": "oracle",
+            "sample": f"full {wl.name} workload, one randQB_FP call (NumPy/OpenBLAS FP64)",
+            "rank": ora.rank}
+
+
+if __name__ == "__main__":
+    main()

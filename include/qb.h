@@ -1,0 +1,172 @@
+/*
+ * qb.h -- C ABI of the MI355X (gfx950) fixed-precision randomized QB library.
+ *
+ * The library computes A ~ Q B with Q (m x k) orthonormal and B = Q^T A, choosing the
+ * rank k adaptively so that ||A - QB||_F < tol ||A||_F, following Yu, Gu, Li,
+ * "Efficient randomized algorithms for the fixed-precision low-rank matrix
+ * approximation" (arXiv 1606.09402):
+ *   - randQB_FP: Algorithm 4 with power parameter P = 0 (Algorithm 3 plus the
+ *     re-orthogonalised steps 9a-9c, eq. (23)); one sweep G = A Omega, H = A^T G per
+ *     chunk of Omega columns, then a block loop that touches only G, H, Omega, Q, B.
+ *   - randQB_EI: Algorithm 2, two passes over A per block.
+ *   - both stop with the Frobenius error indicator of Theorem 1 / Algorithm 1,
+ *     decremented row by row (Section 3.1, steps 7a-8e) unless row_by_row == 0.
+ *
+ * Conventions shared by every entry point
+ *   - All matrix pointers are DEVICE pointers owned by the caller.  The library never
+ *     allocates or frees them; scratch memory comes from the caller's workspace.
+ *   - All device work is enqueued on the caller's stream; calls that return a rank
+ *     synchronise that stream before returning (the rank is decided on the host,
+ *     one b-vector copy per block).
+ *   - Dense A is row-major: A(i, j) at a[i * lda + j], lda >= n.
+ *   - Q is column-major m x l_max: Q(i, j) at Q[j * ldq + i], ldq >= m.
+ *   - B is row-major l_max x n: B(i, j) at B[i * ldb + j], ldb >= n.
+ *     On return columns [0, rank) of Q and rows [0, rank) of B are valid; the rest
+ *     of the l_max capacity may hold scratch values.
+ *   - Omega is the bit-specified Gaussian matrix described at qb_gaussian_fill.
+ *   - No C++ exception crosses this interface; every function returns a qb_status.
+ */
+#ifndef QB_H
+#define QB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QB_API __attribute__((visibility("default")))
+
+typedef enum {
+    QB_OK = 0,               /* converged: E < (tol ||A||_F)^2                                   */
+    QB_NOT_CONVERGED = 1,    /* warning: l_max reached, or the numerical rank of A was exhausted
+                                (info.exhausted = 1) with E >= eps^2; outputs valid for [0,rank) */
+    QB_WARN_TOL_FLOOR = 2,   /* warning: tol below the Theorem 3 floor sqrt(4u/0.01) = 2.1e-7 for
+                                binary64; E may be inaccurate.  The call still runs.            */
+    QB_ERR_ARG = -1,         /* invalid argument (sizes, strides, NULL pointers, b, l_tilde ...) */
+    QB_ERR_NONFINITE = -2,   /* ||A||_F^2 is NaN or Inf                                          */
+    QB_ERR_WORKSPACE = -3,   /* workspace smaller than qb_workspace_bytes() reports              */
+    QB_ERR_HIP = -4,         /* a HIP runtime call failed                                        */
+    QB_ERR_UNSUPPORTED = -5  /* e.g. power > 0 or an element type this entry point lacks       */
+} qb_status;
+
+typedef enum { QB_ALGO_FP = 0, QB_ALGO_EI = 1 } qb_algo;
+
+typedef enum { QB_F64 = 0 } qb_dtype;
+
+/* Dense row-major matrix.  dtype must be QB_F64. */
+typedef struct {
+    int64_t m, n;       /* rows, columns (m, n >= 1)                         */
+    int64_t lda;        /* row stride in elements, lda >= n                  */
+    int32_t dtype;      /* qb_dtype                                          */
+    int32_t reserved;
+    const void* a;      /* device pointer to A(0,0)                          */
+} qb_dense;
+
+/* Compressed sparse row matrix (Section 5.1 stores sparse A in CSR).  Column indices
+ * must lie in [0, n); duplicates are summed as in the usual CSR semantics. */
+typedef struct {
+    int64_t m, n, nnz;
+    const int64_t* rowptr;  /* device, m + 1 entries, rowptr[0] = 0, rowptr[m] = nnz */
+    const int32_t* colind;  /* device, nnz entries                                    */
+    const double* val;      /* device, nnz entries                                    */
+} qb_csr;
+
+typedef struct {
+    double tol_rel;      /* stop when E < (tol_rel ||A||_F)^2 (strict), 0 <= tol_rel       */
+    int32_t b;           /* block size, 1 <= b <= 128                                        */
+    int32_t power;       /* power-scheme parameter P of Algorithm 4; must be 0               */
+    int64_t l_max;       /* capacity of Q / B, 1 <= l_max <= min(m, n)                       */
+    int64_t l_tilde;     /* randQB_FP chunk width: a multiple of b, or 0 for min(50 b, l_max)
+                            (Section 5.4).  A chunk that runs out is followed by the next
+                            l_tilde columns of Omega and a fresh G, H sweep.                 */
+    uint64_t seed;       /* Philox key of Omega                                              */
+    int32_t row_by_row;  /* 1: steps 7a-8e (rank any integer); 0: whole-block stopping      */
+    int32_t reserved;
+} qb_params;
+
+typedef struct {
+    int64_t rank;        /* number of valid columns of Q / rows of B                        */
+    double E;            /* final indicator ||A||^2 - ||B||^2 (may be negative, Section 3.3)  */
+    double normA2;       /* ||A||_F^2                                                        */
+    int32_t status;      /* same as the return value                                         */
+    int32_t passes;      /* passes over A (FP: 2 per chunk; EI: 2 per block)                 */
+    int32_t blocks;      /* blocks processed                                                 */
+    int32_t chunks;      /* Omega chunks drawn (FP)                                          */
+    int32_t exhausted;   /* 1 if R_i(j,j) <= 2^-40 ||A Omega(:,j)||_2 ended the run            */
+    int32_t fallbacks;   /* panels orthonormalised by the Householder fallback               */
+    double ms[8];        /* device time per phase (ms): 0 ||A||^2, 1 Omega, 2 G = A Omega,
+                            3 H = A^T G (EI: 2 = the A Omega_i GEMMs, 3 = the A^T Q_i GEMMs),
+                            4 block loop without 2-3, 5 whole call                           */
+    double gemm_flops[2];/* algorithmic flops of the timed G and H GEMMs (2 m n l each)      */
+} qb_info;
+
+/* Bytes of workspace qb_{fp,ei}_{dense,csr} need for this problem (algo = qb_algo,
+ * sparse = 0/1, nnz ignored for dense).  Returns 0 for invalid arguments. */
+QB_API size_t qb_workspace_bytes(int algo, int sparse, int64_t m, int64_t n, int64_t nnz,
+                          const qb_params* p);
+
+/* randQB_FP (Algorithm 4, P = 0) on dense row-major A.  ws must hold at least
+ * qb_workspace_bytes(QB_ALGO_FP, 0, ...) bytes of device memory (256-byte aligned). */
+QB_API int qb_fp_dense(const qb_dense* A, const qb_params* p, double* Q, int64_t ldq, double* B,
+                int64_t ldb, void* ws, size_t ws_bytes, hipStream_t stream, qb_info* info);
+
+/* randQB_EI (Algorithm 2) on dense row-major A; EI's Omega_i is column block i of the
+ * same Omega as randQB_FP uses. */
+QB_API int qb_ei_dense(const qb_dense* A, const qb_params* p, double* Q, int64_t ldq, double* B,
+                int64_t ldb, void* ws, size_t ws_bytes, hipStream_t stream, qb_info* info);
+
+/* randQB_FP on CSR A: G = A Omega by a row-parallel SpMM, H = A^T G by the same SpMM
+ * on CSR(A^T), which the call builds once in the workspace. */
+QB_API int qb_fp_csr(const qb_csr* A, const qb_params* p, double* Q, int64_t ldq, double* B,
+              int64_t ldb, void* ws, size_t ws_bytes, hipStream_t stream, qb_info* info);
+
+/* randQB_EI on CSR A. */
+QB_API int qb_ei_csr(const qb_csr* A, const qb_params* p, double* Q, int64_t ldq, double* B,
+              int64_t ldb, void* ws, size_t ws_bytes, hipStream_t stream, qb_info* info);
+
+/* Omega(row0 + r, col0 + c) for r < rows, c < cols into out[r * ld + c] (row-major,
+ * ld >= cols).  The paper only asks for a standard Gaussian matrix (randn in
+ * Algorithms 2 and 4); this library pins the draw so that runs are reproducible:
+ *   entry (i, 2p + q), q in {0, 1}: Philox4x32-10 with counter (i, p, stream, batch) and
+ *   key (seed mod 2^32, seed div 2^32) gives words w0..w3;
+ *   u1 = (((w0 << 32 | w1) >> 12) + 1/2) 2^-52, u2 likewise from (w2, w3);
+ *   r = sqrt(-2 ln u1); q = 0 -> r cos(2 pi u2), q = 1 -> r sin(2 pi u2);
+ *   ln, sqrt, sin, cos evaluated with IEEE binary64 +,-,*,/ only in a fixed order
+ *   (atanh series for ln, six Newton steps for sqrt, degree-17/16 Taylor polynomials
+ *   on [0, pi/4] with quadrant folding for sin / cos).
+ * Enqueued on stream; does not synchronise. */
+QB_API int qb_gaussian_fill(uint64_t seed, uint32_t stream_id, uint32_t batch, int64_t row0,
+                     int64_t col0, int64_t rows, int64_t cols, double* out, int64_t ld,
+                     hipStream_t stream);
+
+/* ||A||_F^2 (Theorem 1 / Algorithm 1 step 2) of dense row-major A, as a deterministic
+ * FP64 tree sum of squares; *out_host receives the value.  ws needs
+ * qb_sumsq_workspace_bytes() bytes.  Synchronises the stream. */
+QB_API size_t qb_sumsq_workspace_bytes(void);
+QB_API int qb_sumsq_dense(const qb_dense* A, double* out_host, void* ws, hipStream_t stream);
+
+/* One sketch sweep of randQB_FP (Algorithm 4 steps 2, 7, 8 with P = 0):
+ * Omega(:, col0:col0+l) drawn as in qb_gaussian_fill (stream 0, batch 0) into om
+ * (n x l, row-major, ld l), G = A Omega into g (m x l row-major, ld l), H = A^T G into
+ * h (n x l row-major, ld l).  Enqueued on stream; does not synchronise. */
+QB_API int qb_sketch_dense(const qb_dense* A, uint64_t seed, int64_t col0, int64_t l, double* om,
+                    double* g, double* h, hipStream_t stream);
+
+/* Same sweep for CSR A; csc_ws must hold qb_csr_transpose_bytes(A) bytes and is
+ * filled with CSR(A^T) on the first call (set *csc_ready = 0 before it). */
+QB_API size_t qb_csr_transpose_bytes(const qb_csr* A);
+QB_API int qb_sketch_csr(const qb_csr* A, uint64_t seed, int64_t col0, int64_t l, double* om,
+                  double* g, double* h, void* csc_ws, int* csc_ready, hipStream_t stream);
+
+/* Human-readable name of a qb_status value (static storage). */
+QB_API const char* qb_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QB_H */

@@ -1,0 +1,302 @@
+"""Python binding of the MI355X fixed-precision randomized QB library (libqb.so).
+
+Thin ctypes marshalling over the C ABI declared in include/qb.h: the functions here
+carry the same names as the C entry points, turn torch tensors into device pointers
+and the current HIP stream, allocate the caller-owned outputs / workspace with torch,
+and raise on error statuses.  Every step of the method runs in the library's HIP
+kernels; there is no CPU fallback -- if libqb.so is missing the import of the library
+fails loudly (build it with ``paper_1606_09402_amd.build.build()``).
+
+Method: Yu, Gu, Li, "Efficient randomized algorithms for the fixed-precision low-rank
+matrix approximation" (arXiv 1606.09402): randQB_FP (Algorithm 4, P = 0) and randQB_EI
+(Algorithm 2) with the Frobenius error indicator of Theorem 1 / Algorithm 1.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import torch  # noqa: F401  (load torch's HIP runtime first: libqb.so then binds to it)
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "_lib", "libqb.so")
+
+QB_OK, QB_NOT_CONVERGED, QB_WARN_TOL_FLOOR = 0, 1, 2
+QB_ERR_ARG, QB_ERR_NONFINITE, QB_ERR_WORKSPACE, QB_ERR_HIP, QB_ERR_UNSUPPORTED = -1, -2, -3, -4, -5
+QB_ALGO_FP, QB_ALGO_EI = 0, 1
+
+_c_i64 = ctypes.c_int64
+_c_i32 = ctypes.c_int32
+_vp = ctypes.c_void_p
+
+
+class QbDense(ctypes.Structure):
+    _fields_ = [("m", _c_i64), ("n", _c_i64), ("lda", _c_i64), ("dtype", _c_i32),
+                ("reserved", _c_i32), ("a", _vp)]
+
+
+class QbCsr(ctypes.Structure):
+    _fields_ = [("m", _c_i64), ("n", _c_i64), ("nnz", _c_i64), ("rowptr", _vp), ("colind", _vp),
+                ("val", _vp)]
+
+
+class QbParams(ctypes.Structure):
+    _fields_ = [("tol_rel", ctypes.c_double), ("b", _c_i32), ("power", _c_i32), ("l_max", _c_i64),
+                ("l_tilde", _c_i64), ("seed", ctypes.c_uint64), ("row_by_row", _c_i32),
+                ("reserved", _c_i32)]
+
+
+class QbInfo(ctypes.Structure):
+    _fields_ = [("rank", _c_i64), ("E", ctypes.c_double), ("normA2", ctypes.c_double),
+                ("status", _c_i32), ("passes", _c_i32), ("blocks", _c_i32), ("chunks", _c_i32),
+                ("exhausted", _c_i32), ("fallbacks", _c_i32), ("ms", ctypes.c_double * 8),
+                ("gemm_flops", ctypes.c_double * 2)]
+
+
+class QBError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__(f"{where}: {qb_status_string(status)} ({status})")
+        self.status = status
+
+
+_LIB = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libqb.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_1606_09402_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        L.qb_workspace_bytes.argtypes = [ctypes.c_int, ctypes.c_int, _c_i64, _c_i64, _c_i64, P(QbParams)]
+        L.qb_workspace_bytes.restype = ctypes.c_size_t
+        for nm in ("qb_fp_dense", "qb_ei_dense"):
+            f = getattr(L, nm)
+            f.argtypes = [P(QbDense), P(QbParams), _vp, _c_i64, _vp, _c_i64, _vp, ctypes.c_size_t, _vp,
+                          P(QbInfo)]
+            f.restype = ctypes.c_int
+        for nm in ("qb_fp_csr", "qb_ei_csr"):
+            f = getattr(L, nm)
+            f.argtypes = [P(QbCsr), P(QbParams), _vp, _c_i64, _vp, _c_i64, _vp, ctypes.c_size_t, _vp,
+                          P(QbInfo)]
+            f.restype = ctypes.c_int
+        L.qb_gaussian_fill.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, _c_i64, _c_i64,
+                                       _c_i64, _c_i64, _vp, _c_i64, _vp]
+        L.qb_gaussian_fill.restype = ctypes.c_int
+        L.qb_sumsq_workspace_bytes.argtypes = []
+        L.qb_sumsq_workspace_bytes.restype = ctypes.c_size_t
+        L.qb_sumsq_dense.argtypes = [P(QbDense), P(ctypes.c_double), _vp, _vp]
+        L.qb_sumsq_dense.restype = ctypes.c_int
+        L.qb_sketch_dense.argtypes = [P(QbDense), ctypes.c_uint64, _c_i64, _c_i64, _vp, _vp, _vp, _vp]
+        L.qb_sketch_dense.restype = ctypes.c_int
+        L.qb_csr_transpose_bytes.argtypes = [P(QbCsr)]
+        L.qb_csr_transpose_bytes.restype = ctypes.c_size_t
+        L.qb_sketch_csr.argtypes = [P(QbCsr), ctypes.c_uint64, _c_i64, _c_i64, _vp, _vp, _vp, _vp,
+                                    P(ctypes.c_int), _vp]
+        L.qb_sketch_csr.restype = ctypes.c_int
+        L.qb_status_string.argtypes = [ctypes.c_int]
+        L.qb_status_string.restype = ctypes.c_char_p
+        _LIB = L
+    return _LIB
+
+
+def qb_status_string(status: int) -> str:
+    return lib().qb_status_string(int(status)).decode()
+
+
+# ------------------------------------------------------------------ marshalling helpers
+
+
+def _stream_ptr(dev: torch.device):
+    return _vp(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def _check_dev(t: torch.Tensor, name: str, dtype=torch.float64):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}")
+
+
+def _dense(A: torch.Tensor) -> QbDense:
+    _check_dev(A, "A")
+    if A.dim() != 2 or A.stride(1) != 1 or A.stride(0) < A.shape[1]:
+        raise ValueError("A must be a row-major 2-D view (stride(1) == 1)")
+    return QbDense(A.shape[0], A.shape[1], A.stride(0), 0, 0, A.data_ptr())
+
+
+def _csr(m: int, n: int, rowptr: torch.Tensor, colind: torch.Tensor, val: torch.Tensor) -> QbCsr:
+    _check_dev(rowptr, "rowptr", torch.int64)
+    _check_dev(colind, "colind", torch.int32)
+    _check_dev(val, "val")
+    for t, nm in ((rowptr, "rowptr"), (colind, "colind"), (val, "val")):
+        if not t.is_contiguous():
+            raise ValueError(f"{nm} must be contiguous")
+    if rowptr.numel() != m + 1 or colind.numel() != val.numel():
+        raise ValueError("CSR arrays have inconsistent sizes")
+    return QbCsr(m, n, val.numel(), rowptr.data_ptr(), colind.data_ptr(), val.data_ptr())
+
+
+def _params(tol, b, l_max, l_tilde, seed, row_by_row, power=0) -> QbParams:
+    return QbParams(float(tol), int(b), int(power), int(l_max), int(l_tilde), int(seed) & (2 ** 64 - 1),
+                    1 if row_by_row else 0, 0)
+
+
+@dataclass
+class QBResult:
+    Q: torch.Tensor          # m x rank view (column-major storage)
+    B: torch.Tensor          # rank x n view
+    rank: int
+    E: float
+    normA2: float
+    status: int
+    passes: int
+    blocks: int
+    chunks: int
+    exhausted: int
+    fallbacks: int
+    ms: list = field(default_factory=list)
+    gemm_flops: list = field(default_factory=list)
+    Q_store: torch.Tensor | None = None   # l_max x m (row i = column i of Q)
+    B_store: torch.Tensor | None = None   # l_max x n
+
+
+def _run(kind: str, algo: int, sparse: bool, mat, m: int, n: int, dev, tol, b, l_max, l_tilde,
+         seed, row_by_row, Q_store, B_store, ws, power=0) -> QBResult:
+    L = lib()
+    l_max = min(m, n) if l_max is None else int(l_max)
+    p = _params(tol, b, l_max, l_tilde, seed, row_by_row, power)
+    need = L.qb_workspace_bytes(algo, 1 if sparse else 0, m, n, mat.nnz if sparse else 0,
+                                ctypes.byref(p))
+    fn = getattr(L, kind)
+    if need == 0:   # invalid parameters: let the entry point report which status applies
+        st = fn(ctypes.byref(mat), ctypes.byref(p), None, 0, None, 0, None, 0, _stream_ptr(dev), None)
+        raise QBError(st if st < 0 else QB_ERR_ARG, kind)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    if Q_store is None:
+        Q_store = torch.empty((l_max, m), dtype=torch.float64, device=dev)
+    if B_store is None:
+        B_store = torch.empty((l_max, n), dtype=torch.float64, device=dev)
+    if Q_store.shape[0] < l_max or Q_store.stride(1) != 1 or Q_store.stride(0) < m:
+        raise ValueError("Q_store must be at least l_max x m with unit column stride")
+    if B_store.shape[0] < l_max or B_store.stride(1) != 1 or B_store.stride(0) < n:
+        raise ValueError("B_store must be at least l_max x n with unit column stride")
+    info = QbInfo()
+    st = fn(ctypes.byref(mat), ctypes.byref(p), Q_store.data_ptr(), Q_store.stride(0),
+            B_store.data_ptr(), B_store.stride(0), ws.data_ptr(), ws.numel(), _stream_ptr(dev),
+            ctypes.byref(info))
+    if st < 0:
+        raise QBError(st, kind)
+    r = int(info.rank)
+    return QBResult(Q=Q_store[:r].T, B=B_store[:r], rank=r, E=info.E, normA2=info.normA2, status=st,
+                    passes=info.passes, blocks=info.blocks, chunks=info.chunks,
+                    exhausted=info.exhausted, fallbacks=info.fallbacks, ms=list(info.ms),
+                    gemm_flops=list(info.gemm_flops), Q_store=Q_store, B_store=B_store)
+
+
+# ------------------------------------------------------------------ public entry points
+
+
+def qb_fp_dense(A: torch.Tensor, tol: float, b: int, seed: int, l_max=None, l_tilde: int = 0,
+                row_by_row: bool = True, Q_store=None, B_store=None, ws=None, power: int = 0) -> QBResult:
+    """randQB_FP (Algorithm 4, P = 0) on dense float64 A (GPU, row-major)."""
+    d = _dense(A)
+    return _run("qb_fp_dense", QB_ALGO_FP, False, d, d.m, d.n, A.device, tol, b, l_max, l_tilde,
+                seed, row_by_row, Q_store, B_store, ws, power)
+
+
+def qb_ei_dense(A: torch.Tensor, tol: float, b: int, seed: int, l_max=None, row_by_row: bool = True,
+                Q_store=None, B_store=None, ws=None, power: int = 0) -> QBResult:
+    """randQB_EI (Algorithm 2) on dense float64 A (GPU, row-major)."""
+    d = _dense(A)
+    return _run("qb_ei_dense", QB_ALGO_EI, False, d, d.m, d.n, A.device, tol, b, l_max, 0, seed,
+                row_by_row, Q_store, B_store, ws, power)
+
+
+def qb_fp_csr(m: int, n: int, rowptr, colind, val, tol: float, b: int, seed: int, l_max=None,
+              l_tilde: int = 0, row_by_row: bool = True, Q_store=None, B_store=None, ws=None) -> QBResult:
+    """randQB_FP on a CSR matrix (rowptr int64, colind int32, val float64; GPU tensors)."""
+    c = _csr(m, n, rowptr, colind, val)
+    return _run("qb_fp_csr", QB_ALGO_FP, True, c, m, n, val.device, tol, b, l_max, l_tilde, seed,
+                row_by_row, Q_store, B_store, ws)
+
+
+def qb_ei_csr(m: int, n: int, rowptr, colind, val, tol: float, b: int, seed: int, l_max=None,
+              row_by_row: bool = True, Q_store=None, B_store=None, ws=None) -> QBResult:
+    """randQB_EI on a CSR matrix."""
+    c = _csr(m, n, rowptr, colind, val)
+    return _run("qb_ei_csr", QB_ALGO_EI, True, c, m, n, val.device, tol, b, l_max, 0, seed,
+                row_by_row, Q_store, B_store, ws)
+
+
+def qb_workspace_bytes(algo: int, sparse: bool, m: int, n: int, nnz: int, tol: float, b: int,
+                       l_max: int, l_tilde: int = 0) -> int:
+    p = _params(tol, b, l_max, l_tilde, 0, True)
+    return int(lib().qb_workspace_bytes(algo, 1 if sparse else 0, m, n, nnz, ctypes.byref(p)))
+
+
+def qb_gaussian_fill(seed: int, rows: int, cols: int, row0: int = 0, col0: int = 0,
+                     stream_id: int = 0, batch: int = 0, out: torch.Tensor | None = None,
+                     device="cuda") -> torch.Tensor:
+    """Omega[row0:row0+rows, col0:col0+cols] (row-major float64 on the GPU)."""
+    if out is None:
+        out = torch.empty((rows, cols), dtype=torch.float64, device=device)
+    _check_dev(out, "out")
+    if out.dim() != 2 or out.shape[0] < rows or out.shape[1] < cols or out.stride(1) != 1:
+        raise ValueError("out must be a row-major rows x cols view")
+    st = lib().qb_gaussian_fill(int(seed) & (2 ** 64 - 1), stream_id, batch, row0, col0, rows, cols,
+                                out.data_ptr(), out.stride(0), _stream_ptr(out.device))
+    if st < 0:
+        raise QBError(st, "qb_gaussian_fill")
+    return out
+
+
+def qb_sumsq_dense(A: torch.Tensor) -> float:
+    """||A||_F^2 of dense float64 A as a deterministic GPU sum of squares."""
+    L = lib()
+    d = _dense(A)
+    ws = torch.empty(L.qb_sumsq_workspace_bytes(), dtype=torch.uint8, device=A.device)
+    out = ctypes.c_double(0.0)
+    st = L.qb_sumsq_dense(ctypes.byref(d), ctypes.byref(out), ws.data_ptr(), _stream_ptr(A.device))
+    if st < 0:
+        raise QBError(st, "qb_sumsq_dense")
+    return out.value
+
+
+def qb_sketch_dense(A: torch.Tensor, seed: int, col0: int, l: int):
+    """(Omega, G = A Omega, H = A^T G) for Omega columns [col0, col0 + l)."""
+    d = _dense(A)
+    dev = A.device
+    om = torch.empty((d.n, l), dtype=torch.float64, device=dev)
+    g = torch.empty((d.m, l), dtype=torch.float64, device=dev)
+    h = torch.empty((d.n, l), dtype=torch.float64, device=dev)
+    st = lib().qb_sketch_dense(ctypes.byref(d), int(seed) & (2 ** 64 - 1), col0, l, om.data_ptr(),
+                               g.data_ptr(), h.data_ptr(), _stream_ptr(dev))
+    if st < 0:
+        raise QBError(st, "qb_sketch_dense")
+    return om, g, h
+
+
+def qb_sketch_csr(m: int, n: int, rowptr, colind, val, seed: int, col0: int, l: int, csc_ws=None):
+    """(Omega, G = A Omega, H = A^T G) for CSR A; returns also the CSR(A^T) workspace."""
+    L = lib()
+    c = _csr(m, n, rowptr, colind, val)
+    dev = val.device
+    ready = ctypes.c_int(0)
+    if csc_ws is None:
+        csc_ws = torch.empty(L.qb_csr_transpose_bytes(ctypes.byref(c)), dtype=torch.uint8, device=dev)
+    else:
+        ready = ctypes.c_int(1)
+    om = torch.empty((n, l), dtype=torch.float64, device=dev)
+    g = torch.empty((m, l), dtype=torch.float64, device=dev)
+    h = torch.empty((n, l), dtype=torch.float64, device=dev)
+    st = L.qb_sketch_csr(ctypes.byref(c), int(seed) & (2 ** 64 - 1), col0, l, om.data_ptr(),
+                         g.data_ptr(), h.data_ptr(), csc_ws.data_ptr(), ctypes.byref(ready),
+                         _stream_ptr(dev))
+    if st < 0:
+        raise QBError(st, "qb_sketch_csr")
+    return om, g, h, csc_ws

@@ -1,0 +1,333 @@
+// FP64 GEMM on CDNA4 matrix cores (v_mfma_f64_16x16x4_f64) for every product of the
+// QB method: the sketch sweep G = A Omega, H = A^T G (Algorithm 4 steps 7-8), EI's
+// A Omega_i and A^T Q_i (Algorithm 2 steps 5, 7), and the tall-skinny block products
+// B Omega_i, G_i - Q W, Q^T Q_i, Y^T Q, H_i^T - D B of steps 11-15.
+//
+//   out(i, j) = alpha * sum_k Aop(i, k) Bop(k, j) + beta * C0(i, j)
+//
+// Aop(i, k) = A[i*sai + k*sak] with either sak == 1 (layout 0, k contiguous: row-major
+// A in A Omega) or sai == 1 (layout 1, i contiguous: A^T of a row-major A, or a
+// column-major Q).  Bop(k, j) = B[k*sbk + j*sbj] with sbj == 1 (layout 0) or sbk == 1
+// (layout 1).  Tiles are staged through LDS in the operand's own global orientation
+// (no transposing stores) with pitches chosen so that the MFMA operand reads of a
+// 32-lane pass hit 64 distinct banks.  A reduction over a long K can be split across
+// workgroups (split-K); partial tiles are then summed in a fixed order by a second
+// kernel, so results are bit-reproducible.  Optionally the epilogue emits per-row-tile
+// column sums of squares of the output (used for ||B_i(j,:)||^2 and ||A Omega(:,j)||^2).
+#include "kernels.h"
+
+namespace qb {
+
+struct GemmArgs {
+    int64_t M, N, K;
+    const double* A;
+    int64_t lda;           // stride of the non-contiguous operand index
+    const double* B;
+    int64_t ldb;
+    double alpha, beta;
+    const double* C0;      // read when beta != 0
+    int64_t c0_si, c0_sj;
+    double* C;             // final output (nsplit == 1)
+    int64_t c_si, c_sj;
+    double* P;             // split-K partials, nsplit x M x N row-major (nsplit > 1)
+    int64_t kchunk;        // K range per split (multiple of BK)
+    double* colsq;         // [tiles_m][N] partial column sums of squares, or nullptr
+    int tiles_m, tiles_n;
+    int vec_a, vec_b;      // 16-byte aligned rows: double2 loads allowed
+};
+
+// Output element (row, col) inside a 16x16 f64 MFMA accumulator for lane l, slot r:
+// slot r of lane l holds row 4 r + l / 16, column l mod 16 (measured on gfx950; the
+// A operand is A(l mod 16, l / 16) and the B operand B(l / 16, l mod 16)).
+QB_DEV int acc_row(int lane, int r) { return (r << 2) + (lane >> 4); }
+QB_DEV int acc_col(int lane) { return lane & 15; }
+
+QB_DEV int xcd_remap(int wg, int nwg) {
+    // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a contiguous
+    // range of logical tiles so that tiles sharing an A row-slab share one L2.
+    const int xcd = wg & 7, local = wg >> 3;
+    const int per = nwg >> 3, rem = nwg & 7;
+    return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
+}
+
+// Staging of one operand tile of OUTER x INNER elements whose INNER index is contiguous
+// in global memory (row stride ld).  Thread t owns the element pair at inner offset
+// 2 (t mod INNER/2) of rows t div (INNER/2) + p RPP, p < PASSES.
+template <int OUTER, int INNER, int NT>
+struct Stage {
+    static constexpr int TPR = INNER / 2;          // threads per row
+    static constexpr int RPP = NT / TPR;           // rows per pass
+    static constexpr int PASSES = OUTER / RPP;
+    static_assert(NT % TPR == 0 && OUTER % RPP == 0, "staging shape");
+    double2 r[PASSES];
+
+    // rows [o0, o0 + OUTER) limited by olim, inner [i0, i0 + INNER) limited by ilim
+    QB_DEV void load(const double* __restrict__ g, int64_t ld, int64_t o0, int64_t i0, int64_t olim,
+                     int64_t ilim, bool vec) {
+        const int tid = threadIdx.x;
+        const int ro = tid / TPR, ri = 2 * (tid % TPR);
+        const double* p0 = g + (o0 + ro) * ld + i0 + ri;
+        const bool interior = o0 + OUTER <= olim && i0 + INNER <= ilim;
+        if (interior && vec) {
+#pragma unroll
+            for (int p = 0; p < PASSES; ++p)
+                r[p] = *reinterpret_cast<const double2*>(p0 + static_cast<int64_t>(p) * RPP * ld);
+        } else if (interior) {
+#pragma unroll
+            for (int p = 0; p < PASSES; ++p) {
+                const double* q = p0 + static_cast<int64_t>(p) * RPP * ld;
+                r[p] = double2{q[0], q[1]};
+            }
+        } else {
+#pragma unroll
+            for (int p = 0; p < PASSES; ++p) {
+                const int64_t o = o0 + ro + p * RPP;
+                const int64_t i = i0 + ri;
+                const double* q = p0 + static_cast<int64_t>(p) * RPP * ld;
+                const bool ok = o < olim;
+                r[p].x = ok && i < ilim ? q[0] : 0.0;
+                r[p].y = ok && i + 1 < ilim ? q[1] : 0.0;
+            }
+        }
+    }
+    template <int PITCH>
+    QB_DEV void store(double* __restrict__ s) const {
+        const int tid = threadIdx.x;
+        const int ro = tid / TPR, ri = 2 * (tid % TPR);
+#pragma unroll
+        for (int p = 0; p < PASSES; ++p)
+            *reinterpret_cast<double2*>(s + (ro + p * RPP) * PITCH + ri) = r[p];
+    }
+};
+
+template <int BM, int BN, int BK, int WM, int WN, int AL, int BL>
+struct GemmCfg {
+    static constexpr int NT = 64 * WM * WN;
+    static constexpr int TM = BM / WM, TN = BN / WN;
+    static constexpr int FM = TM / 16, FN = TN / 16;
+    // layout 0 tiles are [BM][BK] (k contiguous), layout 1 tiles are [BK][BM]; the
+    // pitches make a 32-lane pass of MFMA operand reads hit 64 distinct banks
+    static constexpr int A_PITCH = AL == 0 ? ((BK + 31) / 32) * 32 + 2 : ((BM + 31) / 32) * 32 + 16;
+    static constexpr int A_ROWS = AL == 0 ? BM : BK;
+    static constexpr int A_INNER = AL == 0 ? BK : BM;
+    static constexpr int B_PITCH = BL == 0 ? ((BN + 31) / 32) * 32 + 16 : ((BK + 31) / 32) * 32 + 2;
+    static constexpr int B_ROWS = BL == 0 ? BK : BN;
+    static constexpr int B_INNER = BL == 0 ? BN : BK;
+    static_assert(TM % 16 == 0 && TN % 16 == 0 && BK % 4 == 0, "bad tile");
+};
+
+template <int BM, int BN, int BK, int WM, int WN, int AL, int BL, int OCC>
+__global__ void __launch_bounds__(64 * WM * WN, OCC) gemm_f64_kernel(const GemmArgs g) {
+    using C = GemmCfg<BM, BN, BK, WM, WN, AL, BL>;
+    __shared__ double As[C::A_ROWS * C::A_PITCH];
+    __shared__ double Bs[C::B_ROWS * C::B_PITCH];
+    __shared__ double red[WM][BN];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave / WN, wn = wave % WN;
+    const int li = lane & 15, lk = lane >> 4;
+
+    const int logical = xcd_remap(blockIdx.x, gridDim.x);
+    const int tile_m = logical / g.tiles_n, tile_n = logical % g.tiles_n;
+    const int64_t m0 = static_cast<int64_t>(tile_m) * BM;
+    const int64_t n0 = static_cast<int64_t>(tile_n) * BN;
+    const int64_t kb = static_cast<int64_t>(blockIdx.y) * g.kchunk;
+    const int64_t ke = kb + g.kchunk < g.K ? kb + g.kchunk : g.K;
+
+    v4d acc[C::FM][C::FN];
+#pragma unroll
+    for (int a = 0; a < C::FM; ++a)
+#pragma unroll
+        for (int b = 0; b < C::FN; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+
+    Stage<C::A_ROWS, C::A_INNER, C::NT> sa;
+    Stage<C::B_ROWS, C::B_INNER, C::NT> sb;
+    auto load_tiles = [&](int64_t k0) {
+        if (AL == 0) sa.load(g.A, g.lda, m0, k0, g.M, ke, g.vec_a);
+        else         sa.load(g.A, g.lda, k0, m0, ke, g.M, g.vec_a);
+        if (BL == 0) sb.load(g.B, g.ldb, k0, n0, ke, g.N, g.vec_b);
+        else         sb.load(g.B, g.ldb, n0, k0, g.N, ke, g.vec_b);
+    };
+
+    const int wm0 = wm * C::TM, wn0 = wn * C::TN;
+    if (kb < ke) load_tiles(kb);
+    for (int64_t k0 = kb; k0 < ke; k0 += BK) {
+        __syncthreads();
+        sa.template store<C::A_PITCH>(As);
+        sb.template store<C::B_PITCH>(Bs);
+        __syncthreads();
+        if (k0 + BK < ke) load_tiles(k0 + BK);
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+            double a[C::FM], b[C::FN];
+#pragma unroll
+            for (int fm = 0; fm < C::FM; ++fm) {
+                const int i = wm0 + fm * 16 + li;
+                a[fm] = AL == 0 ? As[i * C::A_PITCH + kk + lk] : As[(kk + lk) * C::A_PITCH + i];
+            }
+#pragma unroll
+            for (int fn = 0; fn < C::FN; ++fn) {
+                const int j = wn0 + fn * 16 + li;
+                b[fn] = BL == 0 ? Bs[(kk + lk) * C::B_PITCH + j] : Bs[j * C::B_PITCH + kk + lk];
+            }
+#pragma unroll
+            for (int fm = 0; fm < C::FM; ++fm)
+#pragma unroll
+                for (int fn = 0; fn < C::FN; ++fn)
+                    acc[fm][fn] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[fm], b[fn], acc[fm][fn], 0, 0, 0);
+        }
+    }
+
+    // ---------------------------------------------------------------- epilogue
+    if (gridDim.y > 1) {
+        double* P = g.P + static_cast<int64_t>(blockIdx.y) * g.M * g.N;
+#pragma unroll
+        for (int fm = 0; fm < C::FM; ++fm)
+#pragma unroll
+            for (int fn = 0; fn < C::FN; ++fn)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t i = m0 + wm0 + fm * 16 + acc_row(lane, r);
+                    const int64_t j = n0 + wn0 + fn * 16 + acc_col(lane);
+                    if (i < g.M && j < g.N) P[i * g.N + j] = acc[fm][fn][r];
+                }
+        return;
+    }
+    double csq[C::FN];
+#pragma unroll
+    for (int fn = 0; fn < C::FN; ++fn) csq[fn] = 0.0;
+#pragma unroll
+    for (int fm = 0; fm < C::FM; ++fm)
+#pragma unroll
+        for (int fn = 0; fn < C::FN; ++fn)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t i = m0 + wm0 + fm * 16 + acc_row(lane, r);
+                const int64_t j = n0 + wn0 + fn * 16 + acc_col(lane);
+                if (i < g.M && j < g.N) {
+                    double v = g.alpha * acc[fm][fn][r];
+                    if (g.beta != 0.0) v += g.beta * g.C0[i * g.c0_si + j * g.c0_sj];
+                    g.C[i * g.c_si + j * g.c_sj] = v;
+                    csq[fn] += v * v;
+                }
+            }
+    if (g.colsq != nullptr) {
+        // lanes l, l^16, l^32, l^48 share a column; then combine the WM waves in order
+#pragma unroll
+        for (int fn = 0; fn < C::FN; ++fn) {
+            double v = csq[fn];
+            v += __shfl_xor(v, 16, 64);
+            v += __shfl_xor(v, 32, 64);
+            if (lk == 0) red[wm][wn0 + fn * 16 + li] = v;
+        }
+        __syncthreads();
+        for (int j = tid; j < BN; j += C::NT) {
+            double t = 0.0;
+#pragma unroll
+            for (int w = 0; w < WM; ++w) t += red[w][j];
+            if (n0 + j < g.N) g.colsq[static_cast<int64_t>(tile_m) * g.N + n0 + j] = t;
+        }
+    }
+}
+
+// Fixed-order sum of split-K partials with the alpha / beta epilogue.
+__global__ void __launch_bounds__(256)
+splitk_reduce_kernel(const double* __restrict__ P, int nsplit, int64_t M, int64_t N,
+                     double alpha, double beta, const double* C0, int64_t c0_si, int64_t c0_sj,
+                     double* C, int64_t c_si, int64_t c_sj) {
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= M * N) return;
+    double t = 0.0;
+    for (int s = 0; s < nsplit; ++s) t += P[static_cast<int64_t>(s) * M * N + e];
+    const int64_t i = e / N, j = e % N;
+    double v = alpha * t;
+    if (beta != 0.0) v += beta * C0[i * c0_si + j * c0_sj];
+    C[i * c_si + j * c_sj] = v;
+}
+
+// Epilogue-only "GEMM" for K == 0: out = beta * C0 (alpha * empty sum = 0).
+__global__ void __launch_bounds__(256)
+scale_copy_kernel(int64_t M, int64_t N, double beta, const double* C0, int64_t c0_si,
+                  int64_t c0_sj, double* C, int64_t c_si, int64_t c_sj) {
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= M * N) return;
+    const int64_t i = e / N, j = e % N;
+    C[i * c_si + j * c_sj] = beta != 0.0 ? beta * C0[i * c0_si + j * c0_sj] : 0.0;
+}
+
+// ------------------------------------------------------------------------------ host
+
+
+template <int BM, int BN, int BK, int WM, int WN, int AL, int BL, int OCC>
+static hipError_t run_cfg(const GemmDesc& d, hipStream_t s) {
+    GemmArgs g{};
+    g.M = d.M; g.N = d.N; g.K = d.K;
+    g.A = d.A.p; g.lda = AL == 0 ? d.A.si : d.A.sj;
+    g.B = d.B.p; g.ldb = BL == 0 ? d.B.si : d.B.sj;
+    g.alpha = d.alpha; g.beta = d.beta;
+    g.C0 = d.C0.p; g.c0_si = d.C0.si; g.c0_sj = d.C0.sj;
+    g.C = d.C.p; g.c_si = d.C.si; g.c_sj = d.C.sj;
+    g.vec_a = (reinterpret_cast<uintptr_t>(g.A) % 16 == 0) && (g.lda % 2 == 0);
+    g.vec_b = (reinterpret_cast<uintptr_t>(g.B) % 16 == 0) && (g.ldb % 2 == 0);
+    g.tiles_m = static_cast<int>(cdiv(d.M, BM));
+    g.tiles_n = static_cast<int>(cdiv(d.N, BN));
+    const int64_t tiles = static_cast<int64_t>(g.tiles_m) * g.tiles_n;
+    int nsplit = 1;
+    if (d.colsq == nullptr && d.ws != nullptr && tiles < 256) {
+        const int64_t ktiles = cdiv(d.K, BK);
+        int64_t want = cdiv(512, tiles);
+        if (want > ktiles / 4) want = ktiles / 4;
+        if (d.max_split > 0 && want > d.max_split) want = d.max_split;
+        while (want > 1 && want * d.M * d.N > d.ws_elems) --want;
+        if (want > 1) nsplit = static_cast<int>(want);
+    }
+    g.kchunk = cdiv(cdiv(d.K, BK), nsplit) * BK;
+    nsplit = static_cast<int>(cdiv(d.K, g.kchunk));
+    if (nsplit < 1) nsplit = 1;
+    g.P = d.ws;
+    g.colsq = d.colsq;
+    if (d.colsq_groups) *d.colsq_groups = g.tiles_m;
+    dim3 grid(static_cast<unsigned>(tiles), static_cast<unsigned>(nsplit));
+    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, WM, WN, AL, BL, OCC>), grid, dim3(64 * WM * WN), 0,
+                       s, g);
+    if (nsplit > 1) {
+        const int64_t tot = d.M * d.N;
+        hipLaunchKernelGGL(splitk_reduce_kernel, dim3(static_cast<unsigned>(cdiv(tot, 256))),
+                           dim3(256), 0, s, d.ws, nsplit, d.M, d.N, d.alpha, d.beta, d.C0.p,
+                           d.C0.si, d.C0.sj, d.C.p, d.C.si, d.C.sj);
+    }
+    return hipGetLastError();
+}
+
+template <int AL, int BL>
+static hipError_t dispatch_shape(const GemmDesc& d, hipStream_t s) {
+    if (d.N <= 64 && d.M >= 4096)          // tall-skinny output (m x b panels)
+        return run_cfg<128, 64, 32, 4, 1, AL, BL, 2>(d, s);
+    if (d.N <= 64 || d.M <= 2048)          // small output, long reduction (split-K)
+        return run_cfg<64, 64, 32, 2, 2, AL, BL, 2>(d, s);
+    return run_cfg<128, 128, 32, 2, 2, AL, BL, 1>(d, s);   // sketch sweep
+}
+
+hipError_t gemm_f64(const GemmDesc& d, hipStream_t s) {
+    if (d.M <= 0 || d.N <= 0) {
+        if (d.colsq_groups) *d.colsq_groups = 0;
+        return hipSuccess;
+    }
+    if (d.K <= 0) {
+        if (d.colsq != nullptr) return hipErrorInvalidValue;
+        const int64_t tot = d.M * d.N;
+        hipLaunchKernelGGL(scale_copy_kernel, dim3(static_cast<unsigned>(cdiv(tot, 256))), dim3(256),
+                           0, s, d.M, d.N, d.beta, d.C0.p, d.C0.si, d.C0.sj, d.C.p, d.C.si, d.C.sj);
+        return hipGetLastError();
+    }
+    const int al = d.A.sj == 1 ? 0 : 1;
+    const int bl = d.B.sj == 1 ? 0 : 1;
+    if ((al == 1 && d.A.si != 1) || (bl == 1 && d.B.si != 1)) return hipErrorInvalidValue;
+    if (al == 0 && bl == 0) return dispatch_shape<0, 0>(d, s);
+    if (al == 0 && bl == 1) return dispatch_shape<0, 1>(d, s);
+    if (al == 1 && bl == 0) return dispatch_shape<1, 0>(d, s);
+    return dispatch_shape<1, 1>(d, s);
+}
+
+}  // namespace qb

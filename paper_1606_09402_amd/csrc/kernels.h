@@ -1,0 +1,67 @@
+// Launchers of the library's HIP kernels (host-callable, all enqueue on a stream).
+#pragma once
+
+#include "common.h"
+
+namespace qb {
+
+// rng.hip -- bit-specified Gaussian Omega
+hipError_t launch_gauss_fill(uint64_t seed, uint32_t stream_id, uint32_t batch, int64_t row0,
+                             int64_t col0, int64_t rows, int64_t cols, double* out, int64_t ld,
+                             hipStream_t s);
+
+// reduce.hip -- deterministic sums
+hipError_t launch_sumsq_dense(const double* a, int64_t m, int64_t n, int64_t lda, double* scratch,
+                              double* out, hipStream_t s);
+hipError_t launch_sumsq_vec(const double* x, int64_t len, double* scratch, double* out,
+                            hipStream_t s);
+hipError_t launch_sum_partials(const double* partial, int64_t groups, int64_t stride, int64_t count,
+                               double* out, hipStream_t s);
+
+// gemm.hip -- FP64 MFMA GEMM.  out(i,j) = alpha sum_k Aop(i,k) Bop(k,j) + beta C0(i,j)
+struct GemmDesc {
+    int64_t M, N, K;
+    View A, B;           // Aop(i,k) = A.p[i*A.si + k*A.sj];  Bop(k,j) = B.p[k*B.si + j*B.sj]
+    double alpha, beta;
+    View C0;
+    MutView C;
+    double* colsq;       // optional [tiles_m][N] column sums of squares; forces one K split
+    int* colsq_groups;   // receives tiles_m when colsq is set
+    double* ws;          // split-K scratch (nullptr: no split)
+    int64_t ws_elems;
+    int max_split;       // 0 = automatic
+};
+hipError_t gemm_f64(const GemmDesc& d, hipStream_t s);
+
+// panel.hip -- small dense kernels of the block loop
+hipError_t launch_chol_inv(const double* gram, int b, double tau, double* R, double* Rinv,
+                           int* flag, hipStream_t s);
+hipError_t launch_upper_mul(const double* Ra, const double* Rb, int b, double* Rout, hipStream_t s);
+hipError_t launch_householder(double* X, int64_t m, int b, int64_t ldx, double* Q, int64_t ldq,
+                              double* R, double* tau, hipStream_t s);
+int64_t trsm_groups(int64_t n);
+hipError_t launch_trsm_rowsq(const double* S, int64_t lds, const double* R, int b, int64_t n,
+                             double* out, int64_t ldo, double* rowsq_part, hipStream_t s);
+hipError_t launch_gather_info(const double* rowsq, const double* R, const double* gcol, int b,
+                              double* info, hipStream_t s);
+hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s);
+hipError_t launch_fill_int(int* p, int n, int v, hipStream_t s);
+
+// spmm.hip -- CSR products and the CSR(A^T) build
+hipError_t launch_spmm_csr(const int64_t* rowptr, const int32_t* colind, const double* val,
+                           int64_t m, const double* X, int64_t ldx, double* G, int64_t ldg,
+                           int64_t w, hipStream_t s);
+int64_t colsq_groups(int64_t rows);
+hipError_t launch_colsq_rowmajor(const double* Y, int64_t rows, int64_t w, int64_t ld,
+                                 double* partial, hipStream_t s);
+struct CscLayout {
+    size_t colptr, t_col, t_val, keys_in, keys_out, perm_in, perm_out, rowidx, temp, temp_bytes,
+        total;
+};
+CscLayout csc_layout(int64_t m, int64_t n, int64_t nnz);
+hipError_t build_csc(const int64_t* rowptr, const int32_t* colind, const double* val, int64_t m,
+                     int64_t n, int64_t nnz, char* ws, hipStream_t s);
+void csc_views(int64_t m, int64_t n, int64_t nnz, char* ws, const int64_t** colptr,
+               const int32_t** t_col, const double** t_val);
+
+}  // namespace qb

@@ -1,0 +1,713 @@
+// Host orchestration and C ABI of the QB library.
+//
+// randQB_FP (Algorithm 4 with P = 0, steps 9a-9c / eq. (23)) and randQB_EI
+// (Algorithm 2), both with the row-by-row error indicator of Section 3.1.  Every
+// arithmetic step runs in the HIP kernels of this library; the host only carves the
+// caller's workspace, enqueues kernels on the caller's stream, and after each block
+// copies b row norms (plus diag(R_i) and ||A Omega_i(:,j)||^2 for the exhaustion guard)
+// to decide the rank.
+#include <math.h>
+#include <string.h>
+
+#include <vector>
+
+#include "kernels.h"
+
+namespace qb {
+
+namespace {
+
+constexpr int kMaxB = 128;
+constexpr double kExhaustRel = 0x1p-40;     // R_i(j,j) <= 2^-40 ||A Omega(:,j)|| ends the run
+constexpr double kCholTau = 1e-12;          // CholeskyQR pivot floor relative to max diag
+constexpr double kUnitRoundoff = 0x1p-53;
+constexpr int64_t kGramSplitElems = 1 << 22;
+
+#define QB_HIP(expr)                                  \
+    do {                                              \
+        const hipError_t qb_e_ = (expr);              \
+        if (qb_e_ != hipSuccess) return QB_ERR_HIP;   \
+    } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+// --------------------------------------------------------------------------- workspace
+
+struct Layout {
+    size_t red, scal, om, g, h, gpart, gnorm2, y, x2, s, w, z, d, gram, r1, r1i, rt, rti, ri, tau,
+        rowsq_part, rowsq, info, flags, split, csc, total;
+    int64_t lt, split_elems, gpart_groups;
+};
+
+int64_t chunk_width(const qb_params* p) {
+    int64_t lt = p->l_tilde == 0 ? 50 * static_cast<int64_t>(p->b) : p->l_tilde;
+    return lt < p->l_max ? lt : p->l_max;
+}
+
+Layout make_layout(int algo, int sparse, int64_t m, int64_t n, int64_t nnz, const qb_params* p) {
+    Layout L{};
+    const int64_t b = p->b;
+    const int64_t lmax = p->l_max;
+    const int64_t lt = algo == QB_ALGO_FP ? chunk_width(p) : b;   // EI: one block at a time
+    L.lt = lt;
+    L.split_elems = 512 * b * (b > 64 ? b : 64) + 65536;
+    if (L.split_elems < kGramSplitElems) L.split_elems = kGramSplitElems;
+    // row-tile partials of the G column norms: dense GEMM tiles are >= 64 rows
+    L.gpart_groups = sparse ? colsq_groups(m) : cdiv(m, 64);
+    // per-block row sums of squares of B_i: partials from the triangular solve (FP), the
+    // A^T Q_i GEMM epilogue (dense EI, tiles of >= 64 rows) or the column reduction (CSR EI)
+    int64_t nb_part = trsm_groups(n);
+    if (cdiv(n, 64) > nb_part) nb_part = cdiv(n, 64);
+    if (colsq_groups(n) > nb_part) nb_part = colsq_groups(n);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    L.red = take(sizeof(double) * 1024);
+    L.scal = take(sizeof(double) * 8);
+    L.om = take(sizeof(double) * n * lt);
+    L.g = take(sizeof(double) * m * lt);
+    L.h = algo == QB_ALGO_FP ? take(sizeof(double) * n * lt) : take(0);
+    L.gpart = take(sizeof(double) * L.gpart_groups * lt);
+    L.gnorm2 = take(sizeof(double) * lt);
+    L.y = take(sizeof(double) * m * b);
+    L.x2 = take(sizeof(double) * m * b);
+    L.s = take(sizeof(double) * b * n);
+    L.w = take(sizeof(double) * lmax * b);
+    L.z = take(sizeof(double) * lmax * b);
+    L.d = take(sizeof(double) * lmax * b);
+    L.gram = take(sizeof(double) * b * b);
+    L.r1 = take(sizeof(double) * b * b);
+    L.r1i = take(sizeof(double) * b * b);
+    L.rt = take(sizeof(double) * b * b);
+    L.rti = take(sizeof(double) * b * b);
+    L.ri = take(sizeof(double) * b * b);
+    L.tau = take(sizeof(double) * b);
+    L.rowsq_part = take(sizeof(double) * nb_part * b);
+    L.rowsq = take(sizeof(double) * b);
+    L.info = take(sizeof(double) * 3 * b);
+    L.flags = take(sizeof(int) * 8);
+    L.split = take(sizeof(double) * L.split_elems);
+    L.csc = sparse ? take(csc_layout(m, n, nnz).total) : take(0);
+    L.total = off + 256;
+    return L;
+}
+
+// --------------------------------------------------------------------------- operator
+
+// The matrix A as seen by the algorithm: products with A and A^T, and ||A||^2.
+struct Op {
+    int64_t m, n;
+    bool sparse;
+    const double* a;
+    int64_t lda;
+    const int64_t* rowptr;
+    const int32_t* colind;
+    const double* val;
+    int64_t nnz;
+    const int64_t* t_ptr;
+    const int32_t* t_col;
+    const double* t_val;
+};
+
+struct Timer {
+    hipStream_t s;
+    std::vector<hipEvent_t> ev;
+    std::vector<int> phase;
+    bool ok = true;
+    explicit Timer(hipStream_t st) : s(st) {}
+    ~Timer() {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+    void mark(int ph) {   // start of phase ph (-1 = end of the previous phase)
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) { ok = false; return; }
+        if (hipEventRecord(e, s) != hipSuccess) ok = false;
+        ev.push_back(e);
+        phase.push_back(ph);
+    }
+    // accumulate the time between consecutive marks into the phase of the earlier mark
+    void collect(double* ms) {
+        for (size_t i = 0; i + 1 < ev.size(); ++i) {
+            float t = 0.f;
+            if (phase[i] >= 0 && hipEventElapsedTime(&t, ev[i], ev[i + 1]) == hipSuccess)
+                ms[phase[i]] += t;
+        }
+        if (ev.size() >= 2) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, ev.front(), ev.back()) == hipSuccess) ms[5] = t;
+        }
+    }
+};
+
+struct Ctx {
+    Op A;
+    const qb_params* p;
+    double* Q;
+    int64_t ldq;
+    double* B;
+    int64_t ldb;
+    char* ws;
+    Layout L;
+    hipStream_t s;
+    qb_info* info;
+    Timer* tm;
+    double* host_info;   // 3 b doubles + flags
+    template <class T>
+    T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+};
+
+GemmDesc gdesc(int64_t M, int64_t N, int64_t K, View a, View b, double alpha, double beta, View c0,
+               MutView c, const Ctx& x) {
+    GemmDesc d{};
+    d.M = M; d.N = N; d.K = K; d.A = a; d.B = b; d.alpha = alpha; d.beta = beta; d.C0 = c0; d.C = c;
+    d.colsq = nullptr; d.colsq_groups = nullptr;
+    d.ws = x.at<double>(x.L.split); d.ws_elems = x.L.split_elems; d.max_split = 0;
+    return d;
+}
+
+// G(:, 0:w) = A X (X: n x w row-major, ld ldx); also the column sums of squares of G
+// into gnorm2[0:w].  ldg is G's row stride.
+int apply_A(const Ctx& x, const double* X, int64_t ldx, double* G, int64_t ldg, int64_t w,
+            double* gnorm2) {
+    const Op& A = x.A;
+    double* gpart = x.at<double>(x.L.gpart);
+    int groups = 0;
+    if (!A.sparse) {
+        GemmDesc d = gdesc(A.m, w, A.n, View{A.a, A.lda, 1}, View{X, ldx, 1}, 1.0, 0.0,
+                           View{nullptr, 0, 0}, MutView{G, ldg, 1}, x);
+        d.colsq = gpart;
+        d.colsq_groups = &groups;
+        QB_HIP(gemm_f64(d, x.s));
+    } else {
+        QB_HIP(launch_spmm_csr(A.rowptr, A.colind, A.val, A.m, X, ldx, G, ldg, w, x.s));
+        QB_HIP(launch_colsq_rowmajor(G, A.m, w, ldg, gpart, x.s));
+        groups = static_cast<int>(colsq_groups(A.m));
+    }
+    QB_HIP(launch_sum_partials(gpart, groups, w, w, gnorm2, x.s));
+    return QB_OK;
+}
+
+// H(:, 0:w) = A^T G (G: m x w row-major, ld ldg) into H (n x w row-major, ld ldh).
+int apply_At(const Ctx& x, const double* G, int64_t ldg, double* H, int64_t ldh, int64_t w) {
+    const Op& A = x.A;
+    if (!A.sparse) {
+        GemmDesc d = gdesc(A.n, w, A.m, View{A.a, 1, A.lda}, View{G, ldg, 1}, 1.0, 0.0,
+                           View{nullptr, 0, 0}, MutView{H, ldh, 1}, x);
+        QB_HIP(gemm_f64(d, x.s));
+    } else {
+        QB_HIP(launch_spmm_csr(A.t_ptr, A.t_col, A.t_val, A.n, G, ldg, H, ldh, w, x.s));
+    }
+    return QB_OK;
+}
+
+// CholeskyQR of the m x bw column-major panel X (ld m) into Qout (column-major, ld ldq):
+// gram = X^T X, R, R^{-1}, Qout = X R^{-1}.  A breakdown sets flags[0].
+int cholqr(const Ctx& x, const double* X, int bw, double* Qout, int64_t ldq, double* R,
+           double* Rinv) {
+    const int64_t m = x.A.m;
+    double* gram = x.at<double>(x.L.gram);
+    GemmDesc d = gdesc(bw, bw, m, View{X, m, 1}, View{X, 1, m}, 1.0, 0.0, View{nullptr, 0, 0},
+                       MutView{gram, bw, 1}, x);
+    QB_HIP(gemm_f64(d, x.s));
+    QB_HIP(launch_chol_inv(gram, bw, kCholTau, R, Rinv, x.at<int>(x.L.flags), x.s));
+    GemmDesc q = gdesc(m, bw, bw, View{X, 1, m}, View{Rinv, bw, 1}, 1.0, 0.0, View{nullptr, 0, 0},
+                       MutView{Qout, 1, ldq}, x);
+    QB_HIP(gemm_f64(q, x.s));
+    return QB_OK;
+}
+
+// Steps 11-14 of Algorithm 4 (steps 5-6 of Algorithm 2): given G_J (m x bw, row-major,
+// ld ldgj) and Omega_J (n x bw, row-major, ld ldoj), form W = B Omega_J,
+// Y = G_J - Q W (kept in the y buffer), Q_i = qr(Y), Q_i = qr(Q_i - Q (Q^T Q_i)) and
+// R_i = R~ R.  use_hh selects Householder instead of CholeskyQR for both qr calls.
+int orth_block(const Ctx& x, int64_t k, int bw, const double* GJ, int64_t ldgj, const double* OmJ,
+               int64_t ldoj, bool use_hh) {
+    const int64_t m = x.A.m, n = x.A.n;
+    double* Y = x.at<double>(x.L.y);
+    double* X2 = x.at<double>(x.L.x2);
+    double* W = x.at<double>(x.L.w);
+    double* Z = x.at<double>(x.L.z);
+    double* Qi = x.Q + k * x.ldq;
+    double* R1 = x.at<double>(x.L.r1);
+    double* R1i = x.at<double>(x.L.r1i);
+    double* Rt = x.at<double>(x.L.rt);
+    double* Rti = x.at<double>(x.L.rti);
+    double* tau = x.at<double>(x.L.tau);
+    // W = B(0:k, :) Omega_J   (k x bw, row-major ld bw)
+    if (k > 0) {
+        GemmDesc d = gdesc(k, bw, n, View{x.B, x.ldb, 1}, View{OmJ, ldoj, 1}, 1.0, 0.0,
+                           View{nullptr, 0, 0}, MutView{W, bw, 1}, x);
+        QB_HIP(gemm_f64(d, x.s));
+    }
+    // Y = G_J - Q W   (m x bw, column-major ld m)
+    {
+        GemmDesc d = gdesc(m, bw, k, View{x.Q, 1, x.ldq}, View{W, bw, 1}, -1.0, 1.0,
+                           View{GJ, ldgj, 1}, MutView{Y, 1, m}, x);
+        QB_HIP(gemm_f64(d, x.s));
+    }
+    // first qr
+    if (!use_hh) {
+        if (int st = cholqr(x, Y, bw, Qi, x.ldq, R1, R1i)) return st;
+    } else {
+        QB_HIP(hipMemcpyAsync(X2, Y, sizeof(double) * m * bw, hipMemcpyDeviceToDevice, x.s));
+        QB_HIP(launch_householder(X2, m, bw, m, Qi, x.ldq, R1, tau, x.s));
+    }
+    // re-orthogonalisation: X2 = Q_i - Q (Q^T Q_i)
+    if (k > 0) {
+        GemmDesc d = gdesc(k, bw, m, View{x.Q, x.ldq, 1}, View{Qi, 1, x.ldq}, 1.0, 0.0,
+                           View{nullptr, 0, 0}, MutView{Z, bw, 1}, x);
+        QB_HIP(gemm_f64(d, x.s));
+    }
+    {
+        GemmDesc d = gdesc(m, bw, k, View{x.Q, 1, x.ldq}, View{Z, bw, 1}, -1.0, 1.0,
+                           View{Qi, 1, x.ldq}, MutView{X2, 1, m}, x);
+        QB_HIP(gemm_f64(d, x.s));
+    }
+    if (!use_hh) {
+        if (int st = cholqr(x, X2, bw, Qi, x.ldq, Rt, Rti)) return st;
+    } else {
+        QB_HIP(launch_householder(X2, m, bw, m, Qi, x.ldq, Rt, tau, x.s));
+    }
+    QB_HIP(launch_upper_mul(Rt, R1, bw, x.at<double>(x.L.ri), x.s));
+    return QB_OK;
+}
+
+// Step 15 of Algorithm 4 (eq. (23)):
+//   B_i = R_i^{-T} (H_J^T - (Y^T Q) B - W^T B) = R_i^{-T} (H_J^T - D^T B),  D = Q^T Y + W,
+// written to rows k..k+bw of B with the row sums of squares into the rowsq buffer.
+int fp_block_b(const Ctx& x, int64_t k, int bw, const double* HJ, int64_t ldhj) {
+    const int64_t m = x.A.m, n = x.A.n;
+    double* Y = x.at<double>(x.L.y);
+    double* W = x.at<double>(x.L.w);
+    double* D = x.at<double>(x.L.d);
+    double* S = x.at<double>(x.L.s);
+    if (k > 0) {   // D (k x bw) = Q^T Y + W
+        GemmDesc d = gdesc(k, bw, m, View{x.Q, x.ldq, 1}, View{Y, 1, m}, 1.0, 1.0, View{W, bw, 1},
+                           MutView{D, bw, 1}, x);
+        QB_HIP(gemm_f64(d, x.s));
+    }
+    {   // S^T (n x bw) = H_J - B^T D, stored as S (bw x n row-major)
+        GemmDesc d = gdesc(n, bw, k, View{x.B, 1, x.ldb}, View{D, bw, 1}, -1.0, 1.0,
+                           View{HJ, ldhj, 1}, MutView{S, 1, n}, x);
+        QB_HIP(gemm_f64(d, x.s));
+    }
+    double* part = x.at<double>(x.L.rowsq_part);
+    QB_HIP(launch_trsm_rowsq(S, n, x.at<double>(x.L.ri), bw, n, x.B + k * x.ldb, x.ldb, part, x.s));
+    QB_HIP(launch_sum_partials(part, trsm_groups(n), bw, bw, x.at<double>(x.L.rowsq), x.s));
+    return QB_OK;
+}
+
+// Step 7 of Algorithm 2: B_i = Q_i^T A, computed as (A^T Q_i)^T into rows k..k+bw of B,
+// with the row sums of squares into the rowsq buffer.
+int ei_block_b(const Ctx& x, int64_t k, int bw) {
+    const Op& A = x.A;
+    double* Qi = x.Q + k * x.ldq;
+    double* rowsq = x.at<double>(x.L.rowsq);
+    double* part = x.at<double>(x.L.rowsq_part);
+    if (!A.sparse) {
+        int groups = 0;
+        GemmDesc d = gdesc(A.n, bw, A.m, View{A.a, 1, A.lda}, View{Qi, 1, x.ldq}, 1.0, 0.0,
+                           View{nullptr, 0, 0}, MutView{x.B + k * x.ldb, 1, x.ldb}, x);
+        d.colsq = part;
+        d.colsq_groups = &groups;
+        QB_HIP(gemm_f64(d, x.s));
+        QB_HIP(launch_sum_partials(part, groups, bw, bw, rowsq, x.s));
+    } else {
+        // H-style product into the S buffer (n x bw row-major), then transpose-copy via GEMM
+        double* S = x.at<double>(x.L.s);
+        // Q_i is column-major; make a row-major copy in X2 (m x bw) for the row-wave SpMM
+        double* X2 = x.at<double>(x.L.x2);
+        GemmDesc c = gdesc(A.m, bw, 0, View{nullptr, 0, 0}, View{nullptr, 0, 0}, 0.0, 1.0,
+                           View{Qi, 1, x.ldq}, MutView{X2, bw, 1}, x);
+        QB_HIP(gemm_f64(c, x.s));
+        QB_HIP(launch_spmm_csr(A.t_ptr, A.t_col, A.t_val, A.n, X2, bw, S, bw, bw, x.s));
+        GemmDesc t = gdesc(A.n, bw, 0, View{nullptr, 0, 0}, View{nullptr, 0, 0}, 0.0, 1.0,
+                           View{S, bw, 1}, MutView{x.B + k * x.ldb, 1, x.ldb}, x);
+        QB_HIP(gemm_f64(t, x.s));
+        QB_HIP(launch_colsq_rowmajor(S, A.n, bw, bw, part, x.s));
+        QB_HIP(launch_sum_partials(part, colsq_groups(A.n), bw, bw, rowsq, x.s));
+    }
+    return QB_OK;
+}
+
+// Copy the per-block decision data to the host and wait.  Returns QB_OK or QB_ERR_HIP;
+// *breakdown tells whether CholeskyQR failed in this block.
+int fetch_block(const Ctx& x, int bw, const double* gnorm2_j, bool* breakdown) {
+    double* info = x.at<double>(x.L.info);
+    QB_HIP(launch_gather_info(x.at<double>(x.L.rowsq), x.at<double>(x.L.ri), gnorm2_j, bw, info,
+                              x.s));
+    QB_HIP(hipMemcpyAsync(x.host_info, info, sizeof(double) * 3 * bw, hipMemcpyDeviceToHost, x.s));
+    int* hflag = reinterpret_cast<int*>(x.host_info + 3 * kMaxB);
+    QB_HIP(hipMemcpyAsync(hflag, x.at<int>(x.L.flags), sizeof(int), hipMemcpyDeviceToHost, x.s));
+    QB_HIP(hipStreamSynchronize(x.s));
+    *breakdown = *hflag != 0;
+    return QB_OK;
+}
+
+// Steps 7a-8e (or Algorithm 1 steps 7-8) with the exhaustion guard.
+void scan_rows(const double* hinfo, int bw, bool row_by_row, double eps2, double* E, int* keep,
+               bool* stop, bool* exhausted) {
+    const double* rowsq = hinfo;
+    const double* rdiag = hinfo + bw;
+    const double* g2 = hinfo + 2 * bw;
+    *stop = false;
+    *exhausted = false;
+    *keep = bw;
+    double Et = *E;
+    for (int j = 0; j < bw; ++j) {
+        if (!(rdiag[j] > kExhaustRel * sqrt(g2[j]))) {
+            *keep = j;
+            *stop = true;
+            *exhausted = true;
+            *E = Et;
+            return;
+        }
+        Et -= rowsq[j];
+        if (row_by_row && Et < eps2) {
+            *keep = j + 1;
+            *stop = true;
+            *E = Et;
+            return;
+        }
+    }
+    *E = Et;
+    if (!row_by_row && Et < eps2) *stop = true;
+}
+
+int check_params(const qb_params* p, int64_t m, int64_t n) {
+    if (p == nullptr) return QB_ERR_ARG;
+    if (p->power != 0) return QB_ERR_UNSUPPORTED;
+    if (!(p->tol_rel >= 0.0) || !isfinite(p->tol_rel)) return QB_ERR_ARG;
+    if (p->b < 1 || p->b > kMaxB) return QB_ERR_ARG;
+    const int64_t mn = m < n ? m : n;
+    if (p->l_max < 1 || p->l_max > mn) return QB_ERR_ARG;
+    if (p->l_tilde < 0) return QB_ERR_ARG;
+    if (p->l_tilde != 0 && p->l_tilde % p->b != 0 && p->l_tilde < p->l_max) return QB_ERR_ARG;
+    if (m >= (int64_t(1) << 31) || n >= (int64_t(1) << 31)) return QB_ERR_ARG;
+    return QB_OK;
+}
+
+thread_local double* t_pinned = nullptr;
+
+double* pinned_buffer() {
+    if (t_pinned == nullptr) {
+        void* p = nullptr;
+        if (hipHostMalloc(&p, sizeof(double) * (3 * kMaxB + 64), hipHostMallocDefault) != hipSuccess)
+            return nullptr;
+        t_pinned = static_cast<double*>(p);
+    }
+    return t_pinned;
+}
+
+// The common driver of the four entry points.
+int run(int algo, Op& A, const qb_params* p, double* Q, int64_t ldq, double* B, int64_t ldb,
+        void* ws, size_t ws_bytes, hipStream_t s, qb_info* info) {
+    qb_info local{};
+    qb_info* inf = info ? info : &local;
+    memset(inf, 0, sizeof(*inf));
+    int st = check_params(p, A.m, A.n);
+    if (st != QB_OK) return inf->status = st;
+    if (Q == nullptr || B == nullptr || ws == nullptr || ldq < A.m || ldb < A.n)
+        return inf->status = QB_ERR_ARG;
+    if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return inf->status = QB_ERR_ARG;
+    const Layout L = make_layout(algo, A.sparse, A.m, A.n, A.nnz, p);
+    if (ws_bytes < L.total) return inf->status = QB_ERR_WORKSPACE;
+    double* host = pinned_buffer();
+    if (host == nullptr) return inf->status = QB_ERR_HIP;
+
+    Timer tm(s);
+    const int64_t m = A.m, n = A.n, b = p->b, lmax = p->l_max;
+    char* wsb = static_cast<char*>(ws);
+    double* scal = reinterpret_cast<double*>(wsb + L.scal);
+    double* red = reinterpret_cast<double*>(wsb + L.red);
+
+    // ||A||_F^2 (Algorithm 4 step 9)
+    tm.mark(0);
+    if (!A.sparse) {
+        QB_HIP(launch_sumsq_dense(A.a, m, n, A.lda, red, scal, s));
+    } else {
+        QB_HIP(launch_sumsq_vec(A.val, A.nnz, red, scal, s));
+        // CSR(A^T) for the A^T products, built once; its views must be in A before the
+        // context below takes its copy of the operator
+        QB_HIP(build_csc(A.rowptr, A.colind, A.val, m, n, A.nnz, wsb + L.csc, s));
+        csc_views(m, n, A.nnz, wsb + L.csc, &A.t_ptr, &A.t_col, &A.t_val);
+    }
+    const Ctx x{A, p, Q, ldq, B, ldb, wsb, L, s, inf, &tm, host};
+    QB_HIP(hipMemcpyAsync(host, scal, sizeof(double), hipMemcpyDeviceToHost, s));
+    QB_HIP(hipStreamSynchronize(s));
+    const double normA2 = host[0];
+    inf->normA2 = normA2;
+    if (!isfinite(normA2)) {
+        tm.mark(-1);
+        return inf->status = QB_ERR_NONFINITE;
+    }
+    const double eps2 = p->tol_rel * p->tol_rel * normA2;
+    const double floor_tol = sqrt(4.0 * kUnitRoundoff / 0.01);   // Theorem 3, delta = 1%
+    const int status_tol = p->tol_rel < floor_tol ? QB_WARN_TOL_FLOOR : QB_OK;
+    double E = normA2;
+    int64_t k = 0;
+    bool exhausted = false;
+    if (!(normA2 == 0.0 || E < eps2)) {
+        QB_HIP(launch_fill_int(x.at<int>(L.flags), 8, 0, s));
+        int64_t chunk_lo = 0, chunk_hi = 0;
+        double* Om = x.at<double>(L.om);
+        double* G = x.at<double>(L.g);
+        double* H = x.at<double>(L.h);
+        double* gnorm2 = x.at<double>(L.gnorm2);
+        bool stop = false;
+        while (k < lmax && !stop) {
+            int64_t bw;
+            const double *GJ, *OmJ, *HJ = nullptr, *g2J;
+            int64_t ldj;
+            if (algo == QB_ALGO_FP) {
+                if (k == chunk_hi) {   // draw the next chunk of Omega; G = A Omega, H = A^T G
+                    chunk_lo = k;
+                    chunk_hi = k + L.lt < lmax ? k + L.lt : lmax;
+                    const int64_t w = chunk_hi - chunk_lo;
+                    tm.mark(1);
+                    QB_HIP(launch_gauss_fill(p->seed, 0, 0, 0, chunk_lo, n, w, Om, w, s));
+                    tm.mark(2);
+                    if (int e = apply_A(x, Om, w, G, w, w, gnorm2)) return inf->status = e;
+                    tm.mark(3);
+                    if (int e = apply_At(x, G, w, H, w, w)) return inf->status = e;
+                    tm.mark(4);
+                    inf->passes += 2;
+                    inf->chunks += 1;
+                    inf->gemm_flops[0] += 2.0 * m * n * w;
+                    inf->gemm_flops[1] += 2.0 * m * n * w;
+                }
+                bw = b < chunk_hi - k ? b : chunk_hi - k;
+                ldj = chunk_hi - chunk_lo;
+                const int64_t J0 = k - chunk_lo;
+                GJ = G + J0;
+                OmJ = Om + J0;
+                HJ = H + J0;
+                g2J = gnorm2 + J0;
+            } else {
+                bw = b < lmax - k ? b : lmax - k;
+                ldj = bw;
+                tm.mark(1);
+                QB_HIP(launch_gauss_fill(p->seed, 0, 0, 0, k, n, bw, Om, bw, s));
+                tm.mark(2);
+                if (int e = apply_A(x, Om, bw, G, bw, bw, gnorm2)) return inf->status = e;
+                tm.mark(4);
+                inf->passes += 2;
+                inf->gemm_flops[0] += 2.0 * m * n * bw;
+                inf->gemm_flops[1] += 2.0 * m * n * bw;
+                GJ = G;
+                OmJ = Om;
+                g2J = gnorm2;
+            }
+            const int bwi = static_cast<int>(bw);
+            bool breakdown = false;
+            for (int attempt = 0; attempt < 2; ++attempt) {
+                const bool use_hh = attempt == 1;
+                if (use_hh) {
+                    QB_HIP(launch_fill_int(x.at<int>(L.flags), 8, 0, s));
+                    inf->fallbacks += 1;
+                }
+                if (int e = orth_block(x, k, bwi, GJ, ldj, OmJ, ldj, use_hh)) return inf->status = e;
+                if (algo == QB_ALGO_FP) {
+                    if (int e = fp_block_b(x, k, bwi, HJ, ldj)) return inf->status = e;
+                } else {
+                    tm.mark(3);
+                    if (int e = ei_block_b(x, k, bwi)) return inf->status = e;
+                    tm.mark(4);
+                }
+                if (int e = fetch_block(x, bwi, g2J, &breakdown)) return inf->status = e;
+                if (!breakdown) break;
+            }
+            inf->blocks += 1;
+            int keep = 0;
+            bool exh = false;
+            scan_rows(host, bwi, p->row_by_row != 0, eps2, &E, &keep, &stop, &exh);
+            k += keep;
+            if (exh) exhausted = true;
+        }
+    }
+    tm.mark(-1);
+    QB_HIP(hipStreamSynchronize(s));
+    tm.collect(inf->ms);
+    inf->rank = k;
+    inf->E = E;
+    inf->exhausted = exhausted ? 1 : 0;
+    if (normA2 == 0.0 || E < eps2)
+        st = status_tol;
+    else
+        st = QB_NOT_CONVERGED;
+    return inf->status = st;
+}
+
+Op dense_op(const qb_dense* A) {
+    Op o{};
+    o.m = A->m; o.n = A->n; o.sparse = false;
+    o.a = static_cast<const double*>(A->a); o.lda = A->lda;
+    return o;
+}
+
+Op csr_op(const qb_csr* A) {
+    Op o{};
+    o.m = A->m; o.n = A->n; o.sparse = true;
+    o.rowptr = A->rowptr; o.colind = A->colind; o.val = A->val; o.nnz = A->nnz;
+    return o;
+}
+
+int check_dense(const qb_dense* A) {
+    if (A == nullptr || A->a == nullptr || A->m < 1 || A->n < 1 || A->lda < A->n) return QB_ERR_ARG;
+    if (A->dtype != QB_F64) return QB_ERR_UNSUPPORTED;
+    return QB_OK;
+}
+
+int check_csr(const qb_csr* A) {
+    if (A == nullptr || A->m < 1 || A->n < 1 || A->nnz < 0 || A->rowptr == nullptr) return QB_ERR_ARG;
+    if (A->nnz > 0 && (A->colind == nullptr || A->val == nullptr)) return QB_ERR_ARG;
+    if (A->nnz >= (int64_t(1) << 31)) return QB_ERR_ARG;
+    return QB_OK;
+}
+
+}  // namespace
+}  // namespace qb
+
+using namespace qb;
+
+extern "C" {
+
+size_t qb_workspace_bytes(int algo, int sparse, int64_t m, int64_t n, int64_t nnz,
+                          const qb_params* p) {
+    if ((algo != QB_ALGO_FP && algo != QB_ALGO_EI) || m < 1 || n < 1) return 0;
+    if (check_params(p, m, n) != QB_OK) return 0;
+    return make_layout(algo, sparse != 0, m, n, nnz, p).total;
+}
+
+int qb_fp_dense(const qb_dense* A, const qb_params* p, double* Q, int64_t ldq, double* B,
+                int64_t ldb, void* ws, size_t ws_bytes, hipStream_t stream, qb_info* info) {
+    if (int st = check_dense(A)) {
+        if (info) info->status = st;
+        return st;
+    }
+    Op o = dense_op(A);
+    return run(QB_ALGO_FP, o, p, Q, ldq, B, ldb, ws, ws_bytes, stream, info);
+}
+
+int qb_ei_dense(const qb_dense* A, const qb_params* p, double* Q, int64_t ldq, double* B,
+                int64_t ldb, void* ws, size_t ws_bytes, hipStream_t stream, qb_info* info) {
+    if (int st = check_dense(A)) {
+        if (info) info->status = st;
+        return st;
+    }
+    Op o = dense_op(A);
+    return run(QB_ALGO_EI, o, p, Q, ldq, B, ldb, ws, ws_bytes, stream, info);
+}
+
+int qb_fp_csr(const qb_csr* A, const qb_params* p, double* Q, int64_t ldq, double* B, int64_t ldb,
+              void* ws, size_t ws_bytes, hipStream_t stream, qb_info* info) {
+    if (int st = check_csr(A)) {
+        if (info) info->status = st;
+        return st;
+    }
+    Op o = csr_op(A);
+    return run(QB_ALGO_FP, o, p, Q, ldq, B, ldb, ws, ws_bytes, stream, info);
+}
+
+int qb_ei_csr(const qb_csr* A, const qb_params* p, double* Q, int64_t ldq, double* B, int64_t ldb,
+              void* ws, size_t ws_bytes, hipStream_t stream, qb_info* info) {
+    if (int st = check_csr(A)) {
+        if (info) info->status = st;
+        return st;
+    }
+    Op o = csr_op(A);
+    return run(QB_ALGO_EI, o, p, Q, ldq, B, ldb, ws, ws_bytes, stream, info);
+}
+
+int qb_gaussian_fill(uint64_t seed, uint32_t stream_id, uint32_t batch, int64_t row0, int64_t col0,
+                     int64_t rows, int64_t cols, double* out, int64_t ld, hipStream_t stream) {
+    if (rows < 0 || cols < 0 || row0 < 0 || col0 < 0 || (rows > 0 && cols > 0 && out == nullptr) ||
+        ld < cols || row0 + rows > (int64_t(1) << 32) || col0 + cols > (int64_t(1) << 33))
+        return QB_ERR_ARG;
+    return launch_gauss_fill(seed, stream_id, batch, row0, col0, rows, cols, out, ld, stream) ==
+                   hipSuccess
+               ? QB_OK
+               : QB_ERR_HIP;
+}
+
+size_t qb_sumsq_workspace_bytes(void) { return sizeof(double) * 1040; }
+
+int qb_sumsq_dense(const qb_dense* A, double* out_host, void* ws, hipStream_t stream) {
+    if (int st = check_dense(A)) return st;
+    if (out_host == nullptr || ws == nullptr) return QB_ERR_ARG;
+    double* scratch = static_cast<double*>(ws);
+    double* res = scratch + 1024;
+    QB_HIP(launch_sumsq_dense(static_cast<const double*>(A->a), A->m, A->n, A->lda, scratch, res,
+                              stream));
+    QB_HIP(hipMemcpyAsync(out_host, res, sizeof(double), hipMemcpyDeviceToHost, stream));
+    QB_HIP(hipStreamSynchronize(stream));
+    return QB_OK;
+}
+
+int qb_sketch_dense(const qb_dense* A, uint64_t seed, int64_t col0, int64_t l, double* om, double* g,
+                    double* h, hipStream_t stream) {
+    if (int st = check_dense(A)) return st;
+    if (l < 1 || col0 < 0 || om == nullptr || g == nullptr || h == nullptr) return QB_ERR_ARG;
+    const int64_t m = A->m, n = A->n;
+    QB_HIP(launch_gauss_fill(seed, 0, 0, 0, col0, n, l, om, l, stream));
+    GemmDesc d{};
+    d.M = m; d.N = l; d.K = n;
+    d.A = View{static_cast<const double*>(A->a), A->lda, 1};
+    d.B = View{om, l, 1};
+    d.alpha = 1.0; d.beta = 0.0;
+    d.C = MutView{g, l, 1};
+    QB_HIP(gemm_f64(d, stream));
+    GemmDesc e{};
+    e.M = n; e.N = l; e.K = m;
+    e.A = View{static_cast<const double*>(A->a), 1, A->lda};
+    e.B = View{g, l, 1};
+    e.alpha = 1.0; e.beta = 0.0;
+    e.C = MutView{h, l, 1};
+    QB_HIP(gemm_f64(e, stream));
+    return QB_OK;
+}
+
+size_t qb_csr_transpose_bytes(const qb_csr* A) {
+    if (check_csr(A) != QB_OK) return 0;
+    return csc_layout(A->m, A->n, A->nnz).total;
+}
+
+int qb_sketch_csr(const qb_csr* A, uint64_t seed, int64_t col0, int64_t l, double* om, double* g,
+                  double* h, void* csc_ws, int* csc_ready, hipStream_t stream) {
+    if (int st = check_csr(A)) return st;
+    if (l < 1 || col0 < 0 || om == nullptr || g == nullptr || h == nullptr || csc_ws == nullptr ||
+        csc_ready == nullptr)
+        return QB_ERR_ARG;
+    char* ws = static_cast<char*>(csc_ws);
+    if (!*csc_ready) {
+        QB_HIP(build_csc(A->rowptr, A->colind, A->val, A->m, A->n, A->nnz, ws, stream));
+        *csc_ready = 1;
+    }
+    const int64_t* tp;
+    const int32_t* tc;
+    const double* tv;
+    csc_views(A->m, A->n, A->nnz, ws, &tp, &tc, &tv);
+    QB_HIP(launch_gauss_fill(seed, 0, 0, 0, col0, A->n, l, om, l, stream));
+    QB_HIP(launch_spmm_csr(A->rowptr, A->colind, A->val, A->m, om, l, g, l, l, stream));
+    QB_HIP(launch_spmm_csr(tp, tc, tv, A->n, g, l, h, l, l, stream));
+    return QB_OK;
+}
+
+const char* qb_status_string(int status) {
+    switch (status) {
+        case QB_OK: return "QB_OK";
+        case QB_NOT_CONVERGED: return "QB_NOT_CONVERGED";
+        case QB_WARN_TOL_FLOOR: return "QB_WARN_TOL_FLOOR";
+        case QB_ERR_ARG: return "QB_ERR_ARG";
+        case QB_ERR_NONFINITE: return "QB_ERR_NONFINITE";
+        case QB_ERR_WORKSPACE: return "QB_ERR_WORKSPACE";
+        case QB_ERR_HIP: return "QB_ERR_HIP";
+        case QB_ERR_UNSUPPORTED: return "QB_ERR_UNSUPPORTED";
+        default: return "QB_UNKNOWN_STATUS";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,183 @@
+// Sparse products for CSR input (Section 5.1 stores sparse A in CSR):
+//   G = A X        one wavefront per row of A; the lanes span the dense columns so
+//                  every gathered row of X is read with coalesced 64-lane loads;
+//   H = A^T G      the same kernel on CSR(A^T), built once by a stable sort of the
+//                  nonzeros by column (rows stay ascending inside each column, so the
+//                  accumulation order -- and the result bits -- are reproducible).
+// No floating-point atomics.
+#include <hipcub/hipcub.hpp>
+
+#include "kernels.h"
+
+namespace qb {
+
+constexpr int kSpmmThreads = 256;          // 4 rows per workgroup
+constexpr int kSpmmCols = 64 * 4;          // dense columns per wave pass (4 per lane)
+
+// G(i, c0 + t) = sum_e val[e] X(colind[e], c0 + t) for the columns of this pass.
+__global__ void __launch_bounds__(kSpmmThreads)
+spmm_csr_rowwave_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
+                        const double* __restrict__ val, int64_t m, const double* __restrict__ X,
+                        int64_t ldx, double* __restrict__ G, int64_t ldg, int64_t w) {
+    const int lane = threadIdx.x & 63;
+    const int64_t row = static_cast<int64_t>(blockIdx.x) * (kSpmmThreads / 64) + (threadIdx.x >> 6);
+    if (row >= m) return;
+    const int64_t c0 = static_cast<int64_t>(blockIdx.y) * kSpmmCols;
+    const int64_t e0 = rowptr[row], e1 = rowptr[row + 1];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    bool ok[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) ok[t] = c0 + lane + 64 * t < w;
+    for (int64_t e = e0; e < e1; ++e) {
+        const double v = val[e];
+        const double* xr = X + static_cast<int64_t>(colind[e]) * ldx + c0 + lane;
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            if (ok[t]) acc[t] += v * xr[64 * t];
+    }
+    double* gr = G + row * ldg + c0 + lane;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+        if (ok[t]) gr[64 * t] = acc[t];
+}
+
+// Column sums of squares of a row-major rows x w matrix: workgroup g sums rows
+// g, g + G, ... for 256 columns; partial[g * w + j].
+__global__ void __launch_bounds__(256)
+colsq_rowmajor_kernel(const double* __restrict__ Y, int64_t rows, int64_t w, int64_t ld,
+                      double* __restrict__ partial) {
+    const int64_t j = static_cast<int64_t>(blockIdx.y) * 256 + threadIdx.x;
+    if (j >= w) return;
+    double t = 0.0;
+    for (int64_t i = blockIdx.x; i < rows; i += gridDim.x) {
+        const double v = Y[i * ld + j];
+        t += v * v;
+    }
+    partial[static_cast<int64_t>(blockIdx.x) * w + j] = t;
+}
+
+// rowidx[e] = row of nonzero e
+__global__ void csr_rowidx_kernel(const int64_t* __restrict__ rowptr, int64_t m,
+                                  int32_t* __restrict__ rowidx) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) rowidx[e] = static_cast<int32_t>(i);
+}
+
+__global__ void iota_kernel(int32_t* __restrict__ p, int64_t n) {
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e < n) p[e] = static_cast<int32_t>(e);
+}
+
+// gather the transposed entries and locate column starts by binary search in the
+// sorted keys (no atomics)
+__global__ void csc_finish_kernel(const int32_t* __restrict__ keys_sorted,
+                                  const int32_t* __restrict__ perm, const int32_t* __restrict__ rowidx,
+                                  const double* __restrict__ val, int64_t nnz, int64_t n,
+                                  int64_t* __restrict__ colptr, int32_t* __restrict__ t_col,
+                                  double* __restrict__ t_val) {
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e < nnz) {
+        const int32_t src = perm[e];
+        t_col[e] = rowidx[src];
+        t_val[e] = val[src];
+    }
+    if (e <= n) {
+        int64_t lo = 0, hi = nnz;   // first position with key >= e
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (keys_sorted[mid] < e) lo = mid + 1; else hi = mid;
+        }
+        colptr[e] = lo;
+    }
+}
+
+// ------------------------------------------------------------------------------ host
+
+hipError_t launch_spmm_csr(const int64_t* rowptr, const int32_t* colind, const double* val,
+                           int64_t m, const double* X, int64_t ldx, double* G, int64_t ldg,
+                           int64_t w, hipStream_t s) {
+    if (m <= 0 || w <= 0) return hipSuccess;
+    dim3 grid(static_cast<unsigned>(cdiv(m, kSpmmThreads / 64)),
+              static_cast<unsigned>(cdiv(w, kSpmmCols)));
+    hipLaunchKernelGGL(spmm_csr_rowwave_kernel, grid, dim3(kSpmmThreads), 0, s, rowptr, colind, val,
+                       m, X, ldx, G, ldg, w);
+    return hipGetLastError();
+}
+
+int64_t colsq_groups(int64_t rows) { return rows < 512 ? (rows > 0 ? rows : 1) : 512; }
+
+hipError_t launch_colsq_rowmajor(const double* Y, int64_t rows, int64_t w, int64_t ld,
+                                 double* partial, hipStream_t s) {
+    if (w <= 0) return hipSuccess;
+    dim3 grid(static_cast<unsigned>(colsq_groups(rows)), static_cast<unsigned>(cdiv(w, 256)));
+    hipLaunchKernelGGL(colsq_rowmajor_kernel, grid, dim3(256), 0, s, Y, rows, w, ld, partial);
+    return hipGetLastError();
+}
+
+
+static size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+CscLayout csc_layout(int64_t m, int64_t n, int64_t nnz) {
+    (void)m;
+    CscLayout L{};
+    size_t temp_bytes = 0;
+    hipcub::DeviceRadixSort::SortPairs(nullptr, temp_bytes, static_cast<const int32_t*>(nullptr),
+                                       static_cast<int32_t*>(nullptr),
+                                       static_cast<const int32_t*>(nullptr),
+                                       static_cast<int32_t*>(nullptr), static_cast<int>(nnz));
+    size_t off = 0;
+    L.colptr = off; off = align256(off + sizeof(int64_t) * (n + 1));
+    L.t_col = off; off = align256(off + sizeof(int32_t) * nnz);
+    L.t_val = off; off = align256(off + sizeof(double) * nnz);
+    L.keys_in = off; off = align256(off + sizeof(int32_t) * nnz);
+    L.keys_out = off; off = align256(off + sizeof(int32_t) * nnz);
+    L.perm_in = off; off = align256(off + sizeof(int32_t) * nnz);
+    L.perm_out = off; off = align256(off + sizeof(int32_t) * nnz);
+    L.rowidx = off; off = align256(off + sizeof(int32_t) * nnz);
+    L.temp = off; off = align256(off + temp_bytes + 256);
+    L.temp_bytes = temp_bytes + 256;
+    L.total = off;
+    return L;
+}
+
+// Build CSR(A^T) (= CSC of A) inside ws.  Column count of A^T rows = n.
+hipError_t build_csc(const int64_t* rowptr, const int32_t* colind, const double* val, int64_t m,
+                     int64_t n, int64_t nnz, char* ws, hipStream_t s) {
+    const CscLayout L = csc_layout(m, n, nnz);
+    int64_t* colptr = reinterpret_cast<int64_t*>(ws + L.colptr);
+    int32_t* t_col = reinterpret_cast<int32_t*>(ws + L.t_col);
+    double* t_val = reinterpret_cast<double*>(ws + L.t_val);
+    int32_t* keys_in = reinterpret_cast<int32_t*>(ws + L.keys_in);
+    int32_t* keys_out = reinterpret_cast<int32_t*>(ws + L.keys_out);
+    int32_t* perm_in = reinterpret_cast<int32_t*>(ws + L.perm_in);
+    int32_t* perm_out = reinterpret_cast<int32_t*>(ws + L.perm_out);
+    int32_t* rowidx = reinterpret_cast<int32_t*>(ws + L.rowidx);
+    hipError_t e;
+    if (nnz > 0) {
+        hipLaunchKernelGGL(csr_rowidx_kernel, dim3(static_cast<unsigned>(cdiv(m, 256))), dim3(256), 0,
+                           s, rowptr, m, rowidx);
+        hipLaunchKernelGGL(iota_kernel, dim3(static_cast<unsigned>(cdiv(nnz, 256))), dim3(256), 0, s,
+                           perm_in, nnz);
+        e = hipMemcpyAsync(keys_in, colind, sizeof(int32_t) * nnz, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return e;
+        size_t tb = L.temp_bytes;
+        e = hipcub::DeviceRadixSort::SortPairs(ws + L.temp, tb, keys_in, keys_out, perm_in, perm_out,
+                                               static_cast<int>(nnz), 0, 32, s);
+        if (e != hipSuccess) return e;
+    }
+    const int64_t cnt = (nnz > n + 1 ? nnz : n + 1);
+    hipLaunchKernelGGL(csc_finish_kernel, dim3(static_cast<unsigned>(cdiv(cnt, 256))), dim3(256), 0,
+                       s, keys_out, perm_out, rowidx, val, nnz, n, colptr, t_col, t_val);
+    return hipGetLastError();
+}
+
+void csc_views(int64_t m, int64_t n, int64_t nnz, char* ws, const int64_t** colptr,
+               const int32_t** t_col, const double** t_val) {
+    const CscLayout L = csc_layout(m, n, nnz);
+    *colptr = reinterpret_cast<const int64_t*>(ws + L.colptr);
+    *t_col = reinterpret_cast<const int32_t*>(ws + L.t_col);
+    *t_val = reinterpret_cast<const double*>(ws + L.t_val);
+}
+
+}  // namespace qb
