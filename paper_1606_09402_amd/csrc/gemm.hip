@@ -61,33 +61,30 @@ struct Stage {
     static_assert(NT % TPR == 0 && OUTER % RPP == 0, "staging shape");
     double2 r[PASSES];
 
-    // rows [o0, o0 + OUTER) limited by olim, inner [i0, i0 + INNER) limited by ilim
-    QB_DEV void load(const double* __restrict__ g, int64_t ld, int64_t o0, int64_t i0, int64_t olim,
-                     int64_t ilim, bool vec) {
+    // Whole tile in bounds, 16-byte aligned rows: one double2 load per pass.
+    QB_DEV void load_vec(const double* __restrict__ g, int64_t ld, int64_t o0, int64_t i0) {
         const int tid = threadIdx.x;
         const int ro = tid / TPR, ri = 2 * (tid % TPR);
         const double* p0 = g + (o0 + ro) * ld + i0 + ri;
-        const bool interior = o0 + OUTER <= olim && i0 + INNER <= ilim;
-        if (interior && vec) {
 #pragma unroll
-            for (int p = 0; p < PASSES; ++p)
-                r[p] = *reinterpret_cast<const double2*>(p0 + static_cast<int64_t>(p) * RPP * ld);
-        } else if (interior) {
+        for (int p = 0; p < PASSES; ++p)
+            r[p] = *reinterpret_cast<const double2*>(p0 + static_cast<int64_t>(p) * RPP * ld);
+    }
+    // Rows [o0, o0 + OUTER) limited by olim, inner [i0, i0 + INNER) limited by ilim;
+    // out-of-range elements read as zero.
+    QB_DEV void load_checked(const double* __restrict__ g, int64_t ld, int64_t o0, int64_t i0,
+                             int64_t olim, int64_t ilim) {
+        const int tid = threadIdx.x;
+        const int ro = tid / TPR, ri = 2 * (tid % TPR);
+        const double* p0 = g + (o0 + ro) * ld + i0 + ri;
 #pragma unroll
-            for (int p = 0; p < PASSES; ++p) {
-                const double* q = p0 + static_cast<int64_t>(p) * RPP * ld;
-                r[p] = double2{q[0], q[1]};
-            }
-        } else {
-#pragma unroll
-            for (int p = 0; p < PASSES; ++p) {
-                const int64_t o = o0 + ro + p * RPP;
-                const int64_t i = i0 + ri;
-                const double* q = p0 + static_cast<int64_t>(p) * RPP * ld;
-                const bool ok = o < olim;
-                r[p].x = ok && i < ilim ? q[0] : 0.0;
-                r[p].y = ok && i + 1 < ilim ? q[1] : 0.0;
-            }
+        for (int p = 0; p < PASSES; ++p) {
+            const int64_t o = o0 + ro + p * RPP;
+            const int64_t i = i0 + ri;
+            const double* q = p0 + static_cast<int64_t>(p) * RPP * ld;
+            const bool ok = o < olim;
+            r[p].x = ok && i < ilim ? q[0] : 0.0;
+            r[p].y = ok && i + 1 < ilim ? q[1] : 0.0;
         }
     }
     template <int PITCH>
@@ -116,11 +113,13 @@ struct GemmCfg {
     static_assert(TM % 16 == 0 && TN % 16 == 0 && BK % 4 == 0, "bad tile");
 };
 
-template <int BM, int BN, int BK, int WM, int WN, int AL, int BL, int OCC>
+template <int BM, int BN, int BK, int WM, int WN, int AL, int BL, int OCC, int STAGES>
 __global__ void __launch_bounds__(64 * WM * WN, OCC) gemm_f64_kernel(const GemmArgs g) {
     using C = GemmCfg<BM, BN, BK, WM, WN, AL, BL>;
-    __shared__ double As[C::A_ROWS * C::A_PITCH];
-    __shared__ double Bs[C::B_ROWS * C::B_PITCH];
+    static_assert(STAGES == 1 || STAGES == 2, "one or two LDS stages");
+    constexpr int A_STAGE = C::A_ROWS * C::A_PITCH, B_STAGE = C::B_ROWS * C::B_PITCH;
+    __shared__ __align__(16) double As[STAGES * A_STAGE];
+    __shared__ __align__(16) double Bs[STAGES * B_STAGE];
     __shared__ double red[WM][BN];
 
     const int tid = threadIdx.x;
@@ -143,39 +142,103 @@ __global__ void __launch_bounds__(64 * WM * WN, OCC) gemm_f64_kernel(const GemmA
 
     Stage<C::A_ROWS, C::A_INNER, C::NT> sa;
     Stage<C::B_ROWS, C::B_INNER, C::NT> sb;
-    auto load_tiles = [&](int64_t k0) {
-        if (AL == 0) sa.load(g.A, g.lda, m0, k0, g.M, ke, g.vec_a);
-        else         sa.load(g.A, g.lda, k0, m0, ke, g.M, g.vec_a);
-        if (BL == 0) sb.load(g.B, g.ldb, k0, n0, ke, g.N, g.vec_b);
-        else         sb.load(g.B, g.ldb, n0, k0, g.N, ke, g.vec_b);
+    auto load_fast = [&](int64_t k0) {
+        if (AL == 0) sa.load_vec(g.A, g.lda, m0, k0); else sa.load_vec(g.A, g.lda, k0, m0);
+        if (BL == 0) sb.load_vec(g.B, g.ldb, k0, n0); else sb.load_vec(g.B, g.ldb, n0, k0);
     };
+    auto load_checked = [&](int64_t k0) {
+        if (AL == 0) sa.load_checked(g.A, g.lda, m0, k0, g.M, ke);
+        else         sa.load_checked(g.A, g.lda, k0, m0, ke, g.M);
+        if (BL == 0) sb.load_checked(g.B, g.ldb, k0, n0, ke, g.N);
+        else         sb.load_checked(g.B, g.ldb, n0, k0, g.N, ke);
+    };
+    // tiles fully inside M x N with aligned rows stream their full K tiles through the
+    // branch-free vector path; everything else (edge tiles, the K tail) is checked
+    const bool fast = g.vec_a && g.vec_b && m0 + BM <= g.M && n0 + BN <= g.N;
+    const int64_t kfull = fast ? kb + ((ke - kb) / BK) * BK : kb;   // end of the fast tiles
 
     const int wm0 = wm * C::TM, wn0 = wn * C::TN;
-    if (kb < ke) load_tiles(kb);
-    for (int64_t k0 = kb; k0 < ke; k0 += BK) {
-        __syncthreads();
-        sa.template store<C::A_PITCH>(As);
-        sb.template store<C::B_PITCH>(Bs);
-        __syncthreads();
-        if (k0 + BK < ke) load_tiles(k0 + BK);
+    // MFMA operands of k-step kk from one LDS stage
+    auto read_ops = [&](const double* as, const double* bs, int kk, double (&a)[C::FM],
+                        double (&b)[C::FN]) {
 #pragma unroll
-        for (int kk = 0; kk < BK; kk += 4) {
-            double a[C::FM], b[C::FN];
+        for (int fm = 0; fm < C::FM; ++fm) {
+            const int i = wm0 + fm * 16 + li;
+            a[fm] = AL == 0 ? as[i * C::A_PITCH + kk + lk] : as[(kk + lk) * C::A_PITCH + i];
+        }
 #pragma unroll
-            for (int fm = 0; fm < C::FM; ++fm) {
-                const int i = wm0 + fm * 16 + li;
-                a[fm] = AL == 0 ? As[i * C::A_PITCH + kk + lk] : As[(kk + lk) * C::A_PITCH + i];
-            }
+        for (int fn = 0; fn < C::FN; ++fn) {
+            const int j = wn0 + fn * 16 + li;
+            b[fn] = BL == 0 ? bs[(kk + lk) * C::B_PITCH + j] : bs[j * C::B_PITCH + kk + lk];
+        }
+    };
+    // BK/4 k-steps on one stage; the operands of step kk + 4 are read while the MFMAs
+    // of step kk run
+    auto compute = [&](const double* as, const double* bs) {
+        double a0[C::FM], b0[C::FN], a1[C::FM], b1[C::FN];
+        read_ops(as, bs, 0, a0, b0);
 #pragma unroll
-            for (int fn = 0; fn < C::FN; ++fn) {
-                const int j = wn0 + fn * 16 + li;
-                b[fn] = BL == 0 ? Bs[(kk + lk) * C::B_PITCH + j] : Bs[j * C::B_PITCH + kk + lk];
-            }
+        for (int kk = 0; kk < BK; kk += 8) {
+            read_ops(as, bs, kk + 4, a1, b1);
 #pragma unroll
             for (int fm = 0; fm < C::FM; ++fm)
 #pragma unroll
                 for (int fn = 0; fn < C::FN; ++fn)
-                    acc[fm][fn] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[fm], b[fn], acc[fm][fn], 0, 0, 0);
+                    acc[fm][fn] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[fm], b0[fn], acc[fm][fn], 0, 0, 0);
+            if (kk + 8 < BK) read_ops(as, bs, kk + 8, a0, b0);
+#pragma unroll
+            for (int fm = 0; fm < C::FM; ++fm)
+#pragma unroll
+                for (int fn = 0; fn < C::FN; ++fn)
+                    acc[fm][fn] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[fm], b1[fn], acc[fm][fn], 0, 0, 0);
+        }
+    };
+
+    if (STAGES == 1) {
+        for (int64_t k0 = kb; k0 < kfull; k0 += BK) {
+            load_fast(k0);
+            __syncthreads();
+            sa.template store<C::A_PITCH>(As);
+            sb.template store<C::B_PITCH>(Bs);
+            __syncthreads();
+            compute(As, Bs);
+        }
+        for (int64_t k0 = kfull; k0 < ke; k0 += BK) {
+            load_checked(k0);
+            __syncthreads();
+            sa.template store<C::A_PITCH>(As);
+            sb.template store<C::B_PITCH>(Bs);
+            __syncthreads();
+            compute(As, Bs);
+        }
+    } else {
+        // two-stage ring over the fast tiles: tile t is read from stage t & 1 while tile
+        // t + 1 is written to the other stage; one barrier per tile
+        int st = 0;
+        if (kb < kfull) {
+            load_fast(kb);
+            sa.template store<C::A_PITCH>(As);
+            sb.template store<C::B_PITCH>(Bs);
+            __syncthreads();
+            int64_t k0 = kb;
+            for (; k0 + BK < kfull; k0 += BK) {
+                load_fast(k0 + BK);
+                compute(As + st * A_STAGE, Bs + st * B_STAGE);
+                sa.template store<C::A_PITCH>(As + (st ^ 1) * A_STAGE);
+                sb.template store<C::B_PITCH>(Bs + (st ^ 1) * B_STAGE);
+                __syncthreads();
+                st ^= 1;
+            }
+            compute(As + st * A_STAGE, Bs + st * B_STAGE);
+            st ^= 1;
+        }
+        for (int64_t k0 = kfull; k0 < ke; k0 += BK) {
+            load_checked(k0);
+            __syncthreads();
+            sa.template store<C::A_PITCH>(As + st * A_STAGE);
+            sb.template store<C::B_PITCH>(Bs + st * B_STAGE);
+            __syncthreads();
+            compute(As + st * A_STAGE, Bs + st * B_STAGE);
         }
     }
 
@@ -238,12 +301,55 @@ splitk_reduce_kernel(const double* __restrict__ P, int nsplit, int64_t M, int64_
                      double* C, int64_t c_si, int64_t c_sj) {
     const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (e >= M * N) return;
-    double t = 0.0;
-    for (int s = 0; s < nsplit; ++s) t += P[static_cast<int64_t>(s) * M * N + e];
+    // four interleaved partial sums keep four loads in flight; combined in fixed order
+    const int64_t mn = M * N;
+    double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+    int s = 0;
+    for (; s + 4 <= nsplit; s += 4) {
+        t0 += P[(s + 0) * mn + e];
+        t1 += P[(s + 1) * mn + e];
+        t2 += P[(s + 2) * mn + e];
+        t3 += P[(s + 3) * mn + e];
+    }
+    for (; s < nsplit; ++s) t0 += P[s * mn + e];
+    const double t = (t0 + t1) + (t2 + t3);
     const int64_t i = e / N, j = e % N;
     double v = alpha * t;
     if (beta != 0.0) v += beta * C0[i * c0_si + j * c0_sj];
     C[i * c_si + j * c_sj] = v;
+}
+
+// Column sums of squares of a strided M x N output after a split-K reduction: partial
+// g covers rows [g R, (g + 1) R).  Row-major outputs (sj == 1) put threads on columns;
+// column-major outputs (si == 1) give each column a wave whose lanes stride the rows.
+__global__ void __launch_bounds__(256)
+colsq_strided_kernel(const double* __restrict__ C, int64_t M, int64_t N, int64_t si, int64_t sj,
+                     int64_t rows_per_group, double* __restrict__ partial) {
+    const int64_t g = blockIdx.x;
+    const int64_t r0 = g * rows_per_group;
+    const int64_t r1 = r0 + rows_per_group < M ? r0 + rows_per_group : M;
+    if (sj == 1) {
+        const int64_t j = static_cast<int64_t>(blockIdx.y) * 256 + threadIdx.x;
+        if (j >= N) return;
+        double t = 0.0;
+        for (int64_t i = r0; i < r1; ++i) {
+            const double v = C[i * si + j];
+            t += v * v;
+        }
+        partial[g * N + j] = t;
+    } else {
+        const int64_t j = static_cast<int64_t>(blockIdx.y) * 4 + (threadIdx.x >> 6);
+        const int lane = threadIdx.x & 63;
+        if (j >= N) return;
+        double t = 0.0;
+        for (int64_t i = r0 + lane; i < r1; i += 64) {
+            const double v = C[i + j * sj];
+            t += v * v;
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+        if (lane == 0) partial[g * N + j] = t;
+    }
 }
 
 // Epilogue-only "GEMM" for K == 0: out = beta * C0 (alpha * empty sum = 0).
@@ -259,7 +365,7 @@ scale_copy_kernel(int64_t M, int64_t N, double beta, const double* C0, int64_t c
 // ------------------------------------------------------------------------------ host
 
 
-template <int BM, int BN, int BK, int WM, int WN, int AL, int BL, int OCC>
+template <int BM, int BN, int BK, int WM, int WN, int AL, int BL, int OCC, int STAGES>
 static hipError_t run_cfg(const GemmDesc& d, hipStream_t s) {
     GemmArgs g{};
     g.M = d.M; g.N = d.N; g.K = d.K;
@@ -274,9 +380,10 @@ static hipError_t run_cfg(const GemmDesc& d, hipStream_t s) {
     g.tiles_n = static_cast<int>(cdiv(d.N, BN));
     const int64_t tiles = static_cast<int64_t>(g.tiles_m) * g.tiles_n;
     int nsplit = 1;
-    if (d.colsq == nullptr && d.ws != nullptr && tiles < 256) {
+    if (d.ws != nullptr && tiles < 512) {
         const int64_t ktiles = cdiv(d.K, BK);
-        int64_t want = cdiv(512, tiles);
+        int64_t want = cdiv(640, tiles);
+        if (want > 32) want = 32;
         if (want > ktiles / 4) want = ktiles / 4;
         if (d.max_split > 0 && want > d.max_split) want = d.max_split;
         while (want > 1 && want * d.M * d.N > d.ws_elems) --want;
@@ -286,16 +393,27 @@ static hipError_t run_cfg(const GemmDesc& d, hipStream_t s) {
     nsplit = static_cast<int>(cdiv(d.K, g.kchunk));
     if (nsplit < 1) nsplit = 1;
     g.P = d.ws;
-    g.colsq = d.colsq;
+    g.colsq = nsplit == 1 ? d.colsq : nullptr;   // fused only without a split
     if (d.colsq_groups) *d.colsq_groups = g.tiles_m;
     dim3 grid(static_cast<unsigned>(tiles), static_cast<unsigned>(nsplit));
-    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, WM, WN, AL, BL, OCC>), grid, dim3(64 * WM * WN), 0,
+    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, WM, WN, AL, BL, OCC, STAGES>), grid, dim3(64 * WM * WN), 0,
                        s, g);
     if (nsplit > 1) {
         const int64_t tot = d.M * d.N;
         hipLaunchKernelGGL(splitk_reduce_kernel, dim3(static_cast<unsigned>(cdiv(tot, 256))),
                            dim3(256), 0, s, d.ws, nsplit, d.M, d.N, d.alpha, d.beta, d.C0.p,
                            d.C0.si, d.C0.sj, d.C.p, d.C.si, d.C.sj);
+        if (d.colsq != nullptr) {
+            // at most tiles_m groups of rows, so the caller's [tiles_m][N] buffer fits
+            const int64_t groups = g.tiles_m < 256 ? g.tiles_m : 256;
+            const int64_t rpg = cdiv(d.M, groups);
+            const int64_t ng = cdiv(d.M, rpg);
+            dim3 cg(static_cast<unsigned>(ng),
+                    static_cast<unsigned>(d.C.sj == 1 ? cdiv(d.N, 256) : cdiv(d.N, 4)));
+            hipLaunchKernelGGL(colsq_strided_kernel, cg, dim3(256), 0, s, d.C.p, d.M, d.N, d.C.si,
+                               d.C.sj, rpg, d.colsq);
+            if (d.colsq_groups) *d.colsq_groups = static_cast<int>(ng);
+        }
     }
     return hipGetLastError();
 }
@@ -303,10 +421,10 @@ static hipError_t run_cfg(const GemmDesc& d, hipStream_t s) {
 template <int AL, int BL>
 static hipError_t dispatch_shape(const GemmDesc& d, hipStream_t s) {
     if (d.N <= 64 && d.M >= 4096)          // tall-skinny output (m x b panels)
-        return run_cfg<128, 64, 32, 4, 1, AL, BL, 2>(d, s);
+        return run_cfg<128, 64, 32, 4, 1, AL, BL, 2, 1>(d, s);
     if (d.N <= 64 || d.M <= 2048)          // small output, long reduction (split-K)
-        return run_cfg<64, 64, 32, 2, 2, AL, BL, 2>(d, s);
-    return run_cfg<128, 128, 32, 2, 2, AL, BL, 1>(d, s);   // sketch sweep
+        return run_cfg<64, 64, 32, 2, 2, AL, BL, 2, 1>(d, s);
+    return run_cfg<128, 128, 32, 4, 2, AL, BL, 2, 2>(d, s);   // sketch sweep
 }
 
 hipError_t gemm_f64(const GemmDesc& d, hipStream_t s) {

@@ -25,8 +25,9 @@ struct GemmDesc {
     double alpha, beta;
     View C0;
     MutView C;
-    double* colsq;       // optional [tiles_m][N] column sums of squares; forces one K split
-    int* colsq_groups;   // receives tiles_m when colsq is set
+    double* colsq;       // optional [groups][N] partial column sums of squares of the output,
+                         // groups <= ceil(M / 64); fused into the epilogue without split-K
+    int* colsq_groups;   // receives the number of partial groups when colsq is set
     double* ws;          // split-K scratch (nullptr: no split)
     int64_t ws_elems;
     int max_split;       // 0 = automatic
@@ -36,12 +37,11 @@ hipError_t gemm_f64(const GemmDesc& d, hipStream_t s);
 // panel.hip -- small dense kernels of the block loop
 hipError_t launch_chol_inv(const double* gram, int b, double tau, double* R, double* Rinv,
                            int* flag, hipStream_t s);
-hipError_t launch_upper_mul(const double* Ra, const double* Rb, int b, double* Rout, hipStream_t s);
+hipError_t launch_tri_inv(const double* R, int b, double* Rinv, hipStream_t s);
+hipError_t launch_upper_mul2(const double* A1, const double* B1, const double* A2, const double* B2,
+                             int b, double* Out1, double* Out2, hipStream_t s);
 hipError_t launch_householder(double* X, int64_t m, int b, int64_t ldx, double* Q, int64_t ldq,
                               double* R, double* tau, hipStream_t s);
-int64_t trsm_groups(int64_t n);
-hipError_t launch_trsm_rowsq(const double* S, int64_t lds, const double* R, int b, int64_t n,
-                             double* out, int64_t ldo, double* rowsq_part, hipStream_t s);
 hipError_t launch_gather_info(const double* rowsq, const double* R, const double* gcol, int b,
                               double* info, hipStream_t s);
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s);

@@ -4,89 +4,138 @@
 //  * the Householder thin QR of an m x b panel with diag(R) >= 0 (the fallback, and
 //    the definition of qr used by the paper's steps 12-13);
 //  * R_i = R~_i R_i (Algorithm 4 step 14);
-//  * B_i = R_i^{-T} S by forward substitution (step 15, the "\" of Section 4.1), fused
-//    with the row sums of squares ||B_i(j,:)||^2 of the error indicator (step 17 and
-//    the row-by-row variant 7a-8e of Section 3.1);
+//  * R_i^{-1}, from which the GEMM B_i^T = S^T R_i^{-1} solves R_i^T B_i = S (step 15,
+//    the "\" of Section 4.1);
 //  * gathering the per-block values the host needs for the stopping test.
 #include "kernels.h"
 
 namespace qb {
 
-constexpr int kCholThreads = 256;
 constexpr int kMaxB = 128;   // largest block size b the library accepts
 
-// Gram (b x b, row-major, only the upper triangle is read) -> R upper (row-major, zero
-// below the diagonal) and Rinv = R^{-1}.  flag[0] is set to 1 if some pivot is not
-// above tau * max_i Gram(i,i) (the panel is then too ill-conditioned for CholeskyQR).
-__global__ void __launch_bounds__(kCholThreads)
-chol_upper_inv_kernel(const double* __restrict__ gram, int b, double tau, double* __restrict__ R,
-                      double* __restrict__ Rinv, int* __restrict__ flag) {
-    __shared__ double M[kMaxB * (kMaxB + 1)];   // b x (b + 1), b <= kMaxB
-    __shared__ double dmax;
-    __shared__ int bad;
-    const int ld = b + 1;
-    const int tid = threadIdx.x;
-    for (int e = tid; e < b * b; e += blockDim.x) {
-        const int i = e / b, j = e % b;
-        M[i * ld + j] = j >= i ? gram[i * b + j] : 0.0;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        double d = 0.0;
-        for (int j = 0; j < b; ++j) d = fmax(d, M[j * ld + j]);
-        dmax = d;
-        bad = 0;
-    }
-    __syncthreads();
-    for (int j = 0; j < b; ++j) {
-        const double piv = M[j * ld + j];
-        if (!(piv > tau * dmax)) {   // also catches NaN
-            if (tid == 0) bad = 1;
-            break;
-        }
-        const double r = sqrt(piv);
+// Register layout for the b x b kernels (b <= BMAX): thread t owns column c = t mod BMAX
+// and rows a = t div BMAX + G q, q < Q, of the working matrix (G = 256 / BMAX row groups).
+// One step of a right-looking elimination publishes the pivot row in LDS (double
+// buffered, so one barrier per step) and every thread updates its own rows in registers.
+template <int BMAX>
+struct RegLayout {
+    static constexpr int NT = 256, G = NT / BMAX, Q = BMAX / G;
+};
+
+// In-place inverse of the upper-triangular factor held in Rs (pitch BMAX + 1) by
+// right-looking back substitution R X = I: row i of X is T(i, :) / R(i, i), then rows
+// a < i lose R(a, i) X(i, :).  v[] is the thread's register slice of T.
+template <int BMAX>
+QB_DEV void tri_inverse_rows(const double* Rs, int b, double (&v)[RegLayout<BMAX>::Q],
+                             double (*row)[BMAX], double* __restrict__ Rinv) {
+    using L = RegLayout<BMAX>;
+    const int tid = threadIdx.x, c = tid % BMAX, g = tid / BMAX;
+    constexpr int ld = BMAX + 1;
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) v[q] = (g + L::G * q) == c ? 1.0 : 0.0;
+    for (int i = b - 1; i >= 0; --i) {
+        const int buf = i & 1;
+        if (g == i % L::G) row[buf][c] = v[i / L::G] / Rs[i * ld + i];
         __syncthreads();
-        for (int c = j + 1 + tid; c < b; c += blockDim.x) M[j * ld + c] /= r;
-        if (tid == 0) M[j * ld + j] = r;
-        __syncthreads();
-        // trailing update of the upper triangle: M(a, c) -= R(j, a) R(j, c), j < a <= c
-        const int t = b - j - 1;
-        for (int e = tid; e < t * t; e += blockDim.x) {
-            const int a = j + 1 + e / t, c = j + 1 + e % t;
-            if (c >= a) M[a * ld + c] -= M[j * ld + a] * M[j * ld + c];
-        }
-        __syncthreads();
-    }
-    __syncthreads();
-    if (bad) {
-        if (tid == 0) flag[0] = 1;
-        return;
-    }
-    for (int e = tid; e < b * b; e += blockDim.x) {
-        const int i = e / b, j = e % b;
-        R[e] = j >= i ? M[i * ld + j] : 0.0;
-    }
-    // R^{-1}: column c by back substitution, one thread per column
-    for (int c = tid; c < b; c += blockDim.x) {
-        for (int i = b - 1; i > c; --i) Rinv[i * b + c] = 0.0;
-        for (int i = c; i >= 0; --i) {
-            double t = i == c ? 1.0 : 0.0;
-            for (int p = i + 1; p <= c; ++p) t -= M[i * ld + p] * Rinv[p * b + c];
-            Rinv[i * b + c] = t / M[i * ld + i];
+        const double xc = row[buf][c];
+        if (g == 0 && c < b) Rinv[i * b + c] = c >= i ? xc : 0.0;
+#pragma unroll
+        for (int q = 0; q < L::Q; ++q) {
+            const int a = g + L::G * q;
+            if (a < i) v[q] -= Rs[a * ld + i] * xc;
         }
     }
 }
 
-// Rout = Ra * Rb for upper-triangular b x b row-major matrices (Rout may not alias).
+// Gram (b x b, row-major, only the upper triangle is read) -> R upper (row-major, zero
+// below the diagonal) with Gram = R^T R, and Rinv = R^{-1}.  flag[0] is set to 1 if some
+// pivot is not above tau * max_i Gram(i,i) (the panel is then too ill-conditioned for
+// CholeskyQR).
+template <int BMAX>
 __global__ void __launch_bounds__(256)
-upper_mul_kernel(const double* __restrict__ Ra, const double* __restrict__ Rb, int b,
-                 double* __restrict__ Rout) {
+chol_upper_inv_kernel(const double* __restrict__ gram, int b, double tau, double* __restrict__ R,
+                      double* __restrict__ Rinv, int* __restrict__ flag) {
+    using L = RegLayout<BMAX>;
+    constexpr int ld = BMAX + 1;
+    __shared__ double Rs[BMAX * ld];
+    __shared__ double row[2][BMAX];
+    __shared__ double wmax[L::NT / 64];
+    const int tid = threadIdx.x, c = tid % BMAX, g = tid / BMAX;
+    double v[L::Q];
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) {
+        const int a = g + L::G * q;
+        v[q] = (a < b && c < b && a <= c) ? gram[a * b + c] : 0.0;
+    }
+    double d = tid < b ? gram[tid * b + tid] : 0.0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) d = fmax(d, __shfl_xor(d, off, 64));
+    if ((tid & 63) == 0) wmax[tid >> 6] = d;
+    __syncthreads();
+    double dmax = 0.0;
+#pragma unroll
+    for (int w = 0; w < L::NT / 64; ++w) dmax = fmax(dmax, wmax[w]);
+    const double floor_piv = tau * dmax;
+
+    for (int j = 0; j < b; ++j) {
+        const int buf = j & 1;
+        if (g == j % L::G) row[buf][c] = v[j / L::G];
+        __syncthreads();
+        const double piv = row[buf][j];
+        if (!(piv > floor_piv)) {   // uniform: every thread read the same pivot (NaN included)
+            if (tid == 0) flag[0] = 1;
+            return;
+        }
+        const double ir = 1.0 / sqrt(piv);
+        const double rc = row[buf][c] * ir;   // R(j, c) for c >= j
+        if (g == 0) Rs[j * ld + c] = (c >= j && c < b) ? (c == j ? sqrt(piv) : rc) : 0.0;
+#pragma unroll
+        for (int q = 0; q < L::Q; ++q) {
+            const int a = g + L::G * q;
+            if (a > j && c >= a) v[q] -= (row[buf][a] * ir) * rc;
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < b * b; e += L::NT) {
+        const int i = e / b, jj = e - i * b;
+        R[e] = jj >= i ? Rs[i * ld + jj] : 0.0;
+    }
+    tri_inverse_rows<BMAX>(Rs, b, v, row, Rinv);
+}
+
+// Rinv = R^{-1} for an upper-triangular b x b row-major R.
+template <int BMAX>
+__global__ void __launch_bounds__(256)
+tri_inv_kernel(const double* __restrict__ R, int b, double* __restrict__ Rinv) {
+    using L = RegLayout<BMAX>;
+    constexpr int ld = BMAX + 1;
+    __shared__ double Rs[BMAX * ld];
+    __shared__ double row[2][BMAX];
+    for (int e = threadIdx.x; e < b * b; e += L::NT) {
+        const int i = e / b, jj = e - i * b;
+        Rs[i * ld + jj] = jj >= i ? R[e] : 0.0;
+    }
+    __syncthreads();
+    double v[L::Q];
+    tri_inverse_rows<BMAX>(Rs, b, v, row, Rinv);
+}
+
+// Out1 = A1 B1 and Out2 = A2 B2 for upper-triangular b x b row-major matrices (used for
+// R_i = R~_i R_i and R_i^{-1} = R_i^{-1} R~_i^{-1}); outputs may not alias inputs.
+__global__ void __launch_bounds__(256)
+upper_mul2_kernel(const double* __restrict__ A1, const double* __restrict__ B1,
+                  const double* __restrict__ A2, const double* __restrict__ B2, int b,
+                  double* __restrict__ Out1, double* __restrict__ Out2) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= b * b) return;
-    const int i = e / b, j = e % b;
+    if (e >= 2 * b * b) return;
+    const int which = e >= b * b;
+    const int f = e - which * b * b;
+    const double* A = which ? A2 : A1;
+    const double* B = which ? B2 : B1;
+    const int i = f / b, j = f - i * b;
     double t = 0.0;
-    for (int p = i; p <= j; ++p) t += Ra[i * b + p] * Rb[p * b + j];
-    Rout[e] = j >= i ? t : 0.0;
+    for (int p = i; p <= j; ++p) t += A[i * b + p] * B[p * b + j];
+    (which ? Out2 : Out1)[f] = j >= i ? t : 0.0;
 }
 
 // Householder thin QR of the m x b column-major panel X (leading dimension ldx), one
@@ -180,33 +229,6 @@ householder_panel_kernel(double* __restrict__ X, int64_t m, int b, int64_t ldx,
     }
 }
 
-// Forward substitution R^T X = S for b x n S (row-major, lds) with upper-triangular R
-// (b x b row-major); X is written to out (row j at out + j*ldo), and the sum over this
-// workgroup's columns of X(j, c)^2 to rowsq_part[blockIdx.x * b + j].  One wave per
-// workgroup, one column per lane; the lane's solution vector lives in LDS.
-constexpr int kTrsmThreads = 64;
-
-__global__ void __launch_bounds__(kTrsmThreads)
-trsm_rowsq_kernel(const double* __restrict__ S, int64_t lds, const double* __restrict__ R,
-                  int b, int64_t n, double* __restrict__ out, int64_t ldo,
-                  double* __restrict__ rowsq_part) {
-    __shared__ double xs[kMaxB * kTrsmThreads];   // b x 64
-    const int lane = threadIdx.x;
-    const int64_t c = static_cast<int64_t>(blockIdx.x) * kTrsmThreads + lane;
-    const bool live = c < n;
-    for (int j = 0; j < b; ++j) {
-        double t = live ? S[j * lds + c] : 0.0;
-        for (int p = 0; p < j; ++p) t -= R[p * b + j] * xs[p * kTrsmThreads + lane];
-        const double x = live ? t / R[j * b + j] : 0.0;
-        xs[j * kTrsmThreads + lane] = x;
-        if (live) out[j * ldo + c] = x;
-        double q = x * x;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) q += __shfl_xor(q, off, 64);
-        if (lane == 0) rowsq_part[static_cast<int64_t>(blockIdx.x) * b + j] = q;
-    }
-}
-
 // info[0:b] = rowsq, info[b:2b] = diag(R), info[2b:3b] = guard column sums of squares
 __global__ void gather_block_info(const double* __restrict__ rowsq, const double* __restrict__ R,
                                   const double* __restrict__ gcol, int b,
@@ -232,15 +254,29 @@ __global__ void fill_int_kernel(int* __restrict__ p, int n, int v) {
 
 hipError_t launch_chol_inv(const double* gram, int b, double tau, double* R, double* Rinv,
                            int* flag, hipStream_t s) {
-    hipLaunchKernelGGL(chol_upper_inv_kernel, dim3(1), dim3(kCholThreads), 0, s, gram, b, tau, R,
-                       Rinv, flag);
+    if (b <= 32)
+        hipLaunchKernelGGL(chol_upper_inv_kernel<32>, dim3(1), dim3(256), 0, s, gram, b, tau, R, Rinv, flag);
+    else if (b <= 64)
+        hipLaunchKernelGGL(chol_upper_inv_kernel<64>, dim3(1), dim3(256), 0, s, gram, b, tau, R, Rinv, flag);
+    else
+        hipLaunchKernelGGL(chol_upper_inv_kernel<128>, dim3(1), dim3(256), 0, s, gram, b, tau, R, Rinv, flag);
     return hipGetLastError();
 }
 
-hipError_t launch_upper_mul(const double* Ra, const double* Rb, int b, double* Rout,
-                            hipStream_t s) {
-    hipLaunchKernelGGL(upper_mul_kernel, dim3(static_cast<unsigned>(cdiv(b * b, 256))), dim3(256),
-                       0, s, Ra, Rb, b, Rout);
+hipError_t launch_tri_inv(const double* R, int b, double* Rinv, hipStream_t s) {
+    if (b <= 32)
+        hipLaunchKernelGGL(tri_inv_kernel<32>, dim3(1), dim3(256), 0, s, R, b, Rinv);
+    else if (b <= 64)
+        hipLaunchKernelGGL(tri_inv_kernel<64>, dim3(1), dim3(256), 0, s, R, b, Rinv);
+    else
+        hipLaunchKernelGGL(tri_inv_kernel<128>, dim3(1), dim3(256), 0, s, R, b, Rinv);
+    return hipGetLastError();
+}
+
+hipError_t launch_upper_mul2(const double* A1, const double* B1, const double* A2, const double* B2,
+                             int b, double* Out1, double* Out2, hipStream_t s) {
+    hipLaunchKernelGGL(upper_mul2_kernel, dim3(static_cast<unsigned>(cdiv(2 * b * b, 256))),
+                       dim3(256), 0, s, A1, B1, A2, B2, b, Out1, Out2);
     return hipGetLastError();
 }
 
@@ -248,15 +284,6 @@ hipError_t launch_householder(double* X, int64_t m, int b, int64_t ldx, double* 
                               double* R, double* tau, hipStream_t s) {
     hipLaunchKernelGGL(householder_panel_kernel, dim3(1), dim3(kHhThreads), 0, s, X, m, b, ldx, Q,
                        ldq, R, tau);
-    return hipGetLastError();
-}
-
-int64_t trsm_groups(int64_t n) { return cdiv(n, kTrsmThreads); }
-
-hipError_t launch_trsm_rowsq(const double* S, int64_t lds, const double* R, int b, int64_t n,
-                             double* out, int64_t ldo, double* rowsq_part, hipStream_t s) {
-    hipLaunchKernelGGL(trsm_rowsq_kernel, dim3(static_cast<unsigned>(trsm_groups(n))),
-                       dim3(kTrsmThreads), 0, s, S, lds, R, b, n, out, ldo, rowsq_part);
     return hipGetLastError();
 }
 

@@ -34,7 +34,7 @@ size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 // --------------------------------------------------------------------------- workspace
 
 struct Layout {
-    size_t red, scal, om, g, h, gpart, gnorm2, y, x2, s, w, z, d, gram, r1, r1i, rt, rti, ri, tau,
+    size_t red, scal, om, g, h, gpart, gnorm2, y, x2, s, w, z, d, gram, r1, r1i, rt, rti, ri, rii, tau,
         rowsq_part, rowsq, info, flags, split, csc, total;
     int64_t lt, split_elems, gpart_groups;
 };
@@ -50,14 +50,16 @@ Layout make_layout(int algo, int sparse, int64_t m, int64_t n, int64_t nnz, cons
     const int64_t lmax = p->l_max;
     const int64_t lt = algo == QB_ALGO_FP ? chunk_width(p) : b;   // EI: one block at a time
     L.lt = lt;
+    // split-K partials: small Gram / projection products and tall-skinny (m or n) x b
+    // products with a few K splits
     L.split_elems = 512 * b * (b > 64 ? b : 64) + 65536;
     if (L.split_elems < kGramSplitElems) L.split_elems = kGramSplitElems;
+    if (L.split_elems < 8 * (m > n ? m : n) * b) L.split_elems = 8 * (m > n ? m : n) * b;
     // row-tile partials of the G column norms: dense GEMM tiles are >= 64 rows
     L.gpart_groups = sparse ? colsq_groups(m) : cdiv(m, 64);
-    // per-block row sums of squares of B_i: partials from the triangular solve (FP), the
-    // A^T Q_i GEMM epilogue (dense EI, tiles of >= 64 rows) or the column reduction (CSR EI)
-    int64_t nb_part = trsm_groups(n);
-    if (cdiv(n, 64) > nb_part) nb_part = cdiv(n, 64);
+    // per-block row sums of squares of B_i: partials from a GEMM epilogue over n rows
+    // (tiles of >= 64 rows) or from the column reduction (CSR EI)
+    int64_t nb_part = cdiv(n, 64);
     if (colsq_groups(n) > nb_part) nb_part = colsq_groups(n);
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -84,6 +86,7 @@ Layout make_layout(int algo, int sparse, int64_t m, int64_t n, int64_t nnz, cons
     L.rt = take(sizeof(double) * b * b);
     L.rti = take(sizeof(double) * b * b);
     L.ri = take(sizeof(double) * b * b);
+    L.rii = take(sizeof(double) * b * b);
     L.tau = take(sizeof(double) * b);
     L.rowsq_part = take(sizeof(double) * nb_part * b);
     L.rowsq = take(sizeof(double) * b);
@@ -270,8 +273,11 @@ int orth_block(const Ctx& x, int64_t k, int bw, const double* GJ, int64_t ldgj, 
         if (int st = cholqr(x, X2, bw, Qi, x.ldq, Rt, Rti)) return st;
     } else {
         QB_HIP(launch_householder(X2, m, bw, m, Qi, x.ldq, Rt, tau, x.s));
+        QB_HIP(launch_tri_inv(R1, bw, R1i, x.s));
+        QB_HIP(launch_tri_inv(Rt, bw, Rti, x.s));
     }
-    QB_HIP(launch_upper_mul(Rt, R1, bw, x.at<double>(x.L.ri), x.s));
+    // R_i = R~ R (step 14) and its inverse R^{-1} R~^{-1}
+    QB_HIP(launch_upper_mul2(Rt, R1, R1i, Rti, bw, x.at<double>(x.L.ri), x.at<double>(x.L.rii), x.s));
     return QB_OK;
 }
 
@@ -294,9 +300,16 @@ int fp_block_b(const Ctx& x, int64_t k, int bw, const double* HJ, int64_t ldhj) 
                            View{HJ, ldhj, 1}, MutView{S, 1, n}, x);
         QB_HIP(gemm_f64(d, x.s));
     }
+    // B_i^T = S^T R_i^{-1} (the triangular solve R_i^T B_i = S), written to rows k.. of B
+    // with the column sums of squares = ||B_i(j,:)||^2
     double* part = x.at<double>(x.L.rowsq_part);
-    QB_HIP(launch_trsm_rowsq(S, n, x.at<double>(x.L.ri), bw, n, x.B + k * x.ldb, x.ldb, part, x.s));
-    QB_HIP(launch_sum_partials(part, trsm_groups(n), bw, bw, x.at<double>(x.L.rowsq), x.s));
+    int groups = 0;
+    GemmDesc d = gdesc(n, bw, bw, View{S, 1, n}, View{x.at<double>(x.L.rii), bw, 1}, 1.0, 0.0,
+                       View{nullptr, 0, 0}, MutView{x.B + k * x.ldb, 1, x.ldb}, x);
+    d.colsq = part;
+    d.colsq_groups = &groups;
+    QB_HIP(gemm_f64(d, x.s));
+    QB_HIP(launch_sum_partials(part, groups, bw, bw, x.at<double>(x.L.rowsq), x.s));
     return QB_OK;
 }
 

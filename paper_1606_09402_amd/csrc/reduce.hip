@@ -58,16 +58,20 @@ sumsq_vec_partial(const double* __restrict__ x, int64_t len, int64_t chunk,
     if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
-// out[j] = sum_{g < groups} partial[g * stride + j] in order g = 0, 1, ...; one thread
-// per output.  Used for the final stage of every reduction in the library.
+// out[j] = sum_{g < groups} partial[g * stride + j]; one wave per output: lane l sums
+// groups l, l + 64, ... in order, then the 64 lane sums are combined by a fixed xor
+// tree.  Used for the final stage of every reduction of per-workgroup partials.
 __global__ void __launch_bounds__(256)
 sum_partials_kernel(const double* __restrict__ partial, int64_t groups, int64_t stride,
                     int64_t count, double* __restrict__ out) {
-    const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t j = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (j >= count) return;
     double t = 0.0;
-    for (int64_t g = 0; g < groups; ++g) t += partial[g * stride + j];
-    out[j] = t;
+    for (int64_t g = lane; g < groups; g += 64) t += partial[g * stride + j];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+    if (lane == 0) out[j] = t;
 }
 
 // Single workgroup sum of `count` partials (pairwise over threads, fixed order).
@@ -104,7 +108,7 @@ hipError_t launch_sumsq_vec(const double* x, int64_t len, double* scratch, doubl
 hipError_t launch_sum_partials(const double* partial, int64_t groups, int64_t stride,
                                int64_t count, double* out, hipStream_t s) {
     if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(sum_partials_kernel, dim3(static_cast<unsigned>(cdiv(count, 256))),
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(static_cast<unsigned>(cdiv(count, 4))),
                        dim3(256), 0, s, partial, groups, stride, count, out);
     return hipGetLastError();
 }
