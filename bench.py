@@ -2,10 +2,12 @@
 
 Workload (synthetic, seeded): dense FP64 A = U diag(sigma) V^T + noise, 20000 x 15000,
 sigma_j = exp(-j/150) on 3000 Haar columns, iid N(0, (1e-8)^2) noise, block size b = 64,
-relative Frobenius tolerance 1e-3, l~ = 50 b (the paper's Section 5.4 rule).  One step
-is one full call of the library's randQB_FP (||A||^2, Omega, G = A Omega, H = A^T G,
-block loop to the tolerance) with A already resident in HBM; randQB_EI is timed beside
-it on the same matrix.
+relative Frobenius tolerance 1e-3.  One step is one full call of the library's randQB_FP
+(||A||^2, Omega, G = A Omega, H = A^T G, block loop to the tolerance, restarts) with A
+already resident in HBM.  The headline uses the adaptive chunk schedule (l_tilde = -1:
+8 b Omega columns first, later chunks sized from the decay of E, at most 50 b); the
+paper's fixed l~ = 50 b rule (Section 5.4) and randQB_EI are timed beside it on the same
+matrix.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 
@@ -38,7 +40,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ei", action="store_true")
-    ap.add_argument("--l-tilde", type=int, default=0, help="chunk width (0: paper rule 50 b)")
+    ap.add_argument("--l-tilde", type=int, default=-1,
+                    help="headline chunk schedule (-1: adaptive, 0: paper rule 50 b, >0: fixed)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
@@ -66,8 +69,8 @@ def main():
                qb.qb_workspace_bytes(qb.QB_ALGO_EI, False, m, n, 0, wl.tol, wl.b, l_max))
     ws = torch.empty(need, dtype=torch.uint8, device=dev)
 
-    def fp():
-        return qb.qb_fp_dense(A, wl.tol, wl.b, seed, l_max=l_max, l_tilde=args.l_tilde,
+    def fp(l_tilde=args.l_tilde):
+        return qb.qb_fp_dense(A, wl.tol, wl.b, seed, l_max=l_max, l_tilde=l_tilde,
                               Q_store=Qs, B_store=Bs, ws=ws)
 
     def ei():
@@ -91,13 +94,16 @@ def main():
     r = results[-1]
     med = statistics.median(times)
 
-    # dominant kernel: per-launch flops / per-launch device time (HIP events in the library)
-    w_chunks = [min(r.Q_store.shape[0], 50 * wl.b if args.l_tilde == 0 else args.l_tilde)]
+    # dominant kernel: the sketch GEMM with the larger share of device time.  Per launch:
+    # 2 m n w algorithmic flops over the launch's device time (HIP events the library
+    # records on the stream the GEMM runs on); averaged over the chunks of a call.
     g_ms = statistics.median(x.ms[2] for x in results) / max(1, r.chunks)
     h_ms = statistics.median(x.ms[3] for x in results) / max(1, r.chunks)
     flops_per_launch = r.gemm_flops[0] / max(1, r.chunks)
     dom_ms, dom_name = (h_ms, "gemm_f64 H=A^T G") if h_ms >= g_ms else (g_ms, "gemm_f64 G=A Omega")
     achieved = flops_per_launch / (dom_ms * 1e-3) / 1e12
+    schedule = {-1: "adaptive (8b first, <= 50b)", 0: "paper rule 50b"}.get(args.l_tilde,
+                                                                          str(args.l_tilde))
 
     # accuracy of the returned factorisation (verification, not timed)
     Q = r.Q
@@ -119,11 +125,12 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": wl.name, "m": m, "n": n, "b": wl.b, "tol": wl.tol,
-                   "l_tilde": args.l_tilde or 50 * wl.b, "algo": "randQB_FP", "power": 0},
+                   "l_tilde": schedule, "algo": "randQB_FP", "power": 0},
         "rank": r.rank,
         "E_rel": (max(r.E, 0.0) / r.normA2) ** 0.5,
         "true_rel_err": true_rel,
         "passes": r.passes,
+        "chunks": r.chunks,
         "blocks": r.blocks,
         "phase_ms": {"normA2": r.ms[0], "omega": r.ms[1], "G": r.ms[2], "H": r.ms[3],
                      "block_loop": r.ms[4], "total": r.ms[5]},
@@ -132,6 +139,22 @@ def main():
                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None},
     }
+    if args.l_tilde != 0:   # the paper's fixed l~ = 50 b beside the headline schedule
+        fp(0)
+        pt = []
+        for _ in range(max(1, min(args.steps, 3))):
+            t = time.perf_counter()
+            rp = fp(0)
+            torch.cuda.synchronize()
+            pt.append(time.perf_counter() - t)
+        out["paper_rule"] = {"time_to_tol_s": round(statistics.median(pt), 6), "rank": rp.rank,
+                             "l_tilde": 50 * wl.b, "passes": rp.passes,
+                             "sketch_tflops": (rp.gemm_flops[0] + rp.gemm_flops[1])
+                             / ((rp.ms[2] + rp.ms[3]) * 1e-3) / 1e12,
+                             "phase_ms": {"G": rp.ms[2], "H": rp.ms[3], "block_loop": rp.ms[4],
+                                          "total": rp.ms[5]}}
+        print(f"# paper rule: {statistics.median(pt) * 1e3:.1f} ms rank {rp.rank}", file=sys.stderr,
+              flush=True)
     if not args.no_ei:
         ei()
         torch.cuda.synchronize()
@@ -148,12 +171,12 @@ def main():
               file=sys.stderr, flush=True)
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(A, wl, seed)
+        out["cpu_baseline"] = cpu_baseline(A, wl, seed, args.l_tilde)
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(A, wl, seed):
-    """The FP64 oracle's randQB_FP on the same matrix, once, on the host cores."""
+def cpu_baseline(A, wl, seed, l_tilde):
+    """The FP64 oracle's randQB_FP on the same matrix and schedule, once, on the host cores."""
     import numpy as np
 
     from oracle import randqb as R
@@ -165,11 +188,12 @@ def cpu_baseline(A, wl, seed):
     An = A.cpu().numpy()
     print("# cpu baseline: oracle randQB_FP on the full workload ...", file=sys.stderr, flush=True)
     t = time.perf_counter()
-    ora = R.randqb_fp(An, wl.tol, wl.b, seed)
+    ora = R.randqb_fp(An, wl.tol, wl.b, seed, l_tilde=l_tilde)
     dt = time.perf_counter() - t
     print(f"# cpu baseline: {dt:.1f} s rank {ora.rank}", file=sys.stderr, flush=True)
     return {"value": round(dt, 3), "unit": "s", "cores": threads, "kind": "oracle",
-            "sample": f"full {wl.name} workload, one randQB_FP call (NumPy/OpenBLAS FP64)",
+            "sample": f"full {wl.name} workload, one randQB_FP call with the same chunk schedule "
+                      "(NumPy/OpenBLAS FP64)",
             "rank": ora.rank}
 
 

@@ -28,6 +28,11 @@ design notes of the repository):
 * l~ (chunk width) defaults to min(50 b, l_max) (Section 5.4); when a chunk is
   used up without convergence the next l~ columns of Omega are drawn and G, H
   recomputed (the restart described after Algorithm 4), keeping Q, B and E;
+* l_tilde = -1 selects an adaptive chunk schedule (the paper leaves the choice of l~
+  open): the first chunk has 8 b columns; after a chunk of w columns moved the
+  indicator from E_prev to E_now, the decay per column is taken as geometric and the
+  next chunk is 1.25 times the columns needed to reach eps^2 plus b, rounded up to a
+  multiple of b and kept in [b, 4 w]; no chunk exceeds min(50 b, l_max);
 * exhaustion guard: before row j of a block is accepted, R_i(j,j) must exceed
   2^-40 ||G_J(:,j)||_2, otherwise the method stops before row j (the numerical
   rank of A has been reached and R_i^{-T} would divide by round-off);
@@ -166,14 +171,36 @@ def _finish(st, E, normA2, status_tol, exhausted, l_max, k, eps2, **kw):
                     exhausted=int(exhausted), **kw)
 
 
+def _chunk_width(adaptive: bool, cap: int, b: int, left: int, w_prev: int, e_prev: float,
+                 e_now: float, eps2: float) -> int:
+    """Width of the next chunk of Omega columns (see the module notes)."""
+    if not adaptive:
+        w = cap
+    elif w_prev == 0:
+        w = 8 * b
+    elif e_now > 0.0 and e_prev > e_now and 0.0 < eps2 < e_now:
+        rate = np.log(e_now / e_prev) / w_prev
+        need = np.log(eps2 / e_now) / rate
+        want = 1.25 * need + b
+        if want >= 4.0 * w_prev:
+            w = 4 * w_prev
+        else:
+            w = max(b, -(-int(np.ceil(want)) // b) * b)
+    else:
+        w = 2 * w_prev
+    return min(w, cap, left)
+
+
 def randqb_fp(A, tol_rel: float, b: int, seed: int, l_max=None, l_tilde: int = 0,
               row_by_row: bool = True) -> QBResult:
     """randQB_FP for the fixed-precision problem (Algorithm 4 with P = 0)."""
     m, n, l_max = _check(A, tol_rel, b, l_max)
-    if l_tilde == 0:
+    adaptive = l_tilde == -1
+    if l_tilde in (0, -1):
         l_tilde = min(50 * b, l_max)
-    if l_tilde <= 0 or (l_tilde % b != 0 and l_tilde != l_max):
+    if l_tilde <= 0 or (l_tilde % b != 0 and l_tilde < l_max):
         raise ValueError("l_tilde must be a multiple of b")
+    l_tilde = min(l_tilde, l_max)
     normA2 = sumsq(A)
     if not np.isfinite(normA2):
         return QBResult(np.empty((m, 0)), np.empty((0, n)), 0, normA2, normA2, QB_ERR_NONFINITE)
@@ -187,12 +214,15 @@ def randqb_fp(A, tol_rel: float, b: int, seed: int, l_max=None, l_tilde: int = 0
     exhausted = False
     trace, rdiag = [], []
     chunk_lo = chunk_hi = 0
+    e_start = E
     Om = G = H = Gnorm = None
     while st.k < l_max:
         k = st.k
         if k == chunk_hi:                       # draw the next chunk of Omega
+            w = _chunk_width(adaptive, l_tilde, b, l_max - k, chunk_hi - chunk_lo, e_start, E, eps2)
+            e_start = E
             chunk_lo = k
-            chunk_hi = min(k + l_tilde, l_max)
+            chunk_hi = k + w
             Om = omega(seed, n, chunk_lo, chunk_hi - chunk_lo)
             G = A @ Om
             H = A.T @ G

@@ -22,29 +22,82 @@ struct RegLayout {
     static constexpr int NT = 256, G = NT / BMAX, Q = BMAX / G;
 };
 
-// In-place inverse of the upper-triangular factor held in Rs (pitch BMAX + 1) by
-// right-looking back substitution R X = I: row i of X is T(i, :) / R(i, i), then rows
-// a < i lose R(a, i) X(i, :).  v[] is the thread's register slice of T.
+// One elimination step per row j = g0 + G Q0 of the right-looking Cholesky, for the
+// row slot Q0 (a template parameter, so v[Q0] is a compile-time register); recurses to
+// the next slot.  Returns false on a pivot at or below floor_piv.
+template <int BMAX, int Q0>
+QB_DEV bool chol_slots(double (&v)[RegLayout<BMAX>::Q], double (*row)[BMAX], double* Rs, int b,
+                       double floor_piv, int& step) {
+    using L = RegLayout<BMAX>;
+    if constexpr (Q0 >= L::Q) {
+        return true;
+    } else {
+        constexpr int ld = BMAX + 1;
+        const int tid = threadIdx.x, c = tid % BMAX, g = tid / BMAX;
+        for (int g0 = 0; g0 < L::G; ++g0) {
+            const int j = g0 + L::G * Q0;
+            if (j >= b) return true;                  // uniform
+            const int buf = step & 1;
+            ++step;
+            if (g == g0) row[buf][c] = v[Q0];         // publish row j
+            __syncthreads();
+            const double piv = row[buf][j];
+            if (!(piv > floor_piv)) return false;     // uniform (NaN included)
+            const double rjj = sqrt(piv);
+            const double ir = 1.0 / rjj;
+            const double rc = row[buf][c] * ir;       // R(j, c) for c >= j
+            if (g == 0) Rs[j * ld + c] = (c >= j && c < b) ? (c == j ? rjj : rc) : 0.0;
+#pragma unroll
+            for (int q = 0; q < L::Q; ++q) {
+                const int a = g + L::G * q;
+                const double upd = v[q] - (row[buf][a] * ir) * rc;
+                v[q] = (a > j && c >= a) ? upd : v[q];
+            }
+        }
+        return chol_slots<BMAX, Q0 + 1>(v, row, Rs, b, floor_piv, step);
+    }
+}
+
+// Back substitution R X = I for the rows of slot Q0 (descending), then the lower slots:
+// row i of X is T(i, :) / R(i, i), then rows a < i lose R(a, i) X(i, :).
+template <int BMAX, int Q0>
+QB_DEV void inv_slots(double (&v)[RegLayout<BMAX>::Q], double (*row)[BMAX], const double* Rs,
+                      int b, double* __restrict__ Rinv, int& step) {
+    using L = RegLayout<BMAX>;
+    if constexpr (Q0 >= 0) {
+        constexpr int ld = BMAX + 1;
+        const int tid = threadIdx.x, c = tid % BMAX, g = tid / BMAX;
+        for (int g0 = L::G - 1; g0 >= 0; --g0) {
+            const int i = g0 + L::G * Q0;
+            if (i >= b) continue;                     // uniform
+            const int buf = step & 1;
+            ++step;
+            if (g == g0) row[buf][c] = v[Q0] / Rs[i * ld + i];
+            __syncthreads();
+            const double xc = row[buf][c];
+            if (g == 0 && c < b) Rinv[i * b + c] = c >= i ? xc : 0.0;
+#pragma unroll
+            for (int q = 0; q < L::Q; ++q) {
+                const int a = g + L::G * q;
+                const double upd = v[q] - Rs[a * ld + i] * xc;
+                v[q] = a < i ? upd : v[q];
+            }
+        }
+        inv_slots<BMAX, Q0 - 1>(v, row, Rs, b, Rinv, step);
+    }
+}
+
+// Inverse of the upper-triangular factor held in Rs (pitch BMAX + 1); v[] is the
+// thread's register slice of the working matrix T (initialised to I).
 template <int BMAX>
 QB_DEV void tri_inverse_rows(const double* Rs, int b, double (&v)[RegLayout<BMAX>::Q],
                              double (*row)[BMAX], double* __restrict__ Rinv) {
     using L = RegLayout<BMAX>;
     const int tid = threadIdx.x, c = tid % BMAX, g = tid / BMAX;
-    constexpr int ld = BMAX + 1;
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) v[q] = (g + L::G * q) == c ? 1.0 : 0.0;
-    for (int i = b - 1; i >= 0; --i) {
-        const int buf = i & 1;
-        if (g == i % L::G) row[buf][c] = v[i / L::G] / Rs[i * ld + i];
-        __syncthreads();
-        const double xc = row[buf][c];
-        if (g == 0 && c < b) Rinv[i * b + c] = c >= i ? xc : 0.0;
-#pragma unroll
-        for (int q = 0; q < L::Q; ++q) {
-            const int a = g + L::G * q;
-            if (a < i) v[q] -= Rs[a * ld + i] * xc;
-        }
-    }
+    int step = 0;
+    inv_slots<BMAX, L::Q - 1>(v, row, Rs, b, Rinv, step);
 }
 
 // Gram (b x b, row-major, only the upper triangle is read) -> R upper (row-major, zero
@@ -75,25 +128,10 @@ chol_upper_inv_kernel(const double* __restrict__ gram, int b, double tau, double
     double dmax = 0.0;
 #pragma unroll
     for (int w = 0; w < L::NT / 64; ++w) dmax = fmax(dmax, wmax[w]);
-    const double floor_piv = tau * dmax;
-
-    for (int j = 0; j < b; ++j) {
-        const int buf = j & 1;
-        if (g == j % L::G) row[buf][c] = v[j / L::G];
-        __syncthreads();
-        const double piv = row[buf][j];
-        if (!(piv > floor_piv)) {   // uniform: every thread read the same pivot (NaN included)
-            if (tid == 0) flag[0] = 1;
-            return;
-        }
-        const double ir = 1.0 / sqrt(piv);
-        const double rc = row[buf][c] * ir;   // R(j, c) for c >= j
-        if (g == 0) Rs[j * ld + c] = (c >= j && c < b) ? (c == j ? sqrt(piv) : rc) : 0.0;
-#pragma unroll
-        for (int q = 0; q < L::Q; ++q) {
-            const int a = g + L::G * q;
-            if (a > j && c >= a) v[q] -= (row[buf][a] * ir) * rc;
-        }
+    int step = 0;
+    if (!chol_slots<BMAX, 0>(v, row, Rs, b, tau * dmax, step)) {
+        if (tid == 0) flag[0] = 1;
+        return;
     }
     __syncthreads();
     for (int e = tid; e < b * b; e += L::NT) {

@@ -39,9 +39,41 @@ struct Layout {
     int64_t lt, split_elems, gpart_groups;
 };
 
+// Largest chunk of Omega columns: l_tilde, or the paper's min(50 b, l_max) for 0 and for
+// the adaptive schedule (-1).
 int64_t chunk_width(const qb_params* p) {
-    int64_t lt = p->l_tilde == 0 ? 50 * static_cast<int64_t>(p->b) : p->l_tilde;
+    int64_t lt = p->l_tilde <= 0 ? 50 * static_cast<int64_t>(p->b) : p->l_tilde;
     return lt < p->l_max ? lt : p->l_max;
+}
+
+int64_t round_up(int64_t x, int64_t b) { return ((x + b - 1) / b) * b; }
+
+// Width of the next chunk of Omega columns starting at column k.  Fixed schedules use the
+// full width.  The adaptive schedule starts with 8 b columns; after a chunk of w columns
+// took the indicator from e_prev to e_now, it assumes the same per-column geometric decay
+// and asks for 1.25 x the columns that would reach eps^2 plus one block, rounded up to a
+// multiple of b and kept within [b, 4 w] (never above the fixed width).
+int64_t next_chunk(const qb_params* p, int64_t cap, int64_t k, int64_t w_prev, double e_prev,
+                   double e_now, double eps2) {
+    const int64_t b = p->b;
+    const int64_t left = p->l_max - k;
+    int64_t w;
+    if (p->l_tilde != -1) {
+        w = cap;
+    } else if (w_prev == 0) {
+        w = 8 * b;
+    } else if (e_now > 0.0 && e_prev > e_now && eps2 > 0.0 && eps2 < e_now) {
+        const double rate = log(e_now / e_prev) / static_cast<double>(w_prev);   // < 0
+        const double need = log(eps2 / e_now) / rate;                               // > 0
+        const double want = 1.25 * need + static_cast<double>(b);
+        const double hi = 4.0 * static_cast<double>(w_prev);
+        w = want >= hi ? 4 * w_prev : round_up(static_cast<int64_t>(ceil(want)), b);
+        if (w < b) w = b;
+    } else {
+        w = 2 * w_prev;
+    }
+    if (w > cap) w = cap;
+    return w < left ? w : left;
 }
 
 Layout make_layout(int algo, int sparse, int64_t m, int64_t n, int64_t nnz, const qb_params* p) {
@@ -397,8 +429,8 @@ int check_params(const qb_params* p, int64_t m, int64_t n) {
     if (p->b < 1 || p->b > kMaxB) return QB_ERR_ARG;
     const int64_t mn = m < n ? m : n;
     if (p->l_max < 1 || p->l_max > mn) return QB_ERR_ARG;
-    if (p->l_tilde < 0) return QB_ERR_ARG;
-    if (p->l_tilde != 0 && p->l_tilde % p->b != 0 && p->l_tilde < p->l_max) return QB_ERR_ARG;
+    if (p->l_tilde < -1) return QB_ERR_ARG;
+    if (p->l_tilde > 0 && p->l_tilde % p->b != 0 && p->l_tilde < p->l_max) return QB_ERR_ARG;
     if (m >= (int64_t(1) << 31) || n >= (int64_t(1) << 31)) return QB_ERR_ARG;
     return QB_OK;
 }
@@ -466,6 +498,7 @@ int run(int algo, Op& A, const qb_params* p, double* Q, int64_t ldq, double* B, 
     if (!(normA2 == 0.0 || E < eps2)) {
         QB_HIP(launch_fill_int(x.at<int>(L.flags), 8, 0, s));
         int64_t chunk_lo = 0, chunk_hi = 0;
+        double e_chunk_start = E;
         double* Om = x.at<double>(L.om);
         double* G = x.at<double>(L.g);
         double* H = x.at<double>(L.h);
@@ -477,9 +510,11 @@ int run(int algo, Op& A, const qb_params* p, double* Q, int64_t ldq, double* B, 
             int64_t ldj;
             if (algo == QB_ALGO_FP) {
                 if (k == chunk_hi) {   // draw the next chunk of Omega; G = A Omega, H = A^T G
+                    const int64_t w = next_chunk(p, L.lt, k, chunk_hi - chunk_lo, e_chunk_start, E,
+                                                 eps2);
                     chunk_lo = k;
-                    chunk_hi = k + L.lt < lmax ? k + L.lt : lmax;
-                    const int64_t w = chunk_hi - chunk_lo;
+                    chunk_hi = k + w;
+                    e_chunk_start = E;
                     tm.mark(1);
                     QB_HIP(launch_gauss_fill(p->seed, 0, 0, 0, chunk_lo, n, w, Om, w, s));
                     tm.mark(2);

@@ -133,6 +133,8 @@ CASES = [
     ("b=1", lambda: W.lowrank_dense(90, 80, W.sigma_law("exp7", 80), 6), 1e-4, 1, {}),
     ("multi-chunk l~=32", lambda: W.lowrank_dense(700, 400, W.sigma_law("exp20", 400), 5), 1e-4, 16,
      {"l_tilde": 32}),
+    ("adaptive chunks", lambda: W.lowrank_dense(900, 700, W.sigma_law("exp40", 700), 7), 1e-4, 16,
+     {"l_tilde": -1}),
     ("whole-block stop", lambda: W.lowrank_dense(500, 300, W.sigma_law("poly2", 300), 8), 1e-3, 10,
      {"row_by_row": False}),
     ("l_max reached", lambda: W.lowrank_dense(400, 300, W.sigma_law("poly2", 300), 9), 1e-6, 10,
@@ -164,13 +166,14 @@ def test_c2_small_parity(qb):
     """The benchmark workload's law at an oracle-friendly size (4000 x 3000)."""
     A = W.C2_SMALL.make()
     An = A.numpy()
-    for algo in ("fp", "ei"):
-        _log(f"C2-small {algo}")
+    for algo, kw in (("fp", {}), ("fp", {"l_tilde": -1}), ("ei", {})):
+        _log(f"C2-small {algo} {kw}")
         f = qb.qb_fp_dense if algo == "fp" else qb.qb_ei_dense
         g = R.randqb_fp if algo == "fp" else R.randqb_ei
-        res = f(A.cuda(), W.C2_SMALL.tol, W.C2_SMALL.b, SEED)
-        ora = g(An, W.C2_SMALL.tol, W.C2_SMALL.b, SEED)
-        _compare(res, ora, An, f"C2-small {algo}")
+        res = f(A.cuda(), W.C2_SMALL.tol, W.C2_SMALL.b, SEED, **kw)
+        ora = g(An, W.C2_SMALL.tol, W.C2_SMALL.b, SEED, **kw)
+        _compare(res, ora, An, f"C2-small {algo} {kw}")
+        assert res.chunks == ora.chunks
 
 
 def test_degenerate_inputs(qb):
@@ -272,11 +275,11 @@ def test_benchmark_workload_full_size(qb):
     A = wl.make(device="cuda")
     torch.cuda.synchronize()
     An = A.cpu().numpy()
-    for algo in ("fp", "ei"):
-        _log(f"full-size {algo} {wl.name}")
+    for algo, kw in (("fp", {}), ("fp", {"l_tilde": -1}), ("ei", {})):
+        _log(f"full-size {algo} {kw} {wl.name}")
         f = qb.qb_fp_dense if algo == "fp" else qb.qb_ei_dense
         g = R.randqb_fp if algo == "fp" else R.randqb_ei
-        res = f(A, wl.tol, wl.b, seed, l_max=min(wl.m, wl.n))
-        ora = g(An, wl.tol, wl.b, seed)
+        res = f(A, wl.tol, wl.b, seed, l_max=min(wl.m, wl.n), **kw)
+        ora = g(An, wl.tol, wl.b, seed, **kw)
         _compare(res, ora, An, f"full-size {algo}")
         assert res.rank >= R.svd_optimal_rank(wl.sigma(), wl.tol) - 1

@@ -323,3 +323,31 @@ def test_planted_omega_misalignment_is_caught(monkeypatch, m2):
     monkeypatch.setattr(R, "omega", real)
     ei = R.randqb_ei(A, 1e-3, 8, 19)
     assert fp.rank != ei.rank or np.linalg.norm(fp.B - ei.B) > 1e-6 * np.sqrt(fp.normA2)
+
+
+def test_adaptive_chunks_same_factorisation(m2):
+    """The chunk schedule only regroups Omega's columns (the restart after Algorithm 4):
+    Q, B, rank and E do not depend on it."""
+    A, _ = m2
+    fixed = R.randqb_fp(A, 1e-4, 8, 9)
+    adapt = R.randqb_fp(A, 1e-4, 8, 9, l_tilde=-1)
+    assert adapt.chunks >= 2 and adapt.passes == 2 * adapt.chunks
+    assert adapt.rank == fixed.rank
+    # chunk widths change the BLAS blocking of G and H; FP's B carries that round-off
+    # amplified over the blocks (Remark 4.1)
+    assert np.linalg.norm(adapt.B - fixed.B) < 1e-10 * np.sqrt(fixed.normA2)
+    assert abs(adapt.E - fixed.E) < 1e-13 * fixed.normA2
+
+
+def test_adaptive_chunk_width_rule():
+    cw = R._chunk_width
+    assert cw(True, 400, 8, 1000, 0, 1.0, 1.0, 1e-6) == 64          # first chunk 8 b
+    # E fell by e^-2 over 64 columns; reaching eps^2 = e^-10 E needs 320 more -> 1.25*320+8
+    w = cw(True, 4000, 8, 10000, 64, 1.0, np.exp(-2.0), np.exp(-12.0))
+    assert w == 256                                                   # capped at 4 w
+    w = cw(True, 4000, 8, 10000, 128, 1.0, np.exp(-4.0), np.exp(-6.0))
+    assert w == 88                                                    # 1.25*64 + 8 = 88
+    assert cw(True, 50, 8, 1000, 64, 1.0, 0.5, 1e-9) == 50           # never above the cap
+    assert cw(True, 400, 8, 30, 64, 1.0, 0.5, 1e-9) == 30            # nor past l_max
+    assert cw(True, 400, 8, 1000, 64, 1.0, -1e-3, 1e-9) == 128       # no decay info: double
+    assert cw(False, 400, 8, 1000, 64, 1.0, 0.5, 1e-9) == 400        # fixed schedule
