@@ -40,6 +40,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ei", action="store_true")
+    ap.add_argument("--gen-device", default="cuda", choices=["cuda", "cpu"],
+                    help="where the seeded test matrix is generated (cpu keeps the GPU QR of the "
+                         "generator out of counter-collection runs)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one plain 1 GiB device copy first (scale for HBM counter runs)")
     ap.add_argument("--l-tilde", type=int, default=-1,
                     help="headline chunk schedule (-1: adaptive, 0: paper rule 50 b, >0: fixed)")
     args = ap.parse_args()
@@ -58,7 +63,7 @@ def main():
     seed = W.SEED_OMEGA | 2
     dev = torch.device("cuda:0")
     t0 = time.time()
-    A = wl.make(device=dev)
+    A = wl.make(device=dev if args.gen_device == "cuda" else "cpu").to(dev)
     torch.cuda.synchronize()
     print(f"# generated {wl.name} on the GPU in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
     m, n = A.shape
@@ -75,6 +80,13 @@ def main():
 
     def ei():
         return qb.qb_ei_dense(A, wl.tol, wl.b, seed, l_max=l_max, Q_store=Qs, B_store=Bs, ws=ws)
+
+    if args.calib_copy:   # 2^27 doubles read and written once: 1 GiB each way
+        src = torch.ones(2 ** 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     for i in range(args.warmup):
         r = fp()

@@ -14,6 +14,8 @@
 // workgroups (split-K); partial tiles are then summed in a fixed order by a second
 // kernel, so results are bit-reproducible.  Optionally the epilogue emits per-row-tile
 // column sums of squares of the output (used for ||B_i(j,:)||^2 and ||A Omega(:,j)||^2).
+#include <cmath>
+
 #include "kernels.h"
 
 namespace qb {
@@ -380,14 +382,31 @@ static hipError_t run_cfg(const GemmDesc& d, hipStream_t s) {
     g.tiles_n = static_cast<int>(cdiv(d.N, BN));
     const int64_t tiles = static_cast<int64_t>(g.tiles_m) * g.tiles_n;
     int nsplit = 1;
+    const int64_t ktiles = cdiv(d.K, BK);
     if (d.ws != nullptr && tiles < 512) {
-        const int64_t ktiles = cdiv(d.K, BK);
+        // few output tiles: spread the reduction over about 640 workgroups
         int64_t want = cdiv(640, tiles);
-        if (want > 32) want = 32;
+        if (want > 128) want = 128;
         if (want > ktiles / 4) want = ktiles / 4;
         if (d.max_split > 0 && want > d.max_split) want = d.max_split;
         while (want > 1 && want * d.M * d.N > d.ws_elems) --want;
         if (want > 1) nsplit = static_cast<int>(want);
+    } else if (d.ws != nullptr) {
+        // pick 1..4 K splits to shrink the idle tail of the last round of workgroups
+        // (the split partials cost one extra pass over M x N); the resident workgroups
+        // per CU follow from the LDS footprint
+        using Cf = GemmCfg<BM, BN, BK, WM, WN, AL, BL>;
+        constexpr int64_t lds = 8 * (STAGES * (Cf::A_ROWS * Cf::A_PITCH + Cf::B_ROWS * Cf::B_PITCH) +
+                                     WM * BN);
+        constexpr int64_t per_cu = (160 * 1024) / lds < 1 ? 1 : (160 * 1024) / lds;
+        const int64_t slots = 256 * per_cu;
+        double best = 0.0;
+        for (int ns = 1; ns <= 4; ++ns) {
+            if (ns > 1 && (ktiles < 16 * ns || ns * d.M * d.N > d.ws_elems)) break;
+            const double work = static_cast<double>(tiles * ns) / slots;
+            const double eff = work / std::ceil(work) * (1.0 - 0.02 * (ns - 1));
+            if (eff > best + 1e-9) { best = eff; nsplit = ns; }
+        }
     }
     g.kchunk = cdiv(cdiv(d.K, BK), nsplit) * BK;
     nsplit = static_cast<int>(cdiv(d.K, g.kchunk));

@@ -87,6 +87,9 @@ Layout make_layout(int algo, int sparse, int64_t m, int64_t n, int64_t nnz, cons
     L.split_elems = 512 * b * (b > 64 ? b : 64) + 65536;
     if (L.split_elems < kGramSplitElems) L.split_elems = kGramSplitElems;
     if (L.split_elems < 8 * (m > n ? m : n) * b) L.split_elems = 8 * (m > n ? m : n) * b;
+    // dense randQB_FP: room for two K splits of the widest sketch GEMM (G, m x l~)
+    if (algo == QB_ALGO_FP && !sparse && L.split_elems < 2 * (m > n ? m : n) * lt)
+        L.split_elems = 2 * (m > n ? m : n) * lt;
     // row-tile partials of the G column norms: dense GEMM tiles are >= 64 rows
     L.gpart_groups = sparse ? colsq_groups(m) : cdiv(m, 64);
     // per-block row sums of squares of B_i: partials from a GEMM epilogue over n rows
