@@ -46,7 +46,7 @@ import numpy as np
 import scipy.linalg
 import scipy.sparse as sp
 
-from . import rng
+from . import lowp, rng
 
 # status codes (same meaning as the C ABI)
 QB_OK = 0
@@ -192,9 +192,19 @@ def _chunk_width(adaptive: bool, cap: int, b: int, left: int, w_prev: int, e_pre
 
 
 def randqb_fp(A, tol_rel: float, b: int, seed: int, l_max=None, l_tilde: int = 0,
-              row_by_row: bool = True) -> QBResult:
-    """randQB_FP for the fixed-precision problem (Algorithm 4 with P = 0)."""
+              row_by_row: bool = True, precision: str = "f64") -> QBResult:
+    """randQB_FP for the fixed-precision problem (Algorithm 4 with P = 0).
+
+    precision = "bf16" is the precision form: A must hold bfloat16 values (A_q); each
+    chunk's Omega is rounded to bfloat16 (Omega_q), G = A_q Omega_q is rounded to
+    bfloat16 (G_q), and H = A_q^T G_q is formed from that same G_q.  The block loop uses
+    Omega_q, G_q and H in binary64, so eq. (23) still yields B_i = Q_i^T A_q and
+    Theorem 1 holds for A_q with E starting from ||A_q||^2."""
     m, n, l_max = _check(A, tol_rel, b, l_max)
+    if precision not in ("f64", "bf16"):
+        raise ValueError("precision must be 'f64' or 'bf16'")
+    if precision == "bf16" and not lowp.is_bf16(A if not sp.issparse(A) else A.data):
+        raise ValueError("the precision form takes A already stored in bfloat16")
     adaptive = l_tilde == -1
     if l_tilde in (0, -1):
         l_tilde = min(50 * b, l_max)
@@ -224,7 +234,11 @@ def randqb_fp(A, tol_rel: float, b: int, seed: int, l_max=None, l_tilde: int = 0
             chunk_lo = k
             chunk_hi = k + w
             Om = omega(seed, n, chunk_lo, chunk_hi - chunk_lo)
-            G = A @ Om
+            if precision == "bf16":
+                Om = lowp.round_bf16(Om)
+                G = lowp.round_bf16(np.asarray(A @ Om))
+            else:
+                G = A @ Om
             H = A.T @ G
             G = np.asarray(G)
             H = np.asarray(H)

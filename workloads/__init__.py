@@ -201,6 +201,21 @@ C2_SMALL = DenseWorkload("dense_4000x3000_exp150_noise1e-8_b64_tol1e-3", 4000, 3
                          1500, 1e-8, 64, 1e-3, SEED_GEN + 12)
 
 
+# Precision form: 32768 x 32768, sigma_j = j^-1.5 on 4096 Stiefel columns (the dropped
+# tail is 1.6e-4 of ||A||_F, far below tol), b = 128, tol 1e-2; A is stored in bfloat16
+C4 = DenseWorkload("dense_32768x32768_poly1.5_b128_tol1e-2", 32768, 32768, "poly1.5", 4096, 0.0,
+                   128, 1e-2, SEED_GEN + 4)
+# the same law on a separate full-rank 4096 x 4096 instance for oracle-size parity runs
+C4_SMALL = DenseWorkload("dense_4096x4096_poly1.5_b128_tol1e-2", 4096, 4096, "poly1.5", 4096, 0.0,
+                         128, 1e-2, SEED_GEN + 14)
+
+
+def to_bf16(A: torch.Tensor) -> torch.Tensor:
+    """Storage of a float64 matrix in bfloat16 (input preparation of the precision form:
+    the stored values are the matrix the method factorises)."""
+    return A.to(torch.bfloat16).contiguous()
+
+
 @dataclass
 class SparseWorkload:
     name: str
