@@ -55,9 +55,23 @@ typedef enum {
 
 typedef enum { QB_ALGO_FP = 0, QB_ALGO_EI = 1 } qb_algo;
 
-typedef enum { QB_F64 = 0 } qb_dtype;
+/* Element type of a dense A.
+ *   QB_F64  binary64.
+ *   QB_BF16 bfloat16 storage (the precision form of randQB_FP): the matrix factorised
+ *           is the stored A_q.  ||A_q||^2 is summed in binary64 from the stored values
+ *           (their squares are exact), so Theorem 1 holds for A_q.  The two sketch
+ *           products run on bfloat16 matrix cores with binary32 accumulation:
+ *             Omega_q = bf16(Omega)       (round to nearest even from binary64),
+ *             G_q     = bf16(A_q Omega_q) (binary32 accumulation, then rounded),
+ *             H       = A_q^T G_q         (binary32 accumulation, kept in binary64);
+ *           the block loop (W, Y_i, both QRs, eq. (23), the indicator) runs in binary64
+ *           on Omega_q, G_q and H, i.e. on exactly the operands of the two products,
+ *           so B_i = Q_i^T A_q up to the accumulation error of H.  Only randQB_FP
+ *           accepts it (randQB_EI forms B_i = Q_i^T A directly and would need Q_i in
+ *           bfloat16: QB_ERR_UNSUPPORTED). */
+typedef enum { QB_F64 = 0, QB_BF16 = 1 } qb_dtype;
 
-/* Dense row-major matrix.  dtype must be QB_F64. */
+/* Dense row-major matrix of element type dtype (a qb_dtype). */
 typedef struct {
     int64_t m, n;       /* rows, columns (m, n >= 1)                         */
     int64_t lda;        /* row stride in elements, lda >= n                  */
@@ -105,22 +119,31 @@ typedef struct {
     int32_t fallbacks;   /* panels orthonormalised by the Householder fallback               */
     double ms[8];        /* device time per phase (ms): 0 ||A||^2, 1 Omega, 2 G = A Omega,
                             3 H = A^T G (EI: 2 = the A Omega_i GEMMs, 3 = the A^T Q_i GEMMs),
-                            4 block loop without 2-3, 5 whole call                           */
+                            4 block loop without 2-3, 5 whole call, 6 the transpose of a
+                            bfloat16 A_q (0 for binary64 A)                                  */
     double gemm_flops[2];/* algorithmic flops of the timed G and H GEMMs (2 m n l each)      */
 } qb_info;
 
 /* Bytes of workspace qb_{fp,ei}_{dense,csr} need for this problem (algo = qb_algo,
- * sparse = 0/1, nnz ignored for dense).  Returns 0 for invalid arguments. */
+ * sparse = 0/1, nnz ignored for dense) with binary64 A.  Returns 0 for invalid
+ * arguments. */
 QB_API size_t qb_workspace_bytes(int algo, int sparse, int64_t m, int64_t n, int64_t nnz,
                           const qb_params* p);
 
-/* randQB_FP (Algorithm 4, P = 0) on dense row-major A.  ws must hold at least
- * qb_workspace_bytes(QB_ALGO_FP, 0, ...) bytes of device memory (256-byte aligned). */
+/* Bytes of workspace qb_fp_dense / qb_ei_dense need for dense A of any dtype (the
+ * bfloat16 form adds A_q^T, n x m, and the bfloat16 copies of Omega_q and G_q).
+ * A->a is not read.  Returns 0 for invalid arguments or an unsupported combination. */
+QB_API size_t qb_dense_workspace_bytes(int algo, const qb_dense* A, const qb_params* p);
+
+/* randQB_FP (Algorithm 4, P = 0) on dense row-major A of dtype QB_F64 or QB_BF16.  ws
+ * must hold at least qb_dense_workspace_bytes(QB_ALGO_FP, A, p) bytes of device memory
+ * (256-byte aligned).  For QB_BF16, info->ms[6] is the time of the once-per-call
+ * transpose of A_q and the relative tolerance is taken against ||A_q||_F. */
 QB_API int qb_fp_dense(const qb_dense* A, const qb_params* p, double* Q, int64_t ldq, double* B,
                 int64_t ldb, void* ws, size_t ws_bytes, hipStream_t stream, qb_info* info);
 
-/* randQB_EI (Algorithm 2) on dense row-major A; EI's Omega_i is column block i of the
- * same Omega as randQB_FP uses. */
+/* randQB_EI (Algorithm 2) on dense row-major binary64 A; EI's Omega_i is column block
+ * i of the same Omega as randQB_FP uses. */
 QB_API int qb_ei_dense(const qb_dense* A, const qb_params* p, double* Q, int64_t ldq, double* B,
                 int64_t ldb, void* ws, size_t ws_bytes, hipStream_t stream, qb_info* info);
 
@@ -148,9 +171,9 @@ QB_API int qb_gaussian_fill(uint64_t seed, uint32_t stream_id, uint32_t batch, i
                      int64_t col0, int64_t rows, int64_t cols, double* out, int64_t ld,
                      hipStream_t stream);
 
-/* ||A||_F^2 (Theorem 1 / Algorithm 1 step 2) of dense row-major A, as a deterministic
- * FP64 tree sum of squares; *out_host receives the value.  ws needs
- * qb_sumsq_workspace_bytes() bytes.  Synchronises the stream. */
+/* ||A||_F^2 (Theorem 1 / Algorithm 1 step 2) of dense row-major A (QB_F64 or
+ * QB_BF16), as a deterministic FP64 tree sum of squares; *out_host receives the value.
+ * ws needs qb_sumsq_workspace_bytes() bytes.  Synchronises the stream. */
 QB_API size_t qb_sumsq_workspace_bytes(void);
 QB_API int qb_sumsq_dense(const qb_dense* A, double* out_host, void* ws, hipStream_t stream);
 
@@ -160,6 +183,14 @@ QB_API int qb_sumsq_dense(const qb_dense* A, double* out_host, void* ws, hipStre
  * h (n x l row-major, ld l).  Enqueued on stream; does not synchronise. */
 QB_API int qb_sketch_dense(const qb_dense* A, uint64_t seed, int64_t col0, int64_t l, double* om,
                     double* g, double* h, hipStream_t stream);
+
+/* The same sweep for bfloat16 A (dtype QB_BF16), exactly as qb_fp_dense runs it:
+ * om receives the dequantised Omega_q (n x l, ld l), g the dequantised G_q (m x l,
+ * ld l) and h = A_q^T G_q (n x l, ld l), all binary64.  ws (256-byte aligned) needs
+ * qb_sketch_lowp_bytes(A, l) bytes.  Enqueued on stream; does not synchronise. */
+QB_API size_t qb_sketch_lowp_bytes(const qb_dense* A, int64_t l);
+QB_API int qb_sketch_lowp(const qb_dense* A, uint64_t seed, int64_t col0, int64_t l, double* om,
+                          double* g, double* h, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* Same sweep for CSR A; csc_ws must hold qb_csr_transpose_bytes(A) bytes and is
  * filled with CSR(A^T) on the first call (set *csc_ready = 0 before it). */

@@ -25,6 +25,7 @@ LIB_PATH = os.path.join(PKG, "_lib", "libqb.so")
 QB_OK, QB_NOT_CONVERGED, QB_WARN_TOL_FLOOR = 0, 1, 2
 QB_ERR_ARG, QB_ERR_NONFINITE, QB_ERR_WORKSPACE, QB_ERR_HIP, QB_ERR_UNSUPPORTED = -1, -2, -3, -4, -5
 QB_ALGO_FP, QB_ALGO_EI = 0, 1
+QB_F64, QB_BF16 = 0, 1
 
 _c_i64 = ctypes.c_int64
 _c_i32 = ctypes.c_int32
@@ -73,6 +74,13 @@ def lib() -> ctypes.CDLL:
         P = ctypes.POINTER
         L.qb_workspace_bytes.argtypes = [ctypes.c_int, ctypes.c_int, _c_i64, _c_i64, _c_i64, P(QbParams)]
         L.qb_workspace_bytes.restype = ctypes.c_size_t
+        L.qb_dense_workspace_bytes.argtypes = [ctypes.c_int, P(QbDense), P(QbParams)]
+        L.qb_dense_workspace_bytes.restype = ctypes.c_size_t
+        L.qb_sketch_lowp_bytes.argtypes = [P(QbDense), _c_i64]
+        L.qb_sketch_lowp_bytes.restype = ctypes.c_size_t
+        L.qb_sketch_lowp.argtypes = [P(QbDense), ctypes.c_uint64, _c_i64, _c_i64, _vp, _vp, _vp, _vp,
+                                     ctypes.c_size_t, _vp]
+        L.qb_sketch_lowp.restype = ctypes.c_int
         for nm in ("qb_fp_dense", "qb_ei_dense"):
             f = getattr(L, nm)
             f.argtypes = [P(QbDense), P(QbParams), _vp, _c_i64, _vp, _c_i64, _vp, ctypes.c_size_t, _vp,
@@ -121,11 +129,17 @@ def _check_dev(t: torch.Tensor, name: str, dtype=torch.float64):
         raise ValueError(f"{name} must be {dtype}")
 
 
+_DTYPES = {torch.float64: QB_F64, torch.bfloat16: QB_BF16}
+
+
 def _dense(A: torch.Tensor) -> QbDense:
-    _check_dev(A, "A")
+    if not A.is_cuda:
+        raise ValueError("A must be a GPU tensor")
+    if A.dtype not in _DTYPES:
+        raise ValueError("A must be float64 or bfloat16")
     if A.dim() != 2 or A.stride(1) != 1 or A.stride(0) < A.shape[1]:
         raise ValueError("A must be a row-major 2-D view (stride(1) == 1)")
-    return QbDense(A.shape[0], A.shape[1], A.stride(0), 0, 0, A.data_ptr())
+    return QbDense(A.shape[0], A.shape[1], A.stride(0), _DTYPES[A.dtype], 0, A.data_ptr())
 
 
 def _csr(m: int, n: int, rowptr: torch.Tensor, colind: torch.Tensor, val: torch.Tensor) -> QbCsr:
@@ -169,8 +183,10 @@ def _run(kind: str, algo: int, sparse: bool, mat, m: int, n: int, dev, tol, b, l
     L = lib()
     l_max = min(m, n) if l_max is None else int(l_max)
     p = _params(tol, b, l_max, l_tilde, seed, row_by_row, power)
-    need = L.qb_workspace_bytes(algo, 1 if sparse else 0, m, n, mat.nnz if sparse else 0,
-                                ctypes.byref(p))
+    if sparse:
+        need = L.qb_workspace_bytes(algo, 1, m, n, mat.nnz, ctypes.byref(p))
+    else:
+        need = L.qb_dense_workspace_bytes(algo, ctypes.byref(mat), ctypes.byref(p))
     fn = getattr(L, kind)
     if need == 0:   # invalid parameters: let the entry point report which status applies
         st = fn(ctypes.byref(mat), ctypes.byref(p), None, 0, None, 0, None, 0, _stream_ptr(dev), None)
@@ -203,7 +219,8 @@ def _run(kind: str, algo: int, sparse: bool, mat, m: int, n: int, dev, tol, b, l
 
 def qb_fp_dense(A: torch.Tensor, tol: float, b: int, seed: int, l_max=None, l_tilde: int = 0,
                 row_by_row: bool = True, Q_store=None, B_store=None, ws=None, power: int = 0) -> QBResult:
-    """randQB_FP (Algorithm 4, P = 0) on dense float64 A (GPU, row-major)."""
+    """randQB_FP (Algorithm 4, P = 0) on dense A (GPU, row-major): float64, or bfloat16
+    for the precision form (bfloat16 sketch products, binary64 block loop)."""
     d = _dense(A)
     return _run("qb_fp_dense", QB_ALGO_FP, False, d, d.m, d.n, A.device, tol, b, l_max, l_tilde,
                 seed, row_by_row, Q_store, B_store, ws, power)
@@ -239,6 +256,13 @@ def qb_workspace_bytes(algo: int, sparse: bool, m: int, n: int, nnz: int, tol: f
     return int(lib().qb_workspace_bytes(algo, 1 if sparse else 0, m, n, nnz, ctypes.byref(p)))
 
 
+def qb_dense_workspace_bytes(algo: int, A: torch.Tensor, tol: float, b: int, l_max: int,
+                             l_tilde: int = 0) -> int:
+    """Workspace bytes of qb_fp_dense / qb_ei_dense for this A (any supported dtype)."""
+    p = _params(tol, b, l_max, l_tilde, 0, True)
+    return int(lib().qb_dense_workspace_bytes(algo, ctypes.byref(_dense(A)), ctypes.byref(p)))
+
+
 def qb_gaussian_fill(seed: int, rows: int, cols: int, row0: int = 0, col0: int = 0,
                      stream_id: int = 0, batch: int = 0, out: torch.Tensor | None = None,
                      device="cuda") -> torch.Tensor:
@@ -256,7 +280,7 @@ def qb_gaussian_fill(seed: int, rows: int, cols: int, row0: int = 0, col0: int =
 
 
 def qb_sumsq_dense(A: torch.Tensor) -> float:
-    """||A||_F^2 of dense float64 A as a deterministic GPU sum of squares."""
+    """||A||_F^2 of dense float64 or bfloat16 A as a deterministic GPU sum of squares."""
     L = lib()
     d = _dense(A)
     ws = torch.empty(L.qb_sumsq_workspace_bytes(), dtype=torch.uint8, device=A.device)
@@ -278,6 +302,27 @@ def qb_sketch_dense(A: torch.Tensor, seed: int, col0: int, l: int):
                                g.data_ptr(), h.data_ptr(), _stream_ptr(dev))
     if st < 0:
         raise QBError(st, "qb_sketch_dense")
+    return om, g, h
+
+
+def qb_sketch_lowp(A: torch.Tensor, seed: int, col0: int, l: int):
+    """Precision-form sweep on bfloat16 A: (Omega_q, G_q, H = A_q^T G_q) as binary64."""
+    L = lib()
+    d = _dense(A)
+    if d.dtype != QB_BF16:
+        raise ValueError("qb_sketch_lowp takes a bfloat16 A")
+    dev = A.device
+    need = L.qb_sketch_lowp_bytes(ctypes.byref(d), l)
+    if need == 0:
+        raise QBError(QB_ERR_ARG, "qb_sketch_lowp")
+    ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    om = torch.empty((d.n, l), dtype=torch.float64, device=dev)
+    g = torch.empty((d.m, l), dtype=torch.float64, device=dev)
+    h = torch.empty((d.n, l), dtype=torch.float64, device=dev)
+    st = L.qb_sketch_lowp(ctypes.byref(d), int(seed) & (2 ** 64 - 1), col0, l, om.data_ptr(),
+                          g.data_ptr(), h.data_ptr(), ws.data_ptr(), need, _stream_ptr(dev))
+    if st < 0:
+        raise QBError(st, "qb_sketch_lowp")
     return om, g, h
 
 

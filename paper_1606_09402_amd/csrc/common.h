@@ -25,4 +25,12 @@ struct MutView {
     int64_t si, sj;
 };
 
+// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a contiguous range
+// of logical tiles so that tiles sharing an operand row-slab share one L2.
+QB_DEV int xcd_remap(int wg, int nwg) {
+    const int xcd = wg & 7, local = wg >> 3;
+    const int per = nwg >> 3, rem = nwg & 7;
+    return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
+}
+
 }  // namespace qb

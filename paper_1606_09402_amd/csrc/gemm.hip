@@ -44,13 +44,6 @@ struct GemmArgs {
 QB_DEV int acc_row(int lane, int r) { return (r << 2) + (lane >> 4); }
 QB_DEV int acc_col(int lane) { return lane & 15; }
 
-QB_DEV int xcd_remap(int wg, int nwg) {
-    // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a contiguous
-    // range of logical tiles so that tiles sharing an A row-slab share one L2.
-    const int xcd = wg & 7, local = wg >> 3;
-    const int per = nwg >> 3, rem = nwg & 7;
-    return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
-}
 
 // Staging of one operand tile of OUTER x INNER elements whose INNER index is contiguous
 // in global memory (row stride ld).  Thread t owns the element pair at inner offset

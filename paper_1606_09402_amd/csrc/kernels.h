@@ -17,6 +17,7 @@ hipError_t launch_sumsq_vec(const double* x, int64_t len, double* scratch, doubl
                             hipStream_t s);
 hipError_t launch_sum_partials(const double* partial, int64_t groups, int64_t stride, int64_t count,
                                double* out, hipStream_t s);
+hipError_t launch_sum_vector(const double* partial, int64_t count, double* out, hipStream_t s);
 
 // gemm.hip -- FP64 MFMA GEMM.  out(i,j) = alpha sum_k Aop(i,k) Bop(k,j) + beta C0(i,j)
 struct GemmDesc {
@@ -33,6 +34,23 @@ struct GemmDesc {
     int max_split;       // 0 = automatic
 };
 hipError_t gemm_f64(const GemmDesc& d, hipStream_t s);
+
+// lowp.hip -- the bfloat16 precision form of the sketch sweep
+hipError_t launch_quant_transpose_omega(double* om, int64_t n, int64_t w, uint16_t* omT,
+                                        int64_t ldt, hipStream_t s);
+hipError_t launch_transpose_bf16(const uint16_t* a, int64_t m, int64_t n, int64_t lda,
+                                 uint16_t* at, int64_t ldt, hipStream_t s);
+hipError_t launch_sumsq_bf16(const uint16_t* a, int64_t m, int64_t n, int64_t lda,
+                             double* scratch, double* out, hipStream_t s);
+// out(i, j) = sum_k A(i, k) B(j, k) for bfloat16 A (M x K) and B (N x K), both with K
+// contiguous; binary32 accumulation.  outT == nullptr: out = the binary32 sums as
+// binary64.  outT != nullptr (the G epilogue): out = bf16(sums) as binary64, outT (N x M,
+// ld ldt) the same bfloat16 values, and colsq (if set) [ceil(M/128)][N] partial column
+// sums of squares of out.
+int64_t bf16_gemm_row_groups(int64_t M);
+hipError_t gemm_bf16_nt(int64_t M, int64_t N, int64_t K, const uint16_t* A, int64_t lda,
+                        const uint16_t* B, int64_t ldb, double* out, int64_t ldo, uint16_t* outT,
+                        int64_t ldt, double* colsq, hipStream_t s);
 
 // panel.hip -- small dense kernels of the block loop
 hipError_t launch_chol_inv(const double* gram, int b, double tau, double* R, double* Rinv,

@@ -35,8 +35,9 @@ size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
 struct Layout {
     size_t red, scal, om, g, h, gpart, gnorm2, y, x2, s, w, z, d, gram, r1, r1i, rt, rti, ri, rii, tau,
-        rowsq_part, rowsq, info, flags, split, csc, total;
+        rowsq_part, rowsq, info, flags, split, csc, aqt, omt, gqt, total;
     int64_t lt, split_elems, gpart_groups;
+    int64_t ldm16, ldn16;   // row strides (elements) of the bfloat16 copies: m, n rounded to 8
 };
 
 // Largest chunk of Omega columns: l_tilde, or the paper's min(50 b, l_max) for 0 and for
@@ -76,8 +77,10 @@ int64_t next_chunk(const qb_params* p, int64_t cap, int64_t k, int64_t w_prev, d
     return w < left ? w : left;
 }
 
-Layout make_layout(int algo, int sparse, int64_t m, int64_t n, int64_t nnz, const qb_params* p) {
+Layout make_layout(int algo, int sparse, int dtype, int64_t m, int64_t n, int64_t nnz,
+                   const qb_params* p) {
     Layout L{};
+    const bool lowp = dtype == QB_BF16;
     const int64_t b = p->b;
     const int64_t lmax = p->l_max;
     const int64_t lt = algo == QB_ALGO_FP ? chunk_width(p) : b;   // EI: one block at a time
@@ -88,7 +91,7 @@ Layout make_layout(int algo, int sparse, int64_t m, int64_t n, int64_t nnz, cons
     if (L.split_elems < kGramSplitElems) L.split_elems = kGramSplitElems;
     if (L.split_elems < 8 * (m > n ? m : n) * b) L.split_elems = 8 * (m > n ? m : n) * b;
     // dense randQB_FP: room for two K splits of the widest sketch GEMM (G, m x l~)
-    if (algo == QB_ALGO_FP && !sparse && L.split_elems < 2 * (m > n ? m : n) * lt)
+    if (algo == QB_ALGO_FP && !sparse && !lowp && L.split_elems < 2 * (m > n ? m : n) * lt)
         L.split_elems = 2 * (m > n ? m : n) * lt;
     // row-tile partials of the G column norms: dense GEMM tiles are >= 64 rows
     L.gpart_groups = sparse ? colsq_groups(m) : cdiv(m, 64);
@@ -129,6 +132,13 @@ Layout make_layout(int algo, int sparse, int64_t m, int64_t n, int64_t nnz, cons
     L.flags = take(sizeof(int) * 8);
     L.split = take(sizeof(double) * L.split_elems);
     L.csc = sparse ? take(csc_layout(m, n, nnz).total) : take(0);
+    // bfloat16 form: A_q^T (n x m), Omega_q^T (l~ x n) and G_q^T (l~ x m), rows padded to
+    // multiples of 8 elements so that every row starts 16-byte aligned
+    L.ldm16 = round_up(m, 8);
+    L.ldn16 = round_up(n, 8);
+    L.aqt = lowp ? take(sizeof(uint16_t) * n * L.ldm16) : take(0);
+    L.omt = lowp ? take(sizeof(uint16_t) * lt * L.ldn16) : take(0);
+    L.gqt = lowp ? take(sizeof(uint16_t) * lt * L.ldm16) : take(0);
     L.total = off + 256;
     return L;
 }
@@ -139,7 +149,9 @@ Layout make_layout(int algo, int sparse, int64_t m, int64_t n, int64_t nnz, cons
 struct Op {
     int64_t m, n;
     bool sparse;
+    int dtype;
     const double* a;
+    const uint16_t* aq;   // bfloat16 A (dtype QB_BF16)
     int64_t lda;
     const int64_t* rowptr;
     const int32_t* colind;
@@ -238,6 +250,25 @@ int apply_At(const Ctx& x, const double* G, int64_t ldg, double* H, int64_t ldh,
     } else {
         QB_HIP(launch_spmm_csr(A.t_ptr, A.t_col, A.t_val, A.n, G, ldg, H, ldh, w, x.s));
     }
+    return QB_OK;
+}
+
+// The bfloat16 sketch of a chunk: Omega (n x w, ld w, binary64 on entry) is replaced by
+// its bfloat16 rounding Omega_q (and copied transposed in bfloat16), G = bf16(A_q Omega_q)
+// with its column sums of squares, H = A_q^T G_q; A_q^T was formed once per call.
+int sketch_bf16(const Ctx& x, double* Om, double* G, double* H, int64_t w, double* gnorm2,
+                bool time_phases) {
+    const Op& A = x.A;
+    uint16_t* omt = x.at<uint16_t>(x.L.omt);
+    uint16_t* gqt = x.at<uint16_t>(x.L.gqt);
+    const uint16_t* aqt = x.at<uint16_t>(x.L.aqt);
+    double* gpart = x.at<double>(x.L.gpart);
+    QB_HIP(launch_quant_transpose_omega(Om, A.n, w, omt, x.L.ldn16, x.s));
+    if (time_phases) x.tm->mark(2);
+    QB_HIP(gemm_bf16_nt(A.m, w, A.n, A.aq, A.lda, omt, x.L.ldn16, G, w, gqt, x.L.ldm16, gpart, x.s));
+    QB_HIP(launch_sum_partials(gpart, bf16_gemm_row_groups(A.m), w, w, gnorm2, x.s));
+    if (time_phases) x.tm->mark(3);
+    QB_HIP(gemm_bf16_nt(A.n, w, A.m, aqt, x.L.ldm16, gqt, x.L.ldm16, H, w, nullptr, 0, nullptr, x.s));
     return QB_OK;
 }
 
@@ -458,10 +489,11 @@ int run(int algo, Op& A, const qb_params* p, double* Q, int64_t ldq, double* B, 
     memset(inf, 0, sizeof(*inf));
     int st = check_params(p, A.m, A.n);
     if (st != QB_OK) return inf->status = st;
+    if (A.dtype != QB_F64 && (algo != QB_ALGO_FP || A.sparse)) return inf->status = QB_ERR_UNSUPPORTED;
     if (Q == nullptr || B == nullptr || ws == nullptr || ldq < A.m || ldb < A.n)
         return inf->status = QB_ERR_ARG;
     if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return inf->status = QB_ERR_ARG;
-    const Layout L = make_layout(algo, A.sparse, A.m, A.n, A.nnz, p);
+    const Layout L = make_layout(algo, A.sparse, A.dtype, A.m, A.n, A.nnz, p);
     if (ws_bytes < L.total) return inf->status = QB_ERR_WORKSPACE;
     double* host = pinned_buffer();
     if (host == nullptr) return inf->status = QB_ERR_HIP;
@@ -474,7 +506,13 @@ int run(int algo, Op& A, const qb_params* p, double* Q, int64_t ldq, double* B, 
 
     // ||A||_F^2 (Algorithm 4 step 9)
     tm.mark(0);
-    if (!A.sparse) {
+    if (A.dtype == QB_BF16) {
+        QB_HIP(launch_sumsq_bf16(A.aq, m, n, A.lda, red, scal, s));
+        tm.mark(6);   // A_q^T once per call, for the K-contiguous operand of H = A_q^T G_q
+        QB_HIP(launch_transpose_bf16(A.aq, m, n, A.lda, reinterpret_cast<uint16_t*>(wsb + L.aqt),
+                                     L.ldm16, s));
+        tm.mark(0);
+    } else if (!A.sparse) {
         QB_HIP(launch_sumsq_dense(A.a, m, n, A.lda, red, scal, s));
     } else {
         QB_HIP(launch_sumsq_vec(A.val, A.nnz, red, scal, s));
@@ -520,10 +558,14 @@ int run(int algo, Op& A, const qb_params* p, double* Q, int64_t ldq, double* B, 
                     e_chunk_start = E;
                     tm.mark(1);
                     QB_HIP(launch_gauss_fill(p->seed, 0, 0, 0, chunk_lo, n, w, Om, w, s));
-                    tm.mark(2);
-                    if (int e = apply_A(x, Om, w, G, w, w, gnorm2)) return inf->status = e;
-                    tm.mark(3);
-                    if (int e = apply_At(x, G, w, H, w, w)) return inf->status = e;
+                    if (A.dtype == QB_BF16) {
+                        if (int e = sketch_bf16(x, Om, G, H, w, gnorm2, true)) return inf->status = e;
+                    } else {
+                        tm.mark(2);
+                        if (int e = apply_A(x, Om, w, G, w, w, gnorm2)) return inf->status = e;
+                        tm.mark(3);
+                        if (int e = apply_At(x, G, w, H, w, w)) return inf->status = e;
+                    }
                     tm.mark(4);
                     inf->passes += 2;
                     inf->chunks += 1;
@@ -594,21 +636,25 @@ int run(int algo, Op& A, const qb_params* p, double* Q, int64_t ldq, double* B, 
 
 Op dense_op(const qb_dense* A) {
     Op o{};
-    o.m = A->m; o.n = A->n; o.sparse = false;
-    o.a = static_cast<const double*>(A->a); o.lda = A->lda;
+    o.m = A->m; o.n = A->n; o.sparse = false; o.dtype = A->dtype;
+    if (A->dtype == QB_BF16)
+        o.aq = static_cast<const uint16_t*>(A->a);
+    else
+        o.a = static_cast<const double*>(A->a);
+    o.lda = A->lda;
     return o;
 }
 
 Op csr_op(const qb_csr* A) {
     Op o{};
-    o.m = A->m; o.n = A->n; o.sparse = true;
+    o.m = A->m; o.n = A->n; o.sparse = true; o.dtype = QB_F64;
     o.rowptr = A->rowptr; o.colind = A->colind; o.val = A->val; o.nnz = A->nnz;
     return o;
 }
 
 int check_dense(const qb_dense* A) {
     if (A == nullptr || A->a == nullptr || A->m < 1 || A->n < 1 || A->lda < A->n) return QB_ERR_ARG;
-    if (A->dtype != QB_F64) return QB_ERR_UNSUPPORTED;
+    if (A->dtype != QB_F64 && A->dtype != QB_BF16) return QB_ERR_UNSUPPORTED;
     return QB_OK;
 }
 
@@ -630,7 +676,14 @@ size_t qb_workspace_bytes(int algo, int sparse, int64_t m, int64_t n, int64_t nn
                           const qb_params* p) {
     if ((algo != QB_ALGO_FP && algo != QB_ALGO_EI) || m < 1 || n < 1) return 0;
     if (check_params(p, m, n) != QB_OK) return 0;
-    return make_layout(algo, sparse != 0, m, n, nnz, p).total;
+    return make_layout(algo, sparse != 0, QB_F64, m, n, nnz, p).total;
+}
+
+size_t qb_dense_workspace_bytes(int algo, const qb_dense* A, const qb_params* p) {
+    if ((algo != QB_ALGO_FP && algo != QB_ALGO_EI) || A == nullptr || A->m < 1 || A->n < 1) return 0;
+    if (A->dtype != QB_F64 && !(A->dtype == QB_BF16 && algo == QB_ALGO_FP)) return 0;
+    if (check_params(p, A->m, A->n) != QB_OK) return 0;
+    return make_layout(algo, 0, A->dtype, A->m, A->n, 0, p).total;
 }
 
 int qb_fp_dense(const qb_dense* A, const qb_params* p, double* Q, int64_t ldq, double* B,
@@ -691,8 +744,12 @@ int qb_sumsq_dense(const qb_dense* A, double* out_host, void* ws, hipStream_t st
     if (out_host == nullptr || ws == nullptr) return QB_ERR_ARG;
     double* scratch = static_cast<double*>(ws);
     double* res = scratch + 1024;
-    QB_HIP(launch_sumsq_dense(static_cast<const double*>(A->a), A->m, A->n, A->lda, scratch, res,
-                              stream));
+    if (A->dtype == QB_BF16)
+        QB_HIP(launch_sumsq_bf16(static_cast<const uint16_t*>(A->a), A->m, A->n, A->lda, scratch, res,
+                                 stream));
+    else
+        QB_HIP(launch_sumsq_dense(static_cast<const double*>(A->a), A->m, A->n, A->lda, scratch, res,
+                                  stream));
     QB_HIP(hipMemcpyAsync(out_host, res, sizeof(double), hipMemcpyDeviceToHost, stream));
     QB_HIP(hipStreamSynchronize(stream));
     return QB_OK;
@@ -701,6 +758,7 @@ int qb_sumsq_dense(const qb_dense* A, double* out_host, void* ws, hipStream_t st
 int qb_sketch_dense(const qb_dense* A, uint64_t seed, int64_t col0, int64_t l, double* om, double* g,
                     double* h, hipStream_t stream) {
     if (int st = check_dense(A)) return st;
+    if (A->dtype != QB_F64) return QB_ERR_UNSUPPORTED;
     if (l < 1 || col0 < 0 || om == nullptr || g == nullptr || h == nullptr) return QB_ERR_ARG;
     const int64_t m = A->m, n = A->n;
     QB_HIP(launch_gauss_fill(seed, 0, 0, 0, col0, n, l, om, l, stream));
@@ -719,6 +777,40 @@ int qb_sketch_dense(const qb_dense* A, uint64_t seed, int64_t col0, int64_t l, d
     e.C = MutView{h, l, 1};
     QB_HIP(gemm_f64(e, stream));
     return QB_OK;
+}
+
+// Workspace of qb_sketch_lowp: the randQB_FP layout with one chunk of l columns (the
+// sketch buffers it uses are Omega_q^T, G_q^T, A_q^T and the column-norm partials).
+static bool sketch_lowp_layout(const qb_dense* A, int64_t l, Layout* L) {
+    if (check_dense(A) != QB_OK || A->dtype != QB_BF16 || l < 1) return false;
+    qb_params p{};
+    p.tol_rel = 0.0; p.b = 1; p.l_max = l; p.l_tilde = l;
+    *L = make_layout(QB_ALGO_FP, 0, QB_BF16, A->m, A->n, 0, &p);
+    return true;
+}
+
+size_t qb_sketch_lowp_bytes(const qb_dense* A, int64_t l) {
+    Layout L{};
+    return sketch_lowp_layout(A, l, &L) ? L.total : 0;
+}
+
+int qb_sketch_lowp(const qb_dense* A, uint64_t seed, int64_t col0, int64_t l, double* om, double* g,
+                   double* h, void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (int st = check_dense(A)) return st;
+    if (A->dtype != QB_BF16) return QB_ERR_UNSUPPORTED;
+    if (l < 1 || col0 < 0 || om == nullptr || g == nullptr || h == nullptr || ws == nullptr)
+        return QB_ERR_ARG;
+    if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return QB_ERR_ARG;
+    Layout L{};
+    if (!sketch_lowp_layout(A, l, &L)) return QB_ERR_ARG;
+    if (ws_bytes < L.total) return QB_ERR_WORKSPACE;
+    char* wsb = static_cast<char*>(ws);
+    Op o = dense_op(A);
+    Timer tm(stream);
+    const Ctx x{o, nullptr, nullptr, 0, nullptr, 0, wsb, L, stream, nullptr, &tm, nullptr};
+    QB_HIP(launch_transpose_bf16(o.aq, o.m, o.n, o.lda, x.at<uint16_t>(L.aqt), L.ldm16, stream));
+    QB_HIP(launch_gauss_fill(seed, 0, 0, 0, col0, o.n, l, om, l, stream));
+    return sketch_bf16(x, om, g, h, l, x.at<double>(L.gnorm2), false);
 }
 
 size_t qb_csr_transpose_bytes(const qb_csr* A) {

@@ -105,6 +105,11 @@ hipError_t launch_sumsq_vec(const double* x, int64_t len, double* scratch, doubl
     return hipGetLastError();
 }
 
+hipError_t launch_sum_vector(const double* partial, int64_t count, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(sum_vector_kernel, dim3(1), dim3(kRedThreads), 0, s, partial, count, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_sum_partials(const double* partial, int64_t groups, int64_t stride,
                                int64_t count, double* out, hipStream_t s) {
     if (count <= 0) return hipSuccess;
