@@ -119,8 +119,7 @@ typedef struct {
     int32_t fallbacks;   /* panels orthonormalised by the Householder fallback               */
     double ms[8];        /* device time per phase (ms): 0 ||A||^2, 1 Omega, 2 G = A Omega,
                             3 H = A^T G (EI: 2 = the A Omega_i GEMMs, 3 = the A^T Q_i GEMMs),
-                            4 block loop without 2-3, 5 whole call, 6 the transpose of a
-                            bfloat16 A_q (0 for binary64 A)                                  */
+                            4 block loop without 2-3, 5 whole call                           */
     double gemm_flops[2];/* algorithmic flops of the timed G and H GEMMs (2 m n l each)      */
 } qb_info;
 
@@ -131,14 +130,13 @@ QB_API size_t qb_workspace_bytes(int algo, int sparse, int64_t m, int64_t n, int
                           const qb_params* p);
 
 /* Bytes of workspace qb_fp_dense / qb_ei_dense need for dense A of any dtype (the
- * bfloat16 form adds A_q^T, n x m, and the bfloat16 copies of Omega_q and G_q).
+ * bfloat16 form adds bfloat16 copies of Omega_q and G_q).
  * A->a is not read.  Returns 0 for invalid arguments or an unsupported combination. */
 QB_API size_t qb_dense_workspace_bytes(int algo, const qb_dense* A, const qb_params* p);
 
 /* randQB_FP (Algorithm 4, P = 0) on dense row-major A of dtype QB_F64 or QB_BF16.  ws
  * must hold at least qb_dense_workspace_bytes(QB_ALGO_FP, A, p) bytes of device memory
- * (256-byte aligned).  For QB_BF16, info->ms[6] is the time of the once-per-call
- * transpose of A_q and the relative tolerance is taken against ||A_q||_F. */
+ * (256-byte aligned).  For QB_BF16 the relative tolerance is taken against ||A_q||_F. */
 QB_API int qb_fp_dense(const qb_dense* A, const qb_params* p, double* Q, int64_t ldq, double* B,
                 int64_t ldb, void* ws, size_t ws_bytes, hipStream_t stream, qb_info* info);
 

@@ -35,7 +35,7 @@ size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
 struct Layout {
     size_t red, scal, om, g, h, gpart, gnorm2, y, x2, s, w, z, d, gram, r1, r1i, rt, rti, ri, rii, tau,
-        rowsq_part, rowsq, info, flags, split, csc, aqt, omt, gqt, total;
+        rowsq_part, rowsq, info, flags, split, csc, omt, gqt, total;
     int64_t lt, split_elems, gpart_groups;
     int64_t ldm16, ldn16;   // row strides (elements) of the bfloat16 copies: m, n rounded to 8
 };
@@ -132,11 +132,10 @@ Layout make_layout(int algo, int sparse, int dtype, int64_t m, int64_t n, int64_
     L.flags = take(sizeof(int) * 8);
     L.split = take(sizeof(double) * L.split_elems);
     L.csc = sparse ? take(csc_layout(m, n, nnz).total) : take(0);
-    // bfloat16 form: A_q^T (n x m), Omega_q^T (l~ x n) and G_q^T (l~ x m), rows padded to
-    // multiples of 8 elements so that every row starts 16-byte aligned
+    // bfloat16 form: Omega_q^T (l~ x n) and G_q^T (l~ x m), rows padded to multiples of 8
+    // elements so that every row starts 16-byte aligned
     L.ldm16 = round_up(m, 8);
     L.ldn16 = round_up(n, 8);
-    L.aqt = lowp ? take(sizeof(uint16_t) * n * L.ldm16) : take(0);
     L.omt = lowp ? take(sizeof(uint16_t) * lt * L.ldn16) : take(0);
     L.gqt = lowp ? take(sizeof(uint16_t) * lt * L.ldm16) : take(0);
     L.total = off + 256;
@@ -255,20 +254,20 @@ int apply_At(const Ctx& x, const double* G, int64_t ldg, double* H, int64_t ldh,
 
 // The bfloat16 sketch of a chunk: Omega (n x w, ld w, binary64 on entry) is replaced by
 // its bfloat16 rounding Omega_q (and copied transposed in bfloat16), G = bf16(A_q Omega_q)
-// with its column sums of squares, H = A_q^T G_q; A_q^T was formed once per call.
+// with its column sums of squares, H = A_q^T G_q reading A_q in place.
 int sketch_bf16(const Ctx& x, double* Om, double* G, double* H, int64_t w, double* gnorm2,
                 bool time_phases) {
     const Op& A = x.A;
     uint16_t* omt = x.at<uint16_t>(x.L.omt);
     uint16_t* gqt = x.at<uint16_t>(x.L.gqt);
-    const uint16_t* aqt = x.at<uint16_t>(x.L.aqt);
     double* gpart = x.at<double>(x.L.gpart);
     QB_HIP(launch_quant_transpose_omega(Om, A.n, w, omt, x.L.ldn16, x.s));
     if (time_phases) x.tm->mark(2);
-    QB_HIP(gemm_bf16_nt(A.m, w, A.n, A.aq, A.lda, omt, x.L.ldn16, G, w, gqt, x.L.ldm16, gpart, x.s));
-    QB_HIP(launch_sum_partials(gpart, bf16_gemm_row_groups(A.m), w, w, gnorm2, x.s));
+    QB_HIP(gemm_bf16(A.m, w, A.n, A.aq, A.lda, false, omt, x.L.ldn16, G, w, gqt, x.L.ldm16, gpart,
+                     x.s));
+    QB_HIP(launch_sum_partials(gpart, bf16_gemm_row_groups(A.m, w), w, w, gnorm2, x.s));
     if (time_phases) x.tm->mark(3);
-    QB_HIP(gemm_bf16_nt(A.n, w, A.m, aqt, x.L.ldm16, gqt, x.L.ldm16, H, w, nullptr, 0, nullptr, x.s));
+    QB_HIP(gemm_bf16(A.n, w, A.m, A.aq, A.lda, true, gqt, x.L.ldm16, H, w, nullptr, 0, nullptr, x.s));
     return QB_OK;
 }
 
@@ -508,10 +507,6 @@ int run(int algo, Op& A, const qb_params* p, double* Q, int64_t ldq, double* B, 
     tm.mark(0);
     if (A.dtype == QB_BF16) {
         QB_HIP(launch_sumsq_bf16(A.aq, m, n, A.lda, red, scal, s));
-        tm.mark(6);   // A_q^T once per call, for the K-contiguous operand of H = A_q^T G_q
-        QB_HIP(launch_transpose_bf16(A.aq, m, n, A.lda, reinterpret_cast<uint16_t*>(wsb + L.aqt),
-                                     L.ldm16, s));
-        tm.mark(0);
     } else if (!A.sparse) {
         QB_HIP(launch_sumsq_dense(A.a, m, n, A.lda, red, scal, s));
     } else {
@@ -808,7 +803,6 @@ int qb_sketch_lowp(const qb_dense* A, uint64_t seed, int64_t col0, int64_t l, do
     Op o = dense_op(A);
     Timer tm(stream);
     const Ctx x{o, nullptr, nullptr, 0, nullptr, 0, wsb, L, stream, nullptr, &tm, nullptr};
-    QB_HIP(launch_transpose_bf16(o.aq, o.m, o.n, o.lda, x.at<uint16_t>(L.aqt), L.ldm16, stream));
     QB_HIP(launch_gauss_fill(seed, 0, 0, 0, col0, o.n, l, om, l, stream));
     return sketch_bf16(x, om, g, h, l, x.at<double>(L.gnorm2), false);
 }
