@@ -234,3 +234,28 @@ C3 = SparseWorkload("csr_500000x200000_nnz5e6_powerlaw2.1_b50_tol0.6", 500000, 2
                     5_000_000, 50, 0.6, SEED_GEN + 3)
 C3_SMALL = SparseWorkload("csr_20000x8000_nnz2e5_powerlaw2.1_b50_tol0.6", 20000, 8000, 200_000,
                           50, 0.6, SEED_GEN + 13)
+
+
+@dataclass
+class BatchWorkload:
+    """A batch of dense matrices U_z diag(sigma) V_z^T with their own U_z, V_z per item."""
+    name: str
+    batch: int
+    m: int
+    n: int
+    sigma_kind: str
+    k: int
+    b: int
+    seed: int
+
+    def make(self, device="cpu", dtype=torch.float32, items=None) -> torch.Tensor:
+        items = list(range(self.batch)) if items is None else list(items)
+        sig = sigma_law(self.sigma_kind, min(self.m, self.n))
+        out = torch.empty((len(items), self.m, self.n), dtype=dtype, device=device)
+        for z, it in enumerate(items):
+            out[z] = lowrank_dense(self.m, self.n, sig, self.seed + 1009 * it, device=device).to(dtype)
+        return out
+
+
+# Differentiation form: 64 binary32 matrices 2048 x 1024, sigma_j = e^{-j/40}, rank 128, b = 32
+C5 = BatchWorkload("batch64_2048x1024_exp40_k128_b32", 64, 2048, 1024, "exp40", 128, 32, SEED_GEN + 5)
