@@ -38,6 +38,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
 BF16_PEAK_TFLOPS = 2500.0
 
 
@@ -49,6 +50,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ei", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
+    ap.add_argument("--no-diff", action="store_true")
     ap.add_argument("--gen-device", default="cuda", choices=["cuda", "cpu"],
                     help="where the seeded test matrix is generated (cpu keeps the GPU QR of the "
                          "generator out of counter-collection runs)")
@@ -197,6 +199,8 @@ def main():
         del A, Qs, Bs, ws
         torch.cuda.empty_cache()
         out["precision"] = precision_block(qb, W, torch, max(1, min(args.steps, 5)), args.l_tilde)
+    if not args.no_diff:
+        out["diff"] = diff_block(qb, W, torch, max(1, min(args.steps, 5)))
     print(json.dumps(out), flush=True)
 
 
@@ -259,6 +263,52 @@ def precision_block(qb, W, torch, steps, l_tilde):
     res["note"] = ("both runs factorise the same binary64 matrix (bf16: its bfloat16 storage) "
                    "to tol 1e-2; true_rel_err is ||A - QB||_F / ||A||_F against the binary64 A")
     del A64, Aq, Qs, Bs, ws
+    torch.cuda.empty_cache()
+    return res
+
+
+def diff_block(qb, W, torch, steps):
+    """Differentiation form: fixed-rank randQB_FP forward and the hand-written backward on
+    the 64 x 2048 x 1024 binary32 batch (k = 128, b = 32), with fixed random adjoints."""
+    import statistics
+
+    wl = W.C5
+    seed = W.SEED_OMEGA | 5
+    dev = torch.device("cuda:0")
+    A = wl.make(device=dev)
+    g = torch.Generator(device=dev)
+    g.manual_seed(5)
+    dQ = torch.randn((wl.batch, wl.m, wl.k), generator=g, device=dev, dtype=torch.float32)
+    dB = torch.randn((wl.batch, wl.k, wl.n), generator=g, device=dev, dtype=torch.float32)
+    ws = torch.empty(qb.qb_fixed_rank_workspace_bytes(A, wl.k, wl.b), dtype=torch.uint8, device=dev)
+    Q, B = qb.qb_fixed_rank_fwd(A, wl.k, wl.b, seed, ws=ws)
+    qb.qb_fixed_rank_bwd(A, wl.k, wl.b, seed, Q, dQ, dB, ws=ws)
+    torch.cuda.synchronize()
+    tf, tb = [], []
+    for _ in range(steps):
+        t = time.perf_counter()
+        Q, B = qb.qb_fixed_rank_fwd(A, wl.k, wl.b, seed, ws=ws)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        qb.qb_fixed_rank_bwd(A, wl.k, wl.b, seed, Q, dQ, dB, ws=ws)
+        torch.cuda.synchronize()
+        tb.append(time.perf_counter() - t1)
+        tf.append(t1 - t)
+    bt, m, n, k, b = wl.batch, wl.m, wl.n, wl.k, wl.b
+    sk = b * (k // b) * (k // b - 1) // 2            # sum of the ranks before each block
+    f_fwd = bt * (4.0 * m * n * k + 2.0 * (4 * m + 2 * n) * b * sk + 2.0 * (4 * m + n) * b * k
+                  + 4.0 * b * b * k)
+    f_bwd = bt * (8.0 * m * n * k + 8.0 * m * k * k)
+    mf, mb = statistics.median(tf), statistics.median(tb)
+    res = {"workload": wl.name, "dtype": "f32", "forward_ms": round(mf * 1e3, 3),
+           "backward_ms": round(mb * 1e3, 3), "step_ms": round((mf + mb) * 1e3, 3),
+           "forward_tflops": round(f_fwd / mf / 1e12, 2), "backward_tflops": round(f_bwd / mb / 1e12, 2),
+           "peak_tflops": FP32_PEAK_TFLOPS,
+           "frac_fwd_bwd": round((f_fwd + f_bwd) / (mf + mb) / 1e12 / FP32_PEAK_TFLOPS, 4),
+           "note": "forward includes one stream synchronisation (CholeskyQR breakdown flag); "
+                   "backward recomputes G = A Omega and R = Q^T G"}
+    print(f"# diff: forward {mf * 1e3:.2f} ms, backward {mb * 1e3:.2f} ms", file=sys.stderr, flush=True)
+    del A, dQ, dB, ws, Q, B
     torch.cuda.empty_cache()
     return res
 

@@ -69,7 +69,7 @@ typedef enum { QB_ALGO_FP = 0, QB_ALGO_EI = 1 } qb_algo;
  *           so B_i = Q_i^T A_q up to the accumulation error of H.  Only randQB_FP
  *           accepts it (randQB_EI forms B_i = Q_i^T A directly and would need Q_i in
  *           bfloat16: QB_ERR_UNSUPPORTED). */
-typedef enum { QB_F64 = 0, QB_BF16 = 1 } qb_dtype;
+typedef enum { QB_F64 = 0, QB_BF16 = 1, QB_F32 = 2 } qb_dtype;
 
 /* Dense row-major matrix of element type dtype (a qb_dtype). */
 typedef struct {
@@ -195,6 +195,53 @@ QB_API int qb_sketch_lowp(const qb_dense* A, uint64_t seed, int64_t col0, int64_
 QB_API size_t qb_csr_transpose_bytes(const qb_csr* A);
 QB_API int qb_sketch_csr(const qb_csr* A, uint64_t seed, int64_t col0, int64_t l, double* om,
                   double* g, double* h, void* csc_ws, int* csc_ready, hipStream_t stream);
+
+/* ------------------------------------------------------------------------------------
+ * Differentiation form: fixed-rank randQB_FP on a batch of matrices and its adjoint.
+ *
+ * For each matrix A (m x n) of the batch and the fixed Gaussian Omega (n x k, drawn as in
+ * qb_gaussian_fill with stream 0, batch 0, columns 0..k-1, rounded to the element type),
+ * the forward runs randQB_FP without stopping for t = k / b blocks (Algorithm 3 with the
+ * re-orthogonalised steps 9a-9c / eq. (23); G = A Omega and H = A^T G once).  In exact
+ * arithmetic the result is Q = qf(A Omega) with diag(R) > 0 and B = Q^T A, a
+ * differentiable function of A; the backward computes dL/dA from dL/dQ and dL/dB by the
+ * adjoints of B = Q^T A, of the thin QR (R-bar = 0) and of the triangular solve with R,
+ * recomputing G = A Omega and R = Q^T G instead of keeping them from the forward.
+ * The element type is QB_F32 (binary32 MFMA throughout) or QB_F64.
+ * ------------------------------------------------------------------------------------ */
+
+/* A batch of row-major matrices: matrix z, element (i, j) at a[z * stride_a + i * lda + j]. */
+typedef struct {
+    int64_t batch;      /* 1 .. 65535                                        */
+    int64_t m, n;       /* rows, columns                                     */
+    int64_t lda;        /* row stride, lda >= n                              */
+    int64_t stride_a;   /* batch stride, >= m * lda when batch > 1           */
+    int32_t dtype;      /* QB_F32 or QB_F64                                  */
+    int32_t reserved;
+    const void* a;      /* device pointer                                    */
+} qb_batch;
+
+/* Workspace bytes of qb_fixed_rank_fwd / _bwd (the same buffer serves both): k a
+ * multiple of b, 1 <= b <= 64, k <= 256, k <= min(m, n).  0 for invalid arguments. */
+QB_API size_t qb_fixed_rank_workspace_bytes(const qb_batch* A, int64_t k, int32_t b);
+
+/* Forward.  Q: per matrix m x k row-major (row stride ldq >= k, batch stride stride_q);
+ * B: per matrix k x n row-major (ldb >= n, stride_b).  Synchronises the stream.  Returns
+ * QB_NOT_CONVERGED (a warning) if CholeskyQR met a pivot below 1e-6 (binary32) or 1e-12
+ * (binary64) of the largest Gram diagonal in some block: A Omega is then numerically
+ * rank deficient at rank k and Q, B are unreliable. */
+QB_API int qb_fixed_rank_fwd(const qb_batch* A, int64_t k, int32_t b, uint64_t seed, void* Q,
+                             int64_t ldq, int64_t stride_q, void* B, int64_t ldb, int64_t stride_b,
+                             void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Backward: dA = dL/dA (per matrix m x n row-major, ldda >= n) from the forward's Q and
+ * the adjoints dQ (m x k, may be NULL for zero) and dB (k x n, may be NULL).  dA is
+ * overwritten.  Enqueued on stream; does not synchronise. */
+QB_API int qb_fixed_rank_bwd(const qb_batch* A, int64_t k, int32_t b, uint64_t seed, const void* Q,
+                             int64_t ldq, int64_t stride_q, const void* dQ, int64_t lddq,
+                             int64_t stride_dq, const void* dB, int64_t lddb, int64_t stride_db,
+                             void* dA, int64_t ldda, int64_t stride_da, void* ws, size_t ws_bytes,
+                             hipStream_t stream);
 
 /* Human-readable name of a qb_status value (static storage). */
 QB_API const char* qb_status_string(int status);

@@ -25,7 +25,7 @@ LIB_PATH = os.path.join(PKG, "_lib", "libqb.so")
 QB_OK, QB_NOT_CONVERGED, QB_WARN_TOL_FLOOR = 0, 1, 2
 QB_ERR_ARG, QB_ERR_NONFINITE, QB_ERR_WORKSPACE, QB_ERR_HIP, QB_ERR_UNSUPPORTED = -1, -2, -3, -4, -5
 QB_ALGO_FP, QB_ALGO_EI = 0, 1
-QB_F64, QB_BF16 = 0, 1
+QB_F64, QB_BF16, QB_F32 = 0, 1, 2
 
 _c_i64 = ctypes.c_int64
 _c_i32 = ctypes.c_int32
@@ -40,6 +40,11 @@ class QbDense(ctypes.Structure):
 class QbCsr(ctypes.Structure):
     _fields_ = [("m", _c_i64), ("n", _c_i64), ("nnz", _c_i64), ("rowptr", _vp), ("colind", _vp),
                 ("val", _vp)]
+
+
+class QbBatch(ctypes.Structure):
+    _fields_ = [("batch", _c_i64), ("m", _c_i64), ("n", _c_i64), ("lda", _c_i64), ("stride_a", _c_i64),
+                ("dtype", _c_i32), ("reserved", _c_i32), ("a", _vp)]
 
 
 class QbParams(ctypes.Structure):
@@ -105,6 +110,15 @@ def lib() -> ctypes.CDLL:
         L.qb_sketch_csr.argtypes = [P(QbCsr), ctypes.c_uint64, _c_i64, _c_i64, _vp, _vp, _vp, _vp,
                                     P(ctypes.c_int), _vp]
         L.qb_sketch_csr.restype = ctypes.c_int
+        L.qb_fixed_rank_workspace_bytes.argtypes = [P(QbBatch), _c_i64, _c_i32]
+        L.qb_fixed_rank_workspace_bytes.restype = ctypes.c_size_t
+        L.qb_fixed_rank_fwd.argtypes = [P(QbBatch), _c_i64, _c_i32, ctypes.c_uint64, _vp, _c_i64, _c_i64,
+                                        _vp, _c_i64, _c_i64, _vp, ctypes.c_size_t, _vp]
+        L.qb_fixed_rank_fwd.restype = ctypes.c_int
+        L.qb_fixed_rank_bwd.argtypes = [P(QbBatch), _c_i64, _c_i32, ctypes.c_uint64, _vp, _c_i64, _c_i64,
+                                        _vp, _c_i64, _c_i64, _vp, _c_i64, _c_i64, _vp, _c_i64, _c_i64,
+                                        _vp, ctypes.c_size_t, _vp]
+        L.qb_fixed_rank_bwd.restype = ctypes.c_int
         L.qb_status_string.argtypes = [ctypes.c_int]
         L.qb_status_string.restype = ctypes.c_char_p
         _LIB = L
@@ -345,3 +359,94 @@ def qb_sketch_csr(m: int, n: int, rowptr, colind, val, seed: int, col0: int, l: 
     if st < 0:
         raise QBError(st, "qb_sketch_csr")
     return om, g, h, csc_ws
+
+
+# ------------------------------------------------------------------ differentiation form
+
+_BATCH_DTYPES = {torch.float32: QB_F32, torch.float64: QB_F64}
+
+
+def _batch(A: torch.Tensor) -> QbBatch:
+    """A (batch, m, n) GPU tensor, rows contiguous."""
+    if not A.is_cuda or A.dtype not in _BATCH_DTYPES:
+        raise ValueError("A must be a float32 or float64 GPU tensor")
+    if A.dim() != 3 or A.stride(2) != 1 or A.stride(1) < A.shape[2]:
+        raise ValueError("A must be (batch, m, n) with unit column stride")
+    return QbBatch(A.shape[0], A.shape[1], A.shape[2], A.stride(1), A.stride(0), _BATCH_DTYPES[A.dtype], 0,
+                   A.data_ptr())
+
+
+def qb_fixed_rank_workspace_bytes(A: torch.Tensor, k: int, b: int) -> int:
+    return int(lib().qb_fixed_rank_workspace_bytes(ctypes.byref(_batch(A)), int(k), int(b)))
+
+
+def _ws_for(A, k, b, ws):
+    need = qb_fixed_rank_workspace_bytes(A, k, b)
+    if need == 0:
+        raise QBError(QB_ERR_ARG, "qb_fixed_rank")
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=A.device)
+    return ws, need
+
+
+def qb_fixed_rank_fwd(A: torch.Tensor, k: int, b: int, seed: int, ws=None):
+    """Fixed-rank randQB_FP of every matrix of A (batch, m, n): (Q (batch, m, k), B (batch, k, n))."""
+    d = _batch(A)
+    ws, need = _ws_for(A, k, b, ws)
+    bt, m, n = A.shape
+    Q = torch.empty((bt, m, k), dtype=A.dtype, device=A.device)
+    B = torch.empty((bt, k, n), dtype=A.dtype, device=A.device)
+    st = lib().qb_fixed_rank_fwd(ctypes.byref(d), int(k), int(b), int(seed) & (2 ** 64 - 1), Q.data_ptr(),
+                                 Q.stride(1), Q.stride(0), B.data_ptr(), B.stride(1), B.stride(0),
+                                 ws.data_ptr(), ws.numel(), _stream_ptr(A.device))
+    if st < 0 or st == QB_NOT_CONVERGED:
+        raise QBError(st, "qb_fixed_rank_fwd")
+    return Q, B
+
+
+def qb_fixed_rank_bwd(A: torch.Tensor, k: int, b: int, seed: int, Q: torch.Tensor, dQ=None, dB=None,
+                      ws=None) -> torch.Tensor:
+    """dL/dA of the fixed-rank map A -> (Q, B) given dL/dQ and dL/dB (either may be None)."""
+    d = _batch(A)
+    ws, need = _ws_for(A, k, b, ws)
+    for t, nm in ((Q, "Q"), (dQ, "dQ"), (dB, "dB")):
+        if t is not None and (t.dtype != A.dtype or not t.is_cuda or t.dim() != 3 or t.stride(2) != 1):
+            raise ValueError(f"{nm} must be a (batch, rows, cols) GPU tensor of A's dtype, unit column stride")
+    dA = torch.empty_like(A)
+    nul = (None, 0, 0)
+    q = (dQ.data_ptr(), dQ.stride(1), dQ.stride(0)) if dQ is not None else nul
+    bb = (dB.data_ptr(), dB.stride(1), dB.stride(0)) if dB is not None else nul
+    st = lib().qb_fixed_rank_bwd(ctypes.byref(d), int(k), int(b), int(seed) & (2 ** 64 - 1), Q.data_ptr(),
+                                 Q.stride(1), Q.stride(0), *q, *bb, dA.data_ptr(), dA.stride(1),
+                                 dA.stride(0), ws.data_ptr(), ws.numel(), _stream_ptr(A.device))
+    if st < 0:
+        raise QBError(st, "qb_fixed_rank_bwd")
+    return dA
+
+
+class FixedRankQB(torch.autograd.Function):
+    """(Q, B) = fixed-rank randQB_FP(A) for a fixed Omega, with the library's hand-written
+    backward (G = A Omega recomputed, not stored)."""
+
+    @staticmethod
+    def forward(ctx, A, k, b, seed):
+        Q, B = qb_fixed_rank_fwd(A, k, b, seed)
+        ctx.save_for_backward(A, Q)
+        ctx.k, ctx.b, ctx.seed = k, b, seed
+        return Q, B
+
+    @staticmethod
+    def backward(ctx, dQ, dB):
+        A, Q = ctx.saved_tensors
+        dQ = dQ.contiguous() if dQ is not None else None
+        dB = dB.contiguous() if dB is not None else None
+        dA = qb_fixed_rank_bwd(A, ctx.k, ctx.b, ctx.seed, Q, dQ, dB)
+        return dA, None, None, None
+
+
+def fixed_rank_qb(A: torch.Tensor, k: int, b: int, seed: int):
+    """Differentiable fixed-rank QB of A ((batch, m, n) or (m, n), float32 or float64)."""
+    if A.dim() == 2:
+        Q, B = FixedRankQB.apply(A.unsqueeze(0).contiguous(), k, b, seed)
+        return Q[0], B[0]
+    return FixedRankQB.apply(A.contiguous(), k, b, seed)

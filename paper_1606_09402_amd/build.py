@@ -20,7 +20,8 @@ LIBDIR = os.path.join(PKG, "_lib")
 OBJDIR = os.path.join(ROOT, "_build")
 LIBNAME = "libqb.so"
 
-SOURCES = ["rng.hip", "reduce.hip", "gemm.hip", "lowp.hip", "panel.hip", "spmm.hip", "qb_host.hip"]
+SOURCES = ["rng.hip", "reduce.hip", "gemm.hip", "lowp.hip", "panel.hip", "spmm.hip", "qb_host.hip",
+           "diff.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

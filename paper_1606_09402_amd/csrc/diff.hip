@@ -1,0 +1,578 @@
+// Differentiation form: fixed-rank randQB_FP on a batch of matrices and the adjoint of
+// A -> (Q, B) for a fixed Omega.
+//
+// Forward, per matrix (Algorithm 3 with steps 9a-9c, i.e. Algorithm 4 with P = 0 and no
+// stopping; rank k = t b): G = A Omega, H = A^T G once, then per block J
+//   W = B Omega_J, Y = G_J - Q W, [Q_i, R] = qr(Y), [Q_i, R~] = qr(Q_i - Q (Q^T Q_i)),
+//   R_i = R~ R, B_i = R_i^{-T} (H_J^T - (Y^T Q) B - W^T B)     (eq. (23)).
+// In exact arithmetic this is Q = qf(A Omega) (diag(R) > 0) and B = Q^T A, so the map has
+// one derivative whatever the blocking.
+//
+// Backward, given dL/dQ and dL/dB (Qb, Bb):
+//   A-bar  = Q Bb + Y-bar Omega^T                      (B = Q^T A, Y = A Omega)
+//   Qt     = Qb + A Bb^T                               (total adjoint of Q)
+//   Y-bar  = (Qt + Q copyltu(M)) R^{-T},  M = -Qt^T Q  (thin-QR adjoint with R-bar = 0,
+//            copyltu(M) = the symmetric matrix built from the lower triangle of M)
+// where R = Q^T G is recomputed from G = A Omega (G is not kept from the forward).
+//
+// Every product runs on one batched MFMA GEMM templated on the element type (binary32
+// for speed, binary64 for checking the adjoint to round-off); the b x b Cholesky factors
+// and the k x k triangular inverse are one workgroup per matrix.
+#include "kernels.h"
+
+namespace qb {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------------ MFMA traits
+
+template <typename T>
+struct Mfma;
+
+// v_mfma_f32_16x16x4f32: operand lane l holds A(l mod 16, l / 16) and B(l / 16, l mod 16);
+// accumulator slot r of lane l holds row 4 (l / 16) + r, column l mod 16 (measured).
+template <>
+struct Mfma<float> {
+    using acc_t = f32x4;
+    static QB_DEV acc_t op(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static QB_DEV int row(int lane, int r) { return ((lane >> 4) << 2) + r; }
+};
+
+// v_mfma_f64_16x16x4f64: same operands; slot r of lane l holds row 4 r + l / 16 (measured).
+template <>
+struct Mfma<double> {
+    using acc_t = v4d;
+    static QB_DEV acc_t op(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static QB_DEV int row(int lane, int r) { return (r << 2) + (lane >> 4); }
+};
+
+// ------------------------------------------------------------------ batched GEMM
+
+// C[z](i, j) = alpha sum_k A[z](i, k) B[z](k, j) + beta C0[z](i, j), z < batch, with
+// every operand a strided view: X[z](i, j) = X[z * sz + i * si + j * sj].
+template <typename T>
+struct BGemm {
+    int64_t M, N, K;
+    const T* A; int64_t a_si, a_sk, a_sz;
+    const T* B; int64_t b_sk, b_sj, b_sz;
+    T alpha, beta;
+    const T* C0; int64_t c0_si, c0_sj, c0_sz;
+    T* C; int64_t c_si, c_sj, c_sz;
+    int tiles_n;
+};
+
+template <typename T, int BM, int BN, int BK>
+__global__ void __launch_bounds__(256) bgemm_kernel(const BGemm<T> g) {
+    constexpr int NT = 256, WM = 2, WN = 2;
+    constexpr int TM = BM / WM, TN = BN / WN, FM = TM / 16, FN = TN / 16;
+    constexpr int PA = BM + 16, PB = BN + 16;   // a 4 x 16 operand read hits distinct banks
+    constexpr int LA = BM * BK / NT, LB = BN * BK / NT;
+    static_assert(BM * BK % NT == 0 && BN * BK % NT == 0 && BK % 4 == 0, "tile shape");
+    __shared__ T As[BK * PA];
+    __shared__ T Bs[BK * PB];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave / WN, wn = wave % WN;
+    const int li = lane & 15, lk = lane >> 4;
+    const int64_t z = blockIdx.z;
+    const int tile_m = blockIdx.x / g.tiles_n, tile_n = blockIdx.x % g.tiles_n;
+    const int64_t m0 = static_cast<int64_t>(tile_m) * BM, n0 = static_cast<int64_t>(tile_n) * BN;
+    const T* A = g.A + z * g.a_sz;
+    const T* B = g.B + z * g.b_sz;
+    // the contiguous index of each operand runs fastest over the threads
+    const bool a_kfast = g.a_sk == 1, b_jfast = g.b_sj == 1;
+
+    using Acc = typename Mfma<T>::acc_t;
+    Acc acc[FM][FN];
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) acc[a][b] = Acc{};
+
+    const int wm0 = wm * TM, wn0 = wn * TN;
+    for (int64_t k0 = 0; k0 < g.K; k0 += BK) {
+        T ra[LA], rb[LB];
+#pragma unroll
+        for (int p = 0; p < LA; ++p) {
+            const int e = tid + p * NT;
+            const int kk = a_kfast ? e % BK : e / BM, ii = a_kfast ? e / BK : e % BM;
+            const int64_t i = m0 + ii, k = k0 + kk;
+            ra[p] = (i < g.M && k < g.K) ? A[i * g.a_si + k * g.a_sk] : T(0);
+        }
+#pragma unroll
+        for (int p = 0; p < LB; ++p) {
+            const int e = tid + p * NT;
+            const int kk = b_jfast ? e / BN : e % BK, jj = b_jfast ? e % BN : e / BK;
+            const int64_t j = n0 + jj, k = k0 + kk;
+            rb[p] = (j < g.N && k < g.K) ? B[k * g.b_sk + j * g.b_sj] : T(0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int p = 0; p < LA; ++p) {
+            const int e = tid + p * NT;
+            const int kk = a_kfast ? e % BK : e / BM, ii = a_kfast ? e / BK : e % BM;
+            As[kk * PA + ii] = ra[p];
+        }
+#pragma unroll
+        for (int p = 0; p < LB; ++p) {
+            const int e = tid + p * NT;
+            const int kk = b_jfast ? e / BN : e % BK, jj = b_jfast ? e % BN : e / BK;
+            Bs[kk * PB + jj] = rb[p];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+            T a[FM], b[FN];
+#pragma unroll
+            for (int fm = 0; fm < FM; ++fm) a[fm] = As[(kk + lk) * PA + wm0 + fm * 16 + li];
+#pragma unroll
+            for (int fn = 0; fn < FN; ++fn) b[fn] = Bs[(kk + lk) * PB + wn0 + fn * 16 + li];
+#pragma unroll
+            for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+                for (int fn = 0; fn < FN; ++fn) acc[fm][fn] = Mfma<T>::op(a[fm], b[fn], acc[fm][fn]);
+        }
+    }
+
+    const T* C0 = g.C0 + z * g.c0_sz;
+    T* C = g.C + z * g.c_sz;
+#pragma unroll
+    for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+        for (int fn = 0; fn < FN; ++fn)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t i = m0 + wm0 + fm * 16 + Mfma<T>::row(lane, r);
+                const int64_t j = n0 + wn0 + fn * 16 + li;
+                if (i < g.M && j < g.N) {
+                    T v = g.alpha * acc[fm][fn][r];
+                    if (g.beta != T(0)) v += g.beta * C0[i * g.c0_si + j * g.c0_sj];
+                    C[i * g.c_si + j * g.c_sj] = v;
+                }
+            }
+}
+
+// A strided batch view.
+template <typename T>
+struct BV {
+    const T* p;
+    int64_t si, sj, sz;
+};
+template <typename T>
+struct BMV {
+    T* p;
+    int64_t si, sj, sz;
+};
+
+template <typename T>
+hipError_t bgemm(int64_t batch, int64_t M, int64_t N, int64_t K, BV<T> a, BV<T> b, T alpha, T beta,
+                 BV<T> c0, BMV<T> c, hipStream_t s) {
+    if (batch <= 0 || M <= 0 || N <= 0) return hipSuccess;
+    BGemm<T> g{};
+    g.M = M; g.N = N; g.K = K;
+    g.A = a.p; g.a_si = a.si; g.a_sk = a.sj; g.a_sz = a.sz;
+    g.B = b.p; g.b_sk = b.si; g.b_sj = b.sj; g.b_sz = b.sz;
+    g.alpha = alpha; g.beta = beta;
+    g.C0 = c0.p; g.c0_si = c0.si; g.c0_sj = c0.sj; g.c0_sz = c0.sz;
+    g.C = c.p; g.c_si = c.si; g.c_sj = c.sj; g.c_sz = c.sz;
+    if (batch > 65535) return hipErrorInvalidValue;
+    // 64 x 64 tiles; 128 x 64 for tall outputs with few tiles per matrix
+    if (M >= 1024 && N <= 64) {
+        g.tiles_n = static_cast<int>(cdiv(N, 64));
+        dim3 grid(static_cast<unsigned>(cdiv(M, 128) * g.tiles_n), 1, static_cast<unsigned>(batch));
+        hipLaunchKernelGGL((bgemm_kernel<T, 128, 64, 16>), grid, dim3(256), 0, s, g);
+    } else {
+        g.tiles_n = static_cast<int>(cdiv(N, 64));
+        dim3 grid(static_cast<unsigned>(cdiv(M, 64) * g.tiles_n), 1, static_cast<unsigned>(batch));
+        hipLaunchKernelGGL((bgemm_kernel<T, 64, 64, 16>), grid, dim3(256), 0, s, g);
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ small factorisations
+
+// Cholesky of each b x b Gram matrix (row-major, batch stride b*b): Gram = R^T R with R
+// upper triangular, and R^{-1} by back substitution.  A pivot <= tau * max diag(Gram)
+// (or not finite) sets *flag.  One workgroup per matrix, b <= 64.
+template <typename T>
+__global__ void __launch_bounds__(256)
+chol_inv_batched_kernel(const T* __restrict__ gram, int b, T tau, T* __restrict__ R,
+                        T* __restrict__ Rinv, int* __restrict__ flag) {
+    __shared__ T S[64 * 65];
+    __shared__ T piv;
+    const int64_t z = blockIdx.x;
+    const T* Gz = gram + z * b * b;
+    T* Rz = R + z * b * b;
+    T* Iz = Rinv + z * b * b;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < b * b; e += blockDim.x) S[(e / b) * 65 + e % b] = Gz[e];
+    __syncthreads();
+    T dmax = T(0);
+    for (int j = 0; j < b; ++j) dmax = S[j * 65 + j] > dmax ? S[j * 65 + j] : dmax;
+    for (int j = 0; j < b; ++j) {
+        if (tid == 0) {
+            const T d = S[j * 65 + j];
+            if (!(d > tau * dmax)) *flag = 1;
+            piv = d > T(0) ? sqrt(d) : T(1);
+        }
+        __syncthreads();
+        const T p = piv;
+        // row j of R: R(j, c) = S(j, c) / p for c >= j (upper part of S holds the update)
+        for (int c = j + tid; c < b; c += blockDim.x) S[j * 65 + c] = c == j ? p : S[j * 65 + c] / p;
+        __syncthreads();
+        // trailing update S(r, c) -= R(j, r) R(j, c) for j < r <= c
+        const int rem = b - j - 1;
+        for (int e = tid; e < rem * rem; e += blockDim.x) {
+            const int r = j + 1 + e / rem, c = j + 1 + e % rem;
+            if (c >= r) S[r * 65 + c] -= S[j * 65 + r] * S[j * 65 + c];
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < b * b; e += blockDim.x) {
+        const int r = e / b, c = e % b;
+        Rz[e] = c >= r ? S[r * 65 + c] : T(0);
+    }
+    // R^{-1}: thread c solves R x = e_c from the bottom row up (column c of R^{-1})
+    __syncthreads();
+    if (tid < b) {
+        const int c = tid;
+        for (int r = b - 1; r >= 0; --r) {
+            T v = r == c ? T(1) : T(0);
+            for (int t = r + 1; t <= c; ++t) v -= S[r * 65 + t] * Iz[t * b + c];
+            Iz[r * b + c] = r <= c ? v / S[r * 65 + r] : T(0);
+        }
+    }
+}
+
+// Inverse of the upper triangle of each k x k matrix (row-major, row stride ld, batch
+// stride sz) into Rinv (k x k row-major, batch stride k*k).  One workgroup per matrix,
+// k <= 256; thread c computes column c by back substitution reading R from global memory.
+template <typename T>
+__global__ void __launch_bounds__(256)
+tri_inv_batched_kernel(const T* __restrict__ R, int k, int64_t ld, int64_t sz, T* __restrict__ Rinv) {
+    const int64_t z = blockIdx.x;
+    const T* Rz = R + z * sz;
+    T* Iz = Rinv + z * static_cast<int64_t>(k) * k;
+    const int c = threadIdx.x;
+    if (c >= k) return;
+    for (int r = k - 1; r >= 0; --r) {
+        T v = r == c ? T(1) : T(0);
+        if (r <= c) {
+            for (int t = r + 1; t <= c; ++t) v -= Rz[r * ld + t] * Iz[static_cast<int64_t>(t) * k + c];
+            v /= Rz[r * ld + r];
+        } else {
+            v = T(0);
+        }
+        Iz[static_cast<int64_t>(r) * k + c] = v;
+    }
+}
+
+// C = copyltu(M): C(r, c) = M(max(r, c), min(r, c)) for each k x k matrix (batch stride k*k).
+template <typename T>
+__global__ void __launch_bounds__(256)
+copyltu_batched_kernel(const T* __restrict__ M, int k, int64_t total, T* __restrict__ C) {
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    const int64_t kk = static_cast<int64_t>(k) * k;
+    const int64_t z = e / kk, w = e % kk;
+    const int r = static_cast<int>(w / k), c = static_cast<int>(w % k);
+    const int hi = r > c ? r : c, lo = r > c ? c : r;
+    C[e] = M[z * kk + static_cast<int64_t>(hi) * k + lo];
+}
+
+__global__ void __launch_bounds__(256)
+f64_to_f32_kernel(const double* __restrict__ x, int64_t len, float* __restrict__ y) {
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e < len) y[e] = static_cast<float>(x[e]);
+}
+
+// ------------------------------------------------------------------ host
+
+namespace {
+
+constexpr int kMaxDiffB = 64;
+constexpr int kMaxDiffK = 256;
+
+struct DiffLayout {
+    size_t om64, om, g, h, y, x, w, z, d, s, gram, r1, r1i, rt, rti, ri, rii, flag,
+        r, rinv, qt, mm, cs, yb, total;
+};
+
+size_t al256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+template <typename T>
+DiffLayout diff_layout(int64_t batch, int64_t m, int64_t n, int64_t k, int64_t b) {
+    DiffLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = al256(off + bytes);
+        return o;
+    };
+    const size_t E = sizeof(T);
+    L.om64 = take(sizeof(T) == sizeof(float) ? sizeof(double) * n * k : 0);
+    L.om = take(E * n * k);
+    L.g = take(E * batch * m * k);
+    L.h = take(E * batch * n * k);
+    L.y = take(E * batch * m * b);
+    L.x = take(E * batch * m * b);
+    L.w = take(E * batch * k * b);
+    L.z = take(E * batch * k * b);
+    L.d = take(E * batch * k * b);
+    L.s = take(E * batch * n * b);
+    L.gram = take(E * batch * b * b);
+    L.r1 = take(E * batch * b * b);
+    L.r1i = take(E * batch * b * b);
+    L.rt = take(E * batch * b * b);
+    L.rti = take(E * batch * b * b);
+    L.ri = take(E * batch * b * b);
+    L.rii = take(E * batch * b * b);
+    L.flag = take(sizeof(int) * 4);
+    // backward: R = Q^T G and its inverse, Qt, M, copyltu(M), Y-bar
+    L.r = take(E * batch * k * k);
+    L.rinv = take(E * batch * k * k);
+    L.qt = take(E * batch * m * k);
+    L.mm = take(E * batch * k * k);
+    L.cs = take(E * batch * k * k);
+    L.yb = take(E * batch * m * k);
+    L.total = off + 256;
+    return L;
+}
+
+size_t diff_bytes(const qb_batch* A, int64_t k, int32_t b) {
+    if (A->dtype == QB_F32) return diff_layout<float>(A->batch, A->m, A->n, k, b).total;
+    return diff_layout<double>(A->batch, A->m, A->n, k, b).total;
+}
+
+int check_batch(const qb_batch* A, int64_t k, int32_t b) {
+    if (A == nullptr || A->a == nullptr || A->batch < 1 || A->batch > 65535 || A->m < 1 || A->n < 1 ||
+        A->lda < A->n || A->stride_a < 0)
+        return QB_ERR_ARG;
+    if (A->batch > 1 && A->stride_a < A->m * A->lda) return QB_ERR_ARG;
+    if (A->dtype != QB_F32 && A->dtype != QB_F64) return QB_ERR_UNSUPPORTED;
+    if (b < 1 || b > kMaxDiffB || k < 1 || k > kMaxDiffK || k % b != 0) return QB_ERR_ARG;
+    if (k > A->m || k > A->n) return QB_ERR_ARG;
+    return QB_OK;
+}
+
+#define QB_DHIP(expr)                                 \
+    do {                                              \
+        const hipError_t qb_e_ = (expr);              \
+        if (qb_e_ != hipSuccess) return QB_ERR_HIP;   \
+    } while (0)
+
+// Omega (n x k, row-major) in the element type, from the bit-specified generator
+// (binary32: each binary64 value rounded to nearest).
+template <typename T>
+int make_omega(uint64_t seed, int64_t n, int64_t k, char* ws, const DiffLayout& L, hipStream_t s) {
+    if constexpr (sizeof(T) == sizeof(float)) {
+        double* om64 = reinterpret_cast<double*>(ws + L.om64);
+        QB_DHIP(launch_gauss_fill(seed, 0, 0, 0, 0, n, k, om64, k, s));
+        const int64_t len = n * k;
+        hipLaunchKernelGGL(f64_to_f32_kernel, dim3(static_cast<unsigned>(cdiv(len, 256))), dim3(256), 0,
+                           s, om64, len, reinterpret_cast<float*>(ws + L.om));
+        QB_DHIP(hipGetLastError());
+    } else {
+        QB_DHIP(launch_gauss_fill(seed, 0, 0, 0, 0, n, k, reinterpret_cast<double*>(ws + L.om), k, s));
+    }
+    return QB_OK;
+}
+
+template <typename T>
+int cholqr_b(int64_t batch, int64_t m, int b, const T* X, int64_t xsz, T* Qout, int64_t q_si,
+             int64_t q_sz, T* gram, T* R, T* Rinv, int* flag, hipStream_t s) {
+    // Gram = X^T X (X: m x b row-major per matrix)
+    QB_DHIP(bgemm<T>(batch, b, b, m, BV<T>{X, 1, b, xsz}, BV<T>{X, b, 1, xsz}, T(1), T(0),
+                     BV<T>{nullptr, 0, 0, 0}, BMV<T>{gram, b, 1, static_cast<int64_t>(b) * b}, s));
+    const T tau = sizeof(T) == sizeof(float) ? T(1e-6) : T(1e-12);
+    hipLaunchKernelGGL((chol_inv_batched_kernel<T>), dim3(static_cast<unsigned>(batch)), dim3(256), 0, s,
+                       gram, b, tau, R, Rinv, flag);
+    QB_DHIP(hipGetLastError());
+    // Q = X R^{-1}
+    QB_DHIP(bgemm<T>(batch, m, b, b, BV<T>{X, b, 1, xsz}, BV<T>{Rinv, b, 1, static_cast<int64_t>(b) * b},
+                     T(1), T(0), BV<T>{nullptr, 0, 0, 0}, BMV<T>{Qout, q_si, 1, q_sz}, s));
+    return QB_OK;
+}
+
+template <typename T>
+int fixed_fwd(const qb_batch* Ab, int64_t k, int b, uint64_t seed, T* Q, int64_t ldq, int64_t sq, T* B,
+              int64_t ldb, int64_t sb, char* ws, const DiffLayout& L, hipStream_t s, int* host_flag) {
+    const int64_t bt = Ab->batch, m = Ab->m, n = Ab->n;
+    const T* A = static_cast<const T*>(Ab->a);
+    const int64_t lda = Ab->lda, sa = Ab->stride_a;
+    auto P = [&](size_t off) { return reinterpret_cast<T*>(ws + off); };
+    T *Om = P(L.om), *G = P(L.g), *H = P(L.h), *Y = P(L.y), *X = P(L.x), *W = P(L.w), *Z = P(L.z),
+      *D = P(L.d), *S = P(L.s), *gram = P(L.gram), *R1 = P(L.r1), *R1i = P(L.r1i), *Rt = P(L.rt),
+      *Rti = P(L.rti), *Ri = P(L.ri), *Rii = P(L.rii);
+    int* flag = reinterpret_cast<int*>(ws + L.flag);
+    const BV<T> none{nullptr, 0, 0, 0};
+    const int64_t bb = static_cast<int64_t>(b) * b;
+    QB_DHIP(launch_fill_int(flag, 1, 0, s));
+    if (int e = make_omega<T>(seed, n, k, ws, L, s)) return e;
+    // G = A Omega (m x k), H = A^T G (n x k), row-major per matrix
+    QB_DHIP(bgemm<T>(bt, m, k, n, BV<T>{A, lda, 1, sa}, BV<T>{Om, k, 1, 0}, T(1), T(0), none,
+                     BMV<T>{G, k, 1, m * k}, s));
+    QB_DHIP(bgemm<T>(bt, n, k, m, BV<T>{A, 1, lda, sa}, BV<T>{G, k, 1, m * k}, T(1), T(0), none,
+                     BMV<T>{H, k, 1, n * k}, s));
+    for (int64_t j0 = 0; j0 < k; j0 += b) {
+        const int64_t ki = j0;   // columns of Q / rows of B so far
+        // W = B(0:ki, :) Omega_J  (ki x b)
+        QB_DHIP(bgemm<T>(bt, ki, b, n, BV<T>{B, ldb, 1, sb}, BV<T>{Om + j0, k, 1, 0}, T(1), T(0), none,
+                         BMV<T>{W, b, 1, k * b}, s));
+        // Y = G_J - Q(:, 0:ki) W  (m x b row-major)
+        QB_DHIP(bgemm<T>(bt, m, b, ki, BV<T>{Q, ldq, 1, sq}, BV<T>{W, b, 1, k * b}, T(-1), T(1),
+                         BV<T>{G + j0, k, 1, m * k}, BMV<T>{Y, b, 1, m * b}, s));
+        // first qr: X = Y R1^{-1}
+        if (int e = cholqr_b<T>(bt, m, b, Y, m * b, X, b, m * b, gram, R1, R1i, flag, s)) return e;
+        // re-orthogonalisation: Z = Q^T X, X2 = X - Q Z -> written into the Q panel
+        QB_DHIP(bgemm<T>(bt, ki, b, m, BV<T>{Q, 1, ldq, sq}, BV<T>{X, b, 1, m * b}, T(1), T(0), none,
+                         BMV<T>{Z, b, 1, k * b}, s));
+        QB_DHIP(bgemm<T>(bt, m, b, ki, BV<T>{Q, ldq, 1, sq}, BV<T>{Z, b, 1, k * b}, T(-1), T(1),
+                         BV<T>{X, b, 1, m * b}, BMV<T>{X, b, 1, m * b}, s));
+        if (int e = cholqr_b<T>(bt, m, b, X, m * b, Q + j0, ldq, sq, gram, Rt, Rti, flag, s)) return e;
+        // R_i = R~ R1 and R_i^{-1} = R1^{-1} R~^{-1}
+        QB_DHIP(bgemm<T>(bt, b, b, b, BV<T>{Rt, b, 1, bb}, BV<T>{R1, b, 1, bb}, T(1), T(0), none,
+                         BMV<T>{Ri, b, 1, bb}, s));
+        QB_DHIP(bgemm<T>(bt, b, b, b, BV<T>{R1i, b, 1, bb}, BV<T>{Rti, b, 1, bb}, T(1), T(0), none,
+                         BMV<T>{Rii, b, 1, bb}, s));
+        // D = Q(:, 0:ki)^T Y + W  (ki x b)
+        QB_DHIP(bgemm<T>(bt, ki, b, m, BV<T>{Q, 1, ldq, sq}, BV<T>{Y, b, 1, m * b}, T(1), T(1),
+                         BV<T>{W, b, 1, k * b}, BMV<T>{D, b, 1, k * b}, s));
+        // S^T = H_J - B(0:ki, :)^T D  (n x b row-major)
+        QB_DHIP(bgemm<T>(bt, n, b, ki, BV<T>{B, 1, ldb, sb}, BV<T>{D, b, 1, k * b}, T(-1), T(1),
+                         BV<T>{H + j0, k, 1, n * k}, BMV<T>{S, b, 1, n * b}, s));
+        // B_i^T = S^T R_i^{-1}, written transposed into rows j0.. of B
+        QB_DHIP(bgemm<T>(bt, n, b, b, BV<T>{S, b, 1, n * b}, BV<T>{Rii, b, 1, bb}, T(1), T(0), none,
+                         BMV<T>{B + j0 * ldb, 1, ldb, sb}, s));
+    }
+    QB_DHIP(hipMemcpyAsync(host_flag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    QB_DHIP(hipStreamSynchronize(s));
+    return QB_OK;
+}
+
+template <typename T>
+int fixed_bwd(const qb_batch* Ab, int64_t k, uint64_t seed, const T* Q, int64_t ldq, int64_t sq,
+              const T* dQ, int64_t lddq, int64_t sdq, const T* dB, int64_t lddb, int64_t sdb, T* dA,
+              int64_t ldda, int64_t sda, char* ws, const DiffLayout& L, hipStream_t s) {
+    const int64_t bt = Ab->batch, m = Ab->m, n = Ab->n;
+    const T* A = static_cast<const T*>(Ab->a);
+    const int64_t lda = Ab->lda, sa = Ab->stride_a;
+    auto P = [&](size_t off) { return reinterpret_cast<T*>(ws + off); };
+    T *Om = P(L.om), *G = P(L.g), *R = P(L.r), *Rinv = P(L.rinv), *Qt = P(L.qt), *Mm = P(L.mm),
+      *Cs = P(L.cs), *Yb = P(L.yb);
+    const BV<T> none{nullptr, 0, 0, 0};
+    const int64_t kk = k * k;
+    if (int e = make_omega<T>(seed, n, k, ws, L, s)) return e;
+    // recompute G = A Omega and R = Q^T G (upper triangular up to round-off)
+    QB_DHIP(bgemm<T>(bt, m, k, n, BV<T>{A, lda, 1, sa}, BV<T>{Om, k, 1, 0}, T(1), T(0), none,
+                     BMV<T>{G, k, 1, m * k}, s));
+    QB_DHIP(bgemm<T>(bt, k, k, m, BV<T>{Q, 1, ldq, sq}, BV<T>{G, k, 1, m * k}, T(1), T(0), none,
+                     BMV<T>{R, k, 1, kk}, s));
+    hipLaunchKernelGGL((tri_inv_batched_kernel<T>), dim3(static_cast<unsigned>(bt)), dim3(256), 0, s, R,
+                       static_cast<int>(k), k, kk, Rinv);
+    QB_DHIP(hipGetLastError());
+    // Qt = dQ + A dB^T  (m x k)
+    const bool has_dq = dQ != nullptr, has_db = dB != nullptr;
+    if (has_db) {
+        QB_DHIP(bgemm<T>(bt, m, k, n, BV<T>{A, lda, 1, sa}, BV<T>{dB, 1, lddb, sdb}, T(1),
+                         has_dq ? T(1) : T(0), has_dq ? BV<T>{dQ, lddq, 1, sdq} : none,
+                         BMV<T>{Qt, k, 1, m * k}, s));
+    } else if (has_dq) {
+        QB_DHIP(bgemm<T>(bt, m, k, 0, none, none, T(0), T(1), BV<T>{dQ, lddq, 1, sdq},
+                         BMV<T>{Qt, k, 1, m * k}, s));
+    } else {
+        QB_DHIP(bgemm<T>(bt, m, k, 0, none, none, T(0), T(0), none, BMV<T>{Qt, k, 1, m * k}, s));
+    }
+    // M = -Qt^T Q (k x k), Cs = copyltu(M)
+    QB_DHIP(bgemm<T>(bt, k, k, m, BV<T>{Qt, 1, k, m * k}, BV<T>{Q, ldq, 1, sq}, T(-1), T(0), none,
+                     BMV<T>{Mm, k, 1, kk}, s));
+    const int64_t tot = bt * kk;
+    hipLaunchKernelGGL((copyltu_batched_kernel<T>), dim3(static_cast<unsigned>(cdiv(tot, 256))), dim3(256), 0,
+                       s, Mm, static_cast<int>(k), tot, Cs);
+    QB_DHIP(hipGetLastError());
+    // Qt <- Qt + Q Cs ; Y-bar = Qt R^{-T}
+    QB_DHIP(bgemm<T>(bt, m, k, k, BV<T>{Q, ldq, 1, sq}, BV<T>{Cs, k, 1, kk}, T(1), T(1),
+                     BV<T>{Qt, k, 1, m * k}, BMV<T>{Qt, k, 1, m * k}, s));
+    QB_DHIP(bgemm<T>(bt, m, k, k, BV<T>{Qt, k, 1, m * k}, BV<T>{Rinv, 1, k, kk}, T(1), T(0), none,
+                     BMV<T>{Yb, k, 1, m * k}, s));
+    // dA = Q dB + Y-bar Omega^T
+    if (has_db) {
+        QB_DHIP(bgemm<T>(bt, m, n, k, BV<T>{Q, ldq, 1, sq}, BV<T>{dB, lddb, 1, sdb}, T(1), T(0), none,
+                         BMV<T>{dA, ldda, 1, sda}, s));
+    }
+    QB_DHIP(bgemm<T>(bt, m, n, k, BV<T>{Yb, k, 1, m * k}, BV<T>{Om, 1, k, 0}, T(1),
+                     has_db ? T(1) : T(0), has_db ? BV<T>{dA, ldda, 1, sda} : none,
+                     BMV<T>{dA, ldda, 1, sda}, s));
+    return QB_OK;
+}
+
+}  // namespace
+}  // namespace qb
+
+using namespace qb;
+
+extern "C" {
+
+size_t qb_fixed_rank_workspace_bytes(const qb_batch* A, int64_t k, int32_t b) {
+    if (check_batch(A, k, b) != QB_OK) return 0;
+    return diff_bytes(A, k, b);
+}
+
+int qb_fixed_rank_fwd(const qb_batch* A, int64_t k, int32_t b, uint64_t seed, void* Q, int64_t ldq,
+                      int64_t stride_q, void* B, int64_t ldb, int64_t stride_b, void* ws,
+                      size_t ws_bytes, hipStream_t stream) {
+    if (int st = check_batch(A, k, b)) return st;
+    if (Q == nullptr || B == nullptr || ws == nullptr || ldq < k || ldb < A->n) return QB_ERR_ARG;
+    if (A->batch > 1 && (stride_q < A->m * ldq || stride_b < k * ldb)) return QB_ERR_ARG;
+    if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return QB_ERR_ARG;
+    if (ws_bytes < diff_bytes(A, k, b)) return QB_ERR_WORKSPACE;
+    char* w = static_cast<char*>(ws);
+    int flag = 0;
+    int st;
+    if (A->dtype == QB_F32) {
+        const DiffLayout L = diff_layout<float>(A->batch, A->m, A->n, k, b);
+        st = fixed_fwd<float>(A, k, b, seed, static_cast<float*>(Q), ldq, stride_q, static_cast<float*>(B),
+                              ldb, stride_b, w, L, stream, &flag);
+    } else {
+        const DiffLayout L = diff_layout<double>(A->batch, A->m, A->n, k, b);
+        st = fixed_fwd<double>(A, k, b, seed, static_cast<double*>(Q), ldq, stride_q,
+                               static_cast<double*>(B), ldb, stride_b, w, L, stream, &flag);
+    }
+    if (st != QB_OK) return st;
+    return flag ? QB_NOT_CONVERGED : QB_OK;
+}
+
+int qb_fixed_rank_bwd(const qb_batch* A, int64_t k, int32_t b, uint64_t seed, const void* Q,
+                      int64_t ldq, int64_t stride_q, const void* dQ, int64_t lddq, int64_t stride_dq,
+                      const void* dB, int64_t lddb, int64_t stride_db, void* dA, int64_t ldda,
+                      int64_t stride_da, void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (int st = check_batch(A, k, b)) return st;
+    if (Q == nullptr || dA == nullptr || ws == nullptr || ldq < k || ldda < A->n) return QB_ERR_ARG;
+    if (dQ != nullptr && lddq < k) return QB_ERR_ARG;
+    if (dB != nullptr && lddb < A->n) return QB_ERR_ARG;
+    if (A->batch > 1 && (stride_q < A->m * ldq || stride_da < A->m * ldda ||
+                         (dQ != nullptr && stride_dq < A->m * lddq) ||
+                         (dB != nullptr && stride_db < k * lddb)))
+        return QB_ERR_ARG;
+    if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return QB_ERR_ARG;
+    if (ws_bytes < diff_bytes(A, k, b)) return QB_ERR_WORKSPACE;
+    char* w = static_cast<char*>(ws);
+    if (A->dtype == QB_F32) {
+        const DiffLayout L = diff_layout<float>(A->batch, A->m, A->n, k, b);
+        return fixed_bwd<float>(A, k, seed, static_cast<const float*>(Q), ldq, stride_q,
+                                static_cast<const float*>(dQ), lddq, stride_dq,
+                                static_cast<const float*>(dB), lddb, stride_db, static_cast<float*>(dA),
+                                ldda, stride_da, w, L, stream);
+    }
+    const DiffLayout L = diff_layout<double>(A->batch, A->m, A->n, k, b);
+    return fixed_bwd<double>(A, k, seed, static_cast<const double*>(Q), ldq, stride_q,
+                             static_cast<const double*>(dQ), lddq, stride_dq,
+                             static_cast<const double*>(dB), lddb, stride_db, static_cast<double*>(dA),
+                             ldda, stride_da, w, L, stream);
+}
+
+}  // extern "C"

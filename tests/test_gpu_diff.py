@@ -1,0 +1,153 @@
+"""GPU parity of the differentiation form: the library's batched fixed-rank randQB_FP
+forward and its hand-written backward (through the C ABI and the torch.autograd.Function
+of the binding) against the float64 reference map and its autograd gradient.
+
+Tolerances: binary64 mode -- Q and B within 1e-10 (relative to ||A||) of the reference
+map, dL/dA within 1e-10 of the reference gradient (relative to its norm), and the
+directional derivative within 1e-6 of central differences (h = 1e-6) of the library's own
+binary64 forward; binary32 mode -- dL/dA within 1e-3 of the binary64 reference gradient
+taken at the same (binary32) A and Omega values."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import diff as D
+from oracle import randqb as R
+
+pytestmark = pytest.mark.gpu
+
+SEED = W.SEED_OMEGA | 5
+
+
+@pytest.fixture(scope="module")
+def qb():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1606_09402_amd as q
+    q.lib()
+    return q
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+def _batch(m, n, kind, count, seed, dtype=torch.float64):
+    sig = W.sigma_law(kind, min(m, n))
+    return torch.stack([W.lowrank_dense(m, n, sig, seed + 7 * z) for z in range(count)]).to(dtype)
+
+
+@pytest.mark.parametrize("m,n,k,b,count", [(96, 64, 32, 16, 1), (300, 200, 48, 16, 3), (257, 190, 60, 20, 2)])
+def test_fixed_rank_forward_f64(qb, m, n, k, b, count):
+    _log(f"fixed-rank forward f64 {count} x {m}x{n} k={k} b={b}")
+    A = _batch(m, n, "exp40", count, 401)
+    Q, B = qb.qb_fixed_rank_fwd(A.cuda(), k, b, SEED)
+    Q, B = Q.cpu().numpy(), B.cpu().numpy()
+    Om = D.omega_fixed(SEED, n, k)
+    for z in range(count):
+        Qo, Bo = R.randqb_fp_fixed(A[z].numpy(), Om, b)
+        nrm = np.linalg.norm(A[z].numpy())
+        assert np.max(np.abs(Q[z] - Qo)) <= 1e-10
+        assert np.linalg.norm(B[z] - Bo) <= 1e-10 * nrm
+        assert np.max(np.abs(Q[z].T @ Q[z] - np.eye(k))) <= 1e-12
+
+
+@pytest.mark.parametrize("m,n,k,b,count", [(96, 64, 32, 16, 1), (300, 200, 48, 16, 3)])
+def test_fixed_rank_backward_f64(qb, m, n, k, b, count):
+    _log(f"fixed-rank backward f64 {count} x {m}x{n} k={k} b={b}")
+    A = _batch(m, n, "exp40", count, 402)
+    rs = np.random.default_rng(11)
+    dQ = torch.tensor(rs.standard_normal((count, m, k)))
+    dB = torch.tensor(rs.standard_normal((count, k, n)))
+    Ad = A.cuda()
+    Q, B = qb.qb_fixed_rank_fwd(Ad, k, b, SEED)
+    dA = qb.qb_fixed_rank_bwd(Ad, k, b, SEED, Q, dQ.cuda(), dB.cuda()).cpu().numpy()
+    Om = D.omega_fixed(SEED, n, k)
+    for z in range(count):
+        ref = D.vjp_reference(A[z].numpy(), Om, dQ[z].numpy(), dB[z].numpy())
+        assert np.linalg.norm(dA[z] - ref) <= 1e-10 * np.linalg.norm(ref)
+    # one adjoint at a time (the other NULL)
+    dA_q = qb.qb_fixed_rank_bwd(Ad, k, b, SEED, Q, dQ.cuda(), None).cpu().numpy()
+    dA_b = qb.qb_fixed_rank_bwd(Ad, k, b, SEED, Q, None, dB.cuda()).cpu().numpy()
+    assert np.allclose(dA_q + dA_b, dA, atol=1e-12 * np.linalg.norm(dA))
+
+
+def _gpu_loss_grad(qb, A, k, b):
+    """L and dL/dA through the library's autograd Function (loss in float64 on the GPU)."""
+    Ad = A.detach().clone().cuda().requires_grad_(True)
+    Q, B = qb.fixed_rank_qb(Ad, k, b, SEED)
+    L = D.loss(Ad.double(), Q.double(), B.double())
+    L.backward()
+    return L.item(), Ad.grad.detach().cpu().double().numpy()
+
+
+def test_autograd_f64_reference_and_fd(qb):
+    """96 x 64, k = 32, b = 16 in binary64: the reference gradient and central differences."""
+    A = _batch(96, 64, "exp40", 1, 403)[0]
+    L, g = _gpu_loss_grad(qb, A, 32, 16)
+    Om = D.omega_fixed(SEED, 64, 32)
+    L_ref, g_ref = D.grad_reference(A.numpy(), Om)
+    _log(f"L gpu {L:.15e} ref {L_ref:.15e}; |g - g_ref| / |g_ref| "
+         f"{np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref):.3e}")
+    assert abs(L - L_ref) <= 1e-12 * abs(L_ref)
+    assert np.linalg.norm(g - g_ref) <= 1e-10 * np.linalg.norm(g_ref)
+
+    def Lgpu(X):
+        with torch.no_grad():
+            Q, B = qb.qb_fixed_rank_fwd(X.cuda().unsqueeze(0).contiguous(), 32, 16, SEED)
+            return D.loss(X.cuda(), Q[0], B[0]).item()
+
+    rs = np.random.default_rng(12)
+    h = 1e-6
+    for _ in range(4):
+        E = torch.tensor(rs.standard_normal(A.shape))
+        E /= torch.linalg.norm(E)
+        fd = (Lgpu(A + h * E) - Lgpu(A - h * E)) / (2 * h)
+        an = float(np.sum(g * E.numpy()))
+        assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-3 * np.linalg.norm(g))
+
+
+def test_autograd_f32_against_f64_reference(qb):
+    """Binary32 forward and backward on matrices of the benchmark law (4 of them) against
+    the binary64 reference gradient at the same binary32 values."""
+    wl = W.C5
+    A = wl.make(items=range(4))
+    Om = D.omega_fixed(SEED, wl.n, wl.k, np.float32)
+    Ad = A.clone().cuda().requires_grad_(True)
+    Q, B = qb.fixed_rank_qb(Ad, wl.k, wl.b, SEED)
+    L = sum(D.loss(Ad[z].double(), Q[z].double(), B[z].double()) for z in range(A.shape[0]))
+    L.backward()
+    g = Ad.grad.cpu().double().numpy()
+    for z in range(A.shape[0]):
+        _, ref = D.grad_reference(A[z].double().numpy(), Om)
+        rel = np.linalg.norm(g[z] - ref) / np.linalg.norm(ref)
+        _log(f"item {z}: |g32 - g64| / |g64| = {rel:.3e}")
+        assert rel <= 1e-3
+
+
+def test_full_batch_f32(qb):
+    """The 64 x 2048 x 1024 binary32 batch (k = 128, b = 32): forward properties for every
+    item and the gradient of two sampled items against the reference."""
+    wl = W.C5
+    dev = torch.device("cuda")
+    A = wl.make(device=dev)
+    Ad = A.clone().requires_grad_(True)
+    Q, B = qb.fixed_rank_qb(Ad, wl.k, wl.b, SEED)
+    eye = torch.eye(wl.k, device=dev)
+    orth = (Q.transpose(1, 2) @ Q - eye).abs().amax().item()
+    nrm = torch.linalg.matrix_norm(A)
+    bq = (torch.linalg.matrix_norm(B - Q.transpose(1, 2) @ A) / nrm).max().item()
+    # B_i comes out of eq. (23) with the binary32 rounding of H amplified by R_i^{-T}
+    # (Remark 4.1): about u32 sqrt(n) sigma_1^2 / sigma_k with sigma_j = e^{-j/40}
+    bound = 2.0 ** -24 * np.sqrt(wl.n) * np.exp(wl.k / 40.0)
+    _log(f"full batch: max |Q^T Q - I| {orth:.2e}; max |B - Q^T A| / |A| {bq:.2e} (bound {bound:.2e})")
+    assert orth <= 1e-4 and bq <= bound
+    L = sum(D.loss(Ad[z].double(), Q[z].double(), B[z].double()) for z in range(wl.batch))
+    L.backward()
+    Om = D.omega_fixed(SEED, wl.n, wl.k, np.float32)
+    for z in (0, 63):
+        _, ref = D.grad_reference(A[z].double().cpu().numpy(), Om)
+        rel = np.linalg.norm(Ad.grad[z].double().cpu().numpy() - ref) / np.linalg.norm(ref)
+        _log(f"item {z}: |g32 - g64| / |g64| = {rel:.3e}")
+        assert rel <= 1e-3
