@@ -51,6 +51,7 @@ def main():
     ap.add_argument("--no-ei", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-diff", action="store_true")
+    ap.add_argument("--no-sparse", action="store_true")
     ap.add_argument("--gen-device", default="cuda", choices=["cuda", "cpu"],
                     help="where the seeded test matrix is generated (cpu keeps the GPU QR of the "
                          "generator out of counter-collection runs)")
@@ -198,13 +199,16 @@ def main():
     if not args.no_precision:
         del A, Qs, Bs, ws
         torch.cuda.empty_cache()
-        out["precision"] = precision_block(qb, W, torch, max(1, min(args.steps, 5)), args.l_tilde)
+        out["precision"] = precision_block(qb, W, torch, max(1, min(args.steps, 5)), args.l_tilde,
+                                           args.gen_device)
     if not args.no_diff:
         out["diff"] = diff_block(qb, W, torch, max(1, min(args.steps, 5)))
+    if not args.no_sparse:
+        out["sparse"] = sparse_block(qb, W, torch, max(1, min(args.steps, 3)))
     print(json.dumps(out), flush=True)
 
 
-def precision_block(qb, W, torch, steps, l_tilde):
+def precision_block(qb, W, torch, steps, l_tilde, gen_device="cuda"):
     """BF16 precision form against the FP64 path on the 32768 x 32768 workload."""
     import statistics
 
@@ -212,7 +216,7 @@ def precision_block(qb, W, torch, steps, l_tilde):
     seed = W.SEED_OMEGA | 4
     dev = torch.device("cuda:0")
     t0 = time.time()
-    A64 = wl.make(device=dev)
+    A64 = wl.make(device=dev if gen_device == "cuda" else "cpu").to(dev)
     Aq = W.to_bf16(A64)
     torch.cuda.synchronize()
     print(f"# generated {wl.name} in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
@@ -224,10 +228,16 @@ def precision_block(qb, W, torch, steps, l_tilde):
                for X in (A64, Aq))
     ws = torch.empty(need, dtype=torch.uint8, device=dev)
     a64_norm = float(torch.linalg.matrix_norm(A64))
+    A8, e8, _ = W.to_e4m3_rows(A64)
     res = {}
-    for name, X in (("f64", A64), ("bf16", Aq)):
-        run = lambda: qb.qb_fp_dense(X, wl.tol, wl.b, seed, l_max=l_max, l_tilde=l_tilde,
-                                     Q_store=Qs, B_store=Bs, ws=ws)
+    # e4m3 storage: its rounding error (2.6e-2 of ||A||) lies above tol 1e-2, so it runs at
+    # tol 5e-2 and the FP64 path is timed again at the error the e4m3 run achieved
+    for name, X, tol, rexp in (("f64", A64, wl.tol, None), ("bf16", Aq, wl.tol, None),
+                               ("fp8_e4m3", A8, 5e-2, e8), ("f64_at_fp8_error", A64, None, None)):
+        if tol is None:
+            tol = res["fp8_e4m3"]["true_rel_err"]
+        run = lambda: qb.qb_fp_dense(X, tol, wl.b, seed, l_max=l_max, l_tilde=l_tilde,
+                                     Q_store=Qs, B_store=Bs, ws=ws, row_exp=rexp)
         run()
         torch.cuda.synchronize()
         ts, rs = [], []
@@ -242,16 +252,17 @@ def precision_block(qb, W, torch, steps, l_tilde):
         g_ms = statistics.median(x.ms[2] for x in rs) / max(1, r.chunks)
         h_ms = statistics.median(x.ms[3] for x in rs) / max(1, r.chunks)
         per_launch = r.gemm_flops[0] / max(1, r.chunks)
-        peak = BF16_PEAK_TFLOPS if name == "bf16" else FP64_PEAK_TFLOPS
+        peak = FP64_PEAK_TFLOPS if name.startswith("f64") else BF16_PEAK_TFLOPS
         dom_ms = max(g_ms, h_ms)
         achieved = per_launch / (dom_ms * 1e-3) / 1e12
-        res[name] = {"time_to_tol_s": round(statistics.median(ts), 6), "rank": r.rank,
+        res[name] = {"tol": tol, "time_to_tol_s": round(statistics.median(ts), 6), "rank": r.rank,
                      "true_rel_err": true_rel, "E_rel": (max(r.E, 0.0) / r.normA2) ** 0.5,
                      "passes": r.passes, "chunks": r.chunks,
                      "phase_ms": {"normA2": r.ms[0], "omega": r.ms[1], "G": r.ms[2], "H": r.ms[3],
                                   "block_loop": r.ms[4], "total": r.ms[5]},
-                     "sketch_gemm": {"kernel": "gemm_bf16 (MFMA 32x32x16 bf16, FP32 acc)"
-                                     if name == "bf16" else "gemm_f64 (MFMA 16x16x4 f64)",
+                     "sketch_gemm": {"kernel": "gemm_f64 (MFMA 16x16x4 f64)" if name.startswith("f64")
+                                     else "gemm_bf16 (MFMA 32x32x16 bf16, FP32 acc)"
+                                     + (", e4m3 A widened on load" if name == "fp8_e4m3" else ""),
                                      "G_ms_per_launch": g_ms, "H_ms_per_launch": h_ms,
                                      "achieved_tflops": round(achieved, 2), "peak_tflops": peak,
                                      "frac": round(achieved / peak, 4)}}
@@ -260,9 +271,12 @@ def precision_block(qb, W, torch, steps, l_tilde):
     res["workload"] = wl.name
     res["schedule"] = {-1: "adaptive (8b first, <= 50b)", 0: "paper rule 50b"}.get(l_tilde, str(l_tilde))
     res["speedup_bf16_vs_f64"] = round(res["f64"]["time_to_tol_s"] / res["bf16"]["time_to_tol_s"], 3)
-    res["note"] = ("both runs factorise the same binary64 matrix (bf16: its bfloat16 storage) "
-                   "to tol 1e-2; true_rel_err is ||A - QB||_F / ||A||_F against the binary64 A")
-    del A64, Aq, Qs, Bs, ws
+    res["speedup_fp8_vs_f64_at_fp8_error"] = round(
+        res["f64_at_fp8_error"]["time_to_tol_s"] / res["fp8_e4m3"]["time_to_tol_s"], 3)
+    res["note"] = ("all runs factorise the same binary64 matrix (bf16 / fp8_e4m3: its bfloat16 / "
+                   "row-scaled e4m3 storage); true_rel_err is ||A - QB||_F / ||A||_F against the "
+                   "binary64 A; f64_at_fp8_error runs the FP64 path at the error the e4m3 run achieved")
+    del A64, Aq, A8, e8, Qs, Bs, ws
     torch.cuda.empty_cache()
     return res
 
@@ -309,6 +323,66 @@ def diff_block(qb, W, torch, steps):
                    "backward recomputes G = A Omega and R = Q^T G"}
     print(f"# diff: forward {mf * 1e3:.2f} ms, backward {mb * 1e3:.2f} ms", file=sys.stderr, flush=True)
     del A, dQ, dB, ws, Q, B
+    torch.cuda.empty_cache()
+    return res
+
+
+def sparse_block(qb, W, torch, steps):
+    """CSR workload: randQB_FP (paper rule and adaptive) and randQB_EI on the 500000 x 200000
+    power-law matrix (nnz 5e6, b = 50, tol 0.6), with the SpMM sweep rate."""
+    import statistics
+
+    import numpy as np
+
+    wl = W.C3
+    seed = W.SEED_OMEGA | 3
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    c = wl.make()
+    print(f"# generated {wl.name} in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    rowptr = torch.from_numpy(c.rowptr).to(dev)
+    colind = torch.from_numpy(c.colind).to(dev)
+    val = torch.from_numpy(c.val).to(dev)
+    l_max = 8192   # capacity of Q / B (the expected rank is about 3300)
+    Qs = torch.empty((l_max, c.m), dtype=torch.float64, device=dev)
+    Bs = torch.empty((l_max, c.n), dtype=torch.float64, device=dev)
+    res = {"workload": wl.name, "l_max": l_max}
+    runs = (("fp_paper_rule", lambda: qb.qb_fp_csr(c.m, c.n, rowptr, colind, val, wl.tol, wl.b, seed,
+                                                    l_max=l_max, l_tilde=0, Q_store=Qs, B_store=Bs)),
+            ("fp_adaptive", lambda: qb.qb_fp_csr(c.m, c.n, rowptr, colind, val, wl.tol, wl.b, seed,
+                                                  l_max=l_max, l_tilde=-1, Q_store=Qs, B_store=Bs)),
+            ("ei", lambda: qb.qb_ei_csr(c.m, c.n, rowptr, colind, val, wl.tol, wl.b, seed, l_max=l_max,
+                                        Q_store=Qs, B_store=Bs)))
+    for name, fn in runs:
+        fn()
+        torch.cuda.synchronize()
+        ts, rs = [], []
+        for _ in range(steps):
+            t = time.perf_counter()
+            r = fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+            rs.append(r)
+        r = rs[-1]
+        entry = {"time_to_tol_s": round(statistics.median(ts), 6), "rank": r.rank,
+                 "E_rel": (max(r.E, 0.0) / r.normA2) ** 0.5, "status": r.status, "passes": r.passes,
+                 "blocks": r.blocks, "chunks": r.chunks,
+                 "phase_ms": {"normA2_and_csc": r.ms[0], "omega": r.ms[1], "A_X": r.ms[2],
+                              "At_X": r.ms[3], "block_loop": r.ms[4], "total": r.ms[5]}}
+        if name.startswith("fp"):
+            # algorithmic bytes of the two SpMM passes per chunk: CSR arrays once, the dense
+            # operand once, the dense result once
+            w_tot = r.gemm_flops[0] / (2.0 * c.m * c.n) if r.gemm_flops[0] else 0.0
+            csr_b = c.nnz * 12 + (c.m + 1) * 8
+            bytes_g = r.chunks * csr_b + 8.0 * w_tot * (c.n + c.m)
+            bytes_h = r.chunks * (c.nnz * 12 + (c.n + 1) * 8) + 8.0 * w_tot * (c.m + c.n)
+            entry["spmm_GBps"] = {"A_X": round(bytes_g / (r.ms[2] * 1e-3) / 1e9, 1) if r.ms[2] else None,
+                                  "At_X": round(bytes_h / (r.ms[3] * 1e-3) / 1e9, 1) if r.ms[3] else None,
+                                  "peak": 8000.0}
+        res[name] = entry
+        print(f"# sparse {name}: {statistics.median(ts) * 1e3:.1f} ms rank {r.rank} passes {r.passes}",
+              file=sys.stderr, flush=True)
+    del Qs, Bs, rowptr, colind, val
     torch.cuda.empty_cache()
     return res
 

@@ -68,8 +68,16 @@ typedef enum { QB_ALGO_FP = 0, QB_ALGO_EI = 1 } qb_algo;
  *           on Omega_q, G_q and H, i.e. on exactly the operands of the two products,
  *           so B_i = Q_i^T A_q up to the accumulation error of H.  Only randQB_FP
  *           accepts it (randQB_EI forms B_i = Q_i^T A directly and would need Q_i in
- *           bfloat16: QB_ERR_UNSUPPORTED). */
-typedef enum { QB_F64 = 0, QB_BF16 = 1, QB_F32 = 2 } qb_dtype;
+ *           bfloat16: QB_ERR_UNSUPPORTED).
+ *   QB_FP8E4M3 8-bit storage (OCP e4m3fn: 4 exponent bits, bias 7, 3 stored significand
+ *           bits, finite values up to 448) with a power-of-two scale per row:
+ *           A_q(i, j) = 2^row_exp[i] * e4m3(a[i * lda + j]).  Every such value is a
+ *           bfloat16 value, so the precision form above applies unchanged to A_q: the
+ *           tiles are widened to bfloat16 on their way into LDS, the row scales enter the
+ *           G epilogue (and the H operand) as exact power-of-two multiplications, and
+ *           ||A_q||^2 is summed in binary64 from the scaled stored values.
+ *   QB_F32  binary32 (the differentiation form's batches, qb_batch). */
+typedef enum { QB_F64 = 0, QB_BF16 = 1, QB_F32 = 2, QB_FP8E4M3 = 3 } qb_dtype;
 
 /* Dense row-major matrix of element type dtype (a qb_dtype). */
 typedef struct {
@@ -78,6 +86,8 @@ typedef struct {
     int32_t dtype;      /* qb_dtype                                          */
     int32_t reserved;
     const void* a;      /* device pointer to A(0,0)                          */
+    const int32_t* row_exp; /* QB_FP8E4M3: device, m per-row exponents in
+                               [-100, 100]; ignored for other types           */
 } qb_dense;
 
 /* Compressed sparse row matrix (Section 5.1 stores sparse A in CSR).  Column indices
@@ -182,7 +192,8 @@ QB_API int qb_sumsq_dense(const qb_dense* A, double* out_host, void* ws, hipStre
 QB_API int qb_sketch_dense(const qb_dense* A, uint64_t seed, int64_t col0, int64_t l, double* om,
                     double* g, double* h, hipStream_t stream);
 
-/* The same sweep for bfloat16 A (dtype QB_BF16), exactly as qb_fp_dense runs it:
+/* The same sweep for bfloat16 or row-scaled e4m3 A (dtype QB_BF16 or QB_FP8E4M3),
+ * exactly as qb_fp_dense runs it:
  * om receives the dequantised Omega_q (n x l, ld l), g the dequantised G_q (m x l,
  * ld l) and h = A_q^T G_q (n x l, ld l), all binary64.  ws (256-byte aligned) needs
  * qb_sketch_lowp_bytes(A, l) bytes.  Enqueued on stream; does not synchronise. */

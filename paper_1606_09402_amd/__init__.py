@@ -25,7 +25,7 @@ LIB_PATH = os.path.join(PKG, "_lib", "libqb.so")
 QB_OK, QB_NOT_CONVERGED, QB_WARN_TOL_FLOOR = 0, 1, 2
 QB_ERR_ARG, QB_ERR_NONFINITE, QB_ERR_WORKSPACE, QB_ERR_HIP, QB_ERR_UNSUPPORTED = -1, -2, -3, -4, -5
 QB_ALGO_FP, QB_ALGO_EI = 0, 1
-QB_F64, QB_BF16, QB_F32 = 0, 1, 2
+QB_F64, QB_BF16, QB_F32, QB_FP8E4M3 = 0, 1, 2, 3
 
 _c_i64 = ctypes.c_int64
 _c_i32 = ctypes.c_int32
@@ -34,7 +34,7 @@ _vp = ctypes.c_void_p
 
 class QbDense(ctypes.Structure):
     _fields_ = [("m", _c_i64), ("n", _c_i64), ("lda", _c_i64), ("dtype", _c_i32),
-                ("reserved", _c_i32), ("a", _vp)]
+                ("reserved", _c_i32), ("a", _vp), ("row_exp", _vp)]
 
 
 class QbCsr(ctypes.Structure):
@@ -143,17 +143,25 @@ def _check_dev(t: torch.Tensor, name: str, dtype=torch.float64):
         raise ValueError(f"{name} must be {dtype}")
 
 
-_DTYPES = {torch.float64: QB_F64, torch.bfloat16: QB_BF16}
+_DTYPES = {torch.float64: QB_F64, torch.bfloat16: QB_BF16, torch.float8_e4m3fn: QB_FP8E4M3}
 
 
-def _dense(A: torch.Tensor) -> QbDense:
+def _dense(A: torch.Tensor, row_exp: torch.Tensor | None = None) -> QbDense:
+    """A: float64, bfloat16, or float8_e4m3fn with row_exp (int32, one per row): the
+    matrix 2^row_exp[i] * A[i, j]."""
     if not A.is_cuda:
         raise ValueError("A must be a GPU tensor")
     if A.dtype not in _DTYPES:
-        raise ValueError("A must be float64 or bfloat16")
+        raise ValueError("A must be float64, bfloat16 or float8_e4m3fn")
     if A.dim() != 2 or A.stride(1) != 1 or A.stride(0) < A.shape[1]:
         raise ValueError("A must be a row-major 2-D view (stride(1) == 1)")
-    return QbDense(A.shape[0], A.shape[1], A.stride(0), _DTYPES[A.dtype], 0, A.data_ptr())
+    re_ptr = None
+    if A.dtype == torch.float8_e4m3fn:
+        if (row_exp is None or not row_exp.is_cuda or row_exp.dtype != torch.int32
+                or row_exp.numel() != A.shape[0] or not row_exp.is_contiguous()):
+            raise ValueError("an e4m3 A needs row_exp: a contiguous int32 GPU tensor with one entry per row")
+        re_ptr = row_exp.data_ptr()
+    return QbDense(A.shape[0], A.shape[1], A.stride(0), _DTYPES[A.dtype], 0, A.data_ptr(), re_ptr)
 
 
 def _csr(m: int, n: int, rowptr: torch.Tensor, colind: torch.Tensor, val: torch.Tensor) -> QbCsr:
@@ -232,10 +240,12 @@ def _run(kind: str, algo: int, sparse: bool, mat, m: int, n: int, dev, tol, b, l
 
 
 def qb_fp_dense(A: torch.Tensor, tol: float, b: int, seed: int, l_max=None, l_tilde: int = 0,
-                row_by_row: bool = True, Q_store=None, B_store=None, ws=None, power: int = 0) -> QBResult:
-    """randQB_FP (Algorithm 4, P = 0) on dense A (GPU, row-major): float64, or bfloat16
-    for the precision form (bfloat16 sketch products, binary64 block loop)."""
-    d = _dense(A)
+                row_by_row: bool = True, Q_store=None, B_store=None, ws=None, power: int = 0,
+                row_exp: torch.Tensor | None = None) -> QBResult:
+    """randQB_FP (Algorithm 4, P = 0) on dense A (GPU, row-major): float64, or for the
+    precision form bfloat16 / float8_e4m3fn with row_exp (bfloat16 sketch products,
+    binary64 block loop)."""
+    d = _dense(A, row_exp)
     return _run("qb_fp_dense", QB_ALGO_FP, False, d, d.m, d.n, A.device, tol, b, l_max, l_tilde,
                 seed, row_by_row, Q_store, B_store, ws, power)
 
@@ -271,10 +281,10 @@ def qb_workspace_bytes(algo: int, sparse: bool, m: int, n: int, nnz: int, tol: f
 
 
 def qb_dense_workspace_bytes(algo: int, A: torch.Tensor, tol: float, b: int, l_max: int,
-                             l_tilde: int = 0) -> int:
+                             l_tilde: int = 0, row_exp: torch.Tensor | None = None) -> int:
     """Workspace bytes of qb_fp_dense / qb_ei_dense for this A (any supported dtype)."""
     p = _params(tol, b, l_max, l_tilde, 0, True)
-    return int(lib().qb_dense_workspace_bytes(algo, ctypes.byref(_dense(A)), ctypes.byref(p)))
+    return int(lib().qb_dense_workspace_bytes(algo, ctypes.byref(_dense(A, row_exp)), ctypes.byref(p)))
 
 
 def qb_gaussian_fill(seed: int, rows: int, cols: int, row0: int = 0, col0: int = 0,
@@ -293,10 +303,11 @@ def qb_gaussian_fill(seed: int, rows: int, cols: int, row0: int = 0, col0: int =
     return out
 
 
-def qb_sumsq_dense(A: torch.Tensor) -> float:
-    """||A||_F^2 of dense float64 or bfloat16 A as a deterministic GPU sum of squares."""
+def qb_sumsq_dense(A: torch.Tensor, row_exp: torch.Tensor | None = None) -> float:
+    """||A||_F^2 of dense float64, bfloat16 or row-scaled e4m3 A as a deterministic GPU
+    sum of squares."""
     L = lib()
-    d = _dense(A)
+    d = _dense(A, row_exp)
     ws = torch.empty(L.qb_sumsq_workspace_bytes(), dtype=torch.uint8, device=A.device)
     out = ctypes.c_double(0.0)
     st = L.qb_sumsq_dense(ctypes.byref(d), ctypes.byref(out), ws.data_ptr(), _stream_ptr(A.device))
@@ -319,12 +330,13 @@ def qb_sketch_dense(A: torch.Tensor, seed: int, col0: int, l: int):
     return om, g, h
 
 
-def qb_sketch_lowp(A: torch.Tensor, seed: int, col0: int, l: int):
-    """Precision-form sweep on bfloat16 A: (Omega_q, G_q, H = A_q^T G_q) as binary64."""
+def qb_sketch_lowp(A: torch.Tensor, seed: int, col0: int, l: int, row_exp: torch.Tensor | None = None):
+    """Precision-form sweep on bfloat16 or row-scaled e4m3 A: (Omega_q, G_q, H = A_q^T G_q)
+    as binary64."""
     L = lib()
-    d = _dense(A)
-    if d.dtype != QB_BF16:
-        raise ValueError("qb_sketch_lowp takes a bfloat16 A")
+    d = _dense(A, row_exp)
+    if d.dtype not in (QB_BF16, QB_FP8E4M3):
+        raise ValueError("qb_sketch_lowp takes a bfloat16 or float8_e4m3fn A")
     dev = A.device
     need = L.qb_sketch_lowp_bytes(ctypes.byref(d), l)
     if need == 0:

@@ -123,7 +123,8 @@ __global__ void __launch_bounds__(64 * WM * WN, OCC) gemm_f64_kernel(const GemmA
     const int li = lane & 15, lk = lane >> 4;
 
     const int logical = xcd_remap(blockIdx.x, gridDim.x);
-    const int tile_m = logical / g.tiles_n, tile_n = logical % g.tiles_n;
+    int tile_m, tile_n;
+    group_tiles(logical, g.tiles_m, g.tiles_n, tile_m, tile_n);
     const int64_t m0 = static_cast<int64_t>(tile_m) * BM;
     const int64_t n0 = static_cast<int64_t>(tile_n) * BN;
     const int64_t kb = static_cast<int64_t>(blockIdx.y) * g.kchunk;

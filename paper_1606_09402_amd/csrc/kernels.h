@@ -35,21 +35,25 @@ struct GemmDesc {
 };
 hipError_t gemm_f64(const GemmDesc& d, hipStream_t s);
 
-// lowp.hip -- the bfloat16 precision form of the sketch sweep
+// lowp.hip -- the low-precision (bfloat16 / e4m3-stored) form of the sketch sweep
 hipError_t launch_quant_transpose_omega(double* om, int64_t n, int64_t w, uint16_t* omT,
                                         int64_t ldt, hipStream_t s);
 hipError_t launch_sumsq_bf16(const uint16_t* a, int64_t m, int64_t n, int64_t lda,
                              double* scratch, double* out, hipStream_t s);
-// out(i, j) = sum_k A(i, k) B(j, k) for bfloat16 A and B with binary32 accumulation.
-// B is N x K with K contiguous (row stride ldb).  a_km == false: A is M x K with K
-// contiguous (row stride lda), and outT must be set (the G epilogue): out = bf16(sums) as
-// binary64, outT (N x M, ld ldt) the same bfloat16 values and colsq (if set)
-// [bf16_gemm_row_groups(M, N)][N] partial column sums of squares of out.  a_km == true:
-// A(i, k) = A[k * lda + i] and outT must be nullptr: out = the binary32 sums as binary64.
+hipError_t launch_sumsq_fp8(const uint8_t* a, const int32_t* row_exp, int64_t m, int64_t n,
+                            int64_t lda, double* scratch, double* out, hipStream_t s);
+// out(i, j) = sum_k A(i, k) B(j, k) on bfloat16 matrix cores with binary32 accumulation.
+// B is N x K bfloat16 with K contiguous (row stride ldb).  A is bfloat16, or e4m3 bytes
+// (a_fp8) widened to bfloat16 on load.  a_km == false: A is M x K with K contiguous (row
+// stride lda), and outT must be set (the G epilogue): out = bf16(sums) as binary64 (for
+// an e4m3 A: bf16(2^row_exp[i] sums)), outT (N x M, ld ldt) the same bfloat16 values (for
+// an e4m3 A: times 2^row_exp[i] once more), colsq (if set) [bf16_gemm_row_groups(M, N)][N]
+// partial column sums of squares of out.  a_km == true: A(i, k) = A[k * lda + i] and
+// outT must be nullptr: out = the binary32 sums as binary64.
 int64_t bf16_gemm_row_groups(int64_t M, int64_t N);
-hipError_t gemm_bf16(int64_t M, int64_t N, int64_t K, const uint16_t* A, int64_t lda, bool a_km,
-                     const uint16_t* B, int64_t ldb, double* out, int64_t ldo, uint16_t* outT,
-                     int64_t ldt, double* colsq, hipStream_t s);
+hipError_t gemm_bf16(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, bool a_km,
+                     bool a_fp8, const int32_t* row_exp, const uint16_t* B, int64_t ldb, double* out,
+                     int64_t ldo, uint16_t* outT, int64_t ldt, double* colsq, hipStream_t s);
 
 // panel.hip -- small dense kernels of the block loop
 hipError_t launch_chol_inv(const double* gram, int b, double tau, double* R, double* Rinv,

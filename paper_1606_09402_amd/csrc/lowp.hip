@@ -15,6 +15,8 @@
 //     transposed on its way into LDS, so A_q is never copied).  Two epilogues: G (FP64
 //     dequantised BF16 rounding + the transposed BF16 copy + column sums of squares) and
 //     H (FP64).
+#include <type_traits>
+
 #include "kernels.h"
 
 namespace qb {
@@ -63,6 +65,29 @@ QB_DEV uint16_t f64_to_bf16_rne(double x) {
 
 QB_DEV double bf16_to_f64(uint16_t h) {
     return static_cast<double>(__uint_as_float(static_cast<uint32_t>(h) << 16));
+}
+
+// OCP e4m3fn byte -> bfloat16 bits (exact: 3 significand bits, exponents 2^-9 .. 2^8).
+// Normal bytes keep their significand and rebias the exponent (bias 7 -> 127); the
+// subnormals m 2^-9 (m = 1..7) are renormalised.  The NaN byte does not occur in data.
+QB_DEV uint32_t e4m3_to_bf16(uint32_t v) {
+    const uint32_t s = (v & 0x80u) << 8;
+    const uint32_t mag = v & 0x7Fu, m = v & 7u;
+    const uint32_t normal = (mag << 4) + 0x3C00u;   // (e + 120) << 7 | m << 4
+    // m 2^-9: the binary32 value m with its exponent lowered by 9, truncated to 16 bits
+    const uint32_t sub = (__float_as_uint(static_cast<float>(m)) - (9u << 23)) >> 16;
+    return s | (mag >= 8u ? normal : (m != 0u ? sub : 0u));
+}
+
+// 8 e4m3 bytes -> 8 bfloat16 values (same order)
+QB_DEV uint4 e4m3x8_to_bf16x8(uint2 q) {
+    uint32_t h[8];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        h[e] = e4m3_to_bf16((q.x >> (8 * e)) & 0xFFu);
+        h[e + 4] = e4m3_to_bf16((q.y >> (8 * e)) & 0xFFu);
+    }
+    return uint4{h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16)};
 }
 
 // binary32 -> bfloat16 bits, round to nearest, ties to even (finite inputs)
@@ -131,12 +156,36 @@ sumsq_bf16_partial(const uint16_t* __restrict__ a, int64_t m, int64_t n, int64_t
     if (threadIdx.x == 0) partial[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
 }
 
+// Partial sums of squares (FP64) of an e4m3 matrix with power-of-two row scales:
+// (2^e_i v)^2 is exact in FP64.
+__global__ void __launch_bounds__(256)
+sumsq_fp8_partial(const uint8_t* __restrict__ a, int64_t m, int64_t n, int64_t lda,
+                  const int32_t* __restrict__ row_exp, double* __restrict__ partial) {
+    __shared__ double sh[4];
+    double acc = 0.0;
+    for (int64_t i = blockIdx.x; i < m; i += gridDim.x) {
+        const uint8_t* row = a + i * lda;
+        double r = 0.0;
+        for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
+            const double v = static_cast<double>(__uint_as_float(e4m3_to_bf16(row[j]) << 16));
+            r += v * v;
+        }
+        acc += ldexp(r, 2 * row_exp[i]);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
 // ------------------------------------------------------------------ BF16 GEMM
 
 struct Bf16GemmArgs {
     int64_t M, N, K;
     const uint16_t* A;   // a_km == 0: M x K, element (i, k) at A[i * lda + k]
                          // a_km == 1: element (i, k) at A[k * lda + i]
+                         // (bytes of e4m3 values when the kernel reads an FP8 A)
     int64_t lda;
     const uint16_t* B;   // N x K, element (j, k) at B[j * ldb + k]
     int64_t ldb;
@@ -145,6 +194,7 @@ struct Bf16GemmArgs {
     uint16_t* outT;      // G epilogue: N x M BF16 copy, row stride ldt
     int64_t ldt;
     double* colsq;       // G epilogue: [tiles_m][N] column sums of squares
+    const int32_t* row_exp;  // G epilogue of an FP8 A: output row i scaled by 2^row_exp[i]
     int tiles_m, tiles_n;
     int vec;             // 16-byte aligned operands with row strides divisible by 8
 };
@@ -167,7 +217,7 @@ QB_DEV int lds_off(int row, int chunk) {
 QB_DEV uint32_t pack_lo(uint32_t a, uint32_t b) { return (a & 0xFFFFu) | (b << 16); }
 QB_DEV uint32_t pack_hi(uint32_t a, uint32_t b) { return (a >> 16) | (b & 0xFFFF0000u); }
 
-template <int BM, int BN, int BK, int WM, int WN, int EPI, bool AKM>
+template <int BM, int BN, int BK, int WM, int WN, int EPI, bool AKM, bool AF8>
 __global__ void __launch_bounds__(64 * WM * WN, (64 * WM * WN >= 512 ? 1 : 2))
 gemm_bf16_kernel(const Bf16GemmArgs g) {
     constexpr int NT = 64 * WM * WN;
@@ -176,7 +226,10 @@ gemm_bf16_kernel(const Bf16GemmArgs g) {
     constexpr int CPR = BK / 8;                         // 16-byte chunks per tile row
     constexpr int PA = BM * CPR / NT, PB = BN * CPR / NT;
     static_assert(BM * CPR % NT == 0 && BN * CPR % NT == 0 && BK % 16 == 0, "tile shape");
-    static_assert(!AKM || ((BM / 8) * (BK / 4) == NT && PA == 4), "K-major A: one k-quad x m-octet per thread");
+    // K-major A: the BM/8 x BK/4 blocks of 4 (k) x 8 (m) elements are dealt out to the
+    // threads, PA/4 blocks each
+    static_assert(!AKM || ((BM / 8) * (BK / 4) % NT == 0 && PA == 4 * ((BM / 8) * (BK / 4) / NT)),
+                  "K-major A: whole 4 x 8 blocks per thread");
     __shared__ __align__(16) uint16_t As[2][BM * PITCH];
     __shared__ __align__(16) uint16_t Bs[2][BN * PITCH];
     __shared__ double red[WM][BN];
@@ -184,7 +237,8 @@ gemm_bf16_kernel(const Bf16GemmArgs g) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave / WN, wn = wave % WN;
     const int logical = xcd_remap(blockIdx.x, gridDim.x);
-    const int tile_m = logical / g.tiles_n, tile_n = logical % g.tiles_n;
+    int tile_m, tile_n;
+    group_tiles(logical, g.tiles_m, g.tiles_n, tile_m, tile_n);
     const int64_t m0 = static_cast<int64_t>(tile_m) * BM, n0 = static_cast<int64_t>(tile_n) * BN;
     const bool fast = g.vec && m0 + BM <= g.M && n0 + BN <= g.N;
 
@@ -194,9 +248,14 @@ gemm_bf16_kernel(const Bf16GemmArgs g) {
 #pragma unroll
         for (int b = 0; b < FN; ++b) acc[a][b] = f32x16{};
 
-    // K-major A: thread owns rows k0 + 4 kq .. + 3 and columns m0 + 8 mo .. + 7
-    const int mo = tid % (BM / 8), kq = tid / (BM / 8);
-    uint4 ra[PA], rb[PB];
+    // K-major A: block u of this thread covers rows k0 + 4 kq(u) .. + 3 and columns
+    // m0 + 8 mo(u) .. + 7
+    auto blk_mo = [&](int u) { return (tid + u * NT) % (BM / 8); };
+    auto blk_kq = [&](int u) { return (tid + u * NT) / (BM / 8); };
+    // staging registers: 8 elements per entry (bfloat16, or e4m3 bytes widened at the store)
+    using RawA = typename std::conditional<AF8, uint2, uint4>::type;
+    RawA ra[PA];
+    uint4 rb[PB];
     auto gather8 = [](const uint16_t* p, int64_t lim) {   // 8 elements, the first lim valid
         uint16_t t[8];
 #pragma unroll
@@ -204,28 +263,43 @@ gemm_bf16_kernel(const Bf16GemmArgs g) {
         return uint4{t[0] | (uint32_t(t[1]) << 16), t[2] | (uint32_t(t[3]) << 16),
                      t[4] | (uint32_t(t[5]) << 16), t[6] | (uint32_t(t[7]) << 16)};
     };
+    const uint8_t* A8 = reinterpret_cast<const uint8_t*>(g.A);
+    auto gather8_f8 = [](const uint8_t* p, int64_t lim) {   // 8 e4m3 bytes, the first lim valid
+        uint32_t t[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) t[e] = e < lim ? p[e] : 0u;
+        return uint2{t[0] | (t[1] << 8) | (t[2] << 16) | (t[3] << 24),
+                     t[4] | (t[5] << 8) | (t[6] << 16) | (t[7] << 24)};
+    };
+    // 8 consecutive elements of A starting at element offset off (first lim valid)
+    auto loadA8 = [&](int64_t off, bool full, int64_t lim) -> RawA {
+        if constexpr (AF8) {
+            return full ? *reinterpret_cast<const uint2*>(A8 + off) : gather8_f8(A8 + off, lim);
+        } else {
+            return full ? *reinterpret_cast<const uint4*>(g.A + off) : gather8(g.A + off, lim);
+        }
+    };
+    auto widen = [](const RawA& r) -> uint4 {
+        if constexpr (AF8) return e4m3x8_to_bf16x8(r);
+        else return r;
+    };
     auto load = [&](int64_t k0) {
         const bool kin = k0 + BK <= g.K;
         if constexpr (AKM) {
 #pragma unroll
             for (int q = 0; q < PA; ++q) {
-                const int64_t gk = k0 + 4 * kq + q, gi = m0 + 8 * mo;
-                if (fast && kin) {
-                    ra[q] = *reinterpret_cast<const uint4*>(g.A + gk * g.lda + gi);
-                } else {
-                    const int64_t lim = gk < g.K ? g.M - gi : 0;
-                    ra[q] = gather8(g.A + (gk < g.K ? gk : 0) * g.lda + gi, lim);
-                }
+                const int64_t gk = k0 + 4 * blk_kq(q / 4) + q % 4, gi = m0 + 8 * blk_mo(q / 4);
+                const bool full = fast && kin;
+                const int64_t lim = gk < g.K ? g.M - gi : 0;
+                ra[q] = loadA8((full || gk < g.K ? gk : 0) * g.lda + gi, full, lim);
             }
         } else {
 #pragma unroll
             for (int p = 0; p < PA; ++p) {
                 const int c = tid + p * NT, row = c / CPR, col = (c % CPR) * 8;
                 const int64_t gi = m0 + row, gk = k0 + col;
-                if (fast && kin)
-                    ra[p] = *reinterpret_cast<const uint4*>(g.A + gi * g.lda + gk);
-                else
-                    ra[p] = gather8(g.A + (gi < g.M ? gi : 0) * g.lda + gk, gi < g.M ? g.K - gk : 0);
+                const bool full = fast && kin;
+                ra[p] = loadA8((full || gi < g.M ? gi : 0) * g.lda + gk, full, gi < g.M ? g.K - gk : 0);
             }
         }
 #pragma unroll
@@ -240,24 +314,30 @@ gemm_bf16_kernel(const Bf16GemmArgs g) {
     };
     auto store = [&](int st) {
         if constexpr (AKM) {
-            // transpose the 4 x 8 block: row 8 mo + e of the tile gets k 4 kq .. 4 kq + 3
-            const uint32_t w0[4] = {ra[0].x, ra[0].y, ra[0].z, ra[0].w};
-            const uint32_t w1[4] = {ra[1].x, ra[1].y, ra[1].z, ra[1].w};
-            const uint32_t w2[4] = {ra[2].x, ra[2].y, ra[2].z, ra[2].w};
-            const uint32_t w3[4] = {ra[3].x, ra[3].y, ra[3].z, ra[3].w};
+            // transpose each 4 x 8 block: row 8 mo + e of the tile gets k 4 kq .. 4 kq + 3
 #pragma unroll
-            for (int h = 0; h < 4; ++h) {
-                const int r_even = 8 * mo + 2 * h;
-                const uint2 ev{pack_lo(w0[h], w1[h]), pack_lo(w2[h], w3[h])};
-                const uint2 od{pack_hi(w0[h], w1[h]), pack_hi(w2[h], w3[h])};
-                *reinterpret_cast<uint2*>(&As[st][lds_off<BK>(r_even, kq >> 1) + 4 * (kq & 1)]) = ev;
-                *reinterpret_cast<uint2*>(&As[st][lds_off<BK>(r_even + 1, kq >> 1) + 4 * (kq & 1)]) = od;
+            for (int u = 0; u < PA / 4; ++u) {
+                const int mo = blk_mo(u), kq = blk_kq(u);
+                const uint4 c0 = widen(ra[4 * u]), c1 = widen(ra[4 * u + 1]), c2 = widen(ra[4 * u + 2]),
+                            c3 = widen(ra[4 * u + 3]);
+                const uint32_t w0[4] = {c0.x, c0.y, c0.z, c0.w};
+                const uint32_t w1[4] = {c1.x, c1.y, c1.z, c1.w};
+                const uint32_t w2[4] = {c2.x, c2.y, c2.z, c2.w};
+                const uint32_t w3[4] = {c3.x, c3.y, c3.z, c3.w};
+#pragma unroll
+                for (int h = 0; h < 4; ++h) {
+                    const int r_even = 8 * mo + 2 * h;
+                    const uint2 ev{pack_lo(w0[h], w1[h]), pack_lo(w2[h], w3[h])};
+                    const uint2 od{pack_hi(w0[h], w1[h]), pack_hi(w2[h], w3[h])};
+                    *reinterpret_cast<uint2*>(&As[st][lds_off<BK>(r_even, kq >> 1) + 4 * (kq & 1)]) = ev;
+                    *reinterpret_cast<uint2*>(&As[st][lds_off<BK>(r_even + 1, kq >> 1) + 4 * (kq & 1)]) = od;
+                }
             }
         } else {
 #pragma unroll
             for (int p = 0; p < PA; ++p) {
                 const int c = tid + p * NT, row = c / CPR, ch = c % CPR;
-                *reinterpret_cast<uint4*>(&As[st][lds_off<BK>(row, ch)]) = ra[p];
+                *reinterpret_cast<uint4*>(&As[st][lds_off<BK>(row, ch)]) = widen(ra[p]);
             }
         }
 #pragma unroll
@@ -316,6 +396,16 @@ gemm_bf16_kernel(const Bf16GemmArgs g) {
                 if (i < g.M && j < g.N) {
                     if (EPI == 0) {
                         g.out[i * g.ldo + j] = static_cast<double>(acc[fm][fn][r]);
+                    } else if (AF8) {
+                        // G_q = bf16(2^e_i (A8 Omega_q)(i, j)); the H operand carries the row
+                        // scale once more, 2^e_i G_q, so that A8^T (that) = A_q^T G_q
+                        const int e = g.row_exp[i];
+                        const uint16_t h = f32_to_bf16_rne(ldexpf(acc[fm][fn][r], e));
+                        const double v = bf16_to_f64(h);
+                        g.out[i * g.ldo + j] = v;
+                        g.outT[j * g.ldt + i] =
+                            static_cast<uint16_t>(__float_as_uint(ldexpf(__uint_as_float(uint32_t(h) << 16), e)) >> 16);
+                        csq[fn] += v * v;
                     } else {
                         const uint16_t h = f32_to_bf16_rne(acc[fm][fn][r]);
                         const double v = bf16_to_f64(h);
@@ -353,6 +443,16 @@ hipError_t launch_quant_transpose_omega(double* om, int64_t n, int64_t w, uint16
     return hipGetLastError();
 }
 
+hipError_t launch_sumsq_fp8(const uint8_t* a, const int32_t* row_exp, int64_t m, int64_t n,
+                            int64_t lda, double* scratch, double* out, hipStream_t s) {
+    const int64_t g = m < 1024 ? m : 1024;
+    hipLaunchKernelGGL(sumsq_fp8_partial, dim3(static_cast<unsigned>(g)), dim3(256), 0, s, a, m, n, lda,
+                       row_exp, scratch);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_sum_vector(scratch, g, out, s);
+}
+
 hipError_t launch_sumsq_bf16(const uint16_t* a, int64_t m, int64_t n, int64_t lda,
                              double* scratch, double* out, hipStream_t s) {
     const int64_t g = m < 1024 ? m : 1024;
@@ -378,17 +478,20 @@ int64_t bf16_gemm_row_groups(int64_t M, int64_t N) {
     return cdiv(M, use_big(M, N) ? kBigTile : kSmallTile);
 }
 
-hipError_t gemm_bf16(int64_t M, int64_t N, int64_t K, const uint16_t* A, int64_t lda, bool a_km,
-                     const uint16_t* B, int64_t ldb, double* out, int64_t ldo, uint16_t* outT,
-                     int64_t ldt, double* colsq, hipStream_t s) {
+hipError_t gemm_bf16(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, bool a_km,
+                     bool a_fp8, const int32_t* row_exp, const uint16_t* B, int64_t ldb, double* out,
+                     int64_t ldo, uint16_t* outT, int64_t ldt, double* colsq, hipStream_t s) {
     if (M <= 0 || N <= 0) return hipSuccess;
     // the two products of the sketch: G (K-contiguous A, G epilogue) and H (K-major A,
     // FP64 epilogue)
     if (a_km == (outT != nullptr)) return hipErrorInvalidValue;
+    if (a_fp8 && !a_km && row_exp == nullptr) return hipErrorInvalidValue;
     Bf16GemmArgs g{};
-    g.M = M; g.N = N; g.K = K; g.A = A; g.lda = lda; g.B = B; g.ldb = ldb;
-    g.out = out; g.ldo = ldo; g.outT = outT; g.ldt = ldt; g.colsq = colsq;
-    g.vec = (reinterpret_cast<uintptr_t>(A) % 16 == 0) && (reinterpret_cast<uintptr_t>(B) % 16 == 0) &&
+    g.M = M; g.N = N; g.K = K; g.A = static_cast<const uint16_t*>(A); g.lda = lda; g.B = B; g.ldb = ldb;
+    g.out = out; g.ldo = ldo; g.outT = outT; g.ldt = ldt; g.colsq = colsq; g.row_exp = row_exp;
+    // 8-element chunks: 16 bytes of bfloat16 or 8 bytes of e4m3
+    const uintptr_t a_align = a_fp8 ? 8 : 16;
+    g.vec = (reinterpret_cast<uintptr_t>(A) % a_align == 0) && (reinterpret_cast<uintptr_t>(B) % 16 == 0) &&
             (lda % 8 == 0) && (ldb % 8 == 0);
     const bool big = use_big(M, N);
     const int t = big ? kBigTile : kSmallTile;
@@ -396,15 +499,23 @@ hipError_t gemm_bf16(int64_t M, int64_t N, int64_t K, const uint16_t* A, int64_t
     g.tiles_n = static_cast<int>(cdiv(N, t));
     dim3 grid(static_cast<unsigned>(static_cast<int64_t>(g.tiles_m) * g.tiles_n));
     if (big) {
-        if (a_km)
-            hipLaunchKernelGGL((gemm_bf16_kernel<256, 256, 64, 2, 4, 0, true>), grid, dim3(512), 0, s, g);
+        if (a_km && a_fp8)
+            hipLaunchKernelGGL((gemm_bf16_kernel<256, 256, 64, 2, 4, 0, true, true>), grid, dim3(512), 0, s, g);
+        else if (a_km)
+            hipLaunchKernelGGL((gemm_bf16_kernel<256, 256, 64, 2, 4, 0, true, false>), grid, dim3(512), 0, s, g);
+        else if (a_fp8)
+            hipLaunchKernelGGL((gemm_bf16_kernel<256, 256, 64, 2, 4, 1, false, true>), grid, dim3(512), 0, s, g);
         else
-            hipLaunchKernelGGL((gemm_bf16_kernel<256, 256, 64, 2, 4, 1, false>), grid, dim3(512), 0, s, g);
+            hipLaunchKernelGGL((gemm_bf16_kernel<256, 256, 64, 2, 4, 1, false, false>), grid, dim3(512), 0, s, g);
     } else {
-        if (a_km)
-            hipLaunchKernelGGL((gemm_bf16_kernel<128, 128, 64, 2, 2, 0, true>), grid, dim3(256), 0, s, g);
+        if (a_km && a_fp8)
+            hipLaunchKernelGGL((gemm_bf16_kernel<128, 128, 64, 2, 2, 0, true, true>), grid, dim3(256), 0, s, g);
+        else if (a_km)
+            hipLaunchKernelGGL((gemm_bf16_kernel<128, 128, 64, 2, 2, 0, true, false>), grid, dim3(256), 0, s, g);
+        else if (a_fp8)
+            hipLaunchKernelGGL((gemm_bf16_kernel<128, 128, 64, 2, 2, 1, false, true>), grid, dim3(256), 0, s, g);
         else
-            hipLaunchKernelGGL((gemm_bf16_kernel<128, 128, 64, 2, 2, 1, false>), grid, dim3(256), 0, s, g);
+            hipLaunchKernelGGL((gemm_bf16_kernel<128, 128, 64, 2, 2, 1, false, false>), grid, dim3(256), 0, s, g);
     }
     return hipGetLastError();
 }

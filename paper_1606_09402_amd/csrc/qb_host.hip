@@ -80,7 +80,7 @@ int64_t next_chunk(const qb_params* p, int64_t cap, int64_t k, int64_t w_prev, d
 Layout make_layout(int algo, int sparse, int dtype, int64_t m, int64_t n, int64_t nnz,
                    const qb_params* p) {
     Layout L{};
-    const bool lowp = dtype == QB_BF16;
+    const bool lowp = dtype == QB_BF16 || dtype == QB_FP8E4M3;
     const int64_t b = p->b;
     const int64_t lmax = p->l_max;
     const int64_t lt = algo == QB_ALGO_FP ? chunk_width(p) : b;   // EI: one block at a time
@@ -151,6 +151,8 @@ struct Op {
     int dtype;
     const double* a;
     const uint16_t* aq;   // bfloat16 A (dtype QB_BF16)
+    const uint8_t* a8;    // e4m3 A (dtype QB_FP8E4M3) and its row exponents
+    const int32_t* row_exp;
     int64_t lda;
     const int64_t* rowptr;
     const int32_t* colind;
@@ -252,9 +254,10 @@ int apply_At(const Ctx& x, const double* G, int64_t ldg, double* H, int64_t ldh,
     return QB_OK;
 }
 
-// The bfloat16 sketch of a chunk: Omega (n x w, ld w, binary64 on entry) is replaced by
-// its bfloat16 rounding Omega_q (and copied transposed in bfloat16), G = bf16(A_q Omega_q)
-// with its column sums of squares, H = A_q^T G_q reading A_q in place.
+// The low-precision sketch of a chunk: Omega (n x w, ld w, binary64 on entry) is replaced
+// by its bfloat16 rounding Omega_q (and copied transposed in bfloat16), G = bf16(A_q Omega_q)
+// with its column sums of squares, H = A_q^T G_q reading A_q in place (bfloat16, or e4m3
+// with power-of-two row scales).
 int sketch_bf16(const Ctx& x, double* Om, double* G, double* H, int64_t w, double* gnorm2,
                 bool time_phases) {
     const Op& A = x.A;
@@ -263,11 +266,14 @@ int sketch_bf16(const Ctx& x, double* Om, double* G, double* H, int64_t w, doubl
     double* gpart = x.at<double>(x.L.gpart);
     QB_HIP(launch_quant_transpose_omega(Om, A.n, w, omt, x.L.ldn16, x.s));
     if (time_phases) x.tm->mark(2);
-    QB_HIP(gemm_bf16(A.m, w, A.n, A.aq, A.lda, false, omt, x.L.ldn16, G, w, gqt, x.L.ldm16, gpart,
-                     x.s));
+    const bool f8 = A.dtype == QB_FP8E4M3;
+    const void* a = f8 ? static_cast<const void*>(A.a8) : static_cast<const void*>(A.aq);
+    QB_HIP(gemm_bf16(A.m, w, A.n, a, A.lda, false, f8, A.row_exp, omt, x.L.ldn16, G, w, gqt, x.L.ldm16,
+                     gpart, x.s));
     QB_HIP(launch_sum_partials(gpart, bf16_gemm_row_groups(A.m, w), w, w, gnorm2, x.s));
     if (time_phases) x.tm->mark(3);
-    QB_HIP(gemm_bf16(A.n, w, A.m, A.aq, A.lda, true, gqt, x.L.ldm16, H, w, nullptr, 0, nullptr, x.s));
+    QB_HIP(gemm_bf16(A.n, w, A.m, a, A.lda, true, f8, nullptr, gqt, x.L.ldm16, H, w, nullptr, 0, nullptr,
+                     x.s));
     return QB_OK;
 }
 
@@ -507,6 +513,8 @@ int run(int algo, Op& A, const qb_params* p, double* Q, int64_t ldq, double* B, 
     tm.mark(0);
     if (A.dtype == QB_BF16) {
         QB_HIP(launch_sumsq_bf16(A.aq, m, n, A.lda, red, scal, s));
+    } else if (A.dtype == QB_FP8E4M3) {
+        QB_HIP(launch_sumsq_fp8(A.a8, A.row_exp, m, n, A.lda, red, scal, s));
     } else if (!A.sparse) {
         QB_HIP(launch_sumsq_dense(A.a, m, n, A.lda, red, scal, s));
     } else {
@@ -553,7 +561,7 @@ int run(int algo, Op& A, const qb_params* p, double* Q, int64_t ldq, double* B, 
                     e_chunk_start = E;
                     tm.mark(1);
                     QB_HIP(launch_gauss_fill(p->seed, 0, 0, 0, chunk_lo, n, w, Om, w, s));
-                    if (A.dtype == QB_BF16) {
+                    if (A.dtype == QB_BF16 || A.dtype == QB_FP8E4M3) {
                         if (int e = sketch_bf16(x, Om, G, H, w, gnorm2, true)) return inf->status = e;
                     } else {
                         tm.mark(2);
@@ -632,10 +640,14 @@ int run(int algo, Op& A, const qb_params* p, double* Q, int64_t ldq, double* B, 
 Op dense_op(const qb_dense* A) {
     Op o{};
     o.m = A->m; o.n = A->n; o.sparse = false; o.dtype = A->dtype;
-    if (A->dtype == QB_BF16)
+    if (A->dtype == QB_BF16) {
         o.aq = static_cast<const uint16_t*>(A->a);
-    else
+    } else if (A->dtype == QB_FP8E4M3) {
+        o.a8 = static_cast<const uint8_t*>(A->a);
+        o.row_exp = A->row_exp;
+    } else {
         o.a = static_cast<const double*>(A->a);
+    }
     o.lda = A->lda;
     return o;
 }
@@ -649,7 +661,8 @@ Op csr_op(const qb_csr* A) {
 
 int check_dense(const qb_dense* A) {
     if (A == nullptr || A->a == nullptr || A->m < 1 || A->n < 1 || A->lda < A->n) return QB_ERR_ARG;
-    if (A->dtype != QB_F64 && A->dtype != QB_BF16) return QB_ERR_UNSUPPORTED;
+    if (A->dtype != QB_F64 && A->dtype != QB_BF16 && A->dtype != QB_FP8E4M3) return QB_ERR_UNSUPPORTED;
+    if (A->dtype == QB_FP8E4M3 && A->row_exp == nullptr) return QB_ERR_ARG;
     return QB_OK;
 }
 
@@ -676,7 +689,8 @@ size_t qb_workspace_bytes(int algo, int sparse, int64_t m, int64_t n, int64_t nn
 
 size_t qb_dense_workspace_bytes(int algo, const qb_dense* A, const qb_params* p) {
     if ((algo != QB_ALGO_FP && algo != QB_ALGO_EI) || A == nullptr || A->m < 1 || A->n < 1) return 0;
-    if (A->dtype != QB_F64 && !(A->dtype == QB_BF16 && algo == QB_ALGO_FP)) return 0;
+    const bool lowp = A->dtype == QB_BF16 || A->dtype == QB_FP8E4M3;
+    if (A->dtype != QB_F64 && !(lowp && algo == QB_ALGO_FP)) return 0;
     if (check_params(p, A->m, A->n) != QB_OK) return 0;
     return make_layout(algo, 0, A->dtype, A->m, A->n, 0, p).total;
 }
@@ -742,6 +756,9 @@ int qb_sumsq_dense(const qb_dense* A, double* out_host, void* ws, hipStream_t st
     if (A->dtype == QB_BF16)
         QB_HIP(launch_sumsq_bf16(static_cast<const uint16_t*>(A->a), A->m, A->n, A->lda, scratch, res,
                                  stream));
+    else if (A->dtype == QB_FP8E4M3)
+        QB_HIP(launch_sumsq_fp8(static_cast<const uint8_t*>(A->a), A->row_exp, A->m, A->n, A->lda, scratch,
+                                res, stream));
     else
         QB_HIP(launch_sumsq_dense(static_cast<const double*>(A->a), A->m, A->n, A->lda, scratch, res,
                                   stream));
@@ -777,10 +794,10 @@ int qb_sketch_dense(const qb_dense* A, uint64_t seed, int64_t col0, int64_t l, d
 // Workspace of qb_sketch_lowp: the randQB_FP layout with one chunk of l columns (the
 // sketch buffers it uses are Omega_q^T, G_q^T, A_q^T and the column-norm partials).
 static bool sketch_lowp_layout(const qb_dense* A, int64_t l, Layout* L) {
-    if (check_dense(A) != QB_OK || A->dtype != QB_BF16 || l < 1) return false;
+    if (check_dense(A) != QB_OK || (A->dtype != QB_BF16 && A->dtype != QB_FP8E4M3) || l < 1) return false;
     qb_params p{};
     p.tol_rel = 0.0; p.b = 1; p.l_max = l; p.l_tilde = l;
-    *L = make_layout(QB_ALGO_FP, 0, QB_BF16, A->m, A->n, 0, &p);
+    *L = make_layout(QB_ALGO_FP, 0, A->dtype, A->m, A->n, 0, &p);
     return true;
 }
 
@@ -792,7 +809,7 @@ size_t qb_sketch_lowp_bytes(const qb_dense* A, int64_t l) {
 int qb_sketch_lowp(const qb_dense* A, uint64_t seed, int64_t col0, int64_t l, double* om, double* g,
                    double* h, void* ws, size_t ws_bytes, hipStream_t stream) {
     if (int st = check_dense(A)) return st;
-    if (A->dtype != QB_BF16) return QB_ERR_UNSUPPORTED;
+    if (A->dtype != QB_BF16 && A->dtype != QB_FP8E4M3) return QB_ERR_UNSUPPORTED;
     if (l < 1 || col0 < 0 || om == nullptr || g == nullptr || h == nullptr || ws == nullptr)
         return QB_ERR_ARG;
     if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return QB_ERR_ARG;

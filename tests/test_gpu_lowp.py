@@ -226,3 +226,58 @@ def test_fp_bf16_full_size(qb):
     assert abs(direct - res.E) <= 0.05 * eps2
     assert true_rel <= wl.tol
     assert opt - 2 <= res.rank <= int(1.3 * opt) + wl.b
+
+
+# ------------------------------------------------------------------ e4m3 storage
+#
+# A stored in OCP e4m3fn with a power-of-two scale per row: A_q(i, j) = 2^e_i e4m3(...).
+# Every such value is a bfloat16 value, so the oracle's precision form applies to A_q
+# unchanged and the tolerances above carry over.  The storage error (2.6e-2 of ||A||
+# for these matrices) lies above tol 1e-2; the method is run at tol 5e-2, where the true
+# error against the binary64 matrix still meets tol.
+
+
+def _fp8_pair(m, n, kind, seed):
+    A64 = W.lowrank_dense(m, n, W.sigma_law(kind, min(m, n)), seed)
+    A8, e, Aq = W.to_e4m3_rows(A64)
+    return A64, A8, e, Aq
+
+
+@pytest.mark.parametrize("m,n", [(1000, 800), (3, 7001), (4097, 33)])
+def test_sumsq_fp8(qb, m, n):
+    _log(f"sumsq e4m3 {m}x{n}")
+    _, A8, e, Aq = _fp8_pair(m, n, "poly1.5", 31)
+    got = qb.qb_sumsq_dense(A8.cuda(), row_exp=e.cuda())
+    want = R.sumsq(Aq.numpy())
+    assert abs(got - want) <= 1e-14 * want
+
+
+@pytest.mark.parametrize("m,n,l,col0", [(700, 530, 200, 64), (1024, 768, 256, 0), (4096, 256, 128, 128)])
+def test_sketch_fp8(qb, m, n, l, col0):
+    _log(f"sketch e4m3 {m}x{n} l={l} col0={col0}")
+    _, A8, e, Aq = _fp8_pair(m, n, "poly1.5", 32)
+    om, g, h = qb.qb_sketch_lowp(A8.cuda(), SEED, col0, l, row_exp=e.cuda())
+    torch.cuda.synchronize()
+    A = Aq.numpy()
+    om, g, h = om.cpu().numpy(), g.cpu().numpy(), h.cpu().numpy()
+    om_ref = OL.round_bf16(ORNG.gaussian_matrix(SEED, n, l, 0, col0))
+    assert np.array_equal(om.view(np.int64), om_ref.view(np.int64))
+    assert OL.is_bf16(g)
+    exact = A @ om_ref
+    S = np.abs(A) @ np.abs(om_ref)
+    gam = _gamma(n)
+    assert np.all(np.abs(g - exact) <= U16 * (np.abs(exact) + gam * S) + gam * S)
+    g_ora = OL.round_bf16(exact)
+    assert (g != g_ora).mean() <= 0.02
+    hh = A.T @ g
+    assert np.all(np.abs(h - hh) <= _gamma(m) * (np.abs(A).T @ np.abs(g)) + 1e-300)
+
+
+@pytest.mark.parametrize("m,n,b,l_tilde", [(1000, 700, 32, -1), (4096, 4096, 128, -1), (777, 1203, 20, 60)])
+def test_fp_fp8_vs_oracle(qb, m, n, b, l_tilde):
+    tol = 5e-2
+    _log(f"fp e4m3 {m}x{n} b={b} tol={tol} l_tilde={l_tilde}")
+    A64, A8, e, Aq = _fp8_pair(m, n, "poly1.5", 33)
+    ora = R.randqb_fp(Aq.numpy(), tol, b, SEED, l_tilde=l_tilde, precision="bf16")
+    res = qb.qb_fp_dense(A8.cuda(), tol, b, SEED, l_tilde=l_tilde, row_exp=e.cuda())
+    _check_method(res, ora, A64.cuda(), Aq.cuda(), tol, f"e4m3 {m}x{n}")

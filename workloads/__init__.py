@@ -216,6 +216,19 @@ def to_bf16(A: torch.Tensor) -> torch.Tensor:
     return A.to(torch.bfloat16).contiguous()
 
 
+def to_e4m3_rows(A: torch.Tensor):
+    """Storage of a float64 matrix in OCP e4m3fn with a power-of-two scale per row (input
+    preparation of the precision form): row i is divided by 2^e_i, e_i the smallest
+    exponent that brings its largest magnitude to at most 448, and converted by torch.
+    Returns (A8 float8_e4m3fn, row_exp int32, A_q float64 = the stored values)."""
+    amax = A.abs().amax(dim=1).clamp_min(1e-300)
+    e = torch.ceil(torch.log2(amax / 448.0)).to(torch.int32)
+    scale = torch.pow(2.0, -e.to(torch.float64))
+    A8 = (A * scale[:, None]).to(torch.float8_e4m3fn).contiguous()
+    Aq = A8.to(torch.float64) * torch.pow(2.0, e.to(torch.float64))[:, None]
+    return A8, e.contiguous(), Aq
+
+
 @dataclass
 class SparseWorkload:
     name: str
