@@ -72,6 +72,21 @@ hipError_t launch_fill_int(int* p, int n, int v, hipStream_t s);
 hipError_t launch_spmm_csr(const int64_t* rowptr, const int32_t* colind, const double* val,
                            int64_t m, const double* X, int64_t ldx, double* G, int64_t ldg,
                            int64_t w, hipStream_t s);
+// Load-balanced CSR product through a segment plan (rows split into segments of at most
+// 512 nonzeros, long rows reduced in segment order); built once per matrix per call.
+struct SpmmPlan {
+    int64_t rows, smax, wmax;
+    int64_t* seg_off;    // rows + 1: exclusive prefix of segments per row (last = total)
+    int64_t* mseg_off;   // rows + 1: exclusive prefix of the segments of multi-segment rows
+    int32_t* seg_row;    // smax: row of each segment
+    double* P;           // partial rows of multi-segment rows, wmax columns each
+};
+size_t spmm_plan_bytes(int64_t rows, int64_t nnz, int64_t wmax);
+hipError_t spmm_plan_build(const int64_t* rowptr, int64_t rows, int64_t nnz, int64_t wmax, char* ws,
+                           hipStream_t s, SpmmPlan* plan);
+hipError_t launch_spmm_plan(const SpmmPlan& plan, const int64_t* rowptr, const int32_t* colind,
+                            const double* val, const double* X, int64_t ldx, double* G, int64_t ldg,
+                            int64_t w, hipStream_t s);
 int64_t colsq_groups(int64_t rows);
 hipError_t launch_colsq_rowmajor(const double* Y, int64_t rows, int64_t w, int64_t ld,
                                  double* partial, hipStream_t s);

@@ -157,16 +157,28 @@ sumsq_bf16_partial(const uint16_t* __restrict__ a, int64_t m, int64_t n, int64_t
 }
 
 // Partial sums of squares (FP64) of an e4m3 matrix with power-of-two row scales:
-// (2^e_i v)^2 is exact in FP64.
+// (2^e_i v)^2 is exact in FP64.  8-byte loads when every row starts 8-byte aligned.
 __global__ void __launch_bounds__(256)
-sumsq_fp8_partial(const uint8_t* __restrict__ a, int64_t m, int64_t n, int64_t lda,
+sumsq_fp8_partial(const uint8_t* __restrict__ a, int64_t m, int64_t n, int64_t lda, int vec,
                   const int32_t* __restrict__ row_exp, double* __restrict__ partial) {
     __shared__ double sh[4];
     double acc = 0.0;
+    const int64_t nv = vec ? n / 8 : 0;
     for (int64_t i = blockIdx.x; i < m; i += gridDim.x) {
         const uint8_t* row = a + i * lda;
         double r = 0.0;
-        for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
+        for (int64_t c = threadIdx.x; c < nv; c += blockDim.x) {
+            const uint4 h = e4m3x8_to_bf16x8(*reinterpret_cast<const uint2*>(row + 8 * c));
+            const uint32_t w[4] = {h.x, h.y, h.z, h.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const double lo = static_cast<double>(__uint_as_float(w[e] << 16));
+                const double hi = static_cast<double>(__uint_as_float(w[e] & 0xFFFF0000u));
+                r += lo * lo;
+                r += hi * hi;
+            }
+        }
+        for (int64_t j = 8 * nv + threadIdx.x; j < n; j += blockDim.x) {
             const double v = static_cast<double>(__uint_as_float(e4m3_to_bf16(row[j]) << 16));
             r += v * v;
         }
@@ -446,7 +458,8 @@ hipError_t launch_quant_transpose_omega(double* om, int64_t n, int64_t w, uint16
 hipError_t launch_sumsq_fp8(const uint8_t* a, const int32_t* row_exp, int64_t m, int64_t n,
                             int64_t lda, double* scratch, double* out, hipStream_t s) {
     const int64_t g = m < 1024 ? m : 1024;
-    hipLaunchKernelGGL(sumsq_fp8_partial, dim3(static_cast<unsigned>(g)), dim3(256), 0, s, a, m, n, lda,
+    const int vec = (reinterpret_cast<uintptr_t>(a) % 8 == 0) && (lda % 8 == 0);
+    hipLaunchKernelGGL(sumsq_fp8_partial, dim3(static_cast<unsigned>(g)), dim3(256), 0, s, a, m, n, lda, vec,
                        row_exp, scratch);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -35,7 +35,7 @@ size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
 struct Layout {
     size_t red, scal, om, g, h, gpart, gnorm2, y, x2, s, w, z, d, gram, r1, r1i, rt, rti, ri, rii, tau,
-        rowsq_part, rowsq, info, flags, split, csc, omt, gqt, total;
+        rowsq_part, rowsq, info, flags, split, csc, plan_a, plan_t, omt, gqt, total;
     int64_t lt, split_elems, gpart_groups;
     int64_t ldm16, ldn16;   // row strides (elements) of the bfloat16 copies: m, n rounded to 8
 };
@@ -132,6 +132,9 @@ Layout make_layout(int algo, int sparse, int dtype, int64_t m, int64_t n, int64_
     L.flags = take(sizeof(int) * 8);
     L.split = take(sizeof(double) * L.split_elems);
     L.csc = sparse ? take(csc_layout(m, n, nnz).total) : take(0);
+    // segment plans of CSR(A) and CSR(A^T) for the balanced SpMM (widest product: l~ or b)
+    L.plan_a = sparse ? take(spmm_plan_bytes(m, nnz, lt)) : take(0);
+    L.plan_t = sparse ? take(spmm_plan_bytes(n, nnz, lt)) : take(0);
     // bfloat16 form: Omega_q^T (l~ x n) and G_q^T (l~ x m), rows padded to multiples of 8
     // elements so that every row starts 16-byte aligned
     L.ldm16 = round_up(m, 8);
@@ -161,6 +164,7 @@ struct Op {
     const int64_t* t_ptr;
     const int32_t* t_col;
     const double* t_val;
+    SpmmPlan plan_a, plan_t;   // segment plans of CSR(A) and CSR(A^T)
 };
 
 struct Timer {
@@ -233,7 +237,7 @@ int apply_A(const Ctx& x, const double* X, int64_t ldx, double* G, int64_t ldg, 
         d.colsq_groups = &groups;
         QB_HIP(gemm_f64(d, x.s));
     } else {
-        QB_HIP(launch_spmm_csr(A.rowptr, A.colind, A.val, A.m, X, ldx, G, ldg, w, x.s));
+        QB_HIP(launch_spmm_plan(A.plan_a, A.rowptr, A.colind, A.val, X, ldx, G, ldg, w, x.s));
         QB_HIP(launch_colsq_rowmajor(G, A.m, w, ldg, gpart, x.s));
         groups = static_cast<int>(colsq_groups(A.m));
     }
@@ -249,7 +253,7 @@ int apply_At(const Ctx& x, const double* G, int64_t ldg, double* H, int64_t ldh,
                            View{nullptr, 0, 0}, MutView{H, ldh, 1}, x);
         QB_HIP(gemm_f64(d, x.s));
     } else {
-        QB_HIP(launch_spmm_csr(A.t_ptr, A.t_col, A.t_val, A.n, G, ldg, H, ldh, w, x.s));
+        QB_HIP(launch_spmm_plan(A.plan_t, A.t_ptr, A.t_col, A.t_val, G, ldg, H, ldh, w, x.s));
     }
     return QB_OK;
 }
@@ -407,7 +411,7 @@ int ei_block_b(const Ctx& x, int64_t k, int bw) {
         GemmDesc c = gdesc(A.m, bw, 0, View{nullptr, 0, 0}, View{nullptr, 0, 0}, 0.0, 1.0,
                            View{Qi, 1, x.ldq}, MutView{X2, bw, 1}, x);
         QB_HIP(gemm_f64(c, x.s));
-        QB_HIP(launch_spmm_csr(A.t_ptr, A.t_col, A.t_val, A.n, X2, bw, S, bw, bw, x.s));
+        QB_HIP(launch_spmm_plan(A.plan_t, A.t_ptr, A.t_col, A.t_val, X2, bw, S, bw, bw, x.s));
         GemmDesc t = gdesc(A.n, bw, 0, View{nullptr, 0, 0}, View{nullptr, 0, 0}, 0.0, 1.0,
                            View{S, bw, 1}, MutView{x.B + k * x.ldb, 1, x.ldb}, x);
         QB_HIP(gemm_f64(t, x.s));
@@ -523,6 +527,8 @@ int run(int algo, Op& A, const qb_params* p, double* Q, int64_t ldq, double* B, 
         // context below takes its copy of the operator
         QB_HIP(build_csc(A.rowptr, A.colind, A.val, m, n, A.nnz, wsb + L.csc, s));
         csc_views(m, n, A.nnz, wsb + L.csc, &A.t_ptr, &A.t_col, &A.t_val);
+        QB_HIP(spmm_plan_build(A.rowptr, m, A.nnz, L.lt, wsb + L.plan_a, s, &A.plan_a));
+        QB_HIP(spmm_plan_build(A.t_ptr, n, A.nnz, L.lt, wsb + L.plan_t, s, &A.plan_t));
     }
     const Ctx x{A, p, Q, ldq, B, ldb, wsb, L, s, inf, &tm, host};
     QB_HIP(hipMemcpyAsync(host, scal, sizeof(double), hipMemcpyDeviceToHost, s));

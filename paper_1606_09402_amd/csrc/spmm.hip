@@ -1,10 +1,14 @@
 // Sparse products for CSR input (Section 5.1 stores sparse A in CSR):
-//   G = A X        one wavefront per row of A; the lanes span the dense columns so
-//                  every gathered row of X is read with coalesced 64-lane loads;
-//   H = A^T G      the same kernel on CSR(A^T), built once by a stable sort of the
-//                  nonzeros by column (rows stay ascending inside each column, so the
-//                  accumulation order -- and the result bits -- are reproducible).
-// No floating-point atomics.
+//   G = A X        one wavefront per segment of at most kSeg nonzeros of a row; the
+//                  lanes span the dense columns so every gathered row of X is read with
+//                  coalesced 64-lane loads.  Rows longer than kSeg (the hub columns of a
+//                  power-law matrix, as rows of A^T) are split over several wavefronts
+//                  whose partial rows are summed in segment order by a second kernel, so
+//                  the work is balanced and the result bits are reproducible;
+//   H = A^T G      the same on CSR(A^T), built once by a stable sort of the nonzeros by
+//                  column (rows stay ascending inside each column).
+// The segment plan of a CSR matrix (segments per row, their prefix sums, the row of
+// each segment) is built on the device once per call.  No floating-point atomics.
 #include <hipcub/hipcub.hpp>
 
 #include "kernels.h"
@@ -39,6 +43,86 @@ spmm_csr_rowwave_kernel(const int64_t* __restrict__ rowptr, const int32_t* __res
 #pragma unroll
     for (int t = 0; t < 4; ++t)
         if (ok[t]) gr[64 * t] = acc[t];
+}
+
+constexpr int64_t kSeg = 512;   // nonzeros per segment
+
+// Segments of row i: 1 if it has at most kSeg nonzeros, else ceil(len / kSeg); entry
+// `rows` of both counts is 0 so that the exclusive scans end with the totals.
+__global__ void plan_count_kernel(const int64_t* __restrict__ rowptr, int64_t rows,
+                                  int64_t* __restrict__ cnt_s, int64_t* __restrict__ cnt_m) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i > rows) return;
+    if (i == rows) {
+        cnt_s[i] = 0;
+        cnt_m[i] = 0;
+        return;
+    }
+    const int64_t len = rowptr[i + 1] - rowptr[i];
+    const int64_t ns = len > kSeg ? (len + kSeg - 1) / kSeg : 1;
+    cnt_s[i] = ns;
+    cnt_m[i] = ns > 1 ? ns : 0;
+}
+
+__global__ void plan_fill_kernel(const int64_t* __restrict__ seg_off, int64_t rows,
+                                 int32_t* __restrict__ seg_row) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= rows) return;
+    for (int64_t q = seg_off[i]; q < seg_off[i + 1]; ++q) seg_row[q] = static_cast<int32_t>(i);
+}
+
+// Wavefront per segment: its nonzeros times the rows of X for the 256 columns of this
+// pass; a row with one segment is written to G, the segments of a longer row to P.
+__global__ void __launch_bounds__(kSpmmThreads)
+spmm_seg_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
+                const double* __restrict__ val, int64_t rows, const int64_t* __restrict__ seg_off,
+                const int64_t* __restrict__ mseg_off, const int32_t* __restrict__ seg_row,
+                const double* __restrict__ X, int64_t ldx, double* __restrict__ G, int64_t ldg,
+                double* __restrict__ P, int64_t w) {
+    const int lane = threadIdx.x & 63;
+    const int64_t sg = static_cast<int64_t>(blockIdx.x) * (kSpmmThreads / 64) + (threadIdx.x >> 6);
+    if (sg >= seg_off[rows]) return;
+    const int64_t row = seg_row[sg];
+    const int64_t q = sg - seg_off[row], ns = seg_off[row + 1] - seg_off[row];
+    const int64_t c0 = static_cast<int64_t>(blockIdx.y) * kSpmmCols;
+    const int64_t e0 = rowptr[row] + q * kSeg;
+    const int64_t e1 = e0 + kSeg < rowptr[row + 1] ? e0 + kSeg : rowptr[row + 1];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    bool ok[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) ok[t] = c0 + lane + 64 * t < w;
+    for (int64_t e = e0; e < e1; ++e) {
+        const double v = val[e];
+        const double* xr = X + static_cast<int64_t>(colind[e]) * ldx + c0 + lane;
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            if (ok[t]) acc[t] += v * xr[64 * t];
+    }
+    double* out = ns == 1 ? G + row * ldg + c0 + lane : P + (mseg_off[row] + q) * w + c0 + lane;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+        if (ok[t]) out[64 * t] = acc[t];
+}
+
+// Rows with several segments: G row = sum of the segment partials in segment order.
+__global__ void __launch_bounds__(kSpmmThreads)
+spmm_seg_reduce_kernel(int64_t rows, const int64_t* __restrict__ seg_off,
+                       const int64_t* __restrict__ mseg_off, const double* __restrict__ P,
+                       double* __restrict__ G, int64_t ldg, int64_t w) {
+    const int lane = threadIdx.x & 63;
+    const int64_t row = static_cast<int64_t>(blockIdx.x) * (kSpmmThreads / 64) + (threadIdx.x >> 6);
+    if (row >= rows) return;
+    const int64_t ns = seg_off[row + 1] - seg_off[row];
+    if (ns <= 1) return;
+    const int64_t c0 = static_cast<int64_t>(blockIdx.y) * kSpmmCols;
+    const double* p = P + mseg_off[row] * w + c0 + lane;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        if (c0 + lane + 64 * t >= w) continue;
+        double acc = 0.0;
+        for (int64_t q = 0; q < ns; ++q) acc += p[q * w + 64 * t];
+        G[row * ldg + c0 + lane + 64 * t] = acc;
+    }
 }
 
 // Column sums of squares of a row-major rows x w matrix: workgroup g sums rows
@@ -102,6 +186,76 @@ hipError_t launch_spmm_csr(const int64_t* rowptr, const int32_t* colind, const d
               static_cast<unsigned>(cdiv(w, kSpmmCols)));
     hipLaunchKernelGGL(spmm_csr_rowwave_kernel, grid, dim3(kSpmmThreads), 0, s, rowptr, colind, val,
                        m, X, ldx, G, ldg, w);
+    return hipGetLastError();
+}
+
+static size_t align256_(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+static size_t scan_bytes(int64_t items) {
+    size_t tb = 0;
+    hipcub::DeviceScan::ExclusiveSum(nullptr, tb, static_cast<const int64_t*>(nullptr),
+                                     static_cast<int64_t*>(nullptr), static_cast<int>(items));
+    return tb + 256;
+}
+
+// Segment plan in ws: counts (2 x rows+1), offsets (2 x rows+1), seg_row (rows + nnz/kSeg
+// + 1), scan scratch, and P for the partial rows: at most 2 nnz / kSeg segments belong to
+// rows with more than one segment, each a row of wmax doubles.
+size_t spmm_plan_bytes(int64_t rows, int64_t nnz, int64_t wmax) {
+    size_t b = 0;
+    b += 2 * align256_(sizeof(int64_t) * (rows + 1));
+    b += 2 * align256_(sizeof(int64_t) * (rows + 1));
+    b += align256_(sizeof(int32_t) * (rows + nnz / kSeg + 1));
+    b += align256_(scan_bytes(rows + 1));
+    b += align256_(sizeof(double) * (2 * cdiv(nnz, kSeg) + 1) * wmax);
+    return b;
+}
+
+hipError_t spmm_plan_build(const int64_t* rowptr, int64_t rows, int64_t nnz, int64_t wmax, char* ws,
+                           hipStream_t s, SpmmPlan* plan) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char* p = ws + off;
+        off += align256_(bytes);
+        return p;
+    };
+    int64_t* cnt_s = reinterpret_cast<int64_t*>(take(sizeof(int64_t) * (rows + 1)));
+    int64_t* cnt_m = reinterpret_cast<int64_t*>(take(sizeof(int64_t) * (rows + 1)));
+    plan->rows = rows;
+    plan->smax = rows + nnz / kSeg + 1;
+    plan->seg_off = reinterpret_cast<int64_t*>(take(sizeof(int64_t) * (rows + 1)));
+    plan->mseg_off = reinterpret_cast<int64_t*>(take(sizeof(int64_t) * (rows + 1)));
+    plan->seg_row = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * plan->smax));
+    const size_t sb = scan_bytes(rows + 1);
+    char* tmp = take(sb);
+    plan->P = reinterpret_cast<double*>(take(sizeof(double) * (2 * cdiv(nnz, kSeg) + 1) * wmax));
+    plan->wmax = wmax;
+    const unsigned g = static_cast<unsigned>(cdiv(rows + 1, 256));
+    hipLaunchKernelGGL(plan_count_kernel, dim3(g), dim3(256), 0, s, rowptr, rows, cnt_s, cnt_m);
+    size_t tb = sb;
+    hipError_t e = hipcub::DeviceScan::ExclusiveSum(tmp, tb, cnt_s, plan->seg_off, static_cast<int>(rows + 1), s);
+    if (e != hipSuccess) return e;
+    tb = sb;
+    e = hipcub::DeviceScan::ExclusiveSum(tmp, tb, cnt_m, plan->mseg_off, static_cast<int>(rows + 1), s);
+    if (e != hipSuccess) return e;
+    if (rows > 0)
+        hipLaunchKernelGGL(plan_fill_kernel, dim3(static_cast<unsigned>(cdiv(rows, 256))), dim3(256), 0, s,
+                           plan->seg_off, rows, plan->seg_row);
+    return hipGetLastError();
+}
+
+hipError_t launch_spmm_plan(const SpmmPlan& plan, const int64_t* rowptr, const int32_t* colind,
+                            const double* val, const double* X, int64_t ldx, double* G, int64_t ldg,
+                            int64_t w, hipStream_t s) {
+    if (plan.rows <= 0 || w <= 0) return hipSuccess;
+    if (w > plan.wmax) return hipErrorInvalidValue;
+    const unsigned slabs = static_cast<unsigned>(cdiv(w, kSpmmCols));
+    dim3 grid(static_cast<unsigned>(cdiv(plan.smax, kSpmmThreads / 64)), slabs);
+    hipLaunchKernelGGL(spmm_seg_kernel, grid, dim3(kSpmmThreads), 0, s, rowptr, colind, val, plan.rows,
+                       plan.seg_off, plan.mseg_off, plan.seg_row, X, ldx, G, ldg, plan.P, w);
+    dim3 rgrid(static_cast<unsigned>(cdiv(plan.rows, kSpmmThreads / 64)), slabs);
+    hipLaunchKernelGGL(spmm_seg_reduce_kernel, rgrid, dim3(kSpmmThreads), 0, s, plan.rows, plan.seg_off,
+                       plan.mseg_off, plan.P, G, ldg, w);
     return hipGetLastError();
 }
 
