@@ -204,7 +204,7 @@ def main():
     if not args.no_diff:
         out["diff"] = diff_block(qb, W, torch, max(1, min(args.steps, 5)))
     if not args.no_sparse:
-        out["sparse"] = sparse_block(qb, W, torch, max(1, min(args.steps, 3)))
+        out["sparse"] = sparse_block(qb, W, torch)
     print(json.dumps(out), flush=True)
 
 
@@ -327,9 +327,11 @@ def diff_block(qb, W, torch, steps):
     return res
 
 
-def sparse_block(qb, W, torch, steps):
+def sparse_block(qb, W, torch, steps=1):
     """CSR workload: randQB_FP (paper rule and adaptive) and randQB_EI on the 500000 x 200000
-    power-law matrix (nnz 5e6, b = 50, tol 0.6), with the SpMM sweep rate."""
+    power-law matrix (nnz 5e6, b = 50, tol 0.6), with the SpMM sweep rate.  Each variant
+    runs once untimed (allocation) and once timed: a run takes seconds (rank ~13000; the
+    block loop's 4 (m + n) l^2 flops dominate)."""
     import statistics
 
     import numpy as np
@@ -343,18 +345,20 @@ def sparse_block(qb, W, torch, steps):
     rowptr = torch.from_numpy(c.rowptr).to(dev)
     colind = torch.from_numpy(c.colind).to(dev)
     val = torch.from_numpy(c.val).to(dev)
-    l_max = 8192   # capacity of Q / B (the expected rank is about 3300)
+    l_max = 16384   # capacity of Q / B (P = 0 needs about 2.8x the optimal rank, ~4800)
     Qs = torch.empty((l_max, c.m), dtype=torch.float64, device=dev)
     Bs = torch.empty((l_max, c.n), dtype=torch.float64, device=dev)
+    need = max(qb.qb_workspace_bytes(qb.QB_ALGO_FP, True, c.m, c.n, c.nnz, wl.tol, wl.b, l_max, 0),
+               qb.qb_workspace_bytes(qb.QB_ALGO_EI, True, c.m, c.n, c.nnz, wl.tol, wl.b, l_max))
+    ws = torch.empty(need, dtype=torch.uint8, device=dev)
     res = {"workload": wl.name, "l_max": l_max}
     runs = (("fp_paper_rule", lambda: qb.qb_fp_csr(c.m, c.n, rowptr, colind, val, wl.tol, wl.b, seed,
-                                                    l_max=l_max, l_tilde=0, Q_store=Qs, B_store=Bs)),
+                                                    l_max=l_max, l_tilde=0, Q_store=Qs, B_store=Bs, ws=ws)),
             ("fp_adaptive", lambda: qb.qb_fp_csr(c.m, c.n, rowptr, colind, val, wl.tol, wl.b, seed,
-                                                  l_max=l_max, l_tilde=-1, Q_store=Qs, B_store=Bs)),
+                                                  l_max=l_max, l_tilde=-1, Q_store=Qs, B_store=Bs, ws=ws)),
             ("ei", lambda: qb.qb_ei_csr(c.m, c.n, rowptr, colind, val, wl.tol, wl.b, seed, l_max=l_max,
-                                        Q_store=Qs, B_store=Bs)))
+                                        Q_store=Qs, B_store=Bs, ws=ws)))
     for name, fn in runs:
-        fn()
         torch.cuda.synchronize()
         ts, rs = [], []
         for _ in range(steps):
@@ -382,7 +386,7 @@ def sparse_block(qb, W, torch, steps):
         res[name] = entry
         print(f"# sparse {name}: {statistics.median(ts) * 1e3:.1f} ms rank {r.rank} passes {r.passes}",
               file=sys.stderr, flush=True)
-    del Qs, Bs, rowptr, colind, val
+    del Qs, Bs, ws, rowptr, colind, val
     torch.cuda.empty_cache()
     return res
 

@@ -445,6 +445,157 @@ gemm_bf16_kernel(const Bf16GemmArgs g) {
     }
 }
 
+// ------------------------------------------------------------------ BF16 GEMM, LDS DMA
+
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+typedef __attribute__((address_space(1))) void* global_ptr_t;
+
+// LDS layout of a tile filled by DMA: rows of 64 bfloat16 (8 chunks of 16 bytes, no
+// padding); chunk c of row r sits at slot 8 r + (c ^ ((r / 2) mod 8)), so the 16 rows of a
+// 16-lane operand read cover all 16 bank groups of a 256-byte bank row.
+QB_DEV int dma_slot(int r, int c) { return 8 * r + (c ^ ((r >> 1) & 7)); }
+
+// Same product as gemm_bf16_kernel for K-contiguous A and B (16-byte aligned rows, K a
+// multiple of 64), with the K tiles moved global -> LDS by global_load_lds_dwordx4: a
+// wave's instruction fills 64 consecutive slots (lane l -> slot s0 + l), each lane
+// fetching the chunk that the swizzle puts there.  The next tile's DMA runs during the
+// current tile's MFMAs; no staging registers and no LDS store instructions, which leaves
+// room to read the operands of k-step s + 1 while the MFMAs of step s run.  Rows beyond M
+// (columns beyond N) re-read the last valid row; their results are never stored.
+template <int BM, int BN, int WM, int WN, int EPI>
+__global__ void __launch_bounds__(64 * WM * WN, 1) gemm_bf16_dma_kernel(const Bf16GemmArgs g) {
+    constexpr int BK = 64, NT = 64 * WM * WN, NW = NT / 64;
+    constexpr int TM = BM / WM, TN = BN / WN, FM = TM / 32, FN = TN / 32;
+    constexpr int A_SLOTS = BM * 8, B_SLOTS = BN * 8;
+    constexpr int A_INSTR = A_SLOTS / 64 / NW, B_INSTR = B_SLOTS / 64 / NW;
+    static_assert(A_SLOTS % (64 * NW) == 0 && B_SLOTS % (64 * NW) == 0, "whole DMA instructions per wave");
+    __shared__ __align__(16) uint16_t As[2][BM * BK];
+    __shared__ __align__(16) uint16_t Bs[2][BN * BK];
+    __shared__ double red[WM][BN];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave / WN, wn = wave % WN;
+    const int logical = xcd_remap(blockIdx.x, gridDim.x);
+    int tile_m, tile_n;
+    group_tiles(logical, g.tiles_m, g.tiles_n, tile_m, tile_n);
+    const int64_t m0 = static_cast<int64_t>(tile_m) * BM, n0 = static_cast<int64_t>(tile_n) * BN;
+
+    f32x16 acc[FM][FN];
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) acc[a][b] = f32x16{};
+
+    auto issue = [&](int st, int64_t k0) {
+#pragma unroll
+        for (int j = 0; j < A_INSTR; ++j) {
+            const int s0 = (wave * A_INSTR + j) * 64, sl = s0 + lane;
+            const int r = sl >> 3, c = (sl & 7) ^ ((r >> 1) & 7);
+            const int64_t gi = m0 + r < g.M ? m0 + r : g.M - 1;
+            const uint16_t* src = g.A + gi * g.lda + k0 + 8 * c;
+            __builtin_amdgcn_global_load_lds((global_ptr_t)src, (lds_ptr_t)&As[st][s0 * 8], 16, 0, 0);
+        }
+#pragma unroll
+        for (int j = 0; j < B_INSTR; ++j) {
+            const int s0 = (wave * B_INSTR + j) * 64, sl = s0 + lane;
+            const int r = sl >> 3, c = (sl & 7) ^ ((r >> 1) & 7);
+            const int64_t gj = n0 + r < g.N ? n0 + r : g.N - 1;
+            const uint16_t* src = g.B + gj * g.ldb + k0 + 8 * c;
+            __builtin_amdgcn_global_load_lds((global_ptr_t)src, (lds_ptr_t)&Bs[st][s0 * 8], 16, 0, 0);
+        }
+    };
+    const int wm0 = wm * TM, wn0 = wn * TN;
+    const int lr = lane & 31, lch = lane >> 5;
+    auto read_ops = [&](int st, int kk, bf16x8 (&a)[FM], bf16x8 (&b)[FN]) {
+#pragma unroll
+        for (int fm = 0; fm < FM; ++fm)
+            a[fm] = *reinterpret_cast<const bf16x8*>(&As[st][dma_slot(wm0 + fm * 32 + lr, kk + lch) * 8]);
+#pragma unroll
+        for (int fn = 0; fn < FN; ++fn)
+            b[fn] = *reinterpret_cast<const bf16x8*>(&Bs[st][dma_slot(wn0 + fn * 32 + lr, kk + lch) * 8]);
+    };
+    auto mfmas = [&](const bf16x8 (&a)[FM], const bf16x8 (&b)[FN]) {
+#pragma unroll
+        for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+            for (int fn = 0; fn < FN; ++fn)
+                acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[fm], b[fn], acc[fm][fn], 0, 0, 0);
+    };
+    // four k-steps of 16 per tile; the operands of the next step are read before the
+    // MFMAs of the current one are issued
+    // (scheduling barriers keep the compiler from sinking the reads back to their use)
+    auto compute = [&](int st) {
+        bf16x8 a0[FM], b0[FN], a1[FM], b1[FN];
+        read_ops(st, 0, a0, b0);
+        read_ops(st, 2, a1, b1);
+        __builtin_amdgcn_sched_barrier(0);
+        mfmas(a0, b0);
+        __builtin_amdgcn_sched_barrier(0);
+        read_ops(st, 4, a0, b0);
+        __builtin_amdgcn_sched_barrier(0);
+        mfmas(a1, b1);
+        __builtin_amdgcn_sched_barrier(0);
+        read_ops(st, 6, a1, b1);
+        __builtin_amdgcn_sched_barrier(0);
+        mfmas(a0, b0);
+        __builtin_amdgcn_sched_barrier(0);
+        mfmas(a1, b1);
+    };
+
+    if (g.K > 0) {
+        issue(0, 0);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        int st = 0;
+        for (int64_t k0 = 0; k0 < g.K; k0 += BK) {
+            if (k0 + BK < g.K) issue(st ^ 1, k0 + BK);
+            compute(st);
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            st ^= 1;
+        }
+    }
+
+    double csq[FN];
+#pragma unroll
+    for (int fn = 0; fn < FN; ++fn) csq[fn] = 0.0;
+#pragma unroll
+    for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+        for (int fn = 0; fn < FN; ++fn)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t i = m0 + wm0 + fm * 32 + acc32_row(lane, r);
+                const int64_t j = n0 + wn0 + fn * 32 + (lane & 31);
+                if (i < g.M && j < g.N) {
+                    if (EPI == 0) {
+                        g.out[i * g.ldo + j] = static_cast<double>(acc[fm][fn][r]);
+                    } else {
+                        const uint16_t h = f32_to_bf16_rne(acc[fm][fn][r]);
+                        const double v = bf16_to_f64(h);
+                        g.out[i * g.ldo + j] = v;
+                        g.outT[j * g.ldt + i] = h;
+                        csq[fn] += v * v;
+                    }
+                }
+            }
+    if (EPI == 1 && g.colsq != nullptr) {
+#pragma unroll
+        for (int fn = 0; fn < FN; ++fn) {
+            double v = csq[fn];
+            v += __shfl_xor(v, 32, 64);
+            if (lane < 32) red[wm][wn0 + fn * 32 + lane] = v;
+        }
+        __syncthreads();
+        for (int j = tid; j < BN; j += NT) {
+            double t = 0.0;
+#pragma unroll
+            for (int w = 0; w < WM; ++w) t += red[w][j];
+            if (n0 + j < g.N) g.colsq[static_cast<int64_t>(tile_m) * g.N + n0 + j] = t;
+        }
+    }
+}
+
 // ------------------------------------------------------------------ host
 
 hipError_t launch_quant_transpose_omega(double* om, int64_t n, int64_t w, uint16_t* omT,
@@ -511,7 +662,10 @@ hipError_t gemm_bf16(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda
     g.tiles_m = static_cast<int>(cdiv(M, t));
     g.tiles_n = static_cast<int>(cdiv(N, t));
     dim3 grid(static_cast<unsigned>(static_cast<int64_t>(g.tiles_m) * g.tiles_n));
-    if (big) {
+    if (big && !a_km && !a_fp8 && g.vec && K % 64 == 0) {
+        // K-contiguous bfloat16 operands with 16-byte aligned rows, whole K tiles: LDS DMA
+        hipLaunchKernelGGL((gemm_bf16_dma_kernel<256, 256, 2, 4, 1>), grid, dim3(512), 0, s, g);
+    } else if (big) {
         if (a_km && a_fp8)
             hipLaunchKernelGGL((gemm_bf16_kernel<256, 256, 64, 2, 4, 0, true, true>), grid, dim3(512), 0, s, g);
         else if (a_km)

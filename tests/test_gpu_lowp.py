@@ -76,6 +76,7 @@ def test_sumsq_bf16(qb, m, n):
     (1024, 768, 256, 0, 8),      # 16-byte aligned rows (vector loads), row stride 776
     (129, 4099, 33, 5, 0),       # short and wide, odd widths
     (4096, 256, 128, 128, 0),    # tall and narrow
+    (16300, 1000, 1000, 64, 0),  # 256 tiles of 256 x 256: the LDS-DMA kernel, ragged M, N, K
 ])
 def test_sketch_lowp(qb, m, n, l, col0, pad):
     _log(f"sketch bf16 {m}x{n} l={l} col0={col0} pad={pad}")
