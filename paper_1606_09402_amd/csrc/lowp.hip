@@ -450,27 +450,40 @@ gemm_bf16_kernel(const Bf16GemmArgs g) {
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
 typedef __attribute__((address_space(1))) void* global_ptr_t;
 
-// LDS layout of a tile filled by DMA: rows of 64 bfloat16 (8 chunks of 16 bytes, no
-// padding); chunk c of row r sits at slot 8 r + (c ^ ((r / 2) mod 8)), so the 16 rows of a
-// 16-lane operand read cover all 16 bank groups of a 256-byte bank row.
-QB_DEV int dma_slot(int r, int c) { return 8 * r + (c ^ ((r >> 1) & 7)); }
+// LDS layout of a tile filled by DMA: rows of BK bfloat16 (BK / 8 chunks of 16 bytes, no
+// padding); chunk c of row r sits at slot (BK / 8) r + (c ^ swz(r)), with the XOR chosen so
+// that the 16 rows of a 16-lane operand read cover all 16 bank groups of a 256-byte bank
+// row: swz(r) = (r / 2) mod 8 for 8 chunks per row, (r / 4) mod 4 for 4.
+template <int BK>
+QB_DEV int dma_slot(int r, int c) {
+    constexpr int CPR = BK / 8;
+    return CPR * r + (c ^ (CPR == 8 ? ((r >> 1) & 7) : ((r >> 2) & 3)));
+}
+
+// s_waitcnt immediate that waits until at most n vector-memory operations of this wave
+// are outstanding (export and LDS counters left at their maxima).
+QB_DEV constexpr int vmcnt_imm(int n) { return (n & 0xF) | ((n >> 4) << 14) | (7 << 4) | (15 << 8); }
 
 // Same product as gemm_bf16_kernel for K-contiguous A and B (16-byte aligned rows, K a
-// multiple of 64), with the K tiles moved global -> LDS by global_load_lds_dwordx4: a
-// wave's instruction fills 64 consecutive slots (lane l -> slot s0 + l), each lane
-// fetching the chunk that the swizzle puts there.  The next tile's DMA runs during the
-// current tile's MFMAs; no staging registers and no LDS store instructions, which leaves
-// room to read the operands of k-step s + 1 while the MFMAs of step s run.  Rows beyond M
-// (columns beyond N) re-read the last valid row; their results are never stored.
-template <int BM, int BN, int WM, int WN, int EPI>
+// multiple of BK), with the K tiles moved global -> LDS by global_load_lds_dwordx4 through
+// a ring of STAGES tiles: tile t + STAGES - 1 is requested while tile t is multiplied, so a
+// tile has STAGES - 1 tiles of MFMA time to arrive.  A wave's DMA instruction fills 64
+// consecutive slots (lane l -> slot s0 + l), each lane fetching the chunk that the swizzle
+// puts there; there are no staging registers and no LDS store instructions.  The operands
+// of k-step s + 1 are read while the MFMAs of step s run.  Rows beyond M (columns beyond
+// N) re-read the last valid row; their results are never stored.
+template <int BM, int BN, int BK, int STAGES, int WM, int WN, int EPI>
 __global__ void __launch_bounds__(64 * WM * WN, 1) gemm_bf16_dma_kernel(const Bf16GemmArgs g) {
-    constexpr int BK = 64, NT = 64 * WM * WN, NW = NT / 64;
+    constexpr int NT = 64 * WM * WN, NW = NT / 64, CPR = BK / 8;
     constexpr int TM = BM / WM, TN = BN / WN, FM = TM / 32, FN = TN / 32;
-    constexpr int A_SLOTS = BM * 8, B_SLOTS = BN * 8;
+    constexpr int A_SLOTS = BM * CPR, B_SLOTS = BN * CPR;
     constexpr int A_INSTR = A_SLOTS / 64 / NW, B_INSTR = B_SLOTS / 64 / NW;
+    constexpr int PER_TILE = A_INSTR + B_INSTR;           // DMA instructions per wave per tile
+    constexpr int KSTEPS = BK / 16;
     static_assert(A_SLOTS % (64 * NW) == 0 && B_SLOTS % (64 * NW) == 0, "whole DMA instructions per wave");
-    __shared__ __align__(16) uint16_t As[2][BM * BK];
-    __shared__ __align__(16) uint16_t Bs[2][BN * BK];
+    static_assert((CPR == 8 || CPR == 4) && KSTEPS % 2 == 0, "tile depth 32 or 64");
+    __shared__ __align__(16) uint16_t As[STAGES][BM * BK];
+    __shared__ __align__(16) uint16_t Bs[STAGES][BN * BK];
     __shared__ double red[WM][BN];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -486,33 +499,52 @@ __global__ void __launch_bounds__(64 * WM * WN, 1) gemm_bf16_dma_kernel(const Bf
 #pragma unroll
         for (int b = 0; b < FN; ++b) acc[a][b] = f32x16{};
 
+    auto slot_rc = [](int sl, int& r, int& c) {
+        r = sl / CPR;
+        c = (sl % CPR) ^ (CPR == 8 ? ((r >> 1) & 7) : ((r >> 2) & 3));
+    };
+    // One DMA instruction: 16 bytes per lane from src into LDS at lds_base + 16 lane.  It is
+    // written as inline assembly so that the compiler does not count it among the memory
+    // operations that LDS reads must wait for (it would wait for every tile in flight);
+    // this kernel waits for its DMAs itself (s_waitcnt vmcnt before each barrier).  The
+    // instruction has no register results.  M0 holds the LDS base; no compiler-generated
+    // code of this kernel reads M0 (checked in its gfx950 assembly), so clobbering it here
+    // is safe.
+    auto dma16 = [](const uint16_t* src, const uint16_t* lds_dst) {
+        const uint32_t base = __builtin_amdgcn_readfirstlane(
+            static_cast<uint32_t>(reinterpret_cast<uintptr_t>((lds_ptr_t)lds_dst)));
+        asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off"
+                     :
+                     : "v"(src), "s"(base)
+                     : "memory", "m0");
+    };
     auto issue = [&](int st, int64_t k0) {
 #pragma unroll
         for (int j = 0; j < A_INSTR; ++j) {
-            const int s0 = (wave * A_INSTR + j) * 64, sl = s0 + lane;
-            const int r = sl >> 3, c = (sl & 7) ^ ((r >> 1) & 7);
+            const int s0 = (wave * A_INSTR + j) * 64;
+            int r, c;
+            slot_rc(s0 + lane, r, c);
             const int64_t gi = m0 + r < g.M ? m0 + r : g.M - 1;
-            const uint16_t* src = g.A + gi * g.lda + k0 + 8 * c;
-            __builtin_amdgcn_global_load_lds((global_ptr_t)src, (lds_ptr_t)&As[st][s0 * 8], 16, 0, 0);
+            dma16(g.A + gi * g.lda + k0 + 8 * c, &As[st][s0 * 8]);
         }
 #pragma unroll
         for (int j = 0; j < B_INSTR; ++j) {
-            const int s0 = (wave * B_INSTR + j) * 64, sl = s0 + lane;
-            const int r = sl >> 3, c = (sl & 7) ^ ((r >> 1) & 7);
+            const int s0 = (wave * B_INSTR + j) * 64;
+            int r, c;
+            slot_rc(s0 + lane, r, c);
             const int64_t gj = n0 + r < g.N ? n0 + r : g.N - 1;
-            const uint16_t* src = g.B + gj * g.ldb + k0 + 8 * c;
-            __builtin_amdgcn_global_load_lds((global_ptr_t)src, (lds_ptr_t)&Bs[st][s0 * 8], 16, 0, 0);
+            dma16(g.B + gj * g.ldb + k0 + 8 * c, &Bs[st][s0 * 8]);
         }
     };
     const int wm0 = wm * TM, wn0 = wn * TN;
     const int lr = lane & 31, lch = lane >> 5;
-    auto read_ops = [&](int st, int kk, bf16x8 (&a)[FM], bf16x8 (&b)[FN]) {
+    auto read_ops = [&](int st, int ks, bf16x8 (&a)[FM], bf16x8 (&b)[FN]) {
 #pragma unroll
         for (int fm = 0; fm < FM; ++fm)
-            a[fm] = *reinterpret_cast<const bf16x8*>(&As[st][dma_slot(wm0 + fm * 32 + lr, kk + lch) * 8]);
+            a[fm] = *reinterpret_cast<const bf16x8*>(&As[st][dma_slot<BK>(wm0 + fm * 32 + lr, 2 * ks + lch) * 8]);
 #pragma unroll
         for (int fn = 0; fn < FN; ++fn)
-            b[fn] = *reinterpret_cast<const bf16x8*>(&Bs[st][dma_slot(wn0 + fn * 32 + lr, kk + lch) * 8]);
+            b[fn] = *reinterpret_cast<const bf16x8*>(&Bs[st][dma_slot<BK>(wn0 + fn * 32 + lr, 2 * ks + lch) * 8]);
     };
     auto mfmas = [&](const bf16x8 (&a)[FM], const bf16x8 (&b)[FN]) {
 #pragma unroll
@@ -521,39 +553,46 @@ __global__ void __launch_bounds__(64 * WM * WN, 1) gemm_bf16_dma_kernel(const Bf
             for (int fn = 0; fn < FN; ++fn)
                 acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[fm], b[fn], acc[fm][fn], 0, 0, 0);
     };
-    // four k-steps of 16 per tile; the operands of the next step are read before the
-    // MFMAs of the current one are issued
-    // (scheduling barriers keep the compiler from sinking the reads back to their use)
+    // the k-steps of one tile, two operand sets in flight (scheduling barriers keep the
+    // compiler from sinking the reads back to their use)
     auto compute = [&](int st) {
         bf16x8 a0[FM], b0[FN], a1[FM], b1[FN];
         read_ops(st, 0, a0, b0);
-        read_ops(st, 2, a1, b1);
-        __builtin_amdgcn_sched_barrier(0);
-        mfmas(a0, b0);
-        __builtin_amdgcn_sched_barrier(0);
-        read_ops(st, 4, a0, b0);
-        __builtin_amdgcn_sched_barrier(0);
-        mfmas(a1, b1);
-        __builtin_amdgcn_sched_barrier(0);
-        read_ops(st, 6, a1, b1);
-        __builtin_amdgcn_sched_barrier(0);
-        mfmas(a0, b0);
-        __builtin_amdgcn_sched_barrier(0);
-        mfmas(a1, b1);
+#pragma unroll
+        for (int ks = 0; ks < KSTEPS; ks += 2) {
+            read_ops(st, ks + 1, a1, b1);
+            __builtin_amdgcn_sched_barrier(0);
+            mfmas(a0, b0);
+            __builtin_amdgcn_sched_barrier(0);
+            if (ks + 2 < KSTEPS) read_ops(st, ks + 2, a0, b0);
+            __builtin_amdgcn_sched_barrier(0);
+            mfmas(a1, b1);
+            __builtin_amdgcn_sched_barrier(0);
+        }
     };
 
-    if (g.K > 0) {
-        issue(0, 0);
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
-        int st = 0;
-        for (int64_t k0 = 0; k0 < g.K; k0 += BK) {
-            if (k0 + BK < g.K) issue(st ^ 1, k0 + BK);
-            compute(st);
-            __builtin_amdgcn_s_waitcnt(0);
-            __syncthreads();
-            st ^= 1;
+    const int64_t T = g.K / BK;   // K tiles
+    if (T > 0) {
+#pragma unroll
+        for (int p = 0; p < STAGES - 1; ++p)
+            if (p < T) issue(p, static_cast<int64_t>(p) * BK);
+        for (int64_t t = 0; t < T; ++t) {
+            // this wave's DMAs for tile t have landed once at most the later tiles' remain
+            const int64_t later = T - 1 - t < STAGES - 2 ? T - 1 - t : STAGES - 2;
+            if (later >= STAGES - 2) __builtin_amdgcn_s_waitcnt(vmcnt_imm((STAGES - 2) * PER_TILE));
+            else if (later == 1) __builtin_amdgcn_s_waitcnt(vmcnt_imm(PER_TILE));
+            else __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+            // every wave's part of tile t is in LDS and tile t - 1 is consumed.  A bare
+            // s_barrier: the fence of __syncthreads() would also wait for the later tiles'
+            // DMAs; the empty asm statements keep the compiler from moving LDS accesses
+            // across it.
+            asm volatile("" ::: "memory");
+            __builtin_amdgcn_s_barrier();
+            asm volatile("" ::: "memory");
+            if (t + STAGES - 1 < T) issue(static_cast<int>((t + STAGES - 1) % STAGES), (t + STAGES - 1) * BK);
+            compute(static_cast<int>(t % STAGES));
         }
+        __syncthreads();
     }
 
     double csq[FN];
@@ -662,9 +701,9 @@ hipError_t gemm_bf16(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda
     g.tiles_m = static_cast<int>(cdiv(M, t));
     g.tiles_n = static_cast<int>(cdiv(N, t));
     dim3 grid(static_cast<unsigned>(static_cast<int64_t>(g.tiles_m) * g.tiles_n));
-    if (big && !a_km && !a_fp8 && g.vec && K % 64 == 0) {
+    if (big && !a_km && !a_fp8 && g.vec && K % 32 == 0) {
         // K-contiguous bfloat16 operands with 16-byte aligned rows, whole K tiles: LDS DMA
-        hipLaunchKernelGGL((gemm_bf16_dma_kernel<256, 256, 2, 4, 1>), grid, dim3(512), 0, s, g);
+        hipLaunchKernelGGL((gemm_bf16_dma_kernel<256, 256, 32, 4, 2, 4, 1>), grid, dim3(512), 0, s, g);
     } else if (big) {
         if (a_km && a_fp8)
             hipLaunchKernelGGL((gemm_bf16_kernel<256, 256, 64, 2, 4, 0, true, true>), grid, dim3(512), 0, s, g);
