@@ -38,6 +38,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6
+# HBM bytes per launch of the dominant kernel (G = A Omega of the adaptive schedule, mean of
+# its two launches): rocprofv3 FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, the scales being
+# what the two counters read for a plain 1 GiB device copy.  Measured for the current
+# gemm_f64_kernel; profiles/gemm_f64_sketch_dense_20000x15000_b64_tol1e-3.md.
+G_TRAFFIC_BYTES = (2 * 4067823 + 380000) * 1024
 FP32_PEAK_TFLOPS = 157.3
 BF16_PEAK_TFLOPS = 2500.0
 
@@ -161,7 +166,9 @@ def main():
         "sketch_tflops": (r.gemm_flops[0] + r.gemm_flops[1]) / ((r.ms[2] + r.ms[3]) * 1e-3) / 1e12,
         "roofline": {"bound": "mfma", "kernel": dom_name, "achieved": round(achieved, 3),
                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None},
+                     "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+                     "traffic": G_TRAFFIC_BYTES if args.l_tilde == -1 and dom_name.startswith("gemm_f64 G")
+                     else None},
     }
     if args.l_tilde != 0:   # the paper's fixed l~ = 50 b beside the headline schedule
         fp(0)
