@@ -63,6 +63,8 @@ struct BGemm {
     const T* C0; int64_t c0_si, c0_sj, c0_sz;
     T* C; int64_t c_si, c_sj, c_sz;
     int tiles_n;
+    int64_t kchunk;   // K range of one split (blockIdx.y); several splits write partials to P
+    T* P;             // [split][batch][M][N] partial sums (gridDim.y > 1)
 };
 
 template <typename T, int BM, int BN, int BK>
@@ -94,21 +96,23 @@ __global__ void __launch_bounds__(256) bgemm_kernel(const BGemm<T> g) {
         for (int b = 0; b < FN; ++b) acc[a][b] = Acc{};
 
     const int wm0 = wm * TM, wn0 = wn * TN;
-    for (int64_t k0 = 0; k0 < g.K; k0 += BK) {
+    const int64_t kb = static_cast<int64_t>(blockIdx.y) * g.kchunk;
+    const int64_t ke = kb + g.kchunk < g.K ? kb + g.kchunk : g.K;
+    for (int64_t k0 = kb; k0 < ke; k0 += BK) {
         T ra[LA], rb[LB];
 #pragma unroll
         for (int p = 0; p < LA; ++p) {
             const int e = tid + p * NT;
             const int kk = a_kfast ? e % BK : e / BM, ii = a_kfast ? e / BK : e % BM;
             const int64_t i = m0 + ii, k = k0 + kk;
-            ra[p] = (i < g.M && k < g.K) ? A[i * g.a_si + k * g.a_sk] : T(0);
+            ra[p] = (i < g.M && k < ke) ? A[i * g.a_si + k * g.a_sk] : T(0);
         }
 #pragma unroll
         for (int p = 0; p < LB; ++p) {
             const int e = tid + p * NT;
             const int kk = b_jfast ? e / BN : e % BK, jj = b_jfast ? e % BN : e / BK;
             const int64_t j = n0 + jj, k = k0 + kk;
-            rb[p] = (j < g.N && k < g.K) ? B[k * g.b_sk + j * g.b_sj] : T(0);
+            rb[p] = (j < g.N && k < ke) ? B[k * g.b_sk + j * g.b_sj] : T(0);
         }
         __syncthreads();
 #pragma unroll
@@ -138,6 +142,20 @@ __global__ void __launch_bounds__(256) bgemm_kernel(const BGemm<T> g) {
         }
     }
 
+    if (gridDim.y > 1) {   // split K: raw partial sums, combined by bgemm_splitk_reduce
+        T* P = g.P + (static_cast<int64_t>(blockIdx.y) * gridDim.z + z) * g.M * g.N;
+#pragma unroll
+        for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+            for (int fn = 0; fn < FN; ++fn)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t i = m0 + wm0 + fm * 16 + Mfma<T>::row(lane, r);
+                    const int64_t j = n0 + wn0 + fn * 16 + li;
+                    if (i < g.M && j < g.N) P[i * g.N + j] = acc[fm][fn][r];
+                }
+        return;
+    }
     const T* C0 = g.C0 + z * g.c0_sz;
     T* C = g.C + z * g.c_sz;
 #pragma unroll
@@ -156,6 +174,30 @@ __global__ void __launch_bounds__(256) bgemm_kernel(const BGemm<T> g) {
             }
 }
 
+// Fixed-order sum of the K splits with the alpha / beta epilogue.
+template <typename T>
+__global__ void __launch_bounds__(256)
+bgemm_splitk_reduce(const T* __restrict__ P, int nsplit, int64_t batch, int64_t M, int64_t N, T alpha,
+                    T beta, const T* C0, int64_t c0_si, int64_t c0_sj, int64_t c0_sz, T* C, int64_t c_si,
+                    int64_t c_sj, int64_t c_sz) {
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t per = M * N;
+    if (e >= batch * per) return;
+    T t = T(0);
+    for (int q = 0; q < nsplit; ++q) t += P[static_cast<int64_t>(q) * batch * per + e];
+    const int64_t z = e / per, w = e % per, i = w / N, j = w % N;
+    T v = alpha * t;
+    if (beta != T(0)) v += beta * C0[z * c0_sz + i * c0_si + j * c0_sj];
+    C[z * c_sz + i * c_si + j * c_sj] = v;
+}
+
+// Scratch for split-K partial sums.
+template <typename T>
+struct SplitWs {
+    T* p;
+    int64_t elems;
+};
+
 // A strided batch view.
 template <typename T>
 struct BV {
@@ -170,7 +212,7 @@ struct BMV {
 
 template <typename T>
 hipError_t bgemm(int64_t batch, int64_t M, int64_t N, int64_t K, BV<T> a, BV<T> b, T alpha, T beta,
-                 BV<T> c0, BMV<T> c, hipStream_t s) {
+                 BV<T> c0, BMV<T> c, hipStream_t s, SplitWs<T> sw) {
     if (batch <= 0 || M <= 0 || N <= 0) return hipSuccess;
     BGemm<T> g{};
     g.M = M; g.N = N; g.K = K;
@@ -181,14 +223,31 @@ hipError_t bgemm(int64_t batch, int64_t M, int64_t N, int64_t K, BV<T> a, BV<T> 
     g.C = c.p; g.c_si = c.si; g.c_sj = c.sj; g.c_sz = c.sz;
     if (batch > 65535) return hipErrorInvalidValue;
     // 64 x 64 tiles; 128 x 64 for tall outputs with few tiles per matrix
-    if (M >= 1024 && N <= 64) {
-        g.tiles_n = static_cast<int>(cdiv(N, 64));
-        dim3 grid(static_cast<unsigned>(cdiv(M, 128) * g.tiles_n), 1, static_cast<unsigned>(batch));
+    const bool tall = M >= 1024 && N <= 64;
+    g.tiles_n = static_cast<int>(cdiv(N, 64));
+    const int64_t tiles = cdiv(M, tall ? 128 : 64) * g.tiles_n;
+    // few workgroups and a long reduction (Gram matrices, Q^T X): split K over about 2048
+    // workgroups in chunks of at least 128
+    int64_t nsplit = 1;
+    if (sw.p != nullptr && tiles * batch < 1024 && K >= 256) {
+        nsplit = cdiv(2048, tiles * batch);
+        if (nsplit > K / 128) nsplit = K / 128;
+        while (nsplit > 1 && nsplit * batch * M * N > sw.elems) --nsplit;
+    }
+    g.kchunk = cdiv(cdiv(K, 16), nsplit) * 16;
+    nsplit = K > 0 ? cdiv(K, g.kchunk) : 1;
+    if (nsplit < 1) nsplit = 1;
+    g.P = sw.p;
+    dim3 grid(static_cast<unsigned>(tiles), static_cast<unsigned>(nsplit), static_cast<unsigned>(batch));
+    if (tall)
         hipLaunchKernelGGL((bgemm_kernel<T, 128, 64, 16>), grid, dim3(256), 0, s, g);
-    } else {
-        g.tiles_n = static_cast<int>(cdiv(N, 64));
-        dim3 grid(static_cast<unsigned>(cdiv(M, 64) * g.tiles_n), 1, static_cast<unsigned>(batch));
+    else
         hipLaunchKernelGGL((bgemm_kernel<T, 64, 64, 16>), grid, dim3(256), 0, s, g);
+    if (nsplit > 1) {
+        const int64_t tot = batch * M * N;
+        hipLaunchKernelGGL((bgemm_splitk_reduce<T>), dim3(static_cast<unsigned>(cdiv(tot, 256))), dim3(256), 0, s,
+                           sw.p, static_cast<int>(nsplit), batch, M, N, alpha, beta, c0.p, c0.si, c0.sj, c0.sz,
+                           c.p, c.si, c.sj, c.sz);
     }
     return hipGetLastError();
 }
@@ -203,6 +262,7 @@ __global__ void __launch_bounds__(256)
 chol_inv_batched_kernel(const T* __restrict__ gram, int b, T tau, T* __restrict__ R,
                         T* __restrict__ Rinv, int* __restrict__ flag) {
     __shared__ T S[64 * 65];
+    __shared__ T V[64 * 65];   // R^{-1}
     __shared__ T piv;
     const int64_t z = blockIdx.x;
     const T* Gz = gram + z * b * b;
@@ -236,16 +296,18 @@ chol_inv_batched_kernel(const T* __restrict__ gram, int b, T tau, T* __restrict_
         const int r = e / b, c = e % b;
         Rz[e] = c >= r ? S[r * 65 + c] : T(0);
     }
-    // R^{-1}: thread c solves R x = e_c from the bottom row up (column c of R^{-1})
+    // R^{-1}: thread c solves R x = e_c from the bottom row up (column c of R^{-1}), in LDS
     __syncthreads();
     if (tid < b) {
         const int c = tid;
         for (int r = b - 1; r >= 0; --r) {
             T v = r == c ? T(1) : T(0);
-            for (int t = r + 1; t <= c; ++t) v -= S[r * 65 + t] * Iz[t * b + c];
-            Iz[r * b + c] = r <= c ? v / S[r * 65 + r] : T(0);
+            for (int t = r + 1; t <= c; ++t) v -= S[r * 65 + t] * V[t * 65 + c];
+            V[r * 65 + c] = r <= c ? v / S[r * 65 + r] : T(0);
         }
     }
+    __syncthreads();
+    for (int e = tid; e < b * b; e += blockDim.x) Iz[e] = V[(e / b) * 65 + e % b];
 }
 
 // Inverse of the upper triangle of each k x k matrix (row-major, row stride ld, batch
@@ -269,6 +331,43 @@ tri_inv_batched_kernel(const T* __restrict__ R, int k, int64_t ld, int64_t sz, T
         }
         Iz[static_cast<int64_t>(r) * k + c] = v;
     }
+}
+
+// The same inverse with R and R^{-1} in LDS (k <= KMAX): R's entries are read by all threads
+// at once, each thread's column of R^{-1} stays in LDS.
+template <typename T, int KMAX>
+__global__ void __launch_bounds__(256)
+tri_inv_lds_kernel(const T* __restrict__ R, int k, int64_t ld, int64_t sz, T* __restrict__ Rinv) {
+    __shared__ T S[KMAX * (KMAX + 1)];
+    __shared__ T V[KMAX * (KMAX + 1)];
+    constexpr int P = KMAX + 1;
+    const int64_t z = blockIdx.x;
+    const T* Rz = R + z * sz;
+    T* Iz = Rinv + z * static_cast<int64_t>(k) * k;
+    for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
+        const int r = e / k, c = e % k;
+        S[r * P + c] = c >= r ? Rz[r * ld + c] : T(0);
+    }
+    __syncthreads();
+    const int c = threadIdx.x;
+    if (c < k) {
+        for (int r = k - 1; r >= 0; --r) {
+            // four interleaved partial sums (fixed order) keep the LDS loads in flight
+            T v0 = T(0), v1 = T(0), v2 = T(0), v3 = T(0);
+            int t = r + 1;
+            for (; t + 3 <= c; t += 4) {
+                v0 += S[r * P + t] * V[t * P + c];
+                v1 += S[r * P + t + 1] * V[(t + 1) * P + c];
+                v2 += S[r * P + t + 2] * V[(t + 2) * P + c];
+                v3 += S[r * P + t + 3] * V[(t + 3) * P + c];
+            }
+            for (; t <= c; ++t) v0 += S[r * P + t] * V[t * P + c];
+            const T v = (r == c ? T(1) : T(0)) - ((v0 + v1) + (v2 + v3));
+            V[r * P + c] = r <= c ? v / S[r * P + r] : T(0);
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < k * k; e += blockDim.x) Iz[e] = V[(e / k) * P + e % k];
 }
 
 // C = copyltu(M): C(r, c) = M(max(r, c), min(r, c)) for each k x k matrix (batch stride k*k).
@@ -299,8 +398,17 @@ constexpr int kMaxDiffK = 256;
 
 struct DiffLayout {
     size_t om64, om, g, h, y, x, w, z, d, s, gram, r1, r1i, rt, rti, ri, rii, flag,
-        r, rinv, qt, mm, cs, yb, total;
+        r, rinv, qt, mm, cs, yb, split, total;
+    int64_t split_elems;
 };
+
+// split-K partials: the k x k products of the backward (8 splits) and the k x b ones of
+// the forward (16 splits) fit
+int64_t split_elems(int64_t batch, int64_t k, int64_t b) {
+    int64_t e = 8 * batch * k * k;
+    if (e < 16 * batch * k * b) e = 16 * batch * k * b;
+    return e < (int64_t(1) << 22) ? (int64_t(1) << 22) : e;
+}
 
 size_t al256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
@@ -339,6 +447,8 @@ DiffLayout diff_layout(int64_t batch, int64_t m, int64_t n, int64_t k, int64_t b
     L.mm = take(E * batch * k * k);
     L.cs = take(E * batch * k * k);
     L.yb = take(E * batch * m * k);
+    L.split_elems = split_elems(batch, k, b);
+    L.split = take(E * L.split_elems);
     L.total = off + 256;
     return L;
 }
@@ -384,17 +494,17 @@ int make_omega(uint64_t seed, int64_t n, int64_t k, char* ws, const DiffLayout& 
 
 template <typename T>
 int cholqr_b(int64_t batch, int64_t m, int b, const T* X, int64_t xsz, T* Qout, int64_t q_si,
-             int64_t q_sz, T* gram, T* R, T* Rinv, int* flag, hipStream_t s) {
+             int64_t q_sz, T* gram, T* R, T* Rinv, int* flag, hipStream_t s, SplitWs<T> SW) {
     // Gram = X^T X (X: m x b row-major per matrix)
     QB_DHIP(bgemm<T>(batch, b, b, m, BV<T>{X, 1, b, xsz}, BV<T>{X, b, 1, xsz}, T(1), T(0),
-                     BV<T>{nullptr, 0, 0, 0}, BMV<T>{gram, b, 1, static_cast<int64_t>(b) * b}, s));
+                     BV<T>{nullptr, 0, 0, 0}, BMV<T>{gram, b, 1, static_cast<int64_t>(b) * b}, s, SW));
     const T tau = sizeof(T) == sizeof(float) ? T(1e-6) : T(1e-12);
     hipLaunchKernelGGL((chol_inv_batched_kernel<T>), dim3(static_cast<unsigned>(batch)), dim3(256), 0, s,
                        gram, b, tau, R, Rinv, flag);
     QB_DHIP(hipGetLastError());
     // Q = X R^{-1}
     QB_DHIP(bgemm<T>(batch, m, b, b, BV<T>{X, b, 1, xsz}, BV<T>{Rinv, b, 1, static_cast<int64_t>(b) * b},
-                     T(1), T(0), BV<T>{nullptr, 0, 0, 0}, BMV<T>{Qout, q_si, 1, q_sz}, s));
+                     T(1), T(0), BV<T>{nullptr, 0, 0, 0}, BMV<T>{Qout, q_si, 1, q_sz}, s, SW));
     return QB_OK;
 }
 
@@ -410,44 +520,45 @@ int fixed_fwd(const qb_batch* Ab, int64_t k, int b, uint64_t seed, T* Q, int64_t
       *Rti = P(L.rti), *Ri = P(L.ri), *Rii = P(L.rii);
     int* flag = reinterpret_cast<int*>(ws + L.flag);
     const BV<T> none{nullptr, 0, 0, 0};
+    const SplitWs<T> SW{P(L.split), L.split_elems};
     const int64_t bb = static_cast<int64_t>(b) * b;
     QB_DHIP(launch_fill_int(flag, 1, 0, s));
     if (int e = make_omega<T>(seed, n, k, ws, L, s)) return e;
     // G = A Omega (m x k), H = A^T G (n x k), row-major per matrix
     QB_DHIP(bgemm<T>(bt, m, k, n, BV<T>{A, lda, 1, sa}, BV<T>{Om, k, 1, 0}, T(1), T(0), none,
-                     BMV<T>{G, k, 1, m * k}, s));
+                     BMV<T>{G, k, 1, m * k}, s, SW));
     QB_DHIP(bgemm<T>(bt, n, k, m, BV<T>{A, 1, lda, sa}, BV<T>{G, k, 1, m * k}, T(1), T(0), none,
-                     BMV<T>{H, k, 1, n * k}, s));
+                     BMV<T>{H, k, 1, n * k}, s, SW));
     for (int64_t j0 = 0; j0 < k; j0 += b) {
         const int64_t ki = j0;   // columns of Q / rows of B so far
         // W = B(0:ki, :) Omega_J  (ki x b)
         QB_DHIP(bgemm<T>(bt, ki, b, n, BV<T>{B, ldb, 1, sb}, BV<T>{Om + j0, k, 1, 0}, T(1), T(0), none,
-                         BMV<T>{W, b, 1, k * b}, s));
+                         BMV<T>{W, b, 1, k * b}, s, SW));
         // Y = G_J - Q(:, 0:ki) W  (m x b row-major)
         QB_DHIP(bgemm<T>(bt, m, b, ki, BV<T>{Q, ldq, 1, sq}, BV<T>{W, b, 1, k * b}, T(-1), T(1),
-                         BV<T>{G + j0, k, 1, m * k}, BMV<T>{Y, b, 1, m * b}, s));
+                         BV<T>{G + j0, k, 1, m * k}, BMV<T>{Y, b, 1, m * b}, s, SW));
         // first qr: X = Y R1^{-1}
-        if (int e = cholqr_b<T>(bt, m, b, Y, m * b, X, b, m * b, gram, R1, R1i, flag, s)) return e;
+        if (int e = cholqr_b<T>(bt, m, b, Y, m * b, X, b, m * b, gram, R1, R1i, flag, s, SW)) return e;
         // re-orthogonalisation: Z = Q^T X, X2 = X - Q Z -> written into the Q panel
         QB_DHIP(bgemm<T>(bt, ki, b, m, BV<T>{Q, 1, ldq, sq}, BV<T>{X, b, 1, m * b}, T(1), T(0), none,
-                         BMV<T>{Z, b, 1, k * b}, s));
+                         BMV<T>{Z, b, 1, k * b}, s, SW));
         QB_DHIP(bgemm<T>(bt, m, b, ki, BV<T>{Q, ldq, 1, sq}, BV<T>{Z, b, 1, k * b}, T(-1), T(1),
-                         BV<T>{X, b, 1, m * b}, BMV<T>{X, b, 1, m * b}, s));
-        if (int e = cholqr_b<T>(bt, m, b, X, m * b, Q + j0, ldq, sq, gram, Rt, Rti, flag, s)) return e;
+                         BV<T>{X, b, 1, m * b}, BMV<T>{X, b, 1, m * b}, s, SW));
+        if (int e = cholqr_b<T>(bt, m, b, X, m * b, Q + j0, ldq, sq, gram, Rt, Rti, flag, s, SW)) return e;
         // R_i = R~ R1 and R_i^{-1} = R1^{-1} R~^{-1}
         QB_DHIP(bgemm<T>(bt, b, b, b, BV<T>{Rt, b, 1, bb}, BV<T>{R1, b, 1, bb}, T(1), T(0), none,
-                         BMV<T>{Ri, b, 1, bb}, s));
+                         BMV<T>{Ri, b, 1, bb}, s, SW));
         QB_DHIP(bgemm<T>(bt, b, b, b, BV<T>{R1i, b, 1, bb}, BV<T>{Rti, b, 1, bb}, T(1), T(0), none,
-                         BMV<T>{Rii, b, 1, bb}, s));
+                         BMV<T>{Rii, b, 1, bb}, s, SW));
         // D = Q(:, 0:ki)^T Y + W  (ki x b)
         QB_DHIP(bgemm<T>(bt, ki, b, m, BV<T>{Q, 1, ldq, sq}, BV<T>{Y, b, 1, m * b}, T(1), T(1),
-                         BV<T>{W, b, 1, k * b}, BMV<T>{D, b, 1, k * b}, s));
+                         BV<T>{W, b, 1, k * b}, BMV<T>{D, b, 1, k * b}, s, SW));
         // S^T = H_J - B(0:ki, :)^T D  (n x b row-major)
         QB_DHIP(bgemm<T>(bt, n, b, ki, BV<T>{B, 1, ldb, sb}, BV<T>{D, b, 1, k * b}, T(-1), T(1),
-                         BV<T>{H + j0, k, 1, n * k}, BMV<T>{S, b, 1, n * b}, s));
+                         BV<T>{H + j0, k, 1, n * k}, BMV<T>{S, b, 1, n * b}, s, SW));
         // B_i^T = S^T R_i^{-1}, written transposed into rows j0.. of B
         QB_DHIP(bgemm<T>(bt, n, b, b, BV<T>{S, b, 1, n * b}, BV<T>{Rii, b, 1, bb}, T(1), T(0), none,
-                         BMV<T>{B + j0 * ldb, 1, ldb, sb}, s));
+                         BMV<T>{B + j0 * ldb, 1, ldb, sb}, s, SW));
     }
     QB_DHIP(hipMemcpyAsync(host_flag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
     QB_DHIP(hipStreamSynchronize(s));
@@ -465,48 +576,55 @@ int fixed_bwd(const qb_batch* Ab, int64_t k, uint64_t seed, const T* Q, int64_t 
     T *Om = P(L.om), *G = P(L.g), *R = P(L.r), *Rinv = P(L.rinv), *Qt = P(L.qt), *Mm = P(L.mm),
       *Cs = P(L.cs), *Yb = P(L.yb);
     const BV<T> none{nullptr, 0, 0, 0};
+    const SplitWs<T> SW{P(L.split), L.split_elems};
     const int64_t kk = k * k;
     if (int e = make_omega<T>(seed, n, k, ws, L, s)) return e;
     // recompute G = A Omega and R = Q^T G (upper triangular up to round-off)
     QB_DHIP(bgemm<T>(bt, m, k, n, BV<T>{A, lda, 1, sa}, BV<T>{Om, k, 1, 0}, T(1), T(0), none,
-                     BMV<T>{G, k, 1, m * k}, s));
+                     BMV<T>{G, k, 1, m * k}, s, SW));
     QB_DHIP(bgemm<T>(bt, k, k, m, BV<T>{Q, 1, ldq, sq}, BV<T>{G, k, 1, m * k}, T(1), T(0), none,
-                     BMV<T>{R, k, 1, kk}, s));
-    hipLaunchKernelGGL((tri_inv_batched_kernel<T>), dim3(static_cast<unsigned>(bt)), dim3(256), 0, s, R,
-                       static_cast<int>(k), k, kk, Rinv);
+                     BMV<T>{R, k, 1, kk}, s, SW));
+    // R^{-1} in LDS when it fits (binary32 k <= 128, binary64 k <= 64), else from global
+    constexpr int kLds = sizeof(T) == sizeof(float) ? 128 : 64;
+    if (k <= kLds)
+        hipLaunchKernelGGL((tri_inv_lds_kernel<T, kLds>), dim3(static_cast<unsigned>(bt)), dim3(256), 0, s, R,
+                           static_cast<int>(k), k, kk, Rinv);
+    else
+        hipLaunchKernelGGL((tri_inv_batched_kernel<T>), dim3(static_cast<unsigned>(bt)), dim3(256), 0, s, R,
+                           static_cast<int>(k), k, kk, Rinv);
     QB_DHIP(hipGetLastError());
     // Qt = dQ + A dB^T  (m x k)
     const bool has_dq = dQ != nullptr, has_db = dB != nullptr;
     if (has_db) {
         QB_DHIP(bgemm<T>(bt, m, k, n, BV<T>{A, lda, 1, sa}, BV<T>{dB, 1, lddb, sdb}, T(1),
                          has_dq ? T(1) : T(0), has_dq ? BV<T>{dQ, lddq, 1, sdq} : none,
-                         BMV<T>{Qt, k, 1, m * k}, s));
+                         BMV<T>{Qt, k, 1, m * k}, s, SW));
     } else if (has_dq) {
         QB_DHIP(bgemm<T>(bt, m, k, 0, none, none, T(0), T(1), BV<T>{dQ, lddq, 1, sdq},
-                         BMV<T>{Qt, k, 1, m * k}, s));
+                         BMV<T>{Qt, k, 1, m * k}, s, SW));
     } else {
-        QB_DHIP(bgemm<T>(bt, m, k, 0, none, none, T(0), T(0), none, BMV<T>{Qt, k, 1, m * k}, s));
+        QB_DHIP(bgemm<T>(bt, m, k, 0, none, none, T(0), T(0), none, BMV<T>{Qt, k, 1, m * k}, s, SW));
     }
     // M = -Qt^T Q (k x k), Cs = copyltu(M)
     QB_DHIP(bgemm<T>(bt, k, k, m, BV<T>{Qt, 1, k, m * k}, BV<T>{Q, ldq, 1, sq}, T(-1), T(0), none,
-                     BMV<T>{Mm, k, 1, kk}, s));
+                     BMV<T>{Mm, k, 1, kk}, s, SW));
     const int64_t tot = bt * kk;
     hipLaunchKernelGGL((copyltu_batched_kernel<T>), dim3(static_cast<unsigned>(cdiv(tot, 256))), dim3(256), 0,
                        s, Mm, static_cast<int>(k), tot, Cs);
     QB_DHIP(hipGetLastError());
     // Qt <- Qt + Q Cs ; Y-bar = Qt R^{-T}
     QB_DHIP(bgemm<T>(bt, m, k, k, BV<T>{Q, ldq, 1, sq}, BV<T>{Cs, k, 1, kk}, T(1), T(1),
-                     BV<T>{Qt, k, 1, m * k}, BMV<T>{Qt, k, 1, m * k}, s));
+                     BV<T>{Qt, k, 1, m * k}, BMV<T>{Qt, k, 1, m * k}, s, SW));
     QB_DHIP(bgemm<T>(bt, m, k, k, BV<T>{Qt, k, 1, m * k}, BV<T>{Rinv, 1, k, kk}, T(1), T(0), none,
-                     BMV<T>{Yb, k, 1, m * k}, s));
+                     BMV<T>{Yb, k, 1, m * k}, s, SW));
     // dA = Q dB + Y-bar Omega^T
     if (has_db) {
         QB_DHIP(bgemm<T>(bt, m, n, k, BV<T>{Q, ldq, 1, sq}, BV<T>{dB, lddb, 1, sdb}, T(1), T(0), none,
-                         BMV<T>{dA, ldda, 1, sda}, s));
+                         BMV<T>{dA, ldda, 1, sda}, s, SW));
     }
     QB_DHIP(bgemm<T>(bt, m, n, k, BV<T>{Yb, k, 1, m * k}, BV<T>{Om, 1, k, 0}, T(1),
                      has_db ? T(1) : T(0), has_db ? BV<T>{dA, ldda, 1, sda} : none,
-                     BMV<T>{dA, ldda, 1, sda}, s));
+                     BMV<T>{dA, ldda, 1, sda}, s, SW));
     return QB_OK;
 }
 
