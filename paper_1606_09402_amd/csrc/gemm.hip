@@ -378,8 +378,10 @@ static hipError_t run_cfg(const GemmDesc& d, hipStream_t s) {
     int nsplit = 1;
     const int64_t ktiles = cdiv(d.K, BK);
     if (d.ws != nullptr && tiles < 512) {
-        // few output tiles: spread the reduction over about 640 workgroups
-        int64_t want = cdiv(640, tiles);
+        // few output tiles: spread the reduction over about 2048 workgroups (8 per compute
+        // unit: the long reductions of the block loop stream Q from HBM and need the
+        // occupancy to hide its latency)
+        int64_t want = cdiv(2048, tiles);
         if (want > 128) want = 128;
         if (want > ktiles / 4) want = ktiles / 4;
         if (d.max_split > 0 && want > d.max_split) want = d.max_split;
