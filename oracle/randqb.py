@@ -37,6 +37,14 @@ design notes of the repository):
   2^-40 ||G_J(:,j)||_2, otherwise the method stops before row j (the numerical
   rank of A has been reached and R_i^{-T} would divide by round-off);
 * A = 0 returns rank 0; E < eps^2 before the first block (tol > 1) returns rank 0.
+* power scheme (Algorithm 4 steps 3-6, P >= 1): in the first chunk (Q empty) the P
+  rounds G = orth(A Omega), Omega = orth(A^T G) run as written.  When a later chunk
+  redraws Omega (the restart after Algorithm 4), the rounds act on the current residual
+  A - Q B instead of A, i.e. G = orth(A Omega - Q (B Omega)) and
+  Omega = orth(A^T G - B^T (Q^T G)); on A itself they would steer the new columns back
+  into the range that Q already holds.  G = A Omega and H = A^T G of steps 7-8 then
+  take the full A as written (the block loop deflates).  Each chunk costs 2 P + 2
+  passes.
 """
 from __future__ import annotations
 
@@ -130,6 +138,7 @@ class QBResult:
     exhausted: int = 0
     E_trace: list = field(default_factory=list)   # E after every block (Theorem 2)
     R_diag: list = field(default_factory=list)    # diag(R_i) per block
+    omegas: list = field(default_factory=list)    # each chunk's Omega (keep_omega only)
 
 
 def _check(A, tol_rel, b, l_max):
@@ -191,9 +200,28 @@ def _chunk_width(adaptive: bool, cap: int, b: int, left: int, w_prev: int, e_pre
     return min(w, cap, left)
 
 
+def power_omega(A, Om: np.ndarray, power: int, Q=None, B=None) -> np.ndarray:
+    """Steps 3-6 of Algorithm 4 on the residual A - Q B (Q, B empty in the first chunk):
+    power times G = orth((A - QB) Omega), then Omega = orth((A - QB)^T G)."""
+    deflate = Q is not None and Q.shape[1] > 0
+    for _ in range(power):
+        X = np.asarray(A @ Om)
+        if deflate:
+            X = X - Q @ (B @ Om)
+        G, _ = qr_pos(X)
+        X = np.asarray(A.T @ G)
+        if deflate:
+            X = X - B.T @ (Q.T @ G)
+        Om, _ = qr_pos(X)
+    return Om
+
+
 def randqb_fp(A, tol_rel: float, b: int, seed: int, l_max=None, l_tilde: int = 0,
-              row_by_row: bool = True, precision: str = "f64") -> QBResult:
-    """randQB_FP for the fixed-precision problem (Algorithm 4 with P = 0).
+              row_by_row: bool = True, precision: str = "f64", power: int = 0,
+              keep_omega: bool = False) -> QBResult:
+    """randQB_FP for the fixed-precision problem (Algorithm 4; power scheme with P =
+    power >= 0 rounds per chunk, binary64 only).  keep_omega stores each chunk's final
+    Omega in the result (for tests).
 
     precision = "bf16" is the precision form: A must hold bfloat16 values (A_q); each
     chunk's Omega is rounded to bfloat16 (Omega_q), G = A_q Omega_q is rounded to
@@ -205,6 +233,8 @@ def randqb_fp(A, tol_rel: float, b: int, seed: int, l_max=None, l_tilde: int = 0
         raise ValueError("precision must be 'f64' or 'bf16'")
     if precision == "bf16" and not lowp.is_bf16(A if not sp.issparse(A) else A.data):
         raise ValueError("the precision form takes A already stored in bfloat16")
+    if power < 0 or (power > 0 and precision != "f64"):
+        raise ValueError("the power scheme takes power >= 0 and binary64")
     adaptive = l_tilde == -1
     if l_tilde in (0, -1):
         l_tilde = min(50 * b, l_max)
@@ -222,7 +252,7 @@ def randqb_fp(A, tol_rel: float, b: int, seed: int, l_max=None, l_tilde: int = 0
         return QBResult(st.Q, st.B, 0, E, normA2, status_tol)
     passes = blocks = chunks = 0
     exhausted = False
-    trace, rdiag = [], []
+    trace, rdiag, omegas = [], [], []
     chunk_lo = chunk_hi = 0
     e_start = E
     Om = G = H = Gnorm = None
@@ -234,6 +264,11 @@ def randqb_fp(A, tol_rel: float, b: int, seed: int, l_max=None, l_tilde: int = 0
             chunk_lo = k
             chunk_hi = k + w
             Om = omega(seed, n, chunk_lo, chunk_hi - chunk_lo)
+            if power > 0:                           # steps 3-6
+                Om = power_omega(A, Om, power, st.Q, st.B)
+                passes += 2 * power
+            if keep_omega:
+                omegas.append(Om.copy())
             if precision == "bf16":
                 Om = lowp.round_bf16(Om)
                 G = lowp.round_bf16(np.asarray(A @ Om))
@@ -263,7 +298,7 @@ def randqb_fp(A, tol_rel: float, b: int, seed: int, l_max=None, l_tilde: int = 0
             exhausted = exh
             break
     return _finish(st, E, normA2, status_tol, exhausted, l_max, st.k, eps2, passes=passes,
-                   blocks=blocks, chunks=chunks, E_trace=trace, R_diag=rdiag)
+                   blocks=blocks, chunks=chunks, E_trace=trace, R_diag=rdiag, omegas=omegas)
 
 
 def randqb_ei(A, tol_rel: float, b: int, seed: int, l_max=None,
