@@ -57,6 +57,7 @@ def main():
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-diff", action="store_true")
     ap.add_argument("--no-sparse", action="store_true")
+    ap.add_argument("--no-power", action="store_true")
     ap.add_argument("--gen-device", default="cuda", choices=["cuda", "cpu"],
                     help="where the seeded test matrix is generated (cpu keeps the GPU QR of the "
                          "generator out of counter-collection runs)")
@@ -88,12 +89,13 @@ def main():
     Qs = torch.empty((l_max, m), dtype=torch.float64, device=dev)
     Bs = torch.empty((l_max, n), dtype=torch.float64, device=dev)
     need = max(qb.qb_workspace_bytes(qb.QB_ALGO_FP, False, m, n, 0, wl.tol, wl.b, l_max, args.l_tilde),
+               qb.qb_workspace_bytes(qb.QB_ALGO_FP, False, m, n, 0, wl.tol, wl.b, l_max, args.l_tilde, 1),
                qb.qb_workspace_bytes(qb.QB_ALGO_EI, False, m, n, 0, wl.tol, wl.b, l_max))
     ws = torch.empty(need, dtype=torch.uint8, device=dev)
 
-    def fp(l_tilde=args.l_tilde):
+    def fp(l_tilde=args.l_tilde, power=0):
         return qb.qb_fp_dense(A, wl.tol, wl.b, seed, l_max=l_max, l_tilde=l_tilde,
-                              Q_store=Qs, B_store=Bs, ws=ws)
+                              Q_store=Qs, B_store=Bs, ws=ws, power=power)
 
     def ei():
         return qb.qb_ei_dense(A, wl.tol, wl.b, seed, l_max=l_max, Q_store=Qs, B_store=Bs, ws=ws)
@@ -186,6 +188,23 @@ def main():
                                           "total": rp.ms[5]}}
         print(f"# paper rule: {statistics.median(pt) * 1e3:.1f} ms rank {rp.rank}", file=sys.stderr,
               flush=True)
+    if not args.no_power:   # Algorithm 4's power scheme, P = 1, same schedule
+        fp(power=1)
+        torch.cuda.synchronize()
+        pw = []
+        for _ in range(max(1, min(args.steps, 3))):
+            t = time.perf_counter()
+            rq = fp(power=1)
+            torch.cuda.synchronize()
+            pw.append(time.perf_counter() - t)
+        res2 = float(torch.linalg.matrix_norm(A - rq.Q @ rq.B) ** 2)
+        out["power1"] = {"time_to_tol_s": round(statistics.median(pw), 6), "rank": rq.rank,
+                         "true_rel_err": (res2 / rq.normA2) ** 0.5, "passes": rq.passes,
+                         "chunks": rq.chunks, "fallbacks": rq.fallbacks,
+                         "phase_ms": {"power_rounds": rq.ms[6], "G": rq.ms[2], "H": rq.ms[3],
+                                      "block_loop": rq.ms[4], "total": rq.ms[5]}}
+        print(f"# power 1: {statistics.median(pw) * 1e3:.1f} ms rank {rq.rank} passes {rq.passes}",
+              file=sys.stderr, flush=True)
     if not args.no_ei:
         ei()
         torch.cuda.synchronize()
@@ -356,6 +375,7 @@ def sparse_block(qb, W, torch, steps=1):
     Qs = torch.empty((l_max, c.m), dtype=torch.float64, device=dev)
     Bs = torch.empty((l_max, c.n), dtype=torch.float64, device=dev)
     need = max(qb.qb_workspace_bytes(qb.QB_ALGO_FP, True, c.m, c.n, c.nnz, wl.tol, wl.b, l_max, 0),
+               qb.qb_workspace_bytes(qb.QB_ALGO_FP, True, c.m, c.n, c.nnz, wl.tol, wl.b, l_max, 0, 1),
                qb.qb_workspace_bytes(qb.QB_ALGO_EI, True, c.m, c.n, c.nnz, wl.tol, wl.b, l_max))
     ws = torch.empty(need, dtype=torch.uint8, device=dev)
     res = {"workload": wl.name, "l_max": l_max}
@@ -364,7 +384,10 @@ def sparse_block(qb, W, torch, steps=1):
             ("fp_adaptive", lambda: qb.qb_fp_csr(c.m, c.n, rowptr, colind, val, wl.tol, wl.b, seed,
                                                   l_max=l_max, l_tilde=-1, Q_store=Qs, B_store=Bs, ws=ws)),
             ("ei", lambda: qb.qb_ei_csr(c.m, c.n, rowptr, colind, val, wl.tol, wl.b, seed, l_max=l_max,
-                                        Q_store=Qs, B_store=Bs, ws=ws)))
+                                        Q_store=Qs, B_store=Bs, ws=ws)),
+            ("fp_power1", lambda: qb.qb_fp_csr(c.m, c.n, rowptr, colind, val, wl.tol, wl.b, seed,
+                                                l_max=l_max, l_tilde=0, Q_store=Qs, B_store=Bs, ws=ws,
+                                                power=1)))
     for name, fn in runs:
         torch.cuda.synchronize()
         ts, rs = [], []
@@ -379,7 +402,8 @@ def sparse_block(qb, W, torch, steps=1):
                  "E_rel": (max(r.E, 0.0) / r.normA2) ** 0.5, "status": r.status, "passes": r.passes,
                  "blocks": r.blocks, "chunks": r.chunks,
                  "phase_ms": {"normA2_and_csc": r.ms[0], "omega": r.ms[1], "A_X": r.ms[2],
-                              "At_X": r.ms[3], "block_loop": r.ms[4], "total": r.ms[5]}}
+                              "At_X": r.ms[3], "block_loop": r.ms[4], "power_rounds": r.ms[6],
+                              "total": r.ms[5]}}
         if name.startswith("fp"):
             # algorithmic bytes of the two SpMM passes per chunk: CSR arrays once, the dense
             # operand once, the dense result once

@@ -5,9 +5,11 @@
  * rank k adaptively so that ||A - QB||_F < tol ||A||_F, following Yu, Gu, Li,
  * "Efficient randomized algorithms for the fixed-precision low-rank matrix
  * approximation" (arXiv 1606.09402):
- *   - randQB_FP: Algorithm 4 with power parameter P = 0 (Algorithm 3 plus the
- *     re-orthogonalised steps 9a-9c, eq. (23)); one sweep G = A Omega, H = A^T G per
- *     chunk of Omega columns, then a block loop that touches only G, H, Omega, Q, B.
+ *   - randQB_FP: Algorithm 4 (Algorithm 3 plus the re-orthogonalised steps 9a-9c,
+ *     eq. (23)); one sweep G = A Omega, H = A^T G per chunk of Omega columns, then a
+ *     block loop that touches only G, H, Omega, Q, B.  With power parameter P > 0
+ *     (binary64 A only) each chunk first runs P rounds G = orth(A Omega),
+ *     Omega = orth(A^T G) (steps 3-6), on the residual A - QB after the first chunk.
  *   - randQB_EI: Algorithm 2, two passes over A per block.
  *   - both stop with the Frobenius error indicator of Theorem 1 / Algorithm 1,
  *     decremented row by row (Section 3.1, steps 7a-8e) unless row_by_row == 0.
@@ -102,7 +104,14 @@ typedef struct {
 typedef struct {
     double tol_rel;      /* stop when E < (tol_rel ||A||_F)^2 (strict), 0 <= tol_rel       */
     int32_t b;           /* block size, 1 <= b <= 128                                        */
-    int32_t power;       /* power-scheme parameter P of Algorithm 4; must be 0               */
+    int32_t power;       /* power-scheme parameter P of Algorithm 4 (steps 3-6), 0 <= P <= 16.
+                            P > 0 is accepted by randQB_FP on binary64 A (dense or CSR) and
+                            returns QB_ERR_UNSUPPORTED elsewhere.  Each chunk's Gaussian
+                            Omega is replaced by the result of P rounds
+                            G = orth((A - QB) Omega), Omega = orth((A - QB)^T G) (Q, B the
+                            factors so far; A itself in the first chunk), orth being the Q
+                            factor of a thin QR with positive diag(R); a chunk then costs
+                            2 P + 2 passes over A.                                          */
     int64_t l_max;       /* capacity of Q / B, 1 <= l_max <= min(m, n)                       */
     int64_t l_tilde;     /* randQB_FP chunk width: a multiple of b, or 0 for min(50 b, l_max)
                             (Section 5.4).  A chunk that runs out is followed by the next
@@ -122,14 +131,15 @@ typedef struct {
     double E;            /* final indicator ||A||^2 - ||B||^2 (may be negative, Section 3.3)  */
     double normA2;       /* ||A||_F^2                                                        */
     int32_t status;      /* same as the return value                                         */
-    int32_t passes;      /* passes over A (FP: 2 per chunk; EI: 2 per block)                 */
+    int32_t passes;      /* passes over A (FP: 2 P + 2 per chunk; EI: 2 per block)           */
     int32_t blocks;      /* blocks processed                                                 */
     int32_t chunks;      /* Omega chunks drawn (FP)                                          */
     int32_t exhausted;   /* 1 if R_i(j,j) <= 2^-40 ||A Omega(:,j)||_2 ended the run            */
-    int32_t fallbacks;   /* panels orthonormalised by the Householder fallback               */
+    int32_t fallbacks;   /* blocks (or power-scheme panels) redone by the Householder fallback */
     double ms[8];        /* device time per phase (ms): 0 ||A||^2, 1 Omega, 2 G = A Omega,
                             3 H = A^T G (EI: 2 = the A Omega_i GEMMs, 3 = the A^T Q_i GEMMs),
-                            4 block loop without 2-3, 5 whole call                           */
+                            4 block loop without 2-3, 5 whole call, 6 power-scheme rounds
+                            (their products with A and orthonormalisations)                  */
     double gemm_flops[2];/* algorithmic flops of the timed G and H GEMMs (2 m n l each)      */
 } qb_info;
 

@@ -259,11 +259,12 @@ def qb_ei_dense(A: torch.Tensor, tol: float, b: int, seed: int, l_max=None, row_
 
 
 def qb_fp_csr(m: int, n: int, rowptr, colind, val, tol: float, b: int, seed: int, l_max=None,
-              l_tilde: int = 0, row_by_row: bool = True, Q_store=None, B_store=None, ws=None) -> QBResult:
+              l_tilde: int = 0, row_by_row: bool = True, Q_store=None, B_store=None, ws=None,
+              power: int = 0) -> QBResult:
     """randQB_FP on a CSR matrix (rowptr int64, colind int32, val float64; GPU tensors)."""
     c = _csr(m, n, rowptr, colind, val)
     return _run("qb_fp_csr", QB_ALGO_FP, True, c, m, n, val.device, tol, b, l_max, l_tilde, seed,
-                row_by_row, Q_store, B_store, ws)
+                row_by_row, Q_store, B_store, ws, power)
 
 
 def qb_ei_csr(m: int, n: int, rowptr, colind, val, tol: float, b: int, seed: int, l_max=None,
@@ -275,15 +276,16 @@ def qb_ei_csr(m: int, n: int, rowptr, colind, val, tol: float, b: int, seed: int
 
 
 def qb_workspace_bytes(algo: int, sparse: bool, m: int, n: int, nnz: int, tol: float, b: int,
-                       l_max: int, l_tilde: int = 0) -> int:
-    p = _params(tol, b, l_max, l_tilde, 0, True)
+                       l_max: int, l_tilde: int = 0, power: int = 0) -> int:
+    p = _params(tol, b, l_max, l_tilde, 0, True, power)
     return int(lib().qb_workspace_bytes(algo, 1 if sparse else 0, m, n, nnz, ctypes.byref(p)))
 
 
 def qb_dense_workspace_bytes(algo: int, A: torch.Tensor, tol: float, b: int, l_max: int,
-                             l_tilde: int = 0, row_exp: torch.Tensor | None = None) -> int:
+                             l_tilde: int = 0, row_exp: torch.Tensor | None = None,
+                             power: int = 0) -> int:
     """Workspace bytes of qb_fp_dense / qb_ei_dense for this A (any supported dtype)."""
-    p = _params(tol, b, l_max, l_tilde, 0, True)
+    p = _params(tol, b, l_max, l_tilde, 0, True, power)
     return int(lib().qb_dense_workspace_bytes(algo, ctypes.byref(_dense(A, row_exp)), ctypes.byref(p)))
 
 

@@ -22,6 +22,7 @@ constexpr double kExhaustRel = 0x1p-40;     // R_i(j,j) <= 2^-40 ||A Omega(:,j)|
 constexpr double kCholTau = 1e-12;          // CholeskyQR pivot floor relative to max diag
 constexpr double kUnitRoundoff = 0x1p-53;
 constexpr int64_t kGramSplitElems = 1 << 22;
+constexpr int kMaxPower = 16;               // largest power-scheme parameter P accepted
 
 #define QB_HIP(expr)                                  \
     do {                                              \
@@ -112,8 +113,11 @@ Layout make_layout(int algo, int sparse, int dtype, int64_t m, int64_t n, int64_
     L.h = algo == QB_ALGO_FP ? take(sizeof(double) * n * lt) : take(0);
     L.gpart = take(sizeof(double) * L.gpart_groups * lt);
     L.gnorm2 = take(sizeof(double) * lt);
-    L.y = take(sizeof(double) * m * b);
-    L.x2 = take(sizeof(double) * m * b);
+    // panels of b columns: m rows, or max(m, n) when the power scheme also orthonormalises
+    // n-row panels (Omega = orth(A^T G))
+    const int64_t prow = p->power > 0 && n > m ? n : m;
+    L.y = take(sizeof(double) * prow * b);
+    L.x2 = take(sizeof(double) * prow * b);
     L.s = take(sizeof(double) * b * n);
     L.w = take(sizeof(double) * lmax * b);
     L.z = take(sizeof(double) * lmax * b);
@@ -283,18 +287,22 @@ int sketch_bf16(const Ctx& x, double* Om, double* G, double* H, int64_t w, doubl
 
 // CholeskyQR of the m x bw column-major panel X (ld m) into Qout (column-major, ld ldq):
 // gram = X^T X, R, R^{-1}, Qout = X R^{-1}.  A breakdown sets flags[0].
-int cholqr(const Ctx& x, const double* X, int bw, double* Qout, int64_t ldq, double* R,
-           double* Rinv) {
-    const int64_t m = x.A.m;
+// General form: X is any rows x bw view, Qout any rows x bw destination (not aliasing X).
+int cholqr_v(const Ctx& x, int64_t rows, View X, int bw, MutView Qout, double* R, double* Rinv) {
     double* gram = x.at<double>(x.L.gram);
-    GemmDesc d = gdesc(bw, bw, m, View{X, m, 1}, View{X, 1, m}, 1.0, 0.0, View{nullptr, 0, 0},
+    GemmDesc d = gdesc(bw, bw, rows, View{X.p, X.sj, X.si}, X, 1.0, 0.0, View{nullptr, 0, 0},
                        MutView{gram, bw, 1}, x);
     QB_HIP(gemm_f64(d, x.s));
     QB_HIP(launch_chol_inv(gram, bw, kCholTau, R, Rinv, x.at<int>(x.L.flags), x.s));
-    GemmDesc q = gdesc(m, bw, bw, View{X, 1, m}, View{Rinv, bw, 1}, 1.0, 0.0, View{nullptr, 0, 0},
-                       MutView{Qout, 1, ldq}, x);
+    GemmDesc q = gdesc(rows, bw, bw, X, View{Rinv, bw, 1}, 1.0, 0.0, View{nullptr, 0, 0}, Qout, x);
     QB_HIP(gemm_f64(q, x.s));
     return QB_OK;
+}
+
+int cholqr(const Ctx& x, const double* X, int bw, double* Qout, int64_t ldq, double* R,
+           double* Rinv) {
+    const int64_t m = x.A.m;
+    return cholqr_v(x, m, View{X, 1, m}, bw, MutView{Qout, 1, ldq}, R, Rinv);
 }
 
 // Steps 11-14 of Algorithm 4 (steps 5-6 of Algorithm 2): given G_J (m x bw, row-major,
@@ -421,6 +429,116 @@ int ei_block_b(const Ctx& x, int64_t k, int bw) {
     return QB_OK;
 }
 
+// dst = src - V (V^T src) for a rows x bw panel src and a rows x kb basis V (views of V and
+// of V^T given); dst may be src itself (the update is elementwise).
+int project_out(const Ctx& x, int64_t rows, int bw, View src, MutView dst, View V, View Vt,
+                int64_t kb) {
+    if (kb == 0) {
+        if (dst.p != src.p) {
+            GemmDesc c = gdesc(rows, bw, 0, View{nullptr, 0, 0}, View{nullptr, 0, 0}, 0.0, 1.0, src,
+                               dst, x);
+            QB_HIP(gemm_f64(c, x.s));
+        }
+        return QB_OK;
+    }
+    double* Z = x.at<double>(x.L.z);
+    GemmDesc d = gdesc(kb, bw, rows, Vt, src, 1.0, 0.0, View{nullptr, 0, 0}, MutView{Z, bw, 1}, x);
+    QB_HIP(gemm_f64(d, x.s));
+    GemmDesc u = gdesc(rows, bw, kb, V, View{Z, bw, 1}, -1.0, 1.0, src, dst, x);
+    QB_HIP(gemm_f64(u, x.s));
+    return QB_OK;
+}
+
+// orth() of Algorithm 4 steps 4-5 on the rows x w row-major panel X (ld ldx), in place:
+// block Gram-Schmidt over b-column blocks, each block projected twice against Q(:, 0:kq)
+// and the blocks already done, and orthonormalised after each projection by CholeskyQR
+// (or, with use_hh, by Householder QR).  Block j of the result depends only on blocks
+// 0..j of X and has diag(R) > 0, as the Q factor of a Householder QR of [Q, X] would.
+// A CholeskyQR breakdown sets the flag; the caller then redoes the panel with use_hh.
+int orth_panel(const Ctx& x, double* X, int64_t rows, int64_t w, int64_t ldx, int64_t kq,
+               bool use_hh) {
+    const int b = x.p->b;
+    double* Y = x.at<double>(x.L.y);     // rows x b, column-major
+    double* X2 = x.at<double>(x.L.x2);   // rows x b, column-major
+    double* tau = x.at<double>(x.L.tau);
+    const View Qv{x.Q, 1, x.ldq}, Qt{x.Q, x.ldq, 1};
+    const View Pv{X, ldx, 1}, Pt{X, 1, ldx};   // the finished blocks of X
+    for (int64_t j0 = 0; j0 < w; j0 += b) {
+        const int bw = static_cast<int>(b < w - j0 ? b : w - j0);
+        const View Xj{X + j0, ldx, 1};
+        const MutView Xjm{X + j0, ldx, 1};
+        const View Yv{Y, 1, rows};
+        const MutView Ym{Y, 1, rows};
+        const View X2v{X2, 1, rows};
+        const MutView X2m{X2, 1, rows};
+        // first projection, in place, then qr into Y
+        if (int e = project_out(x, rows, bw, Xj, Xjm, Qv, Qt, kq)) return e;
+        if (int e = project_out(x, rows, bw, Xj, Xjm, Pv, Pt, j0)) return e;
+        if (!use_hh) {
+            if (int e = cholqr_v(x, rows, Xj, bw, Ym, x.at<double>(x.L.r1), x.at<double>(x.L.r1i)))
+                return e;
+        } else {
+            if (int e = project_out(x, rows, bw, Xj, X2m, Pv, Pt, 0)) return e;   // copy
+            QB_HIP(launch_householder(X2, rows, bw, rows, Y, rows, x.at<double>(x.L.r1), tau, x.s));
+        }
+        // re-orthogonalisation: X2 = Y - Q (Q^T Y) - P (P^T .), then qr into block j of X
+        if (int e = project_out(x, rows, bw, Yv, X2m, Qv, Qt, kq)) return e;
+        if (int e = project_out(x, rows, bw, X2v, X2m, Pv, Pt, j0)) return e;
+        if (!use_hh) {
+            if (int e = cholqr_v(x, rows, X2v, bw, Xjm, x.at<double>(x.L.rt), x.at<double>(x.L.rti)))
+                return e;
+        } else {
+            QB_HIP(launch_householder(X2, rows, bw, rows, Y, rows, x.at<double>(x.L.rt), tau, x.s));
+            if (int e = project_out(x, rows, bw, Yv, Xjm, Pv, Pt, 0)) return e;   // copy
+        }
+    }
+    return QB_OK;
+}
+
+// Whether some CholeskyQR since the last reset broke down (waits for the stream).
+int read_flag(const Ctx& x, bool* broken) {
+    int* hflag = reinterpret_cast<int*>(x.host_info + 3 * kMaxB);
+    QB_HIP(hipMemcpyAsync(hflag, x.at<int>(x.L.flags), sizeof(int), hipMemcpyDeviceToHost, x.s));
+    QB_HIP(hipStreamSynchronize(x.s));
+    *broken = *hflag != 0;
+    return QB_OK;
+}
+
+// Steps 3-6 of Algorithm 4 for one chunk of w columns: P rounds of
+// G = orth(A Omega) and Omega = orth(A^T G).  After the first chunk (k > 0) the rounds act
+// on the residual A - Q B: G is also made orthogonal to Q(:, 0:k), and then
+// (A - QB)^T G = A^T G because B = Q^T A.  Omega and H are swapped in every round (the
+// new Omega is formed in the H buffer); on return Omega points at the final iterate.
+int power_rounds(const Ctx& x, int64_t k, int64_t w, double*& Om, double*& H, double* G,
+                 double* gnorm2) {
+    const int64_t m = x.A.m, n = x.A.n;
+    for (int r = 0; r < x.p->power; ++r) {
+        for (int side = 0; side < 2; ++side) {
+            for (int attempt = 0; attempt < 2; ++attempt) {
+                const bool use_hh = attempt == 1;
+                if (use_hh) {
+                    QB_HIP(launch_fill_int(x.at<int>(x.L.flags), 8, 0, x.s));
+                    x.info->fallbacks += 1;
+                }
+                if (side == 0) {   // G = orth((I - Q Q^T) A Omega)
+                    if (int e = apply_A(x, Om, w, G, w, w, gnorm2)) return e;
+                    if (int e = orth_panel(x, G, m, w, w, k, use_hh)) return e;
+                } else {           // Omega = orth(A^T G)
+                    if (int e = apply_At(x, G, w, H, w, w)) return e;
+                    if (int e = orth_panel(x, H, n, w, w, 0, use_hh)) return e;
+                }
+                bool broken = false;
+                if (int e = read_flag(x, &broken)) return e;
+                if (!broken) break;
+            }
+        }
+        double* t = Om;
+        Om = H;
+        H = t;
+    }
+    return QB_OK;
+}
+
 // Copy the per-block decision data to the host and wait.  Returns QB_OK or QB_ERR_HIP;
 // *breakdown tells whether CholeskyQR failed in this block.
 int fetch_block(const Ctx& x, int bw, const double* gnorm2_j, bool* breakdown) {
@@ -467,7 +585,7 @@ void scan_rows(const double* hinfo, int bw, bool row_by_row, double eps2, double
 
 int check_params(const qb_params* p, int64_t m, int64_t n) {
     if (p == nullptr) return QB_ERR_ARG;
-    if (p->power != 0) return QB_ERR_UNSUPPORTED;
+    if (p->power < 0 || p->power > kMaxPower) return QB_ERR_ARG;
     if (!(p->tol_rel >= 0.0) || !isfinite(p->tol_rel)) return QB_ERR_ARG;
     if (p->b < 1 || p->b > kMaxB) return QB_ERR_ARG;
     const int64_t mn = m < n ? m : n;
@@ -499,6 +617,9 @@ int run(int algo, Op& A, const qb_params* p, double* Q, int64_t ldq, double* B, 
     int st = check_params(p, A.m, A.n);
     if (st != QB_OK) return inf->status = st;
     if (A.dtype != QB_F64 && (algo != QB_ALGO_FP || A.sparse)) return inf->status = QB_ERR_UNSUPPORTED;
+    // the power scheme is Algorithm 4's (randQB_FP), on binary64 A
+    if (p->power > 0 && (algo != QB_ALGO_FP || A.dtype != QB_F64))
+        return inf->status = QB_ERR_UNSUPPORTED;
     if (Q == nullptr || B == nullptr || ws == nullptr || ldq < A.m || ldb < A.n)
         return inf->status = QB_ERR_ARG;
     if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return inf->status = QB_ERR_ARG;
@@ -567,6 +688,11 @@ int run(int algo, Op& A, const qb_params* p, double* Q, int64_t ldq, double* B, 
                     e_chunk_start = E;
                     tm.mark(1);
                     QB_HIP(launch_gauss_fill(p->seed, 0, 0, 0, chunk_lo, n, w, Om, w, s));
+                    if (p->power > 0) {
+                        tm.mark(6);
+                        if (int e = power_rounds(x, k, w, Om, H, G, gnorm2)) return inf->status = e;
+                        inf->passes += 2 * p->power;
+                    }
                     if (A.dtype == QB_BF16 || A.dtype == QB_FP8E4M3) {
                         if (int e = sketch_bf16(x, Om, G, H, w, gnorm2, true)) return inf->status = e;
                     } else {

@@ -71,10 +71,20 @@ def test_entry_points_reject_bad_arguments_without_gpu():
     assert L.qb_fp_dense(ctypes.byref(d), ctypes.byref(p), None, 0, None, 0, None, 0, None, None) == -1
     d = qb.QbDense(100, 50, 50, 7, 0, 1 << 20)          # unknown element type
     assert L.qb_fp_dense(ctypes.byref(d), ctypes.byref(p), None, 0, None, 0, None, 0, None, None) == -5
-    p_pow = qb.QbParams(1e-2, 20, 1, 10, 0, 1, 1, 0)   # power scheme not on this path
+    # the power scheme is randQB_FP's on binary64 A: EI and the bfloat16 form reject P > 0,
+    # and P outside [0, 16] is a bad argument, all before any device work
+    p_pow = qb.QbParams(1e-2, 20, 1, 10, 0, 1, 1, 0)
     d = qb.QbDense(100, 50, 50, 0, 0, 1 << 20)
-    assert L.qb_fp_dense(ctypes.byref(d), ctypes.byref(p_pow), 1 << 20, 100, 1 << 20, 50, 1 << 20, 1 << 30,
+    assert L.qb_ei_dense(ctypes.byref(d), ctypes.byref(p_pow), 1 << 20, 100, 1 << 20, 50, 1 << 20, 1 << 30,
                          None, None) == -5
+    d16 = qb.QbDense(100, 50, 50, 1, 0, 1 << 20)
+    assert L.qb_fp_dense(ctypes.byref(d16), ctypes.byref(p_pow), 1 << 20, 100, 1 << 20, 50, 1 << 20,
+                         1 << 30, None, None) == -5
+    for bad in (-1, 17):
+        p_bad = qb.QbParams(1e-2, 20, bad, 10, 0, 1, 1, 0)
+        assert L.qb_fp_dense(ctypes.byref(d), ctypes.byref(p_bad), 1 << 20, 100, 1 << 20, 50, 1 << 20,
+                             1 << 30, None, None) == -1
+        assert L.qb_workspace_bytes(0, 0, 100, 50, 0, ctypes.byref(p_bad)) == 0
     c = qb.QbCsr(100, 50, 10, None, None, None)
     assert L.qb_fp_csr(ctypes.byref(c), ctypes.byref(p), None, 0, None, 0, None, 0, None, None) == -1
     assert L.qb_gaussian_fill(1, 0, 0, 0, 0, 4, 4, None, 4, None) == -1

@@ -191,7 +191,7 @@ def test_degenerate_inputs(qb):
         qb.qb_fp_dense(bad, 1e-2, 4, SEED)
     assert e.value.status == qb.QB_ERR_NONFINITE
     with pytest.raises(qb.QBError) as e:
-        qb.qb_fp_dense(A, 1e-2, 4, SEED, power=1)
+        qb.qb_ei_dense(A, 1e-2, 4, SEED, power=1)
     assert e.value.status == qb.QB_ERR_UNSUPPORTED
 
 
