@@ -23,6 +23,7 @@ constexpr double kCholTau = 1e-12;          // CholeskyQR pivot floor relative t
 constexpr double kUnitRoundoff = 0x1p-53;
 constexpr int64_t kGramSplitElems = 1 << 22;
 constexpr int kMaxPower = 16;               // largest power-scheme parameter P accepted
+constexpr int kPowerBlock = 128;            // column block of the power-scheme orth()
 
 #define QB_HIP(expr)                                  \
     do {                                              \
@@ -113,23 +114,25 @@ Layout make_layout(int algo, int sparse, int dtype, int64_t m, int64_t n, int64_
     L.h = algo == QB_ALGO_FP ? take(sizeof(double) * n * lt) : take(0);
     L.gpart = take(sizeof(double) * L.gpart_groups * lt);
     L.gnorm2 = take(sizeof(double) * lt);
-    // panels of b columns: m rows, or max(m, n) when the power scheme also orthonormalises
-    // n-row panels (Omega = orth(A^T G))
-    const int64_t prow = p->power > 0 && n > m ? n : m;
-    L.y = take(sizeof(double) * prow * b);
-    L.x2 = take(sizeof(double) * prow * b);
+    // panels of b columns of m rows; the power scheme's orth() also takes n-row panels
+    // (Omega = orth(A^T G)) in blocks of kPowerBlock columns
+    const bool pw = p->power > 0;
+    const int64_t prow = pw && n > m ? n : m;
+    const int64_t pb = pw && b < kPowerBlock ? kPowerBlock : b;   // widest panel block
+    L.y = take(sizeof(double) * prow * pb);
+    L.x2 = take(sizeof(double) * prow * pb);
     L.s = take(sizeof(double) * b * n);
     L.w = take(sizeof(double) * lmax * b);
-    L.z = take(sizeof(double) * lmax * b);
+    L.z = take(sizeof(double) * lmax * pb);
     L.d = take(sizeof(double) * lmax * b);
-    L.gram = take(sizeof(double) * b * b);
-    L.r1 = take(sizeof(double) * b * b);
-    L.r1i = take(sizeof(double) * b * b);
-    L.rt = take(sizeof(double) * b * b);
-    L.rti = take(sizeof(double) * b * b);
+    L.gram = take(sizeof(double) * pb * pb);
+    L.r1 = take(sizeof(double) * pb * pb);
+    L.r1i = take(sizeof(double) * pb * pb);
+    L.rt = take(sizeof(double) * pb * pb);
+    L.rti = take(sizeof(double) * pb * pb);
     L.ri = take(sizeof(double) * b * b);
     L.rii = take(sizeof(double) * b * b);
-    L.tau = take(sizeof(double) * b);
+    L.tau = take(sizeof(double) * pb);
     L.rowsq_part = take(sizeof(double) * nb_part * b);
     L.rowsq = take(sizeof(double) * b);
     L.info = take(sizeof(double) * 3 * b);
@@ -450,16 +453,17 @@ int project_out(const Ctx& x, int64_t rows, int bw, View src, MutView dst, View 
 }
 
 // orth() of Algorithm 4 steps 4-5 on the rows x w row-major panel X (ld ldx), in place:
-// block Gram-Schmidt over b-column blocks, each block projected twice against Q(:, 0:kq)
+// block Gram-Schmidt over kPowerBlock-column blocks (the widest the CholeskyQR kernel
+// takes, so that the projections are wide GEMMs), each projected twice against Q(:, 0:kq)
 // and the blocks already done, and orthonormalised after each projection by CholeskyQR
 // (or, with use_hh, by Householder QR).  Block j of the result depends only on blocks
 // 0..j of X and has diag(R) > 0, as the Q factor of a Householder QR of [Q, X] would.
 // A CholeskyQR breakdown sets the flag; the caller then redoes the panel with use_hh.
 int orth_panel(const Ctx& x, double* X, int64_t rows, int64_t w, int64_t ldx, int64_t kq,
                bool use_hh) {
-    const int b = x.p->b;
-    double* Y = x.at<double>(x.L.y);     // rows x b, column-major
-    double* X2 = x.at<double>(x.L.x2);   // rows x b, column-major
+    const int b = kPowerBlock;
+    double* Y = x.at<double>(x.L.y);     // rows x kPowerBlock, column-major
+    double* X2 = x.at<double>(x.L.x2);   // rows x kPowerBlock, column-major
     double* tau = x.at<double>(x.L.tau);
     const View Qv{x.Q, 1, x.ldq}, Qt{x.Q, x.ldq, 1};
     const View Pv{X, ldx, 1}, Pt{X, 1, ldx};   // the finished blocks of X
