@@ -38,7 +38,8 @@ size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 struct Layout {
     size_t red, scal, om, g, h, gpart, gnorm2, y, x2, s, w, z, d, gram, r1, r1i, rt, rti, ri, rii, tau,
         rowsq_part, rowsq, info, flags, split, csc, plan_a, plan_t, omt, gqt, total;
-    int64_t lt, split_elems, gpart_groups;
+    size_t split2;          // split-K partials of the products issued on the side stream
+    int64_t lt, split_elems, split2_elems, gpart_groups;
     int64_t ldm16, ldn16;   // row strides (elements) of the bfloat16 copies: m, n rounded to 8
 };
 
@@ -92,6 +93,9 @@ Layout make_layout(int algo, int sparse, int dtype, int64_t m, int64_t n, int64_
     L.split_elems = 512 * b * (b > 64 ? b : 64) + 65536;
     if (L.split_elems < kGramSplitElems) L.split_elems = kGramSplitElems;
     if (L.split_elems < 8 * (m > n ? m : n) * b) L.split_elems = 8 * (m > n ? m : n) * b;
+    // randQB_FP overlaps D = Q^T Y + W and S = H_J - B^T D with the panel QR on a second
+    // stream: those products get their own partials buffer
+    L.split2_elems = algo == QB_ALGO_FP ? L.split_elems : 0;
     // dense randQB_FP: room for two K splits of the widest sketch GEMM (G, m x l~)
     if (algo == QB_ALGO_FP && !sparse && !lowp && L.split_elems < 2 * (m > n ? m : n) * lt)
         L.split_elems = 2 * (m > n ? m : n) * lt;
@@ -138,6 +142,7 @@ Layout make_layout(int algo, int sparse, int dtype, int64_t m, int64_t n, int64_
     L.info = take(sizeof(double) * 3 * b);
     L.flags = take(sizeof(int) * 8);
     L.split = take(sizeof(double) * L.split_elems);
+    L.split2 = take(sizeof(double) * L.split2_elems);
     L.csc = sparse ? take(csc_layout(m, n, nnz).total) : take(0);
     // segment plans of CSR(A) and CSR(A^T) for the balanced SpMM (widest product: l~ or b)
     L.plan_a = sparse ? take(spmm_plan_bytes(m, nnz, lt)) : take(0);
@@ -217,6 +222,8 @@ struct Ctx {
     qb_info* info;
     Timer* tm;
     double* host_info;   // 3 b doubles + flags
+    hipStream_t side = nullptr;   // randQB_FP: stream of the D, S products (or none)
+    hipEvent_t ev_y = nullptr, ev_s = nullptr;
     template <class T>
     T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
 };
@@ -312,8 +319,10 @@ int cholqr(const Ctx& x, const double* X, int bw, double* Qout, int64_t ldq, dou
 // ld ldgj) and Omega_J (n x bw, row-major, ld ldoj), form W = B Omega_J,
 // Y = G_J - Q W (kept in the y buffer), Q_i = qr(Y), Q_i = qr(Q_i - Q (Q^T Q_i)) and
 // R_i = R~ R.  use_hh selects Householder instead of CholeskyQR for both qr calls.
+int fp_block_ds(const Ctx& x, int64_t k, int bw, const double* HJ, int64_t ldhj);
+
 int orth_block(const Ctx& x, int64_t k, int bw, const double* GJ, int64_t ldgj, const double* OmJ,
-               int64_t ldoj, bool use_hh) {
+               int64_t ldoj, bool use_hh, const double* HJ, int64_t ldhj) {
     const int64_t m = x.A.m, n = x.A.n;
     double* Y = x.at<double>(x.L.y);
     double* X2 = x.at<double>(x.L.x2);
@@ -336,6 +345,10 @@ int orth_block(const Ctx& x, int64_t k, int bw, const double* GJ, int64_t ldgj, 
         GemmDesc d = gdesc(m, bw, k, View{x.Q, 1, x.ldq}, View{W, bw, 1}, -1.0, 1.0,
                            View{GJ, ldgj, 1}, MutView{Y, 1, m}, x);
         QB_HIP(gemm_f64(d, x.s));
+    }
+    // randQB_FP: the parts of eq. (23) that need only Y and W, beside the QR below
+    if (HJ != nullptr) {
+        if (int st = fp_block_ds(x, k, bw, HJ, ldhj)) return st;
     }
     // first qr
     if (!use_hh) {
@@ -368,26 +381,51 @@ int orth_block(const Ctx& x, int64_t k, int bw, const double* GJ, int64_t ldgj, 
 }
 
 // Step 15 of Algorithm 4 (eq. (23)):
-//   B_i = R_i^{-T} (H_J^T - (Y^T Q) B - W^T B) = R_i^{-T} (H_J^T - D^T B),  D = Q^T Y + W,
-// written to rows k..k+bw of B with the row sums of squares into the rowsq buffer.
-int fp_block_b(const Ctx& x, int64_t k, int bw, const double* HJ, int64_t ldhj) {
+//   B_i = R_i^{-T} (H_J^T - (Y^T Q) B - W^T B) = R_i^{-T} (H_J^T - D^T B),  D = Q^T Y + W.
+// fp_block_ds forms D and S = H_J^T - D^T B; they need only Y and W, so when the context has
+// a side stream they run there, beside the panel QR of Y on the main stream (the two touch
+// disjoint buffers: Q(:, 0:k), Y, W, B and H are only read, D and S only written, and the
+// side products have their own split-K partials).
+int fp_block_ds(const Ctx& x, int64_t k, int bw, const double* HJ, int64_t ldhj) {
     const int64_t m = x.A.m, n = x.A.n;
     double* Y = x.at<double>(x.L.y);
     double* W = x.at<double>(x.L.w);
     double* D = x.at<double>(x.L.d);
     double* S = x.at<double>(x.L.s);
+    hipStream_t st = x.s;
+    if (x.side != nullptr) {
+        QB_HIP(hipEventRecord(x.ev_y, x.s));
+        QB_HIP(hipStreamWaitEvent(x.side, x.ev_y, 0));
+        st = x.side;
+    }
+    auto side_ws = [&](GemmDesc& d) {
+        if (x.side != nullptr) {
+            d.ws = x.at<double>(x.L.split2);
+            d.ws_elems = x.L.split2_elems;
+        }
+    };
     if (k > 0) {   // D (k x bw) = Q^T Y + W
         GemmDesc d = gdesc(k, bw, m, View{x.Q, x.ldq, 1}, View{Y, 1, m}, 1.0, 1.0, View{W, bw, 1},
                            MutView{D, bw, 1}, x);
-        QB_HIP(gemm_f64(d, x.s));
+        side_ws(d);
+        QB_HIP(gemm_f64(d, st));
     }
     {   // S^T (n x bw) = H_J - B^T D, stored as S (bw x n row-major)
         GemmDesc d = gdesc(n, bw, k, View{x.B, 1, x.ldb}, View{D, bw, 1}, -1.0, 1.0,
                            View{HJ, ldhj, 1}, MutView{S, 1, n}, x);
-        QB_HIP(gemm_f64(d, x.s));
+        side_ws(d);
+        QB_HIP(gemm_f64(d, st));
     }
-    // B_i^T = S^T R_i^{-1} (the triangular solve R_i^T B_i = S), written to rows k.. of B
-    // with the column sums of squares = ||B_i(j,:)||^2
+    if (x.side != nullptr) QB_HIP(hipEventRecord(x.ev_s, x.side));
+    return QB_OK;
+}
+
+// B_i^T = S^T R_i^{-1} (the triangular solve R_i^T B_i = S), written to rows k..k+bw of B
+// with the row sums of squares ||B_i(j,:)||^2 into the rowsq buffer.
+int fp_block_b(const Ctx& x, int64_t k, int bw) {
+    const int64_t n = x.A.n;
+    double* S = x.at<double>(x.L.s);
+    if (x.side != nullptr) QB_HIP(hipStreamWaitEvent(x.s, x.ev_s, 0));
     double* part = x.at<double>(x.L.rowsq_part);
     int groups = 0;
     GemmDesc d = gdesc(n, bw, bw, View{S, 1, n}, View{x.at<double>(x.L.rii), bw, 1}, 1.0, 0.0,
@@ -587,6 +625,30 @@ void scan_rows(const double* hinfo, int bw, bool row_by_row, double eps2, double
     if (!row_by_row && Et < eps2) *stop = true;
 }
 
+// The second stream and its two events for the randQB_FP block loop, released on every
+// return path.  Non-blocking, so that only the explicit events order it against the caller's
+// stream (which may be the legacy default stream); default priority.  If it cannot be made,
+// the products run on the caller's stream.
+struct SideStream {
+    hipStream_t s = nullptr;
+    hipEvent_t ev_y = nullptr, ev_s = nullptr;
+    void make() {
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) s = nullptr;
+        if (s != nullptr && (hipEventCreateWithFlags(&ev_y, hipEventDisableTiming) != hipSuccess ||
+                             hipEventCreateWithFlags(&ev_s, hipEventDisableTiming) != hipSuccess))
+            release();
+        (void)hipGetLastError();
+    }
+    void release() {
+        if (ev_y) (void)hipEventDestroy(ev_y);
+        if (ev_s) (void)hipEventDestroy(ev_s);
+        if (s) (void)hipStreamDestroy(s);
+        s = nullptr;
+        ev_y = ev_s = nullptr;
+    }
+    ~SideStream() { release(); }
+};
+
 int check_params(const qb_params* p, int64_t m, int64_t n) {
     if (p == nullptr) return QB_ERR_ARG;
     if (p->power < 0 || p->power > kMaxPower) return QB_ERR_ARG;
@@ -655,7 +717,9 @@ int run(int algo, Op& A, const qb_params* p, double* Q, int64_t ldq, double* B, 
         QB_HIP(spmm_plan_build(A.rowptr, m, A.nnz, L.lt, wsb + L.plan_a, s, &A.plan_a));
         QB_HIP(spmm_plan_build(A.t_ptr, n, A.nnz, L.lt, wsb + L.plan_t, s, &A.plan_t));
     }
-    const Ctx x{A, p, Q, ldq, B, ldb, wsb, L, s, inf, &tm, host};
+    SideStream side;
+    if (algo == QB_ALGO_FP) side.make();
+    const Ctx x{A, p, Q, ldq, B, ldb, wsb, L, s, inf, &tm, host, side.s, side.ev_y, side.ev_s};
     QB_HIP(hipMemcpyAsync(host, scal, sizeof(double), hipMemcpyDeviceToHost, s));
     QB_HIP(hipStreamSynchronize(s));
     const double normA2 = host[0];
@@ -741,9 +805,11 @@ int run(int algo, Op& A, const qb_params* p, double* Q, int64_t ldq, double* B, 
                     QB_HIP(launch_fill_int(x.at<int>(L.flags), 8, 0, s));
                     inf->fallbacks += 1;
                 }
-                if (int e = orth_block(x, k, bwi, GJ, ldj, OmJ, ldj, use_hh)) return inf->status = e;
+                if (int e = orth_block(x, k, bwi, GJ, ldj, OmJ, ldj, use_hh,
+                                       algo == QB_ALGO_FP ? HJ : nullptr, ldj))
+                    return inf->status = e;
                 if (algo == QB_ALGO_FP) {
-                    if (int e = fp_block_b(x, k, bwi, HJ, ldj)) return inf->status = e;
+                    if (int e = fp_block_b(x, k, bwi)) return inf->status = e;
                 } else {
                     tm.mark(3);
                     if (int e = ei_block_b(x, k, bwi)) return inf->status = e;
