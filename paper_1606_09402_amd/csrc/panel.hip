@@ -47,8 +47,9 @@ QB_DEV bool chol_slots(double (&v)[RegLayout<BMAX>::Q], double (*row)[BMAX], dou
             const double ir = 1.0 / rjj;
             const double rc = row[buf][c] * ir;       // R(j, c) for c >= j
             if (g == 0) Rs[j * ld + c] = (c >= j && c < b) ? (c == j ? rjj : rc) : 0.0;
+            // rows a = g + G q with q < Q0 lie above j and are final
 #pragma unroll
-            for (int q = 0; q < L::Q; ++q) {
+            for (int q = Q0; q < L::Q; ++q) {
                 const int a = g + L::G * q;
                 const double upd = v[q] - (row[buf][a] * ir) * rc;
                 v[q] = (a > j && c >= a) ? upd : v[q];
@@ -76,8 +77,9 @@ QB_DEV void inv_slots(double (&v)[RegLayout<BMAX>::Q], double (*row)[BMAX], cons
             __syncthreads();
             const double xc = row[buf][c];
             if (g == 0 && c < b) Rinv[i * b + c] = c >= i ? xc : 0.0;
+            // rows a = g + G q with q > Q0 lie below i and are final
 #pragma unroll
-            for (int q = 0; q < L::Q; ++q) {
+            for (int q = 0; q <= Q0; ++q) {
                 const int a = g + L::G * q;
                 const double upd = v[q] - Rs[a * ld + i] * xc;
                 v[q] = a < i ? upd : v[q];
