@@ -290,6 +290,40 @@ __global__ void __launch_bounds__(64 * WM * WN, OCC) gemm_f64_kernel(const GemmA
     }
 }
 
+// Fixed-order sum of split-K partials for small outputs with many splits: 8 threads per
+// element (thread r sums splits r, r + 8, ... in order), the 8 sums then added in the order
+// r = 0..7 through LDS.  A wave reads 32 consecutive elements of two partials.
+constexpr int kRedLanes = 8;
+__global__ void __launch_bounds__(256)
+splitk_reduce_wide_kernel(const double* __restrict__ P, int nsplit, int64_t M, int64_t N,
+                          double alpha, double beta, const double* C0, int64_t c0_si,
+                          int64_t c0_sj, double* C, int64_t c_si, int64_t c_sj) {
+    constexpr int EPB = 256 / kRedLanes;   // elements per block
+    __shared__ double part[kRedLanes][EPB];
+    const int el = threadIdx.x % EPB, r = threadIdx.x / EPB;
+    const int64_t mn = M * N;
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * EPB + el;
+    double t0 = 0.0, t1 = 0.0;
+    if (e < mn) {
+        int s = r;
+        for (; s + kRedLanes < nsplit; s += 2 * kRedLanes) {
+            t0 += P[s * mn + e];
+            t1 += P[(s + kRedLanes) * mn + e];
+        }
+        if (s < nsplit) t0 += P[s * mn + e];
+    }
+    part[r][el] = t0 + t1;
+    __syncthreads();
+    if (r != 0 || e >= mn) return;
+    double t = part[0][el];
+#pragma unroll
+    for (int q = 1; q < kRedLanes; ++q) t += part[q][el];
+    const int64_t i = e / N, j = e % N;
+    double v = alpha * t;
+    if (beta != 0.0) v += beta * C0[i * c0_si + j * c0_sj];
+    C[i * c_si + j * c_sj] = v;
+}
+
 // Fixed-order sum of split-K partials with the alpha / beta epilogue.
 __global__ void __launch_bounds__(256)
 splitk_reduce_kernel(const double* __restrict__ P, int nsplit, int64_t M, int64_t N,
@@ -415,9 +449,17 @@ static hipError_t run_cfg(const GemmDesc& d, hipStream_t s) {
                        s, g);
     if (nsplit > 1) {
         const int64_t tot = d.M * d.N;
-        hipLaunchKernelGGL(splitk_reduce_kernel, dim3(static_cast<unsigned>(cdiv(tot, 256))),
-                           dim3(256), 0, s, d.ws, nsplit, d.M, d.N, d.alpha, d.beta, d.C0.p,
-                           d.C0.si, d.C0.sj, d.C.p, d.C.si, d.C.sj);
+        if (nsplit >= 2 * kRedLanes && tot <= (int64_t(1) << 18)) {
+            // few outputs, long reduction: spread each element over kRedLanes threads
+            hipLaunchKernelGGL(splitk_reduce_wide_kernel,
+                               dim3(static_cast<unsigned>(cdiv(tot, 256 / kRedLanes))), dim3(256), 0,
+                               s, d.ws, nsplit, d.M, d.N, d.alpha, d.beta, d.C0.p, d.C0.si,
+                               d.C0.sj, d.C.p, d.C.si, d.C.sj);
+        } else {
+            hipLaunchKernelGGL(splitk_reduce_kernel, dim3(static_cast<unsigned>(cdiv(tot, 256))),
+                               dim3(256), 0, s, d.ws, nsplit, d.M, d.N, d.alpha, d.beta, d.C0.p,
+                               d.C0.si, d.C0.sj, d.C.p, d.C.si, d.C.sj);
+        }
         if (d.colsq != nullptr) {
             // at most tiles_m groups of rows, so the caller's [tiles_m][N] buffer fits
             const int64_t groups = g.tiles_m < 256 ? g.tiles_m : 256;
