@@ -45,6 +45,38 @@ FP64_PEAK_TFLOPS = 78.6
 G_TRAFFIC_BYTES = (2 * 4067823 + 380000) * 1024
 FP32_PEAK_TFLOPS = 157.3
 BF16_PEAK_TFLOPS = 2500.0
+HBM_PEAK_GBPS = 8000.0
+
+
+def block_loop_work(m, n, b, rank, blocks, ei=False):
+    """Algorithmic flops and HBM bytes of the block loop (FP64, without the products with A).
+    Block i starts at rank k_i = i b (the last block may stop early).  randQB_FP per block:
+    W = B Omega_J and S = H_J^T - D^T B read B (k x n) twice; Y = G_J - Q W, D = Q^T Y,
+    Z = Q^T Q_i and Q_i - Q Z read Q (m x k) four times: 8 m k b + 4 n k b flops, plus the
+    b-column CholeskyQR pair and B_i = S R_i^{-1} (8 m b^2 + 2 n b^2).  randQB_EI drops D and
+    S: Q is read three times and B once."""
+    flops = bytes_ = 0.0
+    for i in range(blocks):
+        k = min(i * b, rank)
+        if ei:
+            flops += 6.0 * m * k * b + 2.0 * n * k * b + 8.0 * m * b * b
+            bytes_ += 8.0 * (3.0 * m * k + n * k)
+        else:
+            flops += 8.0 * m * k * b + 4.0 * n * k * b + 8.0 * m * b * b + 2.0 * n * b * b
+            bytes_ += 8.0 * (4.0 * m * k + 2.0 * n * k)
+    return flops, bytes_
+
+
+def block_loop_roofline(m, n, b, r, ei=False):
+    """Achieved rates of the block loop against the FP64 matrix and HBM peaks (the loop's
+    Q and B sweeps sit near the ridge point: about b / 4 flops per byte)."""
+    f, by = block_loop_work(m, n, b, r.rank, r.blocks, ei)
+    t = r.ms[4] * 1e-3
+    if t <= 0:
+        return None
+    return {"flops": f, "bytes": by, "TFLOPs": round(f / t / 1e12, 2), "GBps": round(by / t / 1e9, 1),
+            "frac_fp64": round(f / t / 1e12 / FP64_PEAK_TFLOPS, 4),
+            "frac_hbm": round(by / t / 1e9 / HBM_PEAK_GBPS, 4)}
 
 
 def main():
@@ -166,6 +198,7 @@ def main():
         "phase_ms": {"normA2": r.ms[0], "omega": r.ms[1], "G": r.ms[2], "H": r.ms[3],
                      "block_loop": r.ms[4], "total": r.ms[5]},
         "sketch_tflops": (r.gemm_flops[0] + r.gemm_flops[1]) / ((r.ms[2] + r.ms[3]) * 1e-3) / 1e12,
+        "block_loop_roofline": block_loop_roofline(m, n, wl.b, r),
         "roofline": {"bound": "mfma", "kernel": dom_name, "achieved": round(achieved, 3),
                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
@@ -404,6 +437,7 @@ def sparse_block(qb, W, torch, steps=1):
                  "phase_ms": {"normA2_and_csc": r.ms[0], "omega": r.ms[1], "A_X": r.ms[2],
                               "At_X": r.ms[3], "block_loop": r.ms[4], "power_rounds": r.ms[6],
                               "total": r.ms[5]}}
+        entry["block_loop_roofline"] = block_loop_roofline(c.m, c.n, wl.b, r, ei=name == "ei")
         if name.startswith("fp"):
             # algorithmic bytes of the two SpMM passes per chunk: CSR arrays once, the dense
             # operand once, the dense result once

@@ -98,3 +98,26 @@ def test_power_reproducible_and_rejections(qb):
     with pytest.raises(qb.QBError) as e:
         qb.qb_fp_dense(W.to_bf16(A), 1e-2, 32, SEED, power=1)
     assert e.value.status == qb.QB_ERR_UNSUPPORTED
+
+
+def test_power_full_size_properties(qb):
+    """The 20000 x 15000 benchmark workload at P = 1 in the launch configuration the
+    benchmark times (adaptive schedule, l_max = min(m, n)): E against the directly computed
+    residual, orthogonality, rank between the SVD rank and the P = 0 rank, 2 P + 2 passes
+    per chunk."""
+    wl = W.C2
+    seed = W.SEED_OMEGA | 2
+    A = wl.make(device="cuda")
+    r1 = qb.qb_fp_dense(A, wl.tol, wl.b, seed, l_max=min(wl.m, wl.n), l_tilde=-1, power=1)
+    r0 = qb.qb_fp_dense(A, wl.tol, wl.b, seed, l_max=min(wl.m, wl.n), l_tilde=-1)
+    res2 = float(torch.linalg.matrix_norm(A - r1.Q @ r1.B) ** 2)
+    k = r1.rank
+    orth = float((r1.Q.T @ r1.Q - torch.eye(k, dtype=torch.float64, device="cuda")).abs().sum(1).max())
+    opt = R.svd_optimal_rank(wl.sigma(), wl.tol)
+    _log(f"C2 P=1: rank {k} (P=0 {r0.rank}, svd {opt}) E/|A|^2 {r1.E / r1.normA2:.4e} "
+         f"residual {res2 / r1.normA2:.4e} orth {orth:.2e} passes {r1.passes}")
+    assert r1.status == qb.QB_OK
+    assert abs(r1.E - res2) <= 1e-10 * r1.normA2
+    assert orth <= 1e-12
+    assert opt - 1 <= k < r0.rank
+    assert r1.passes == 4 * r1.chunks
