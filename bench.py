@@ -42,7 +42,7 @@ FP64_PEAK_TFLOPS = 78.6
 # its two launches): rocprofv3 FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, the scales being
 # what the two counters read for a plain 1 GiB device copy.  Measured for the current
 # gemm_f64_kernel; profiles/gemm_f64_sketch_dense_20000x15000_b64_tol1e-3.md.
-G_TRAFFIC_BYTES = (2 * 4067823 + 380000) * 1024
+G_TRAFFIC_BYTES = (2 * 4068004 + 380000) * 1024
 FP32_PEAK_TFLOPS = 157.3
 BF16_PEAK_TFLOPS = 2500.0
 HBM_PEAK_GBPS = 8000.0
@@ -90,6 +90,8 @@ def main():
     ap.add_argument("--no-diff", action="store_true")
     ap.add_argument("--no-sparse", action="store_true")
     ap.add_argument("--no-power", action="store_true")
+    ap.add_argument("--sparse-only", action="store_true",
+                    help="run only the CSR block and print its JSON (for profiling runs)")
     ap.add_argument("--gen-device", default="cuda", choices=["cuda", "cpu"],
                     help="where the seeded test matrix is generated (cpu keeps the GPU QR of the "
                          "generator out of counter-collection runs)")
@@ -109,6 +111,9 @@ def main():
     import paper_1606_09402_amd as qb
     import workloads as W
 
+    if args.sparse_only:
+        print(json.dumps({"sparse": sparse_block(qb, W, torch)}), flush=True)
+        return
     wl = W.C2
     seed = W.SEED_OMEGA | 2
     dev = torch.device("cuda:0")
