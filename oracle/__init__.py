@@ -11,8 +11,10 @@ Modules
 rng      counter-based Gaussian test matrix (Philox4x32-10 + Box-Muller with
          elementary functions built from IEEE +,-,*,/ only), bit-specified.
 randqb   Algorithm 1 framework, Algorithm 2 (randQB_EI), Algorithm 3 / 4
-         (randQB_FP, power parameter P = 0), the fixed-rank randQB special case,
-         a one-sided Jacobi SVD and the SVD-optimal rank used as pins.
-fixed    fixed-rank randQB_FP as a differentiable map A -> (Q, B) in float64
+         (randQB_FP with the power scheme, P >= 0), the fixed-rank randQB special
+         case, a one-sided Jacobi SVD and the SVD-optimal rank used as pins.
+lowp     bfloat16 rounding for the precision form.
+svd      the approximate SVD from a QB factorisation (eq. (3)).
+diff     fixed-rank randQB_FP as a differentiable map A -> (Q, B) in float64
          torch CPU autograd (reference gradient for the differentiation form).
 """
