@@ -119,6 +119,11 @@ def lib() -> ctypes.CDLL:
                                         _vp, _c_i64, _c_i64, _vp, _c_i64, _c_i64, _vp, _c_i64, _c_i64,
                                         _vp, ctypes.c_size_t, _vp]
         L.qb_fixed_rank_bwd.restype = ctypes.c_int
+        L.qb_svd_workspace_bytes.argtypes = [_c_i64, _c_i64, _c_i64]
+        L.qb_svd_workspace_bytes.restype = ctypes.c_size_t
+        L.qb_svd_from_qb.argtypes = [_c_i64, _c_i64, _c_i64, _vp, _c_i64, _vp, _c_i64, _vp, _c_i64, _vp,
+                                     _vp, _c_i64, _vp, ctypes.c_size_t, _vp, P(_c_i32)]
+        L.qb_svd_from_qb.restype = ctypes.c_int
         L.qb_status_string.argtypes = [ctypes.c_int]
         L.qb_status_string.restype = ctypes.c_char_p
         _LIB = L
@@ -464,3 +469,42 @@ def fixed_rank_qb(A: torch.Tensor, k: int, b: int, seed: int):
         Q, B = FixedRankQB.apply(A.unsqueeze(0).contiguous(), k, b, seed)
         return Q[0], B[0]
     return FixedRankQB.apply(A.contiguous(), k, b, seed)
+
+
+def qb_svd_workspace_bytes(m: int, n: int, k: int) -> int:
+    return int(lib().qb_svd_workspace_bytes(int(m), int(n), int(k)))
+
+
+@dataclass
+class SVDResult:
+    U: torch.Tensor   # m x k view (column-major storage)
+    s: torch.Tensor   # k, descending
+    V: torch.Tensor   # n x k view (column-major storage)
+    sweeps: int
+    status: int
+
+
+def svd_from_qb(Q: torch.Tensor, B: torch.Tensor, ws=None) -> SVDResult:
+    """Eq. (3) on the GPU: A ~ QB = U diag(s) V^T.  Q is m x k with unit row stride
+    (column-major, as QBResult.Q), B is k x n with unit column stride (as QBResult.B)."""
+    m, k = Q.shape
+    k2, n = B.shape
+    if k2 != k or Q.dtype != torch.float64 or B.dtype != torch.float64 or not (Q.is_cuda and B.is_cuda):
+        raise ValueError("Q (m x k) and B (k x n) must be float64 GPU tensors of matching k")
+    if Q.stride(0) != 1 or B.stride(1) != 1:
+        raise ValueError("Q must be column-major (unit row stride) and B row-major")
+    need = qb_svd_workspace_bytes(m, n, k)
+    if need == 0:
+        raise QBError(QB_ERR_ARG, "qb_svd_from_qb")
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=B.device)
+    Ust = torch.empty((k, m), dtype=torch.float64, device=B.device)
+    Vst = torch.empty((k, n), dtype=torch.float64, device=B.device)
+    s = torch.empty(k, dtype=torch.float64, device=B.device)
+    sweeps = _c_i32(0)
+    st = lib().qb_svd_from_qb(m, n, k, Q.data_ptr(), Q.stride(1), B.data_ptr(), B.stride(0), Ust.data_ptr(),
+                              m, s.data_ptr(), Vst.data_ptr(), n, ws.data_ptr(), ws.numel(),
+                              _stream_ptr(B.device), ctypes.byref(sweeps))
+    if st < 0:
+        raise QBError(st, "qb_svd_from_qb")
+    return SVDResult(U=Ust.T, s=s, V=Vst.T, sweeps=int(sweeps.value), status=st)

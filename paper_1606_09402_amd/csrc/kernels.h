@@ -100,4 +100,14 @@ hipError_t build_csc(const int64_t* rowptr, const int32_t* colind, const double*
 void csc_views(int64_t m, int64_t n, int64_t nnz, char* ws, const int64_t** colptr,
                const int32_t** t_col, const double** t_val);
 
+// svd.hip -- one-sided Jacobi SVD of a k x k factor (circle ordering) and its outputs
+int jacobi_players(int k);
+hipError_t launch_jacobi_round(double* X, double* W, int k, int64_t ld, int round, double tol,
+                               int* flag, hipStream_t s);
+hipError_t launch_svd_finish(const double* X, const double* W, int k, int64_t ld, double* sig,
+                             int* pos, double* s_out, double* Ut, double* Ws, hipStream_t s);
+hipError_t launch_sign_rule(double* V, int64_t n, int64_t ldv, double* Ut, int k, int64_t ldu,
+                            hipStream_t s);
+hipError_t launch_identity(double* W, int k, int64_t ld, hipStream_t s);
+
 }  // namespace qb

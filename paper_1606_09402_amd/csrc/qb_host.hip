@@ -875,6 +875,124 @@ int check_csr(const qb_csr* A) {
     return QB_OK;
 }
 
+// Workspace of the SVD from QB: P (n x k, the orthonormalised B^T), T / X (k x k), the
+// rotations W, the sorted Ut and Ws (k x k each), the values and their order, and the
+// buffers of orth_panel (128-column panels of n rows, k x 128 projections, 128 x 128
+// factors, split-K partials).
+Layout svd_layout(int64_t m, int64_t n, int64_t k) {
+    Layout L{};
+    const int64_t pb = kPowerBlock;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    L.split_elems = 4 * (n > k ? n : k) * pb;
+    if (L.split_elems < kGramSplitElems) L.split_elems = kGramSplitElems;
+    L.om = take(sizeof(double) * n * k);   // P
+    L.g = take(sizeof(double) * k * k);    // T, read as X = T^T (column-major)
+    L.h = take(sizeof(double) * k * k);    // W
+    L.s = take(sizeof(double) * k * k);    // Ut
+    L.d = take(sizeof(double) * k * k);    // Ws
+    L.gnorm2 = take(sizeof(double) * k);   // column norms
+    L.info = take(sizeof(int) * k);        // order
+    L.y = take(sizeof(double) * n * pb);
+    L.x2 = take(sizeof(double) * n * pb);
+    L.z = take(sizeof(double) * k * pb);
+    L.gram = take(sizeof(double) * pb * pb);
+    L.r1 = take(sizeof(double) * pb * pb);
+    L.r1i = take(sizeof(double) * pb * pb);
+    L.rt = take(sizeof(double) * pb * pb);
+    L.rti = take(sizeof(double) * pb * pb);
+    L.tau = take(sizeof(double) * pb);
+    L.flags = take(sizeof(int) * 8);
+    L.split = take(sizeof(double) * L.split_elems);
+    L.total = off + 256;
+    (void)m;
+    return L;
+}
+
+constexpr int kMaxSweeps = 40;
+
+int svd_from_qb(int64_t m, int64_t n, int64_t k, const double* Q, int64_t ldq, const double* B,
+                int64_t ldb, double* U, int64_t ldu, double* sv, double* V, int64_t ldv, void* ws,
+                size_t ws_bytes, hipStream_t s, int32_t* sweeps_out) {
+    if (sweeps_out) *sweeps_out = 0;
+    if (k < 1 || m < 1 || n < 1 || k > m || k > n || k >= (int64_t(1) << 31)) return QB_ERR_ARG;
+    if (Q == nullptr || B == nullptr || U == nullptr || sv == nullptr || V == nullptr || ws == nullptr)
+        return QB_ERR_ARG;
+    if (ldq < m || ldb < n || ldu < m || ldv < n) return QB_ERR_ARG;
+    if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return QB_ERR_ARG;
+    const Layout L = svd_layout(m, n, k);
+    if (ws_bytes < L.total) return QB_ERR_WORKSPACE;
+    double* host = pinned_buffer();
+    if (host == nullptr) return QB_ERR_HIP;
+    char* wsb = static_cast<char*>(ws);
+    Op none{};
+    Ctx x{none, nullptr, nullptr, 0, nullptr, 0, wsb, L, s, nullptr, nullptr, host};
+    double* P = x.at<double>(L.om);
+    double* T = x.at<double>(L.g);
+    double* W = x.at<double>(L.h);
+    double* Ut = x.at<double>(L.s);
+    double* Ws = x.at<double>(L.d);
+    double* sig = x.at<double>(L.gnorm2);
+    int* pos = x.at<int>(L.info);
+    int* flags = x.at<int>(L.flags);
+    const int ki = static_cast<int>(k);
+    // B^T = P T: P = orth(B^T) (n x k, row-major), T = P^T B^T
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        QB_HIP(launch_fill_int(flags, 8, 0, s));
+        GemmDesc c = gdesc(n, k, 0, View{nullptr, 0, 0}, View{nullptr, 0, 0}, 0.0, 1.0,
+                           View{B, 1, ldb}, MutView{P, k, 1}, x);
+        QB_HIP(gemm_f64(c, s));
+        if (int e = orth_panel(x, P, n, k, k, 0, attempt == 1)) return e;
+        bool broken = false;
+        if (int e = read_flag(x, &broken)) return e;
+        if (!broken) break;
+    }
+    {
+        GemmDesc d = gdesc(k, k, n, View{P, 1, k}, View{B, 1, ldb}, 1.0, 0.0, View{nullptr, 0, 0},
+                           MutView{T, k, 1}, x);
+        QB_HIP(gemm_f64(d, s));
+    }
+    // one-sided Jacobi on X = T^T (column-major: the same storage as row-major T)
+    QB_HIP(launch_identity(W, ki, k, s));
+    const double tol = sqrt(static_cast<double>(k)) * kUnitRoundoff;
+    const int rounds = jacobi_players(ki) - 1;
+    int st = QB_NOT_CONVERGED;
+    int sweeps = 0;
+    int* hflag = reinterpret_cast<int*>(host + 3 * kMaxB);
+    while (sweeps < kMaxSweeps) {
+        QB_HIP(launch_fill_int(flags + 1, 1, 0, s));
+        for (int r = 0; r < rounds; ++r) QB_HIP(launch_jacobi_round(T, W, ki, k, r, tol, flags + 1, s));
+        ++sweeps;
+        QB_HIP(hipMemcpyAsync(hflag, flags + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+        QB_HIP(hipStreamSynchronize(s));
+        if (*hflag == 0) {
+            st = QB_OK;
+            break;
+        }
+    }
+    if (sweeps_out) *sweeps_out = sweeps;
+    // values, order, normalised left vectors and rotations in descending order
+    QB_HIP(launch_svd_finish(T, W, ki, k, sig, pos, sv, Ut, Ws, s));
+    // V = P Ws (n x k, column-major), the sign rule on V and Ut, then U = Q Ut
+    {
+        GemmDesc d = gdesc(n, k, k, View{P, k, 1}, View{Ws, 1, k}, 1.0, 0.0, View{nullptr, 0, 0},
+                           MutView{V, 1, ldv}, x);
+        QB_HIP(gemm_f64(d, s));
+    }
+    QB_HIP(launch_sign_rule(V, n, ldv, Ut, ki, k, s));
+    {
+        GemmDesc d = gdesc(m, k, k, View{Q, 1, ldq}, View{Ut, 1, k}, 1.0, 0.0, View{nullptr, 0, 0},
+                           MutView{U, 1, ldu}, x);
+        QB_HIP(gemm_f64(d, s));
+    }
+    QB_HIP(hipStreamSynchronize(s));
+    return st;
+}
+
 }  // namespace
 }  // namespace qb
 
@@ -1050,6 +1168,17 @@ int qb_sketch_csr(const qb_csr* A, uint64_t seed, int64_t col0, int64_t l, doubl
     QB_HIP(launch_spmm_csr(A->rowptr, A->colind, A->val, A->m, om, l, g, l, l, stream));
     QB_HIP(launch_spmm_csr(tp, tc, tv, A->n, g, l, h, l, l, stream));
     return QB_OK;
+}
+
+size_t qb_svd_workspace_bytes(int64_t m, int64_t n, int64_t k) {
+    if (k < 1 || m < 1 || n < 1 || k > m || k > n) return 0;
+    return svd_layout(m, n, k).total;
+}
+
+int qb_svd_from_qb(int64_t m, int64_t n, int64_t k, const double* Q, int64_t ldq, const double* B,
+                   int64_t ldb, double* U, int64_t ldu, double* s, double* V, int64_t ldv, void* ws,
+                   size_t ws_bytes, hipStream_t stream, int32_t* sweeps) {
+    return svd_from_qb(m, n, k, Q, ldq, B, ldb, U, ldu, s, V, ldv, ws, ws_bytes, stream, sweeps);
 }
 
 const char* qb_status_string(int status) {
