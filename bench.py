@@ -67,6 +67,19 @@ def block_loop_work(m, n, b, rank, blocks, ei=False):
     return flops, bytes_
 
 
+def end_to_end_roofline(m, n, b, r):
+    """Sum over the phases of a dense randQB_FP call of the time each would take at its
+    roofline (||A||^2 and Omega at HBM speed, the sketch GEMMs and the block loop at the FP64
+    matrix peak or HBM, whichever binds), divided by the call's device time."""
+    w_tot = r.gemm_flops[0] / (2.0 * m * n)
+    t = 8.0 * m * n / (HBM_PEAK_GBPS * 1e9)                                  # ||A||^2
+    t += 8.0 * n * w_tot / (HBM_PEAK_GBPS * 1e9)                             # Omega
+    t += (r.gemm_flops[0] + r.gemm_flops[1]) / (FP64_PEAK_TFLOPS * 1e12)     # G, H
+    f, by = block_loop_work(m, n, b, r.rank, r.blocks)
+    t += max(f / (FP64_PEAK_TFLOPS * 1e12), by / (HBM_PEAK_GBPS * 1e9))      # block loop
+    return round(t / (r.ms[5] * 1e-3), 4) if r.ms[5] > 0 else None
+
+
 def block_loop_roofline(m, n, b, r, ei=False):
     """Achieved rates of the block loop against the FP64 matrix and HBM peaks (the loop's
     Q and B sweeps sit near the ridge point: about b / 4 flops per byte)."""
@@ -219,6 +232,7 @@ def main():
                      "block_loop": r.ms[4], "total": r.ms[5]},
         "sketch_tflops": (r.gemm_flops[0] + r.gemm_flops[1]) / ((r.ms[2] + r.ms[3]) * 1e-3) / 1e12,
         "block_loop_roofline": block_loop_roofline(m, n, wl.b, r),
+        "end_to_end_roofline_frac": end_to_end_roofline(m, n, wl.b, r),
         "svd_from_qb": svd_entry,
         "roofline": {"bound": "mfma", "kernel": dom_name, "achieved": round(achieved, 3),
                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
