@@ -38,11 +38,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6
-# HBM bytes per launch of the dominant kernel (G = A Omega of the adaptive schedule, mean of
-# its two launches): rocprofv3 FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, the scales being
-# what the two counters read for a plain 1 GiB device copy.  Measured for the current
-# gemm_f64_kernel; profiles/gemm_f64_sketch_dense_20000x15000_b64_tol1e-3.md.
-G_TRAFFIC_BYTES = (2 * 4068004 + 380000) * 1024
+# HBM bytes per launch of the sketch GEMMs of the adaptive schedule (chunks of 512 and
+# 1024 columns on the headline workload; mean of the two launches of each product):
+# rocprofv3 FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 in KiB, the scales being what the two
+# counters read for a plain 1 GiB device copy.  Measured for the current gemm_f64_kernel;
+# profiles/gemm_f64_sketch_dense_20000x15000_b64_tol1e-3.md.
+G_TRAFFIC_BYTES = int((2 * (2073048.0 + 3891728.6) / 2 + (160000.0 + 161256.0) / 2) * 1024)
+H_TRAFFIC_BYTES = int((2 * (2345455.8 + 4577801.8) / 2 + (300000.0 + 480000.0) / 2) * 1024)
 FP32_PEAK_TFLOPS = 157.3
 BF16_PEAK_TFLOPS = 2500.0
 HBM_PEAK_GBPS = 8000.0
@@ -237,8 +239,8 @@ def main():
         "roofline": {"bound": "mfma", "kernel": dom_name, "achieved": round(achieved, 3),
                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
-                     "traffic": G_TRAFFIC_BYTES if args.l_tilde == -1 and dom_name.startswith("gemm_f64 G")
-                     else None},
+                     "traffic": (G_TRAFFIC_BYTES if dom_name.startswith("gemm_f64 G") else H_TRAFFIC_BYTES)
+                     if args.l_tilde == -1 and r.chunks == 2 else None},
     }
     if args.l_tilde != 0:   # the paper's fixed l~ = 50 b beside the headline schedule
         fp(0)

@@ -117,10 +117,10 @@ typedef struct {
                             (Section 5.4).  A chunk that runs out is followed by the next
                             l_tilde columns of Omega and a fresh G, H sweep.  -1 selects an
                             adaptive schedule: 8 b columns first, then each new chunk is
-                            sized from the decay of E over the previous one (1.25 x the
-                            columns a geometric extrapolation needs to reach eps^2, plus b,
-                            rounded up to a multiple of b, within [b, 4 x previous]), never
-                            wider than min(50 b, l_max).                                    */
+                            sized from the decay of E over the second half of the previous
+                            one (1.1 x the columns a geometric extrapolation needs to reach
+                            eps^2, plus b, rounded up to a multiple of b, within
+                            [b, 4 x previous]), never wider than min(50 b, l_max).           */
     uint64_t seed;       /* Philox key of Omega                                              */
     int32_t row_by_row;  /* 1: steps 7a-8e (rank any integer); 0: whole-block stopping      */
     int32_t reserved;

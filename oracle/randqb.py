@@ -29,10 +29,11 @@ design notes of the repository):
   used up without convergence the next l~ columns of Omega are drawn and G, H
   recomputed (the restart described after Algorithm 4), keeping Q, B and E;
 * l_tilde = -1 selects an adaptive chunk schedule (the paper leaves the choice of l~
-  open): the first chunk has 8 b columns; after a chunk of w columns moved the
-  indicator from E_prev to E_now, the decay per column is taken as geometric and the
-  next chunk is 1.25 times the columns needed to reach eps^2 plus b, rounded up to a
-  multiple of b and kept in [b, 4 w]; no chunk exceeds min(50 b, l_max);
+  open): the first chunk has 8 b columns; after a chunk of w columns (nb = ceil(w / b)
+  blocks), the decay of the indicator per column over the chunk's second half (from the
+  end of block floor(nb / 2) to the end of the chunk) is taken as geometric, and the next
+  chunk is 1.1 times the columns needed to reach eps^2 plus b, rounded up to a multiple of
+  b and kept in [b, 4 w]; no chunk exceeds min(50 b, l_max);
 * exhaustion guard: before row j of a block is accepted, R_i(j,j) must exceed
   2^-40 ||G_J(:,j)||_2, otherwise the method stops before row j (the numerical
   rank of A has been reached and R_i^{-T} would divide by round-off);
@@ -180,17 +181,19 @@ def _finish(st, E, normA2, status_tol, exhausted, l_max, k, eps2, **kw):
                     exhausted=int(exhausted), **kw)
 
 
-def _chunk_width(adaptive: bool, cap: int, b: int, left: int, w_prev: int, e_prev: float,
-                 e_now: float, eps2: float) -> int:
-    """Width of the next chunk of Omega columns (see the module notes)."""
+def _chunk_width(adaptive: bool, cap: int, b: int, left: int, w_prev: int, span: int,
+                 e_prev: float, e_now: float, eps2: float) -> int:
+    """Width of the next chunk of Omega columns (see the module notes): w_prev is the
+    width of the chunk just used, and the indicator fell from e_prev to e_now over its
+    last span columns."""
     if not adaptive:
         w = cap
     elif w_prev == 0:
         w = 8 * b
-    elif e_now > 0.0 and e_prev > e_now and 0.0 < eps2 < e_now:
-        rate = np.log(e_now / e_prev) / w_prev
+    elif span > 0 and e_now > 0.0 and e_prev > e_now and 0.0 < eps2 < e_now:
+        rate = np.log(e_now / e_prev) / span
         need = np.log(eps2 / e_now) / rate
-        want = 1.25 * need + b
+        want = 1.1 * need + b
         if want >= 4.0 * w_prev:
             w = 4 * w_prev
         else:
@@ -254,15 +257,19 @@ def randqb_fp(A, tol_rel: float, b: int, seed: int, l_max=None, l_tilde: int = 0
     exhausted = False
     trace, rdiag, omegas = [], [], []
     chunk_lo = chunk_hi = 0
-    e_start = E
+    k_half = 0
+    e_half = E
     Om = G = H = Gnorm = None
     while st.k < l_max:
         k = st.k
         if k == chunk_hi:                       # draw the next chunk of Omega
-            w = _chunk_width(adaptive, l_tilde, b, l_max - k, chunk_hi - chunk_lo, e_start, E, eps2)
-            e_start = E
+            w = _chunk_width(adaptive, l_tilde, b, l_max - k, chunk_hi - chunk_lo, chunk_hi - k_half,
+                             e_half, E, eps2)
             chunk_lo = k
             chunk_hi = k + w
+            # the decay over the second half of this chunk sizes the next one
+            k_half = chunk_lo + b * ((-(-w // b)) // 2)
+            e_half = E
             Om = omega(seed, n, chunk_lo, chunk_hi - chunk_lo)
             if power > 0:                           # steps 3-6
                 Om = power_omega(A, Om, power, st.Q, st.B)
@@ -294,6 +301,8 @@ def randqb_fp(A, tol_rel: float, b: int, seed: int, l_max=None, l_tilde: int = 0
         st.append(Qi[:, :keep], Bi[:keep])
         trace.append(E)
         rdiag.append(np.diag(R).copy())
+        if st.k == k_half:
+            e_half = E
         if stop:
             exhausted = exh
             break

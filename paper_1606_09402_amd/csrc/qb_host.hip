@@ -53,12 +53,14 @@ int64_t chunk_width(const qb_params* p) {
 int64_t round_up(int64_t x, int64_t b) { return ((x + b - 1) / b) * b; }
 
 // Width of the next chunk of Omega columns starting at column k.  Fixed schedules use the
-// full width.  The adaptive schedule starts with 8 b columns; after a chunk of w columns
-// took the indicator from e_prev to e_now, it assumes the same per-column geometric decay
-// and asks for 1.25 x the columns that would reach eps^2 plus one block, rounded up to a
-// multiple of b and kept within [b, 4 w] (never above the fixed width).
-int64_t next_chunk(const qb_params* p, int64_t cap, int64_t k, int64_t w_prev, double e_prev,
-                   double e_now, double eps2) {
+// full width.  The adaptive schedule starts with 8 b columns; after a chunk of w_prev
+// columns whose last span columns took the indicator from e_prev to e_now (span covers the
+// chunk's second half: from the end of block floor(nb / 2) of its nb blocks), it assumes
+// that per-column geometric decay and asks for 1.1 x the columns that would reach eps^2
+// plus one block, rounded up to a multiple of b and kept within [b, 4 w_prev] (never above
+// the fixed width).
+int64_t next_chunk(const qb_params* p, int64_t cap, int64_t k, int64_t w_prev, int64_t span,
+                   double e_prev, double e_now, double eps2) {
     const int64_t b = p->b;
     const int64_t left = p->l_max - k;
     int64_t w;
@@ -66,10 +68,10 @@ int64_t next_chunk(const qb_params* p, int64_t cap, int64_t k, int64_t w_prev, d
         w = cap;
     } else if (w_prev == 0) {
         w = 8 * b;
-    } else if (e_now > 0.0 && e_prev > e_now && eps2 > 0.0 && eps2 < e_now) {
-        const double rate = log(e_now / e_prev) / static_cast<double>(w_prev);   // < 0
+    } else if (span > 0 && e_now > 0.0 && e_prev > e_now && eps2 > 0.0 && eps2 < e_now) {
+        const double rate = log(e_now / e_prev) / static_cast<double>(span);      // < 0
         const double need = log(eps2 / e_now) / rate;                               // > 0
-        const double want = 1.25 * need + static_cast<double>(b);
+        const double want = 1.1 * need + static_cast<double>(b);
         const double hi = 4.0 * static_cast<double>(w_prev);
         w = want >= hi ? 4 * w_prev : round_up(static_cast<int64_t>(ceil(want)), b);
         if (w < b) w = b;
@@ -737,7 +739,8 @@ int run(int algo, Op& A, const qb_params* p, double* Q, int64_t ldq, double* B, 
     if (!(normA2 == 0.0 || E < eps2)) {
         QB_HIP(launch_fill_int(x.at<int>(L.flags), 8, 0, s));
         int64_t chunk_lo = 0, chunk_hi = 0;
-        double e_chunk_start = E;
+        int64_t k_half = 0;       // block end where the current chunk's second half starts
+        double e_half = E;        // the indicator there
         double* Om = x.at<double>(L.om);
         double* G = x.at<double>(L.g);
         double* H = x.at<double>(L.h);
@@ -749,11 +752,12 @@ int run(int algo, Op& A, const qb_params* p, double* Q, int64_t ldq, double* B, 
             int64_t ldj;
             if (algo == QB_ALGO_FP) {
                 if (k == chunk_hi) {   // draw the next chunk of Omega; G = A Omega, H = A^T G
-                    const int64_t w = next_chunk(p, L.lt, k, chunk_hi - chunk_lo, e_chunk_start, E,
-                                                 eps2);
+                    const int64_t w = next_chunk(p, L.lt, k, chunk_hi - chunk_lo, chunk_hi - k_half,
+                                                 e_half, E, eps2);
                     chunk_lo = k;
                     chunk_hi = k + w;
-                    e_chunk_start = E;
+                    k_half = chunk_lo + b * (cdiv(w, b) / 2);
+                    e_half = E;
                     tm.mark(1);
                     QB_HIP(launch_gauss_fill(p->seed, 0, 0, 0, chunk_lo, n, w, Om, w, s));
                     if (p->power > 0) {
@@ -823,6 +827,7 @@ int run(int algo, Op& A, const qb_params* p, double* Q, int64_t ldq, double* B, 
             bool exh = false;
             scan_rows(host, bwi, p->row_by_row != 0, eps2, &E, &keep, &stop, &exh);
             k += keep;
+            if (k == k_half) e_half = E;
             if (exh) exhausted = true;
         }
     }

@@ -341,13 +341,33 @@ def test_adaptive_chunks_same_factorisation(m2):
 
 def test_adaptive_chunk_width_rule():
     cw = R._chunk_width
-    assert cw(True, 400, 8, 1000, 0, 1.0, 1.0, 1e-6) == 64          # first chunk 8 b
-    # E fell by e^-2 over 64 columns; reaching eps^2 = e^-10 E needs 320 more -> 1.25*320+8
-    w = cw(True, 4000, 8, 10000, 64, 1.0, np.exp(-2.0), np.exp(-12.0))
+    assert cw(True, 400, 8, 1000, 0, 0, 1.0, 1.0, 1e-6) == 64       # first chunk 8 b
+    # E fell by e^-2 over the last 32 columns; eps^2 = e^-10 E needs 160 more -> 1.1*160+8
+    w = cw(True, 4000, 8, 10000, 64, 32, 1.0, np.exp(-2.0), np.exp(-12.0))
+    assert w == 184
+    w = cw(True, 4000, 8, 10000, 64, 32, 1.0, np.exp(-1.0), np.exp(-12.0))
     assert w == 256                                                   # capped at 4 w
-    w = cw(True, 4000, 8, 10000, 128, 1.0, np.exp(-4.0), np.exp(-6.0))
-    assert w == 88                                                    # 1.25*64 + 8 = 88
-    assert cw(True, 50, 8, 1000, 64, 1.0, 0.5, 1e-9) == 50           # never above the cap
-    assert cw(True, 400, 8, 30, 64, 1.0, 0.5, 1e-9) == 30            # nor past l_max
-    assert cw(True, 400, 8, 1000, 64, 1.0, -1e-3, 1e-9) == 128       # no decay info: double
-    assert cw(False, 400, 8, 1000, 64, 1.0, 0.5, 1e-9) == 400        # fixed schedule
+    assert cw(True, 50, 8, 1000, 64, 32, 1.0, 0.5, 1e-9) == 50       # never above the cap
+    assert cw(True, 400, 8, 30, 64, 32, 1.0, 0.5, 1e-9) == 30        # nor past l_max
+    assert cw(True, 400, 8, 1000, 64, 32, 1.0, -1e-3, 1e-9) == 128   # no decay info: double
+    assert cw(False, 400, 8, 1000, 64, 32, 1.0, 0.5, 1e-9) == 400    # fixed schedule
+
+
+def test_adaptive_schedule_measures_the_second_half(monkeypatch, m2):
+    """The next chunk is sized from the indicator's decay over the previous chunk's second
+    half: the rule sees span = w - b floor(nb / 2) and the E recorded at that block end."""
+    A, _ = m2
+    seen = []
+    real = R._chunk_width
+
+    def spy(adaptive, cap, b, left, w_prev, span, e_prev, e_now, eps2):
+        seen.append((w_prev, span, e_prev, e_now))
+        return real(adaptive, cap, b, left, w_prev, span, e_prev, e_now, eps2)
+
+    monkeypatch.setattr(R, "_chunk_width", spy)
+    res = R.randqb_fp(A, 1e-4, 8, 9, l_tilde=-1)
+    assert len(seen) == res.chunks and seen[0][0] == 0
+    w0, span, e_prev, e_now = seen[1]
+    assert w0 == 64 and span == 32
+    # E after 4 blocks (32 columns) and after 8 blocks of the first chunk
+    assert e_prev == res.E_trace[3] and e_now == res.E_trace[7]
