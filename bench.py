@@ -488,6 +488,22 @@ def sparse_block(qb, W, torch, steps=1):
         res[name] = entry
         print(f"# sparse {name}: {statistics.median(ts) * 1e3:.1f} ms rank {r.rank} passes {r.passes}",
               file=sys.stderr, flush=True)
+    # COO input: the same matrix as shuffled triplets, turned into CSR by the library
+    coo = c.to_scipy().tocoo()
+    perm = np.random.default_rng(7).permutation(coo.nnz)
+    tr = [torch.from_numpy(np.ascontiguousarray(a[perm])).to(dev)
+          for a in (coo.row.astype(np.int32), coo.col.astype(np.int32), coo.data)]
+    del coo, perm
+    qb.coo_to_csr(c.m, c.n, *tr)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    rp2, ci2, va2 = qb.coo_to_csr(c.m, c.n, *tr)
+    torch.cuda.synchronize()
+    t_coo = time.perf_counter() - t
+    same = bool(torch.equal(rp2, rowptr) and torch.equal(ci2, colind) and torch.equal(va2, val))
+    res["coo_to_csr"] = {"time_s": round(t_coo, 6), "nnz": int(c.nnz), "equals_csr": same}
+    print(f"# sparse coo -> csr: {t_coo * 1e3:.1f} ms (identical CSR: {same})", file=sys.stderr, flush=True)
+    del tr, rp2, ci2, va2
     del Qs, Bs, ws, rowptr, colind, val
     torch.cuda.empty_cache()
     return res

@@ -101,6 +101,15 @@ typedef struct {
     const double* val;      /* device, nnz entries                                    */
 } qb_csr;
 
+/* Sparse A as coordinate triplets (the COO format that Remark 3.2's experiments also use):
+ * entries in any order; entries with the same (row, col) are summed, in their input order. */
+typedef struct {
+    int64_t m, n, nnz;      /* nnz < 2^31                                                      */
+    const int32_t* row;     /* device, nnz entries, 0 <= row < m                              */
+    const int32_t* col;     /* device, nnz entries, 0 <= col < n                              */
+    const double* val;      /* device, nnz entries                                            */
+} qb_coo;
+
 typedef struct {
     double tol_rel;      /* stop when E < (tol_rel ||A||_F)^2 (strict), 0 <= tol_rel       */
     int32_t b;           /* block size, 1 <= b <= 128                                        */
@@ -139,7 +148,8 @@ typedef struct {
     double ms[8];        /* device time per phase (ms): 0 ||A||^2, 1 Omega, 2 G = A Omega,
                             3 H = A^T G (EI: 2 = the A Omega_i GEMMs, 3 = the A^T Q_i GEMMs),
                             4 block loop without 2-3, 5 whole call, 6 power-scheme rounds
-                            (their products with A and orthonormalisations)                  */
+                            (their products with A and orthonormalisations), 7 COO to CSR
+                            conversion (qb_*_coo only; not part of 5)                       */
     double gemm_flops[2];/* algorithmic flops of the timed G and H GEMMs (2 m n l each)      */
 } qb_info;
 
@@ -173,6 +183,24 @@ QB_API int qb_fp_csr(const qb_csr* A, const qb_params* p, double* Q, int64_t ldq
 /* randQB_EI on CSR A. */
 QB_API int qb_ei_csr(const qb_csr* A, const qb_params* p, double* Q, int64_t ldq, double* B,
               int64_t ldb, void* ws, size_t ws_bytes, hipStream_t stream, qb_info* info);
+
+/* randQB_FP / randQB_EI on COO input: the triplets are first turned into CSR inside the
+ * workspace (a stable sort by (row, col), duplicates summed in input order, a fixed-order
+ * sum), then the CSR path runs.  Workspace: qb_coo_workspace_bytes.  An index outside the
+ * matrix returns QB_ERR_ARG.  info->ms[7] receives the device time of the conversion. */
+QB_API size_t qb_coo_workspace_bytes(int algo, const qb_coo* A, const qb_params* p);
+QB_API int qb_fp_coo(const qb_coo* A, const qb_params* p, double* Q, int64_t ldq, double* B,
+              int64_t ldb, void* ws, size_t ws_bytes, hipStream_t stream, qb_info* info);
+QB_API int qb_ei_coo(const qb_coo* A, const qb_params* p, double* Q, int64_t ldq, double* B,
+              int64_t ldb, void* ws, size_t ws_bytes, hipStream_t stream, qb_info* info);
+
+/* The conversion alone: CSR arrays of A (rowptr m + 1 entries, colind and val at least
+ * A->nnz entries; device memory of the caller) and the CSR entry count in *nnz_out (host).
+ * Workspace: qb_coo_to_csr_bytes.  Synchronises the stream.  QB_ERR_ARG on an index outside
+ * the matrix. */
+QB_API size_t qb_coo_to_csr_bytes(const qb_coo* A);
+QB_API int qb_coo_to_csr(const qb_coo* A, int64_t* rowptr, int32_t* colind, double* val,
+                         int64_t* nnz_out, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* Omega(row0 + r, col0 + c) for r < rows, c < cols into out[r * ld + c] (row-major,
  * ld >= cols).  The paper only asks for a standard Gaussian matrix (randn in

@@ -42,6 +42,10 @@ class QbCsr(ctypes.Structure):
                 ("val", _vp)]
 
 
+class QbCoo(ctypes.Structure):
+    _fields_ = [("m", _c_i64), ("n", _c_i64), ("nnz", _c_i64), ("row", _vp), ("col", _vp), ("val", _vp)]
+
+
 class QbBatch(ctypes.Structure):
     _fields_ = [("batch", _c_i64), ("m", _c_i64), ("n", _c_i64), ("lda", _c_i64), ("stride_a", _c_i64),
                 ("dtype", _c_i32), ("reserved", _c_i32), ("a", _vp)]
@@ -119,6 +123,17 @@ def lib() -> ctypes.CDLL:
                                         _vp, _c_i64, _c_i64, _vp, _c_i64, _c_i64, _vp, _c_i64, _c_i64,
                                         _vp, ctypes.c_size_t, _vp]
         L.qb_fixed_rank_bwd.restype = ctypes.c_int
+        L.qb_coo_workspace_bytes.argtypes = [ctypes.c_int, P(QbCoo), P(QbParams)]
+        L.qb_coo_workspace_bytes.restype = ctypes.c_size_t
+        for nm in ("qb_fp_coo", "qb_ei_coo"):
+            f = getattr(L, nm)
+            f.argtypes = [P(QbCoo), P(QbParams), _vp, _c_i64, _vp, _c_i64, _vp, ctypes.c_size_t, _vp,
+                          P(QbInfo)]
+            f.restype = ctypes.c_int
+        L.qb_coo_to_csr_bytes.argtypes = [P(QbCoo)]
+        L.qb_coo_to_csr_bytes.restype = ctypes.c_size_t
+        L.qb_coo_to_csr.argtypes = [P(QbCoo), _vp, _vp, _vp, P(_c_i64), _vp, ctypes.c_size_t, _vp]
+        L.qb_coo_to_csr.restype = ctypes.c_int
         L.qb_svd_workspace_bytes.argtypes = [_c_i64, _c_i64, _c_i64]
         L.qb_svd_workspace_bytes.restype = ctypes.c_size_t
         L.qb_svd_from_qb.argtypes = [_c_i64, _c_i64, _c_i64, _vp, _c_i64, _vp, _c_i64, _vp, _c_i64, _vp,
@@ -210,7 +225,9 @@ def _run(kind: str, algo: int, sparse: bool, mat, m: int, n: int, dev, tol, b, l
     L = lib()
     l_max = min(m, n) if l_max is None else int(l_max)
     p = _params(tol, b, l_max, l_tilde, seed, row_by_row, power)
-    if sparse:
+    if kind.endswith("_coo"):
+        need = L.qb_coo_workspace_bytes(algo, ctypes.byref(mat), ctypes.byref(p))
+    elif sparse:
         need = L.qb_workspace_bytes(algo, 1, m, n, mat.nnz, ctypes.byref(p))
     else:
         need = L.qb_dense_workspace_bytes(algo, ctypes.byref(mat), ctypes.byref(p))
@@ -278,6 +295,58 @@ def qb_ei_csr(m: int, n: int, rowptr, colind, val, tol: float, b: int, seed: int
     c = _csr(m, n, rowptr, colind, val)
     return _run("qb_ei_csr", QB_ALGO_EI, True, c, m, n, val.device, tol, b, l_max, 0, seed,
                 row_by_row, Q_store, B_store, ws)
+
+
+def _coo(m: int, n: int, row: torch.Tensor, col: torch.Tensor, val: torch.Tensor) -> QbCoo:
+    _check_dev(row, "row", torch.int32)
+    _check_dev(col, "col", torch.int32)
+    _check_dev(val, "val")
+    for t, nm in ((row, "row"), (col, "col"), (val, "val")):
+        if not t.is_contiguous():
+            raise ValueError(f"{nm} must be contiguous")
+    if not (row.numel() == col.numel() == val.numel()):
+        raise ValueError("COO arrays have inconsistent sizes")
+    return QbCoo(m, n, val.numel(), row.data_ptr(), col.data_ptr(), val.data_ptr())
+
+
+def qb_fp_coo(m: int, n: int, row, col, val, tol: float, b: int, seed: int, l_max=None,
+              l_tilde: int = 0, row_by_row: bool = True, Q_store=None, B_store=None, ws=None,
+              power: int = 0) -> QBResult:
+    """randQB_FP on COO triplets (row, col int32, val float64; GPU tensors; any order,
+    duplicates summed).  ms[7] of the result is the conversion to CSR."""
+    c = _coo(m, n, row, col, val)
+    return _run("qb_fp_coo", QB_ALGO_FP, True, c, m, n, val.device, tol, b, l_max, l_tilde, seed,
+                row_by_row, Q_store, B_store, ws, power)
+
+
+def qb_ei_coo(m: int, n: int, row, col, val, tol: float, b: int, seed: int, l_max=None,
+              row_by_row: bool = True, Q_store=None, B_store=None, ws=None) -> QBResult:
+    """randQB_EI on COO triplets."""
+    c = _coo(m, n, row, col, val)
+    return _run("qb_ei_coo", QB_ALGO_EI, True, c, m, n, val.device, tol, b, l_max, 0, seed,
+                row_by_row, Q_store, B_store, ws)
+
+
+def coo_to_csr(m: int, n: int, row, col, val, ws=None):
+    """The library's COO -> CSR conversion: (rowptr int64, colind int32, val float64)."""
+    c = _coo(m, n, row, col, val)
+    L = lib()
+    need = L.qb_coo_to_csr_bytes(ctypes.byref(c))
+    if need == 0:
+        raise QBError(QB_ERR_ARG, "qb_coo_to_csr")
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=val.device)
+    nz = max(1, val.numel())
+    rp = torch.empty(m + 1, dtype=torch.int64, device=val.device)
+    ci = torch.empty(nz, dtype=torch.int32, device=val.device)
+    va = torch.empty(nz, dtype=torch.float64, device=val.device)
+    out = _c_i64(0)
+    st = L.qb_coo_to_csr(ctypes.byref(c), rp.data_ptr(), ci.data_ptr(), va.data_ptr(), ctypes.byref(out),
+                         ws.data_ptr(), ws.numel(), _stream_ptr(val.device))
+    if st < 0:
+        raise QBError(st, "qb_coo_to_csr")
+    k = int(out.value)
+    return rp, ci[:k], va[:k]
 
 
 def qb_workspace_bytes(algo: int, sparse: bool, m: int, n: int, nnz: int, tol: float, b: int,

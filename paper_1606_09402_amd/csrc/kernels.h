@@ -100,6 +100,13 @@ hipError_t build_csc(const int64_t* rowptr, const int32_t* colind, const double*
 void csc_views(int64_t m, int64_t n, int64_t nnz, char* ws, const int64_t** colptr,
                const int32_t** t_col, const double** t_val);
 
+// coo.hip -- COO (any order, duplicates summed) to CSR on the device
+size_t coo_bytes(int64_t m, int64_t n, int64_t nnz);
+hipError_t coo_to_csr(const int32_t* row, const int32_t* col, const double* val, int64_t m, int64_t n,
+                      int64_t nnz, char* ws, int64_t* rowptr, int32_t* colind, double* out_val,
+                      hipStream_t s);
+void coo_counts(int64_t m, int64_t n, int64_t nnz, char* ws, const int64_t** nruns, const int** bad);
+
 // svd.hip -- one-sided Jacobi SVD of a k x k factor (circle ordering) and its outputs
 int jacobi_players(int k);
 hipError_t launch_jacobi_round(double* X, double* W, int k, int64_t ld, int round, double tol,

@@ -998,6 +998,96 @@ int svd_from_qb(int64_t m, int64_t n, int64_t k, const double* Q, int64_t ldq, c
     return st;
 }
 
+// COO input: the CSR arrays and the conversion's scratch come first in the workspace, then
+// the CSR path's own workspace (sized for nnz, an upper bound of the CSR entry count).
+struct CooSplit {
+    size_t conv, rowptr, colind, val, run, total;
+};
+
+CooSplit coo_split(int algo, const qb_coo* A, const qb_params* p) {
+    CooSplit c{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    c.conv = take(coo_bytes(A->m, A->n, A->nnz));
+    c.rowptr = take(sizeof(int64_t) * (A->m + 1));
+    c.colind = take(sizeof(int32_t) * (A->nnz > 0 ? A->nnz : 1));
+    c.val = take(sizeof(double) * (A->nnz > 0 ? A->nnz : 1));
+    c.run = off;
+    c.total = p != nullptr ? off + make_layout(algo, 1, QB_F64, A->m, A->n, A->nnz, p).total : off;
+    return c;
+}
+
+int check_coo(const qb_coo* A) {
+    if (A == nullptr || A->m < 1 || A->n < 1 || A->nnz < 0) return QB_ERR_ARG;
+    if (A->nnz >= (int64_t(1) << 31) || A->m >= (int64_t(1) << 31) || A->n >= (int64_t(1) << 31))
+        return QB_ERR_ARG;
+    if (A->nnz > 0 && (A->row == nullptr || A->col == nullptr || A->val == nullptr)) return QB_ERR_ARG;
+    return QB_OK;
+}
+
+// Convert into ws (layout c) and return the CSR entry count on the host; the stream is
+// synchronised.  ms (may be null) receives the device time of the conversion.
+int coo_convert(const qb_coo* A, const CooSplit& c, char* ws, hipStream_t s, int64_t* nnz_out,
+                double* ms) {
+    double* host = pinned_buffer();
+    if (host == nullptr) return QB_ERR_HIP;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const bool timed = ms != nullptr && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+    if (timed) QB_HIP(hipEventRecord(e0, s));
+    QB_HIP(coo_to_csr(A->row, A->col, A->val, A->m, A->n, A->nnz, ws + c.conv,
+                      reinterpret_cast<int64_t*>(ws + c.rowptr), reinterpret_cast<int32_t*>(ws + c.colind),
+                      reinterpret_cast<double*>(ws + c.val), s));
+    if (timed) QB_HIP(hipEventRecord(e1, s));
+    const int64_t* nruns;
+    const int* bad;
+    coo_counts(A->m, A->n, A->nnz, ws + c.conv, &nruns, &bad);
+    QB_HIP(hipMemcpyAsync(host, nruns, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    QB_HIP(hipMemcpyAsync(host + 1, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    QB_HIP(hipStreamSynchronize(s));
+    int64_t cnt;
+    memcpy(&cnt, host, sizeof(cnt));
+    int flag;
+    memcpy(&flag, host + 1, sizeof(flag));
+    if (timed) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, e0, e1) == hipSuccess) *ms = t;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (flag != 0) return QB_ERR_ARG;
+    *nnz_out = cnt;
+    return QB_OK;
+}
+
+int coo_run(int algo, const qb_coo* A, const qb_params* p, double* Q, int64_t ldq, double* B,
+            int64_t ldb, void* ws, size_t ws_bytes, hipStream_t s, qb_info* info) {
+    qb_info local{};
+    qb_info* inf = info ? info : &local;
+    memset(inf, 0, sizeof(*inf));
+    int st = check_coo(A);
+    if (st == QB_OK) st = check_params(p, A->m, A->n);
+    if (st != QB_OK) return inf->status = st;
+    if (Q == nullptr || B == nullptr || ws == nullptr || ldq < A->m || ldb < A->n)
+        return inf->status = QB_ERR_ARG;
+    if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return inf->status = QB_ERR_ARG;
+    const CooSplit c = coo_split(algo, A, p);
+    if (ws_bytes < c.total) return inf->status = QB_ERR_WORKSPACE;
+    char* wsb = static_cast<char*>(ws);
+    int64_t nnz = 0;
+    double conv_ms = 0.0;
+    if (int e = coo_convert(A, c, wsb, s, &nnz, &conv_ms)) return inf->status = e;
+    qb_csr csr{A->m, A->n, nnz, reinterpret_cast<const int64_t*>(wsb + c.rowptr),
+               reinterpret_cast<const int32_t*>(wsb + c.colind), reinterpret_cast<const double*>(wsb + c.val)};
+    Op o = csr_op(&csr);
+    const int r = run(algo, o, p, Q, ldq, B, ldb, wsb + c.run, ws_bytes - c.run, s, inf);
+    inf->ms[7] = conv_ms;
+    return r;
+}
+
 }  // namespace
 }  // namespace qb
 
@@ -1172,6 +1262,52 @@ int qb_sketch_csr(const qb_csr* A, uint64_t seed, int64_t col0, int64_t l, doubl
     QB_HIP(launch_gauss_fill(seed, 0, 0, 0, col0, A->n, l, om, l, stream));
     QB_HIP(launch_spmm_csr(A->rowptr, A->colind, A->val, A->m, om, l, g, l, l, stream));
     QB_HIP(launch_spmm_csr(tp, tc, tv, A->n, g, l, h, l, l, stream));
+    return QB_OK;
+}
+
+size_t qb_coo_workspace_bytes(int algo, const qb_coo* A, const qb_params* p) {
+    if ((algo != QB_ALGO_FP && algo != QB_ALGO_EI) || check_coo(A) != QB_OK) return 0;
+    if (check_params(p, A->m, A->n) != QB_OK) return 0;
+    return coo_split(algo, A, p).total;
+}
+
+int qb_fp_coo(const qb_coo* A, const qb_params* p, double* Q, int64_t ldq, double* B, int64_t ldb,
+              void* ws, size_t ws_bytes, hipStream_t stream, qb_info* info) {
+    return coo_run(QB_ALGO_FP, A, p, Q, ldq, B, ldb, ws, ws_bytes, stream, info);
+}
+
+int qb_ei_coo(const qb_coo* A, const qb_params* p, double* Q, int64_t ldq, double* B, int64_t ldb,
+              void* ws, size_t ws_bytes, hipStream_t stream, qb_info* info) {
+    return coo_run(QB_ALGO_EI, A, p, Q, ldq, B, ldb, ws, ws_bytes, stream, info);
+}
+
+size_t qb_coo_to_csr_bytes(const qb_coo* A) {
+    if (check_coo(A) != QB_OK) return 0;
+    return coo_bytes(A->m, A->n, A->nnz);
+}
+
+int qb_coo_to_csr(const qb_coo* A, int64_t* rowptr, int32_t* colind, double* val, int64_t* nnz_out,
+                  void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (int st = check_coo(A)) return st;
+    if (rowptr == nullptr || (A->nnz > 0 && (colind == nullptr || val == nullptr)) || nnz_out == nullptr ||
+        ws == nullptr)
+        return QB_ERR_ARG;
+    if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return QB_ERR_ARG;
+    if (ws_bytes < coo_bytes(A->m, A->n, A->nnz)) return QB_ERR_WORKSPACE;
+    double* host = pinned_buffer();
+    if (host == nullptr) return QB_ERR_HIP;
+    char* wsb = static_cast<char*>(ws);
+    QB_HIP(coo_to_csr(A->row, A->col, A->val, A->m, A->n, A->nnz, wsb, rowptr, colind, val, stream));
+    const int64_t* nruns;
+    const int* bad;
+    coo_counts(A->m, A->n, A->nnz, wsb, &nruns, &bad);
+    QB_HIP(hipMemcpyAsync(host, nruns, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+    QB_HIP(hipMemcpyAsync(host + 1, bad, sizeof(int), hipMemcpyDeviceToHost, stream));
+    QB_HIP(hipStreamSynchronize(stream));
+    int flag;
+    memcpy(&flag, host + 1, sizeof(flag));
+    if (flag != 0) return QB_ERR_ARG;
+    memcpy(nnz_out, host, sizeof(int64_t));
     return QB_OK;
 }
 

@@ -87,4 +87,11 @@ def test_entry_points_reject_bad_arguments_without_gpu():
         assert L.qb_workspace_bytes(0, 0, 100, 50, 0, ctypes.byref(p_bad)) == 0
     c = qb.QbCsr(100, 50, 10, None, None, None)
     assert L.qb_fp_csr(ctypes.byref(c), ctypes.byref(p), None, 0, None, 0, None, 0, None, None) == -1
+    # COO: NULL descriptor, NULL arrays with nnz > 0, negative nnz
+    assert L.qb_fp_coo(None, ctypes.byref(p), None, 0, None, 0, None, 0, None, None) == -1
+    co = qb.QbCoo(100, 50, 10, None, None, None)
+    assert L.qb_ei_coo(ctypes.byref(co), ctypes.byref(p), None, 0, None, 0, None, 0, None, None) == -1
+    assert L.qb_coo_workspace_bytes(0, ctypes.byref(co), ctypes.byref(p)) == 0
+    assert L.qb_coo_to_csr_bytes(ctypes.byref(qb.QbCoo(100, 50, -1, None, None, None))) == 0
+    assert L.qb_coo_to_csr_bytes(ctypes.byref(qb.QbCoo(100, 50, 0, None, None, None))) > 0
     assert L.qb_gaussian_fill(1, 0, 0, 0, 0, 4, 4, None, 4, None) == -1
