@@ -13,13 +13,19 @@
  *   - randQB_EI: Algorithm 2, two passes over A per block.
  *   - both stop with the Frobenius error indicator of Theorem 1 / Algorithm 1,
  *     decremented row by row (Section 3.1, steps 7a-8e) unless row_by_row == 0.
+ *   - A may be dense (binary64, or bfloat16 / e4m3 for randQB_FP's precision form), CSR,
+ *     or COO (turned into CSR on the device); a batched fixed-rank form with its adjoint
+ *     serves differentiation; qb_svd_from_qb turns a QB factorisation into an approximate
+ *     truncated SVD (eq. (3)).
  *
  * Conventions shared by every entry point
  *   - All matrix pointers are DEVICE pointers owned by the caller.  The library never
  *     allocates or frees them; scratch memory comes from the caller's workspace.
- *   - All device work is enqueued on the caller's stream; calls that return a rank
- *     synchronise that stream before returning (the rank is decided on the host,
- *     one b-vector copy per block).
+ *   - All device work is ordered after earlier work on the caller's stream, and the call's
+ *     results are complete on that stream when it returns (parts may run on private
+ *     streams of default priority, joined to the caller's stream by events); calls that
+ *     return a rank synchronise that stream before returning (the rank is decided on the
+ *     host, one b-vector copy per block).
  *   - Dense A is row-major: A(i, j) at a[i * lda + j], lda >= n.
  *   - Q is column-major m x l_max: Q(i, j) at Q[j * ldq + i], ldq >= m.
  *   - B is row-major l_max x n: B(i, j) at B[i * ldb + j], ldb >= n.
@@ -52,7 +58,8 @@ typedef enum {
     QB_ERR_NONFINITE = -2,   /* ||A||_F^2 is NaN or Inf                                          */
     QB_ERR_WORKSPACE = -3,   /* workspace smaller than qb_workspace_bytes() reports              */
     QB_ERR_HIP = -4,         /* a HIP runtime call failed                                        */
-    QB_ERR_UNSUPPORTED = -5  /* e.g. power > 0 or an element type this entry point lacks       */
+    QB_ERR_UNSUPPORTED = -5  /* e.g. power > 0 with randQB_EI or a low-precision A, or an
+                                element type this entry point lacks                           */
 } qb_status;
 
 typedef enum { QB_ALGO_FP = 0, QB_ALGO_EI = 1 } qb_algo;
