@@ -11,6 +11,7 @@
 namespace qb {
 
 constexpr int kSvdThreads = 256;
+constexpr int kRegK = 8;   // columns of up to kRegK * 256 rows are held in registers
 
 // Fixed-order sum over the workgroup of three values at once.
 QB_DEV void block_sum3(double& a, double& b, double& c, double (*sh)[kSvdThreads / 64]) {
@@ -61,6 +62,47 @@ jacobi_round_kernel(double* __restrict__ X, double* __restrict__ W, int k, int64
     }
     double* xa = X + static_cast<int64_t>(a) * ld;
     double* xb = X + static_cast<int64_t>(b) * ld;
+    double* wa = W + static_cast<int64_t>(a) * ld;
+    double* wb = W + static_cast<int64_t>(b) * ld;
+    if (k <= kRegK * kSvdThreads) {
+        // the pair's columns of X and W are read once, into registers, before the decision,
+        // so that the rotation needs no second trip to memory
+        double u[kRegK], v[kRegK], p[kRegK], q[kRegK];
+        double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+        for (int e = 0; e < kRegK; ++e) {
+            const int i = threadIdx.x + e * kSvdThreads;
+            const bool in = i < k;
+            u[e] = in ? xa[i] : 0.0;
+            v[e] = in ? xb[i] : 0.0;
+            p[e] = in ? wa[i] : 0.0;
+            q[e] = in ? wb[i] : 0.0;
+        }
+#pragma unroll
+        for (int e = 0; e < kRegK; ++e) {
+            al += u[e] * u[e];
+            be += v[e] * v[e];
+            ga += u[e] * v[e];
+        }
+        block_sum3(al, be, ga, sh);
+        if (!(ga != 0.0) || !(fabs(ga) > tol * sqrt(al) * sqrt(be))) return;
+        const double zeta = (be - al) / (2.0 * ga);
+        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / sqrt(1.0 + t * t);
+        const double s = c * t;
+#pragma unroll
+        for (int e = 0; e < kRegK; ++e) {
+            const int i = threadIdx.x + e * kSvdThreads;
+            if (i < k) {
+                xa[i] = c * u[e] - s * v[e];
+                xb[i] = s * u[e] + c * v[e];
+                wa[i] = c * p[e] - s * q[e];
+                wb[i] = s * p[e] + c * q[e];
+            }
+        }
+        if (threadIdx.x == 0) flag[0] = 1;
+        return;
+    }
     double al = 0.0, be = 0.0, ga = 0.0;
     for (int i = threadIdx.x; i < k; i += kSvdThreads) {
         const double u = xa[i], v = xb[i];
@@ -74,8 +116,6 @@ jacobi_round_kernel(double* __restrict__ X, double* __restrict__ W, int k, int64
     const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
     const double c = 1.0 / sqrt(1.0 + t * t);
     const double s = c * t;
-    double* wa = W + static_cast<int64_t>(a) * ld;
-    double* wb = W + static_cast<int64_t>(b) * ld;
     for (int i = threadIdx.x; i < k; i += kSvdThreads) {
         const double u = xa[i], v = xb[i];
         xa[i] = c * u - s * v;
