@@ -121,3 +121,30 @@ def test_power_full_size_properties(qb):
     assert orth <= 1e-12
     assert opt - 1 <= k < r0.rank
     assert r1.passes == 4 * r1.chunks
+
+
+def test_power_csr_full_size_properties(qb):
+    """The 500000 x 200000 CSR workload at P = 1 in the benchmark's launch configuration
+    (l_max 16384, l~ = 50 b).  The residual cannot be formed densely, so: Q^T Q = I, and
+    B = Q^T A on 64 sampled columns (with Q orthonormal this makes E = ||A||^2 - ||B||^2 the
+    squared residual, Theorem 1), the indicator below eps^2, and 2 P + 2 passes per chunk."""
+    wl = W.C3
+    seed = W.SEED_OMEGA | 3
+    csr = wl.make()
+    rp, ci, va = _csr_dev(csr)
+    res = qb.qb_fp_csr(csr.m, csr.n, rp, ci, va, wl.tol, wl.b, seed, l_max=16384, l_tilde=0, power=1)
+    k = res.rank
+    Q, B = res.Q, res.B
+    eye = torch.eye(k, dtype=torch.float64, device="cuda")
+    orth = float((Q.T @ Q - eye).abs().max())
+    cols = np.random.default_rng(91).choice(csr.n, 64, replace=False)
+    S = csr.to_scipy().tocsc()
+    Acols = torch.tensor(S[:, cols].toarray(), device="cuda")
+    dB = float(torch.linalg.matrix_norm(B[:, torch.tensor(cols, device="cuda")] - Q.T @ Acols))
+    nB = float(torch.linalg.matrix_norm(B[:, torch.tensor(cols, device="cuda")]))
+    _log(f"C3 P=1: rank {k} E_rel {np.sqrt(max(res.E, 0) / res.normA2):.4f} orth {orth:.2e} "
+         f"|B - Q^T A|/|B| on sampled columns {dB / nB:.2e} passes {res.passes}")
+    assert res.status == qb.QB_OK and res.E < (wl.tol ** 2) * res.normA2
+    assert orth <= 1e-11
+    assert dB <= 1e-9 * nB
+    assert res.passes == 4 * res.chunks
