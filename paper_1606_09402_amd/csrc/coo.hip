@@ -88,10 +88,10 @@ CooLayout coo_layout(int64_t m, int64_t n, int64_t nnz) {
     CooLayout L{};
     const int cnt = static_cast<int>(nnz > 0 ? nnz : 1);
     size_t sort_bytes = 0, scan_bytes = 0;
-    hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, static_cast<const uint64_t*>(nullptr),
+    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, static_cast<const uint64_t*>(nullptr),
                                        static_cast<uint64_t*>(nullptr), static_cast<const int32_t*>(nullptr),
                                        static_cast<int32_t*>(nullptr), cnt, 0, key_bits(m, n));
-    hipcub::DeviceScan::ExclusiveSum(nullptr, scan_bytes, static_cast<const int32_t*>(nullptr),
+    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, scan_bytes, static_cast<const int32_t*>(nullptr),
                                      static_cast<int32_t*>(nullptr), cnt);
     const size_t tb = (sort_bytes > scan_bytes ? sort_bytes : scan_bytes) + 256;
     size_t off = 0;

@@ -11,8 +11,6 @@
 
 namespace qb {
 
-constexpr int kMaxB = 128;   // largest block size b the library accepts
-
 // Register layout for the b x b kernels (b <= BMAX): thread t owns column c = t mod BMAX
 // and rows a = t div BMAX + G q, q < Q, of the working matrix (G = 256 / BMAX row groups).
 // One step of a right-looking elimination publishes the pivot row in LDS (double

@@ -193,7 +193,7 @@ static size_t align256_(size_t x) { return (x + 255) & ~static_cast<size_t>(255)
 
 static size_t scan_bytes(int64_t items) {
     size_t tb = 0;
-    hipcub::DeviceScan::ExclusiveSum(nullptr, tb, static_cast<const int64_t*>(nullptr),
+    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, tb, static_cast<const int64_t*>(nullptr),
                                      static_cast<int64_t*>(nullptr), static_cast<int>(items));
     return tb + 256;
 }
@@ -276,7 +276,7 @@ CscLayout csc_layout(int64_t m, int64_t n, int64_t nnz) {
     (void)m;
     CscLayout L{};
     size_t temp_bytes = 0;
-    hipcub::DeviceRadixSort::SortPairs(nullptr, temp_bytes, static_cast<const int32_t*>(nullptr),
+    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, temp_bytes, static_cast<const int32_t*>(nullptr),
                                        static_cast<int32_t*>(nullptr),
                                        static_cast<const int32_t*>(nullptr),
                                        static_cast<int32_t*>(nullptr), static_cast<int>(nnz));
