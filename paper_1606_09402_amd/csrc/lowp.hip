@@ -472,7 +472,15 @@ QB_DEV constexpr int vmcnt_imm(int n) { return (n & 0xF) | ((n >> 4) << 14) | (7
 // puts there; there are no staging registers and no LDS store instructions.  The operands
 // of k-step s + 1 are read while the MFMAs of step s run.  Rows beyond M (columns beyond
 // N) re-read the last valid row; their results are never stored.
-template <int BM, int BN, int BK, int STAGES, int WM, int WN, int EPI>
+//
+// AT: A is read in place from an M-contiguous array (element (i, k) at A[k * lda + i], the
+// H = A_q^T G_q product): its tile is moved by DMA as BK rows of BM elements (the chunk c
+// of row k at slot (BM / 8) k + (c ^ 4 (k mod 4)), so that the 8 rows x 4 chunks of one
+// transposed read hit every 16-byte bank group twice), and the operand of a k-step is read
+// with two ds_read_b64_tr_b16: in each 16-lane group, lane j addresses row k0 + j / 4,
+// elements i0 + 4 (j mod 4) .. + 3, and lane i then holds A(i0 + i, k0 .. k0 + 3) (measured
+// on gfx950).
+template <int BM, int BN, int BK, int STAGES, int WM, int WN, int EPI, bool AT = false>
 __global__ void __launch_bounds__(64 * WM * WN, 1) gemm_bf16_dma_kernel(const Bf16GemmArgs g) {
     constexpr int NT = 64 * WM * WN, NW = NT / 64, CPR = BK / 8;
     constexpr int TM = BM / WM, TN = BN / WN, FM = TM / 32, FN = TN / 32;
@@ -503,6 +511,8 @@ __global__ void __launch_bounds__(64 * WM * WN, 1) gemm_bf16_dma_kernel(const Bf
         r = sl / CPR;
         c = (sl % CPR) ^ (CPR == 8 ? ((r >> 1) & 7) : ((r >> 2) & 3));
     };
+    constexpr int CPA = BM / 8;   // AT: 16-byte chunks per row (k) of the A tile
+    static_assert(!AT || (CPA % 16 == 0 && (BK * CPA) % (64 * NW) == 0), "AT tile shape");
     // One DMA instruction: 16 bytes per lane from src into LDS at lds_base + 16 lane.  It is
     // written as inline assembly so that the compiler does not count it among the memory
     // operations that LDS reads must wait for (it would wait for every tile in flight);
@@ -522,10 +532,16 @@ __global__ void __launch_bounds__(64 * WM * WN, 1) gemm_bf16_dma_kernel(const Bf
 #pragma unroll
         for (int j = 0; j < A_INSTR; ++j) {
             const int s0 = (wave * A_INSTR + j) * 64;
-            int r, c;
-            slot_rc(s0 + lane, r, c);
-            const int64_t gi = m0 + r < g.M ? m0 + r : g.M - 1;
-            dma16(g.A + gi * g.lda + k0 + 8 * c, &As[st][s0 * 8]);
+            if constexpr (AT) {
+                const int sl = s0 + lane, kr = sl / CPA, c = (sl % CPA) ^ (4 * (kr & 3));
+                const int64_t ci = m0 + 8 * c < g.M - 8 ? m0 + 8 * c : g.M - 8;
+                dma16(g.A + (k0 + kr) * g.lda + ci, &As[st][s0 * 8]);
+            } else {
+                int r, c;
+                slot_rc(s0 + lane, r, c);
+                const int64_t gi = m0 + r < g.M ? m0 + r : g.M - 1;
+                dma16(g.A + gi * g.lda + k0 + 8 * c, &As[st][s0 * 8]);
+            }
         }
 #pragma unroll
         for (int j = 0; j < B_INSTR; ++j) {
@@ -539,9 +555,27 @@ __global__ void __launch_bounds__(64 * WM * WN, 1) gemm_bf16_dma_kernel(const Bf
     const int wm0 = wm * TM, wn0 = wn * TN;
     const int lr = lane & 31, lch = lane >> 5;
     auto read_ops = [&](int st, int ks, bf16x8 (&a)[FM], bf16x8 (&b)[FN]) {
+        if constexpr (AT) {
+            const int grp = lane >> 4, j = lane & 15;
+            const int kk = 16 * ks + 8 * (grp >> 1) + (j >> 2);
 #pragma unroll
-        for (int fm = 0; fm < FM; ++fm)
-            a[fm] = *reinterpret_cast<const bf16x8*>(&As[st][dma_slot<BK>(wm0 + fm * 32 + lr, 2 * ks + lch) * 8]);
+            for (int fm = 0; fm < FM; ++fm) {
+                const int ii = wm0 + fm * 32 + 16 * (grp & 1) + 4 * (j & 3);
+                const int e0 = kk * BM + (((ii >> 3) ^ (4 * (kk & 3))) << 3) + (ii & 7);
+                const int e1 = e0 + 4 * BM;   // rows kk + 4: same swizzle
+                typedef short s16x4 __attribute__((ext_vector_type(4)));
+                typedef __attribute__((address_space(3))) s16x4* lds_s16x4;
+                const s16x4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4)(lds_ptr_t)&As[st][e0]);
+                const s16x4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4)(lds_ptr_t)&As[st][e1]);
+                typedef short s16x8 __attribute__((ext_vector_type(8)));
+                const s16x8 v = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+                a[fm] = __builtin_bit_cast(bf16x8, v);
+            }
+        } else {
+#pragma unroll
+            for (int fm = 0; fm < FM; ++fm)
+                a[fm] = *reinterpret_cast<const bf16x8*>(&As[st][dma_slot<BK>(wm0 + fm * 32 + lr, 2 * ks + lch) * 8]);
+        }
 #pragma unroll
         for (int fn = 0; fn < FN; ++fn)
             b[fn] = *reinterpret_cast<const bf16x8*>(&Bs[st][dma_slot<BK>(wn0 + fn * 32 + lr, 2 * ks + lch) * 8]);
@@ -704,6 +738,9 @@ hipError_t gemm_bf16(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda
     if (big && !a_km && !a_fp8 && g.vec && K % 32 == 0) {
         // K-contiguous bfloat16 operands with 16-byte aligned rows, whole K tiles: LDS DMA
         hipLaunchKernelGGL((gemm_bf16_dma_kernel<256, 256, 32, 4, 2, 4, 1>), grid, dim3(512), 0, s, g);
+    } else if (big && a_km && !a_fp8 && g.vec && K % 32 == 0 && M % 8 == 0) {
+        // H: bfloat16 A read in place (M-contiguous) through transposed LDS reads
+        hipLaunchKernelGGL((gemm_bf16_dma_kernel<256, 256, 32, 4, 2, 4, 0, true>), grid, dim3(512), 0, s, g);
     } else if (big) {
         if (a_km && a_fp8)
             hipLaunchKernelGGL((gemm_bf16_kernel<256, 256, 64, 2, 4, 0, true, true>), grid, dim3(512), 0, s, g);

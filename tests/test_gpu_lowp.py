@@ -77,6 +77,8 @@ def test_sumsq_bf16(qb, m, n):
     (129, 4099, 33, 5, 0),       # short and wide, odd widths
     (4096, 256, 128, 128, 0),    # tall and narrow
     (16300, 1000, 1000, 64, 0),  # 256 tiles of 256 x 256: the LDS-DMA kernel, ragged M, N, K
+    (2048, 16384, 1024, 0, 0),   # H with 256 tiles: A_q read in place by transposed LDS reads
+    (2048, 16376, 1000, 64, 0),  # the same with ragged H rows (16376 = 8 x 2047) and columns
 ])
 def test_sketch_lowp(qb, m, n, l, col0, pad):
     _log(f"sketch bf16 {m}x{n} l={l} col0={col0} pad={pad}")
