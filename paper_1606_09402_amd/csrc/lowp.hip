@@ -79,15 +79,21 @@ QB_DEV uint32_t e4m3_to_bf16(uint32_t v) {
     return s | (mag >= 8u ? normal : (m != 0u ? sub : 0u));
 }
 
-// 8 e4m3 bytes -> 8 bfloat16 values (same order)
+// 8 e4m3 bytes -> 8 bfloat16 values (same order).  v_cvt_pk_f32_fp8 widens two OCP e4m3
+// bytes of a word exactly to binary32 (gfx950 converts the OCP format); an e4m3 value has
+// 3 significand bits, so its bfloat16 is the high half of that binary32, and one v_perm_b32
+// packs two high halves.  Two conversions and one permute per 4 values.
+QB_DEV uint32_t pack_hi16(float lo, float hi) {
+    return __builtin_amdgcn_perm(__float_as_uint(hi), __float_as_uint(lo), 0x07060302u);
+}
+
 QB_DEV uint4 e4m3x8_to_bf16x8(uint2 q) {
-    uint32_t h[8];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        h[e] = e4m3_to_bf16((q.x >> (8 * e)) & 0xFFu);
-        h[e + 4] = e4m3_to_bf16((q.y >> (8 * e)) & 0xFFu);
-    }
-    return uint4{h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16)};
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    const f32x2 a = __builtin_amdgcn_cvt_pk_f32_fp8(static_cast<int>(q.x), false);
+    const f32x2 b = __builtin_amdgcn_cvt_pk_f32_fp8(static_cast<int>(q.x), true);
+    const f32x2 c = __builtin_amdgcn_cvt_pk_f32_fp8(static_cast<int>(q.y), false);
+    const f32x2 d = __builtin_amdgcn_cvt_pk_f32_fp8(static_cast<int>(q.y), true);
+    return uint4{pack_hi16(a[0], a[1]), pack_hi16(b[0], b[1]), pack_hi16(c[0], c[1]), pack_hi16(d[0], d[1])};
 }
 
 // binary32 -> bfloat16 bits, round to nearest, ties to even (finite inputs)
@@ -480,15 +486,24 @@ QB_DEV constexpr int vmcnt_imm(int n) { return (n & 0xF) | ((n >> 4) << 14) | (7
 // with two ds_read_b64_tr_b16: in each 16-lane group, lane j addresses row k0 + j / 4,
 // elements i0 + 4 (j mod 4) .. + 3, and lane i then holds A(i0 + i, k0 .. k0 + 3) (measured
 // on gfx950).
-template <int BM, int BN, int BK, int STAGES, int WM, int WN, int EPI, bool AT = false>
+//
+// A8 (with AT): A holds e4m3 bytes.  Its tile rows are BM bytes (16 chunks of 16 elements,
+// chunk c of row k at slot c ^ 2 (k mod 8)), and the operand of a k-step is one
+// ds_read_b64_tr_b8: in each 16-lane group lane j addresses row k0 + j / 2, elements
+// i0 + 8 (j mod 2) .. + 7, and lane i then holds A(i0 + i, k0 .. k0 + 7) as 8 bytes
+// (measured on gfx950), widened exactly to bfloat16 in registers.  The e4m3 row scales are
+// already in the other operand (2^e_k G_q).
+template <int BM, int BN, int BK, int STAGES, int WM, int WN, int EPI, bool AT = false, bool A8 = false>
 __global__ void __launch_bounds__(64 * WM * WN, 1) gemm_bf16_dma_kernel(const Bf16GemmArgs g) {
+    static_assert(!A8 || AT, "e4m3 A only in the transposed form");
     constexpr int NT = 64 * WM * WN, NW = NT / 64, CPR = BK / 8;
     constexpr int TM = BM / WM, TN = BN / WN, FM = TM / 32, FN = TN / 32;
-    constexpr int A_SLOTS = BM * CPR, B_SLOTS = BN * CPR;
+    constexpr int A_SLOTS = A8 ? BK * BM / 16 : BM * CPR, B_SLOTS = BN * CPR;
     constexpr int A_INSTR = A_SLOTS / 64 / NW, B_INSTR = B_SLOTS / 64 / NW;
     constexpr int PER_TILE = A_INSTR + B_INSTR;           // DMA instructions per wave per tile
     constexpr int KSTEPS = BK / 16;
     static_assert(A_SLOTS % (64 * NW) == 0 && B_SLOTS % (64 * NW) == 0, "whole DMA instructions per wave");
+    constexpr int CP8 = BM / 16;   // A8: 16-byte chunks per row (k) of the A tile
     static_assert((CPR == 8 || CPR == 4) && KSTEPS % 2 == 0, "tile depth 32 or 64");
     __shared__ __align__(16) uint16_t As[STAGES][BM * BK];
     __shared__ __align__(16) uint16_t Bs[STAGES][BN * BK];
@@ -532,7 +547,12 @@ __global__ void __launch_bounds__(64 * WM * WN, 1) gemm_bf16_dma_kernel(const Bf
 #pragma unroll
         for (int j = 0; j < A_INSTR; ++j) {
             const int s0 = (wave * A_INSTR + j) * 64;
-            if constexpr (AT) {
+            if constexpr (A8) {
+                const int sl = s0 + lane, kr = sl / CP8, c = (sl % CP8) ^ (2 * (kr & 7));
+                const int64_t ci = m0 + 16 * c < g.M - 16 ? m0 + 16 * c : g.M - 16;
+                const uint8_t* a8 = reinterpret_cast<const uint8_t*>(g.A);
+                dma16(reinterpret_cast<const uint16_t*>(a8 + (k0 + kr) * g.lda + ci), &As[st][s0 * 8]);
+            } else if constexpr (AT) {
                 const int sl = s0 + lane, kr = sl / CPA, c = (sl % CPA) ^ (4 * (kr & 3));
                 const int64_t ci = m0 + 8 * c < g.M - 8 ? m0 + 8 * c : g.M - 8;
                 dma16(g.A + (k0 + kr) * g.lda + ci, &As[st][s0 * 8]);
@@ -554,8 +574,24 @@ __global__ void __launch_bounds__(64 * WM * WN, 1) gemm_bf16_dma_kernel(const Bf
     };
     const int wm0 = wm * TM, wn0 = wn * TN;
     const int lr = lane & 31, lch = lane >> 5;
-    auto read_ops = [&](int st, int ks, bf16x8 (&a)[FM], bf16x8 (&b)[FN]) {
-        if constexpr (AT) {
+    // A8 keeps a k-step's A operand as its 8 raw bytes until the MFMAs that use it: the
+    // widening then waits for the LDS read only there, after the previous step's MFMAs
+    using AOp = std::conditional_t<A8, uint2, bf16x8>;
+    auto read_ops = [&](int st, int ks, AOp (&a)[FM], bf16x8 (&b)[FN]) {
+        if constexpr (A8) {
+            const int grp = lane >> 4, j = lane & 15;
+            const int kk = 16 * ks + 8 * (grp >> 1) + (j >> 1);
+            const uint8_t* tile = reinterpret_cast<const uint8_t*>(&As[st][0]);
+#pragma unroll
+            for (int fm = 0; fm < FM; ++fm) {
+                const int ii = wm0 + fm * 32 + 16 * (grp & 1) + 8 * (j & 1);
+                const int off = kk * BM + (((ii >> 4) ^ (2 * (kk & 7))) << 4) + (ii & 15);
+                typedef int i32x2 __attribute__((ext_vector_type(2)));
+                typedef __attribute__((address_space(3))) i32x2* lds_i32x2;
+                const i32x2 v = __builtin_amdgcn_ds_read_tr8_b64_v2i32((lds_i32x2)(lds_ptr_t)(tile + off));
+                a[fm] = make_uint2(static_cast<uint32_t>(v[0]), static_cast<uint32_t>(v[1]));
+            }
+        } else if constexpr (AT) {
             const int grp = lane >> 4, j = lane & 15;
             const int kk = 16 * ks + 8 * (grp >> 1) + (j >> 2);
 #pragma unroll
@@ -580,17 +616,22 @@ __global__ void __launch_bounds__(64 * WM * WN, 1) gemm_bf16_dma_kernel(const Bf
         for (int fn = 0; fn < FN; ++fn)
             b[fn] = *reinterpret_cast<const bf16x8*>(&Bs[st][dma_slot<BK>(wn0 + fn * 32 + lr, 2 * ks + lch) * 8]);
     };
-    auto mfmas = [&](const bf16x8 (&a)[FM], const bf16x8 (&b)[FN]) {
+    auto mfmas = [&](const AOp (&a)[FM], const bf16x8 (&b)[FN]) {
 #pragma unroll
-        for (int fm = 0; fm < FM; ++fm)
+        for (int fm = 0; fm < FM; ++fm) {
+            bf16x8 av;
+            if constexpr (A8) av = __builtin_bit_cast(bf16x8, e4m3x8_to_bf16x8(a[fm]));
+            else av = a[fm];
 #pragma unroll
             for (int fn = 0; fn < FN; ++fn)
-                acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[fm], b[fn], acc[fm][fn], 0, 0, 0);
+                acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, b[fn], acc[fm][fn], 0, 0, 0);
+        }
     };
     // the k-steps of one tile, two operand sets in flight (scheduling barriers keep the
     // compiler from sinking the reads back to their use)
     auto compute = [&](int st) {
-        bf16x8 a0[FM], b0[FN], a1[FM], b1[FN];
+        AOp a0[FM], a1[FM];
+        bf16x8 b0[FN], b1[FN];
         read_ops(st, 0, a0, b0);
 #pragma unroll
         for (int ks = 0; ks < KSTEPS; ks += 2) {
@@ -741,6 +782,10 @@ hipError_t gemm_bf16(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda
     } else if (big && a_km && !a_fp8 && g.vec && K % 32 == 0 && M % 8 == 0) {
         // H: bfloat16 A read in place (M-contiguous) through transposed LDS reads
         hipLaunchKernelGGL((gemm_bf16_dma_kernel<256, 256, 32, 4, 2, 4, 0, true>), grid, dim3(512), 0, s, g);
+    } else if (big && a_km && a_fp8 && g.vec && K % 32 == 0 && M % 16 == 0 && lda % 16 == 0 &&
+               reinterpret_cast<uintptr_t>(A) % 16 == 0) {
+        // H: e4m3 A read in place through transposed byte reads, widened in registers
+        hipLaunchKernelGGL((gemm_bf16_dma_kernel<256, 256, 32, 4, 2, 4, 0, true, true>), grid, dim3(512), 0, s, g);
     } else if (big) {
         if (a_km && a_fp8)
             hipLaunchKernelGGL((gemm_bf16_kernel<256, 256, 64, 2, 4, 0, true, true>), grid, dim3(512), 0, s, g);

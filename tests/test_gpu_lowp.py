@@ -255,7 +255,14 @@ def test_sumsq_fp8(qb, m, n):
     assert abs(got - want) <= 1e-14 * want
 
 
-@pytest.mark.parametrize("m,n,l,col0", [(700, 530, 200, 64), (1024, 768, 256, 0), (4096, 256, 128, 128)])
+@pytest.mark.parametrize("m,n,l,col0", [
+    (700, 530, 200, 64),
+    (1024, 768, 256, 0),
+    (4096, 256, 128, 128),
+    (2048, 16384, 1024, 0),    # H with 256 tiles: e4m3 A read in place by transposed byte reads
+    (2048, 16368, 1000, 64),   # the same with ragged H rows (16368 = 16 x 1023) and columns
+    (2048, 16380, 1000, 64),   # H rows not a multiple of 16: the register-staged kernel
+])
 def test_sketch_fp8(qb, m, n, l, col0):
     _log(f"sketch e4m3 {m}x{n} l={l} col0={col0}")
     _, A8, e, Aq = _fp8_pair(m, n, "poly1.5", 32)
