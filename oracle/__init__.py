@@ -15,6 +15,7 @@ randqb   Algorithm 1 framework, Algorithm 2 (randQB_EI), Algorithm 3 / 4
          case, a one-sided Jacobi SVD and the SVD-optimal rank used as pins.
 lowp     bfloat16 rounding for the precision form.
 svd      the approximate SVD from a QB factorisation (eq. (3)).
+trqrcp   trQRCP (randomized QR with column pivoting) driven by the indicator (Remark 3.2).
 diff     fixed-rank randQB_FP as a differentiable map A -> (Q, B) in float64
          torch CPU autograd (reference gradient for the differentiation form).
 """
