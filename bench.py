@@ -7,7 +7,8 @@ relative Frobenius tolerance 1e-3.  One step is one full call of the library's r
 already resident in HBM.  The headline uses the adaptive chunk schedule (l_tilde = -1:
 8 b Omega columns first, later chunks sized from the decay of E, at most 50 b); the
 paper's fixed l~ = 50 b rule (Section 5.4) and randQB_EI are timed beside it on the same
-matrix.
+matrix, and so is trQRCP (randomized QR with column pivoting) stopped by the same
+indicator (Remark 3.2).
 
 Precision form (reported beside the headline, in "precision"): the 32768 x 32768 matrix
 with sigma_j = j^-1.5 (b = 128, tol 1e-2) factorised once from its binary64 storage by the
@@ -105,6 +106,7 @@ def main():
     ap.add_argument("--no-diff", action="store_true")
     ap.add_argument("--no-sparse", action="store_true")
     ap.add_argument("--no-power", action="store_true")
+    ap.add_argument("--no-trqrcp", action="store_true")
     ap.add_argument("--sparse-only", action="store_true",
                     help="run only the CSR block and print its JSON (for profiling runs)")
     ap.add_argument("--gen-device", default="cuda", choices=["cuda", "cpu"],
@@ -289,6 +291,26 @@ def main():
                      "phase_ms": {"A_Omega_i": re_.ms[2], "At_Q_i": re_.ms[3], "total": re_.ms[5]}}
         print(f"# ei: {statistics.median(et) * 1e3:.1f} ms rank {re_.rank} passes {re_.passes}",
               file=sys.stderr, flush=True)
+    if not args.no_trqrcp:   # trQRCP driven by the same indicator (Remark 3.2), same matrix
+        def qrcp():
+            return qb.qb_trqrcp_dense(A, wl.tol, wl.b, seed, oversample=8, Q_store=Qs, B_store=Bs)
+        qrcp()
+        torch.cuda.synchronize()
+        qt = []
+        for _ in range(max(1, min(args.steps, 3))):
+            t = time.perf_counter()
+            rc = qrcp()
+            torch.cuda.synchronize()
+            qt.append(time.perf_counter() - t)
+        res3 = float(torch.linalg.matrix_norm(A - rc.Q @ rc.B) ** 2)
+        out["trqrcp"] = {"time_to_tol_s": round(statistics.median(qt), 6), "rank": rc.rank,
+                         "true_rel_err": (res3 / rc.normA2) ** 0.5, "oversample": 8,
+                         "passes": rc.passes, "blocks": rc.blocks,
+                         "bi_gemm_tflops": rc.gemm_flops[1] / (rc.ms[3] * 1e-3) / 1e12 if rc.ms[3] > 0 else None,
+                         "phase_ms": {"sketch": rc.ms[2], "At_Q_i": rc.ms[3],
+                                      "pivots_and_blocks": rc.ms[4], "total": rc.ms[5]}}
+        print(f"# trqrcp: {statistics.median(qt) * 1e3:.1f} ms rank {rc.rank} passes {rc.passes} "
+              f"phases {rc.ms[2]:.2f}/{rc.ms[3]:.2f}/{rc.ms[4]:.2f}", file=sys.stderr, flush=True)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, wl, seed, args.l_tilde)

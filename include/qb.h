@@ -209,6 +209,32 @@ QB_API size_t qb_coo_to_csr_bytes(const qb_coo* A);
 QB_API int qb_coo_to_csr(const qb_coo* A, int64_t* rowptr, int32_t* colind, double* val,
                          int64_t* nnz_out, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* trQRCP driven by the indicator (Remark 3.2): the truncated randomized QR with column
+ * pivoting of Duersch and Gu, stopped by the same indicator E = ||A||^2 - ||B||^2 and
+ * row-by-row rule (Section 3.1) as randQB, on dense row-major binary64 A.  The column
+ * permutation does not change the Frobenius norms of B or of its rows, so Theorem 1 holds.
+ *   Sketch: S = Omega^T A once, Omega the m x l Gaussian matrix of qb_gaussian_fill with
+ *   stream 1 (batch 0, rows 0..m-1, columns 0..l-1), l = b + oversample.
+ *   Block (bw = min(b, l_max - k) columns): bw steps of Householder QR with column pivoting
+ *   on the sketch pick the pivots J (the remaining sketch column of largest norm, the
+ *   smallest index among equal norms); then, as a block of Algorithm 2 with A(:, J) in place
+ *   of A Omega_i: Q_i = orth(A(:, J) - Q B(:, J)), re-orthogonalised, B_i = Q_i^T A; the
+ *   indicator is decremented row by row with the exhaustion guard against ||A(:, J_j)||; the
+ *   sketch follows the residual by the sample update S <- S - S(:, J) R_i^{-1} B_i (no
+ *   second pass for it).  passes = 1 + blocks.
+ *   Q    out, m x rank, column-major (ldq >= m), orthonormal columns.
+ *   B    out, rank x n row-major (ldb >= n) in the ORIGINAL column order, i.e. B = R P^T:
+ *        B(:, piv) is upper triangular up to rounding, and A ~ Q B as for randQB.
+ *   piv  out, device, at least l_max int32: the pivot columns in pivot order (0..rank-1).
+ *   p->power must be 0 (else QB_ERR_UNSUPPORTED); p->l_tilde is ignored; A must be QB_F64
+ *   (else QB_ERR_UNSUPPORTED); 0 <= oversample <= 128 (else QB_ERR_ARG).  Workspace:
+ *   qb_trqrcp_workspace_bytes (256-byte aligned; 0 for invalid arguments).  Synchronises the
+ *   stream once per block.  Returns as qb_fp_dense. */
+QB_API size_t qb_trqrcp_workspace_bytes(int64_t m, int64_t n, const qb_params* p, int32_t oversample);
+QB_API int qb_trqrcp_dense(const qb_dense* A, const qb_params* p, int32_t oversample, double* Q,
+                           int64_t ldq, double* B, int64_t ldb, int32_t* piv, void* ws,
+                           size_t ws_bytes, hipStream_t stream, qb_info* info);
+
 /* Omega(row0 + r, col0 + c) for r < rows, c < cols into out[r * ld + c] (row-major,
  * ld >= cols).  The paper only asks for a standard Gaussian matrix (randn in
  * Algorithms 2 and 4); this library pins the draw so that runs are reproducible:

@@ -134,6 +134,11 @@ def lib() -> ctypes.CDLL:
         L.qb_coo_to_csr_bytes.restype = ctypes.c_size_t
         L.qb_coo_to_csr.argtypes = [P(QbCoo), _vp, _vp, _vp, P(_c_i64), _vp, ctypes.c_size_t, _vp]
         L.qb_coo_to_csr.restype = ctypes.c_int
+        L.qb_trqrcp_workspace_bytes.argtypes = [_c_i64, _c_i64, P(QbParams), _c_i32]
+        L.qb_trqrcp_workspace_bytes.restype = ctypes.c_size_t
+        L.qb_trqrcp_dense.argtypes = [P(QbDense), P(QbParams), _c_i32, _vp, _c_i64, _vp, _c_i64, _vp, _vp,
+                                      ctypes.c_size_t, _vp, P(QbInfo)]
+        L.qb_trqrcp_dense.restype = ctypes.c_int
         L.qb_svd_workspace_bytes.argtypes = [_c_i64, _c_i64, _c_i64]
         L.qb_svd_workspace_bytes.restype = ctypes.c_size_t
         L.qb_svd_from_qb.argtypes = [_c_i64, _c_i64, _c_i64, _vp, _c_i64, _vp, _c_i64, _vp, _c_i64, _vp,
@@ -295,6 +300,61 @@ def qb_ei_csr(m: int, n: int, rowptr, colind, val, tol: float, b: int, seed: int
     c = _csr(m, n, rowptr, colind, val)
     return _run("qb_ei_csr", QB_ALGO_EI, True, c, m, n, val.device, tol, b, l_max, 0, seed,
                 row_by_row, Q_store, B_store, ws)
+
+
+@dataclass
+class QRCPResult(QBResult):
+    piv: torch.Tensor | None = None   # pivot columns in pivot order (rank entries, int32)
+
+
+def qb_trqrcp_workspace_bytes(m: int, n: int, tol: float, b: int, l_max: int, oversample: int = 8,
+                              seed: int = 0) -> int:
+    p = _params(tol, b, l_max, 0, seed, True)
+    return int(lib().qb_trqrcp_workspace_bytes(m, n, ctypes.byref(p), int(oversample)))
+
+
+def qb_trqrcp_dense(A: torch.Tensor, tol: float, b: int, seed: int, oversample: int = 8, l_max=None,
+                    row_by_row: bool = True, Q_store=None, B_store=None, piv_store=None,
+                    ws=None) -> QRCPResult:
+    """trQRCP driven by the indicator (Remark 3.2) on dense float64 A (GPU, row-major).
+    B comes back in the original column order (B = R P^T); piv lists the pivot columns."""
+    L = lib()
+    d = _dense(A)
+    m, n = d.m, d.n
+    l_max = min(m, n) if l_max is None else int(l_max)
+    p = _params(tol, b, l_max, 0, seed, row_by_row)
+    dev = A.device
+    need = L.qb_trqrcp_workspace_bytes(m, n, ctypes.byref(p), int(oversample))
+    if need == 0:
+        st = L.qb_trqrcp_dense(ctypes.byref(d), ctypes.byref(p), int(oversample), None, 0, None, 0, None,
+                               None, 0, _stream_ptr(dev), None)
+        raise QBError(st if st < 0 else QB_ERR_ARG, "qb_trqrcp_dense")
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    if Q_store is None:
+        Q_store = torch.empty((l_max, m), dtype=torch.float64, device=dev)
+    if B_store is None:
+        B_store = torch.empty((l_max, n), dtype=torch.float64, device=dev)
+    if piv_store is None:
+        piv_store = torch.empty(l_max, dtype=torch.int32, device=dev)
+    if Q_store.shape[0] < l_max or Q_store.stride(1) != 1 or Q_store.stride(0) < m:
+        raise ValueError("Q_store must be at least l_max x m with unit column stride")
+    if B_store.shape[0] < l_max or B_store.stride(1) != 1 or B_store.stride(0) < n:
+        raise ValueError("B_store must be at least l_max x n with unit column stride")
+    if piv_store.numel() < l_max or piv_store.dtype != torch.int32 or not piv_store.is_contiguous():
+        raise ValueError("piv_store must hold l_max contiguous int32")
+    info = QbInfo()
+    st = L.qb_trqrcp_dense(ctypes.byref(d), ctypes.byref(p), int(oversample), Q_store.data_ptr(),
+                           Q_store.stride(0), B_store.data_ptr(), B_store.stride(0), piv_store.data_ptr(),
+                           ws.data_ptr(), ws.numel(), _stream_ptr(dev), ctypes.byref(info))
+    if st < 0:
+        raise QBError(st, "qb_trqrcp_dense")
+    r = int(info.rank)
+    return QRCPResult(Q=Q_store[:r].T, B=B_store[:r], rank=r, E=info.E, normA2=info.normA2, status=st,
+                      passes=info.passes, blocks=info.blocks, chunks=info.chunks,
+                      exhausted=info.exhausted, fallbacks=info.fallbacks, ms=list(info.ms),
+                      gemm_flops=list(info.gemm_flops), Q_store=Q_store, B_store=B_store,
+                      piv=piv_store[:r])
 
 
 def _coo(m: int, n: int, row: torch.Tensor, col: torch.Tensor, val: torch.Tensor) -> QbCoo:

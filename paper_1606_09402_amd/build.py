@@ -21,7 +21,7 @@ OBJDIR = os.path.join(ROOT, "_build")
 LIBNAME = "libqb.so"
 
 SOURCES = ["rng.hip", "reduce.hip", "gemm.hip", "lowp.hip", "panel.hip", "spmm.hip", "qb_host.hip",
-           "diff.hip", "svd.hip", "coo.hip"]
+           "diff.hip", "svd.hip", "coo.hip", "qrcp.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

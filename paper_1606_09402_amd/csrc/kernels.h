@@ -107,6 +107,16 @@ hipError_t coo_to_csr(const int32_t* row, const int32_t* col, const double* val,
                       hipStream_t s);
 void coo_counts(int64_t m, int64_t n, int64_t nnz, char* ws, const int64_t** nruns, const int** bad);
 
+// qrcp.hip -- trQRCP: pivoted QR of the transposed sketch (n x l), gathers of pivot columns
+int qrcp_max_rows();
+hipError_t launch_qrcp_norms(const double* St, int64_t n, int l, const int* active, double* norm2,
+                             hipStream_t s);
+hipError_t launch_qrcp_step(double* St, int64_t n, int l, int t, double* norm2, int* active, int* piv,
+                            const double* colA, double* g2, double* hh, hipStream_t s);
+hipError_t launch_qrcp_rs(const double* St, int l, const int* piv, int bw, double* Rs, hipStream_t s);
+hipError_t launch_gather_cols(const double* X, int64_t ldx, int64_t rows, const int* piv, int bw,
+                              double* Y, int64_t ldy, hipStream_t s);
+
 // svd.hip -- one-sided Jacobi SVD of a k x k factor (circle ordering) and its outputs
 int jacobi_players(int k);
 hipError_t launch_jacobi_round(double* X, double* W, int k, int64_t ld, int round, double tol,

@@ -24,6 +24,8 @@ constexpr double kUnitRoundoff = 0x1p-53;
 constexpr int64_t kGramSplitElems = 1 << 22;
 constexpr int kMaxPower = 16;               // largest power-scheme parameter P accepted
 constexpr int kPowerBlock = 128;            // column block of the power-scheme orth()
+constexpr int kMaxOversample = 128;         // trQRCP sketch rows beyond b
+constexpr uint32_t kSketchStream = 1;       // generator stream of trQRCP's sketch (randQB: 0)
 
 #define QB_HIP(expr)                                  \
     do {                                              \
@@ -39,6 +41,10 @@ struct Layout {
     size_t red, scal, om, g, h, gpart, gnorm2, y, x2, s, w, z, d, gram, r1, r1i, rt, rti, ri, rii, tau,
         rowsq_part, rowsq, info, flags, split, csc, plan_a, plan_t, omt, gqt, total;
     size_t split2;          // split-K partials of the products issued on the side stream
+    // trQRCP: sketch St (n x l), its Gaussian (m x l), ||A(:, j)||^2 and its partials, the
+    // remaining sketch norms, active flags, reflector, block pivots, their ||A(:, p)||^2,
+    // R~_11 and R~_11 R_i^{-1}
+    size_t sk, skom, cola, colpart, qn, act, hh, bpiv, g2p, rs, mm;
     int64_t lt, split_elems, split2_elems, gpart_groups;
     int64_t ldm16, ldn16;   // row strides (elements) of the bfloat16 copies: m, n rounded to 8
 };
@@ -83,7 +89,7 @@ int64_t next_chunk(const qb_params* p, int64_t cap, int64_t k, int64_t w_prev, i
 }
 
 Layout make_layout(int algo, int sparse, int dtype, int64_t m, int64_t n, int64_t nnz,
-                   const qb_params* p) {
+                   const qb_params* p, int64_t ell = 0) {
     Layout L{};
     const bool lowp = dtype == QB_BF16 || dtype == QB_FP8E4M3;
     const int64_t b = p->b;
@@ -155,6 +161,19 @@ Layout make_layout(int algo, int sparse, int dtype, int64_t m, int64_t n, int64_
     L.ldn16 = round_up(n, 8);
     L.omt = lowp ? take(sizeof(uint16_t) * lt * L.ldn16) : take(0);
     L.gqt = lowp ? take(sizeof(uint16_t) * lt * L.ldm16) : take(0);
+    if (ell > 0) {
+        L.sk = take(sizeof(double) * n * ell);
+        L.skom = take(sizeof(double) * m * ell);
+        L.cola = take(sizeof(double) * n);
+        L.colpart = take(sizeof(double) * colsq_groups(m) * n);
+        L.qn = take(sizeof(double) * n);
+        L.act = take(sizeof(int) * n);
+        L.hh = take(sizeof(double) * (ell + 1));
+        L.bpiv = take(sizeof(int) * b);
+        L.g2p = take(sizeof(double) * b);
+        L.rs = take(sizeof(double) * b * b);
+        L.mm = take(sizeof(double) * b * b);
+    }
     L.total = off + 256;
     return L;
 }
@@ -318,7 +337,8 @@ int cholqr(const Ctx& x, const double* X, int bw, double* Qout, int64_t ldq, dou
 }
 
 // Steps 11-14 of Algorithm 4 (steps 5-6 of Algorithm 2): given G_J (m x bw, row-major,
-// ld ldgj) and Omega_J (n x bw, row-major, ld ldoj), form W = B Omega_J,
+// ld ldgj) and Omega_J (n x bw, row-major, ld ldoj; nullptr when the caller has put W in
+// the w buffer already, as trQRCP does with W = B(:, J)), form W = B Omega_J,
 // Y = G_J - Q W (kept in the y buffer), Q_i = qr(Y), Q_i = qr(Q_i - Q (Q^T Q_i)) and
 // R_i = R~ R.  use_hh selects Householder instead of CholeskyQR for both qr calls.
 int fp_block_ds(const Ctx& x, int64_t k, int bw, const double* HJ, int64_t ldhj);
@@ -337,7 +357,7 @@ int orth_block(const Ctx& x, int64_t k, int bw, const double* GJ, int64_t ldgj, 
     double* Rti = x.at<double>(x.L.rti);
     double* tau = x.at<double>(x.L.tau);
     // W = B(0:k, :) Omega_J   (k x bw, row-major ld bw)
-    if (k > 0) {
+    if (k > 0 && OmJ != nullptr) {
         GemmDesc d = gdesc(k, bw, n, View{x.B, x.ldb, 1}, View{OmJ, ldoj, 1}, 1.0, 0.0,
                            View{nullptr, 0, 0}, MutView{W, bw, 1}, x);
         QB_HIP(gemm_f64(d, x.s));
@@ -880,6 +900,141 @@ int check_csr(const qb_csr* A) {
     return QB_OK;
 }
 
+// trQRCP driven by the indicator (Remark 3.2) on dense binary64 A.  The sketch
+// S = Omega^T A (Omega: m x l, generator stream 1) is taken once and kept transposed.  Per
+// block: bw pivot steps of Householder QR with column pivoting on the sketch choose the
+// columns J; the block is then factored as a block of Algorithm 2 with A(:, J) in place of
+// A Omega_i (W = B(:, J), Y = A(:, J) - Q W, the two QRs, B_i = Q_i^T A), the indicator is
+// decremented row by row, and the sketch follows the residual by the sample update
+// S <- S - S(:, J) R_i^{-1} B_i.  In the sketch's rotated basis (after the pivot steps its
+// pivot columns hold R~_11 over zeros) that update changes only the first bw rows, by
+// R~_11 R_i^{-1} B_i; the pivot columns are inactive from then on.
+int qrcp_run(const qb_dense* Ad, const qb_params* p, int oversample, double* Q, int64_t ldq,
+             double* B, int64_t ldb, int32_t* piv, void* ws, size_t ws_bytes, hipStream_t s,
+             qb_info* info) {
+    qb_info local{};
+    qb_info* inf = info ? info : &local;
+    memset(inf, 0, sizeof(*inf));
+    if (int st = check_dense(Ad)) return inf->status = st;
+    Op A = dense_op(Ad);
+    int st = check_params(p, A.m, A.n);
+    if (st != QB_OK) return inf->status = st;
+    if (A.dtype != QB_F64 || p->power != 0) return inf->status = QB_ERR_UNSUPPORTED;
+    if (oversample < 0 || oversample > kMaxOversample) return inf->status = QB_ERR_ARG;
+    if (Q == nullptr || B == nullptr || piv == nullptr || ws == nullptr || ldq < A.m || ldb < A.n)
+        return inf->status = QB_ERR_ARG;
+    if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return inf->status = QB_ERR_ARG;
+    const int64_t m = A.m, n = A.n, b = p->b, lmax = p->l_max;
+    const int ell = p->b + oversample;
+    if (ell > qrcp_max_rows()) return inf->status = QB_ERR_ARG;
+    const Layout L = make_layout(QB_ALGO_EI, 0, QB_F64, m, n, 0, p, ell);
+    if (ws_bytes < L.total) return inf->status = QB_ERR_WORKSPACE;
+    double* host = pinned_buffer();
+    if (host == nullptr) return inf->status = QB_ERR_HIP;
+
+    Timer tm(s);
+    char* wsb = static_cast<char*>(ws);
+    const Ctx x{A, p, Q, ldq, B, ldb, wsb, L, s, inf, &tm, host};
+    double* scal = x.at<double>(L.scal);
+    tm.mark(0);
+    QB_HIP(launch_sumsq_dense(A.a, m, n, A.lda, x.at<double>(L.red), scal, s));
+    QB_HIP(hipMemcpyAsync(host, scal, sizeof(double), hipMemcpyDeviceToHost, s));
+    QB_HIP(hipStreamSynchronize(s));
+    const double normA2 = host[0];
+    inf->normA2 = normA2;
+    if (!isfinite(normA2)) {
+        tm.mark(-1);
+        return inf->status = QB_ERR_NONFINITE;
+    }
+    const double eps2 = p->tol_rel * p->tol_rel * normA2;
+    const double floor_tol = sqrt(4.0 * kUnitRoundoff / 0.01);
+    const int status_tol = p->tol_rel < floor_tol ? QB_WARN_TOL_FLOOR : QB_OK;
+    double E = normA2;
+    int64_t k = 0;
+    bool exhausted = false;
+    if (!(normA2 == 0.0 || E < eps2)) {
+        double* St = x.at<double>(L.sk);
+        double* colA = x.at<double>(L.cola);
+        double* qn = x.at<double>(L.qn);
+        int* act = x.at<int>(L.act);
+        double* hh = x.at<double>(L.hh);
+        int* bpiv = x.at<int>(L.bpiv);
+        double* g2p = x.at<double>(L.g2p);
+        double* Rs = x.at<double>(L.rs);
+        double* M = x.at<double>(L.mm);
+        double* Y = x.at<double>(L.g);
+        double* Wb = x.at<double>(L.w);
+        QB_HIP(launch_fill_int(x.at<int>(L.flags), 8, 0, s));
+        // ||A(:, j)||^2, the reference of the exhaustion guard
+        QB_HIP(launch_colsq_rowmajor(A.a, m, n, A.lda, x.at<double>(L.colpart), s));
+        QB_HIP(launch_sum_partials(x.at<double>(L.colpart), colsq_groups(m), n, n, colA, s));
+        tm.mark(1);
+        QB_HIP(launch_gauss_fill(p->seed, kSketchStream, 0, 0, 0, m, ell, x.at<double>(L.skom), ell, s));
+        tm.mark(2);
+        if (int e = apply_At(x, x.at<double>(L.skom), ell, St, ell, ell)) return inf->status = e;
+        inf->passes += 1;
+        inf->gemm_flops[0] += 2.0 * m * n * ell;
+        tm.mark(4);
+        QB_HIP(launch_fill_int(act, static_cast<int>(n), 1, s));
+        QB_HIP(launch_qrcp_norms(St, n, ell, act, qn, s));
+        bool stop = false;
+        while (k < lmax && !stop) {
+            const int bwi = static_cast<int>(b < lmax - k ? b : lmax - k);
+            for (int t = 0; t < bwi; ++t)
+                QB_HIP(launch_qrcp_step(St, n, ell, t, qn, act, bpiv, colA, g2p, hh, s));
+            QB_HIP(launch_gather_cols(A.a, A.lda, m, bpiv, bwi, Y, bwi, s));
+            if (k > 0) QB_HIP(launch_gather_cols(B, ldb, k, bpiv, bwi, Wb, bwi, s));
+            bool breakdown = false;
+            for (int attempt = 0; attempt < 2; ++attempt) {
+                const bool use_hh = attempt == 1;
+                if (use_hh) {
+                    QB_HIP(launch_fill_int(x.at<int>(L.flags), 8, 0, s));
+                    inf->fallbacks += 1;
+                }
+                if (int e = orth_block(x, k, bwi, Y, bwi, nullptr, bwi, use_hh, nullptr, 0))
+                    return inf->status = e;
+                tm.mark(3);
+                if (int e = ei_block_b(x, k, bwi)) return inf->status = e;
+                tm.mark(4);
+                if (int e = fetch_block(x, bwi, g2p, &breakdown)) return inf->status = e;
+                if (!breakdown) break;
+            }
+            QB_HIP(hipMemcpyAsync(piv + k, bpiv, sizeof(int) * bwi, hipMemcpyDeviceToDevice, s));
+            inf->blocks += 1;
+            inf->passes += 1;
+            inf->gemm_flops[1] += 2.0 * m * n * bwi;
+            int keep = 0;
+            bool exh = false;
+            const int64_t k0 = k;
+            scan_rows(host, bwi, p->row_by_row != 0, eps2, &E, &keep, &stop, &exh);
+            k += keep;
+            if (exh) exhausted = true;
+            if (!stop && k < lmax) {
+                // sample update in the rotated basis: St(:, 0:bw) -= B_i^T (R~_11 R_i^{-1})^T
+                QB_HIP(launch_qrcp_rs(St, ell, bpiv, bwi, Rs, s));
+                GemmDesc d = gdesc(bwi, bwi, bwi, View{Rs, bwi, 1}, View{x.at<double>(L.rii), bwi, 1}, 1.0,
+                                   0.0, View{nullptr, 0, 0}, MutView{M, bwi, 1}, x);
+                QB_HIP(gemm_f64(d, s));
+                GemmDesc u = gdesc(n, bwi, bwi, View{B + k0 * ldb, 1, ldb}, View{M, 1, bwi}, -1.0, 1.0,
+                                   View{St, ell, 1}, MutView{St, ell, 1}, x);
+                QB_HIP(gemm_f64(u, s));
+                QB_HIP(launch_qrcp_norms(St, n, ell, act, qn, s));
+            }
+        }
+    }
+    tm.mark(-1);
+    QB_HIP(hipStreamSynchronize(s));
+    tm.collect(inf->ms);
+    inf->rank = k;
+    inf->E = E;
+    inf->exhausted = exhausted ? 1 : 0;
+    if (normA2 == 0.0 || E < eps2)
+        st = status_tol;
+    else
+        st = QB_NOT_CONVERGED;
+    return inf->status = st;
+}
+
 // Workspace of the SVD from QB: P (n x k, the orthonormalised B^T), T / X (k x k), the
 // rotations W, the sorted Ut and Ws (k x k each), the values and their order, and the
 // buffers of orth_panel (128-column panels of n rows, k x 128 projections, 128 x 128
@@ -1128,6 +1283,18 @@ int qb_ei_dense(const qb_dense* A, const qb_params* p, double* Q, int64_t ldq, d
     }
     Op o = dense_op(A);
     return run(QB_ALGO_EI, o, p, Q, ldq, B, ldb, ws, ws_bytes, stream, info);
+}
+
+size_t qb_trqrcp_workspace_bytes(int64_t m, int64_t n, const qb_params* p, int32_t oversample) {
+    if (m < 1 || n < 1 || check_params(p, m, n) != QB_OK) return 0;
+    if (oversample < 0 || oversample > kMaxOversample || p->b + oversample > qrcp_max_rows()) return 0;
+    return make_layout(QB_ALGO_EI, 0, QB_F64, m, n, 0, p, p->b + oversample).total;
+}
+
+int qb_trqrcp_dense(const qb_dense* A, const qb_params* p, int32_t oversample, double* Q, int64_t ldq,
+                    double* B, int64_t ldb, int32_t* piv, void* ws, size_t ws_bytes, hipStream_t stream,
+                    qb_info* info) {
+    return qrcp_run(A, p, oversample, Q, ldq, B, ldb, piv, ws, ws_bytes, stream, info);
 }
 
 int qb_fp_csr(const qb_csr* A, const qb_params* p, double* Q, int64_t ldq, double* B, int64_t ldb,

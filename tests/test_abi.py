@@ -95,3 +95,25 @@ def test_entry_points_reject_bad_arguments_without_gpu():
     assert L.qb_coo_to_csr_bytes(ctypes.byref(qb.QbCoo(100, 50, -1, None, None, None))) == 0
     assert L.qb_coo_to_csr_bytes(ctypes.byref(qb.QbCoo(100, 50, 0, None, None, None))) > 0
     assert L.qb_gaussian_fill(1, 0, 0, 0, 0, 4, 4, None, 4, None) == -1
+
+
+def test_trqrcp_argument_checks_without_gpu():
+    L = qb.lib()
+    ok = qb.qb_trqrcp_workspace_bytes(1000, 800, 1e-2, 32, 400, 8)
+    assert ok > 8 * (800 * 40 + 1000 * 40)               # the sketch and its Gaussian
+    assert qb.qb_trqrcp_workspace_bytes(1000, 800, 1e-2, 32, 400, -1) == 0
+    assert qb.qb_trqrcp_workspace_bytes(1000, 800, 1e-2, 32, 400, 129) == 0
+    assert qb.qb_trqrcp_workspace_bytes(1000, 800, 1e-2, 0, 400, 8) == 0
+    assert qb.qb_trqrcp_workspace_bytes(1000, 800, 1e-2, 32, 801, 8) == 0
+    p = qb.QbParams(1e-2, 20, 0, 10, 0, 1, 1, 0)
+    d = qb.QbDense(100, 50, 50, 0, 0, 1 << 20)
+    args = (1 << 20, 100, 1 << 20, 50, 1 << 20, 1 << 20, 1 << 30, None, None)
+    assert L.qb_trqrcp_dense(None, ctypes.byref(p), 8, *args) == -1
+    assert L.qb_trqrcp_dense(ctypes.byref(d), ctypes.byref(p), -1, *args) == -1
+    assert L.qb_trqrcp_dense(ctypes.byref(d), ctypes.byref(p), 129, *args) == -1
+    assert L.qb_trqrcp_dense(ctypes.byref(d), ctypes.byref(p), 8, 1 << 20, 100, 1 << 20, 50, None,
+                             1 << 20, 1 << 30, None, None) == -1          # no pivot output
+    p_pow = qb.QbParams(1e-2, 20, 1, 10, 0, 1, 1, 0)
+    assert L.qb_trqrcp_dense(ctypes.byref(d), ctypes.byref(p_pow), 8, *args) == -5
+    d16 = qb.QbDense(100, 50, 50, 1, 0, 1 << 20)
+    assert L.qb_trqrcp_dense(ctypes.byref(d16), ctypes.byref(p), 8, *args) == -5
