@@ -101,6 +101,9 @@ Layout make_layout(int algo, int sparse, int dtype, int64_t m, int64_t n, int64_
     L.split_elems = 512 * b * (b > 64 ? b : 64) + 65536;
     if (L.split_elems < kGramSplitElems) L.split_elems = kGramSplitElems;
     if (L.split_elems < 8 * (m > n ? m : n) * b) L.split_elems = 8 * (m > n ? m : n) * b;
+    // A^T Q_i (n x b, K = m): room for the split that gives the 128-row tall-skinny tiles
+    // about 2048 workgroups, 2048 * 128 * b partials whatever n is
+    if (L.split_elems < int64_t(2048) * 128 * b) L.split_elems = int64_t(2048) * 128 * b;
     // randQB_FP overlaps D = Q^T Y + W and S = H_J - B^T D with the panel QR on a second
     // stream: those products get their own partials buffer
     L.split2_elems = algo == QB_ALGO_FP ? L.split_elems : 0;
