@@ -286,8 +286,12 @@ def main():
             re_ = ei()
             torch.cuda.synchronize()
             et.append(time.perf_counter() - t)
+        ei_tf = re_.gemm_flops[1] / (re_.ms[3] * 1e-3) / 1e12 if re_.ms[3] > 0 else None
         out["ei"] = {"time_to_tol_s": round(statistics.median(et), 6), "rank": re_.rank,
                      "passes": re_.passes, "blocks": re_.blocks,
+                     "roofline": {"bound": "mfma", "kernel": "gemm_f64 A^T Q_i (all blocks)",
+                                  "achieved": ei_tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                  "frac": ei_tf / FP64_PEAK_TFLOPS if ei_tf else None},
                      "phase_ms": {"A_Omega_i": re_.ms[2], "At_Q_i": re_.ms[3], "total": re_.ms[5]}}
         print(f"# ei: {statistics.median(et) * 1e3:.1f} ms rank {re_.rank} passes {re_.passes}",
               file=sys.stderr, flush=True)
@@ -307,6 +311,11 @@ def main():
                          "true_rel_err": (res3 / rc.normA2) ** 0.5, "oversample": 8,
                          "passes": rc.passes, "blocks": rc.blocks,
                          "bi_gemm_tflops": rc.gemm_flops[1] / (rc.ms[3] * 1e-3) / 1e12 if rc.ms[3] > 0 else None,
+                         "roofline": {"bound": "mfma", "kernel": "gemm_f64 B_i = Q_i^T A (all blocks)",
+                                      "achieved": rc.gemm_flops[1] / (rc.ms[3] * 1e-3) / 1e12 if rc.ms[3] > 0 else None,
+                                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                      "frac": rc.gemm_flops[1] / (rc.ms[3] * 1e-3) / 1e12 / FP64_PEAK_TFLOPS
+                                      if rc.ms[3] > 0 else None},
                          "phase_ms": {"sketch": rc.ms[2], "At_Q_i": rc.ms[3],
                                       "pivots_and_blocks": rc.ms[4], "total": rc.ms[5]}}
         print(f"# trqrcp: {statistics.median(qt) * 1e3:.1f} ms rank {rc.rank} passes {rc.passes} "
