@@ -88,6 +88,26 @@ def test_trqrcp_vs_oracle(qb, m, n, b, ovs, tol, kind, l_max):
     _compare(res, ora, A, label)
 
 
+def test_trqrcp_whole_block_stopping(qb):
+    """Algorithm 1's whole-block test (row_by_row off): the rank is a multiple of b."""
+    A = _np(W.lowrank_dense(600, 450, W.sigma_law("poly2", 450), 19))
+    ora = T.trqrcp(A, 1e-3, 16, SEED, row_by_row=False)
+    res = qb.qb_trqrcp_dense(torch.from_numpy(A).cuda(), 1e-3, 16, SEED, row_by_row=False)
+    assert res.rank % 16 == 0
+    _compare(res, ora, A, "trqrcp whole-block 600x450 b=16")
+
+
+def test_trqrcp_strided_input(qb):
+    """A row-major view with row stride 513 > n = 509 (misaligned rows)."""
+    full = _np(W.lowrank_dense(420, 513, W.sigma_law("exp7", 420), 20))
+    A = np.ascontiguousarray(full[:, :509])
+    ora = T.trqrcp(A, 1e-4, 12, SEED, oversample=5)
+    view = torch.from_numpy(full).cuda()[:, :509]
+    assert view.stride(0) == 513
+    res = qb.qb_trqrcp_dense(view, 1e-4, 12, SEED, oversample=5)
+    _compare(res, ora, A, "trqrcp strided 420x509 ld=513 b=12")
+
+
 def test_trqrcp_benchmark_law_small(qb):
     """The benchmark's spectrum law at 4000 x 3000 (b = 64, tol 1e-3)."""
     wl = W.C2_SMALL
