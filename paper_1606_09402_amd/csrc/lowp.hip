@@ -493,9 +493,15 @@ QB_DEV constexpr int vmcnt_imm(int n) { return (n & 0xF) | ((n >> 4) << 14) | (7
 // i0 + 8 (j mod 2) .. + 7, and lane i then holds A(i0 + i, k0 .. k0 + 7) as 8 bytes
 // (measured on gfx950), widened exactly to bfloat16 in registers.  The e4m3 row scales are
 // already in the other operand (2^e_k G_q).
+//
+// A8 without AT (G = A_q Omega_q for e4m3 A): a tile row (i) is BK bytes, BK / 16 chunks of
+// 16 elements, chunk c of row r at slot c ^ ((r >> 3) & 1); the operand of k-step s of a
+// fragment is the 8 bytes at chunk s, half (lane / 32), read with one ds_read_b64 and widened
+// in registers.  The epilogue applies the row scales: G_q = bf16(2^e_i (A8 Omega_q)), and the
+// H operand 2^e_i G_q.
 template <int BM, int BN, int BK, int STAGES, int WM, int WN, int EPI, bool AT = false, bool A8 = false>
 __global__ void __launch_bounds__(64 * WM * WN, 1) gemm_bf16_dma_kernel(const Bf16GemmArgs g) {
-    static_assert(!A8 || AT, "e4m3 A only in the transposed form");
+    static_assert(!A8 || AT || BK == 32, "e4m3 A in the G form: 32-deep tiles (two chunks per row)");
     constexpr int NT = 64 * WM * WN, NW = NT / 64, CPR = BK / 8;
     constexpr int TM = BM / WM, TN = BN / WN, FM = TM / 32, FN = TN / 32;
     constexpr int A_SLOTS = A8 ? BK * BM / 16 : BM * CPR, B_SLOTS = BN * CPR;
@@ -547,7 +553,12 @@ __global__ void __launch_bounds__(64 * WM * WN, 1) gemm_bf16_dma_kernel(const Bf
 #pragma unroll
         for (int j = 0; j < A_INSTR; ++j) {
             const int s0 = (wave * A_INSTR + j) * 64;
-            if constexpr (A8) {
+            if constexpr (A8 && !AT) {
+                const int sl = s0 + lane, r = sl / (BK / 16), c = (sl % (BK / 16)) ^ ((r >> 3) & 1);
+                const int64_t gi = m0 + r < g.M ? m0 + r : g.M - 1;
+                const uint8_t* a8 = reinterpret_cast<const uint8_t*>(g.A);
+                dma16(reinterpret_cast<const uint16_t*>(a8 + gi * g.lda + k0 + 16 * c), &As[st][s0 * 8]);
+            } else if constexpr (A8) {
                 const int sl = s0 + lane, kr = sl / CP8, c = (sl % CP8) ^ (2 * (kr & 7));
                 const int64_t ci = m0 + 16 * c < g.M - 16 ? m0 + 16 * c : g.M - 16;
                 const uint8_t* a8 = reinterpret_cast<const uint8_t*>(g.A);
@@ -578,7 +589,14 @@ __global__ void __launch_bounds__(64 * WM * WN, 1) gemm_bf16_dma_kernel(const Bf
     // widening then waits for the LDS read only there, after the previous step's MFMAs
     using AOp = std::conditional_t<A8, uint2, bf16x8>;
     auto read_ops = [&](int st, int ks, AOp (&a)[FM], bf16x8 (&b)[FN]) {
-        if constexpr (A8) {
+        if constexpr (A8 && !AT) {
+            const uint8_t* tile = reinterpret_cast<const uint8_t*>(&As[st][0]);
+#pragma unroll
+            for (int fm = 0; fm < FM; ++fm) {
+                const int r = wm0 + fm * 32 + lr;
+                a[fm] = *reinterpret_cast<const uint2*>(tile + r * BK + ((ks ^ ((r >> 3) & 1)) << 4) + 8 * lch);
+            }
+        } else if constexpr (A8) {
             const int grp = lane >> 4, j = lane & 15;
             const int kk = 16 * ks + 8 * (grp >> 1) + (j >> 1);
             const uint8_t* tile = reinterpret_cast<const uint8_t*>(&As[st][0]);
@@ -684,6 +702,15 @@ __global__ void __launch_bounds__(64 * WM * WN, 1) gemm_bf16_dma_kernel(const Bf
                 if (i < g.M && j < g.N) {
                     if (EPI == 0) {
                         g.out[i * g.ldo + j] = static_cast<double>(acc[fm][fn][r]);
+                    } else if constexpr (A8) {
+                        // G_q = bf16(2^e_i (A8 Omega_q)(i, j)); the H operand is 2^e_i G_q
+                        const int e = g.row_exp[i];
+                        const uint16_t h = f32_to_bf16_rne(ldexpf(acc[fm][fn][r], e));
+                        const double v = bf16_to_f64(h);
+                        g.out[i * g.ldo + j] = v;
+                        g.outT[j * g.ldt + i] =
+                            static_cast<uint16_t>(__float_as_uint(ldexpf(__uint_as_float(uint32_t(h) << 16), e)) >> 16);
+                        csq[fn] += v * v;
                     } else {
                         const uint16_t h = f32_to_bf16_rne(acc[fm][fn][r]);
                         const double v = bf16_to_f64(h);
@@ -779,6 +806,10 @@ hipError_t gemm_bf16(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda
     if (big && !a_km && !a_fp8 && g.vec && K % 32 == 0) {
         // K-contiguous bfloat16 operands with 16-byte aligned rows, whole K tiles: LDS DMA
         hipLaunchKernelGGL((gemm_bf16_dma_kernel<256, 256, 32, 4, 2, 4, 1>), grid, dim3(512), 0, s, g);
+    } else if (big && !a_km && a_fp8 && g.vec && K % 32 == 0 && lda % 16 == 0 &&
+               reinterpret_cast<uintptr_t>(A) % 16 == 0) {
+        // G: e4m3 A rows moved by DMA as bytes, widened in registers, row scales in the epilogue
+        hipLaunchKernelGGL((gemm_bf16_dma_kernel<256, 256, 32, 4, 2, 4, 1, false, true>), grid, dim3(512), 0, s, g);
     } else if (big && a_km && !a_fp8 && g.vec && K % 32 == 0 && M % 8 == 0) {
         // H: bfloat16 A read in place (M-contiguous) through transposed LDS reads
         hipLaunchKernelGGL((gemm_bf16_dma_kernel<256, 256, 32, 4, 2, 4, 0, true>), grid, dim3(512), 0, s, g);

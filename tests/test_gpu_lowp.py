@@ -262,6 +262,8 @@ def test_sumsq_fp8(qb, m, n):
     (2048, 16384, 1024, 0),    # H with 256 tiles: e4m3 A read in place by transposed byte reads
     (2048, 16368, 1000, 64),   # the same with ragged H rows (16368 = 16 x 1023) and columns
     (2048, 16380, 1000, 64),   # H rows not a multiple of 16: the register-staged kernel
+    (16384, 2048, 1024, 0),    # G with 256 tiles: e4m3 A rows moved by DMA, row scales in the epilogue
+    (16300, 2048, 1000, 64),   # the same with ragged G rows and columns
 ])
 def test_sketch_fp8(qb, m, n, l, col0):
     _log(f"sketch e4m3 {m}x{n} l={l} col0={col0}")
