@@ -107,6 +107,7 @@ def main():
     ap.add_argument("--no-sparse", action="store_true")
     ap.add_argument("--no-power", action="store_true")
     ap.add_argument("--no-trqrcp", action="store_true")
+    ap.add_argument("--no-onepass", action="store_true")
     ap.add_argument("--sparse-only", action="store_true",
                     help="run only the CSR block and print its JSON (for profiling runs)")
     ap.add_argument("--gen-device", default="cuda", choices=["cuda", "cpu"],
@@ -320,6 +321,26 @@ def main():
                                       "pivots_and_blocks": rc.ms[4], "total": rc.ms[5]}}
         print(f"# trqrcp: {statistics.median(qt) * 1e3:.1f} ms rank {rc.rank} passes {rc.passes} "
               f"phases {rc.ms[2]:.2f}/{rc.ms[3]:.2f}/{rc.ms[4]:.2f}", file=sys.stderr, flush=True)
+
+    if not args.no_onepass:   # the single-pass sketch sweep (Remark 4.2) beside the two-pass one
+        w1 = 1024
+        tp, to = [], []
+        ows = torch.empty(qb.qb_sketch_onepass_bytes_for(A, w1), dtype=torch.uint8, device=dev)
+        for it in range(4):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            qb.qb_sketch_dense(A, seed, 0, w1)
+            torch.cuda.synchronize()
+            tp.append(time.perf_counter() - t)
+            t = time.perf_counter()
+            qb.qb_sketch_onepass(A, seed, 0, w1, ws=ows)
+            torch.cuda.synchronize()
+            to.append(time.perf_counter() - t)
+        del ows
+        out["onepass"] = {"l": w1, "two_pass_s": round(statistics.median(tp[1:]), 6),
+                          "one_pass_s": round(statistics.median(to[1:]), 6)}
+        print(f"# sketch sweep l={w1}: two-pass {statistics.median(tp[1:]) * 1e3:.2f} ms, "
+              f"one-pass {statistics.median(to[1:]) * 1e3:.2f} ms", file=sys.stderr, flush=True)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, wl, seed, args.l_tilde)

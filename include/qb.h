@@ -263,6 +263,19 @@ QB_API int qb_sumsq_dense(const qb_dense* A, double* out_host, void* ws, hipStre
 QB_API int qb_sketch_dense(const qb_dense* A, uint64_t seed, int64_t col0, int64_t l, double* om,
                     double* g, double* h, hipStream_t stream);
 
+/* Single-pass form of the same sweep (Remark 4.2) for binary64 A: A is streamed once in
+ * panels of panel_rows rows (0: panels of at most 96 MiB, a multiple of 128 rows), small
+ * enough to stay in the last-level cache; each panel A_p gives G_p = A_p Omega, and A_p^T G_p
+ * is added to H while A_p is cached, so each element of A leaves HBM once.  om, g, h as in
+ * qb_sketch_dense; H is summed over the panels in row order (a fixed order, so the result is
+ * reproducible; it equals qb_sketch_dense's H up to rounding).  ws (caller-owned device
+ * memory, qb_sketch_onepass_bytes bytes; 0 for invalid arguments) holds the split-K partials
+ * of the panel products.  Enqueued on stream; does not synchronise. */
+QB_API size_t qb_sketch_onepass_bytes(const qb_dense* A, int64_t l, int64_t panel_rows);
+QB_API int qb_sketch_onepass(const qb_dense* A, uint64_t seed, int64_t col0, int64_t l,
+                             int64_t panel_rows, double* om, double* g, double* h, void* ws,
+                             size_t ws_bytes, hipStream_t stream);
+
 /* The same sweep for bfloat16 or row-scaled e4m3 A (dtype QB_BF16 or QB_FP8E4M3),
  * exactly as qb_fp_dense runs it:
  * om receives the dequantised Omega_q (n x l, ld l), g the dequantised G_q (m x l,

@@ -134,6 +134,11 @@ def lib() -> ctypes.CDLL:
         L.qb_coo_to_csr_bytes.restype = ctypes.c_size_t
         L.qb_coo_to_csr.argtypes = [P(QbCoo), _vp, _vp, _vp, P(_c_i64), _vp, ctypes.c_size_t, _vp]
         L.qb_coo_to_csr.restype = ctypes.c_int
+        L.qb_sketch_onepass_bytes.argtypes = [P(QbDense), _c_i64, _c_i64]
+        L.qb_sketch_onepass_bytes.restype = ctypes.c_size_t
+        L.qb_sketch_onepass.argtypes = [P(QbDense), ctypes.c_uint64, _c_i64, _c_i64, _c_i64, _vp, _vp, _vp,
+                                        _vp, ctypes.c_size_t, _vp]
+        L.qb_sketch_onepass.restype = ctypes.c_int
         L.qb_trqrcp_workspace_bytes.argtypes = [_c_i64, _c_i64, P(QbParams), _c_i32]
         L.qb_trqrcp_workspace_bytes.restype = ctypes.c_size_t
         L.qb_trqrcp_dense.argtypes = [P(QbDense), P(QbParams), _c_i32, _vp, _c_i64, _vp, _c_i64, _vp, _vp,
@@ -463,6 +468,31 @@ def qb_sketch_dense(A: torch.Tensor, seed: int, col0: int, l: int):
                                g.data_ptr(), h.data_ptr(), _stream_ptr(dev))
     if st < 0:
         raise QBError(st, "qb_sketch_dense")
+    return om, g, h
+
+
+def qb_sketch_onepass_bytes_for(A: torch.Tensor, l: int, panel_rows: int = 0) -> int:
+    d = _dense(A)
+    return int(lib().qb_sketch_onepass_bytes(ctypes.byref(d), l, panel_rows))
+
+
+def qb_sketch_onepass(A: torch.Tensor, seed: int, col0: int, l: int, panel_rows: int = 0, ws=None):
+    """The single-pass sweep (Remark 4.2): (Omega, G, H) with A streamed once in row panels."""
+    L = lib()
+    d = _dense(A)
+    dev = A.device
+    need = L.qb_sketch_onepass_bytes(ctypes.byref(d), l, panel_rows)
+    if need == 0:
+        raise QBError(QB_ERR_ARG, "qb_sketch_onepass")
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    om = torch.empty((d.n, l), dtype=torch.float64, device=dev)
+    g = torch.empty((d.m, l), dtype=torch.float64, device=dev)
+    h = torch.empty((d.n, l), dtype=torch.float64, device=dev)
+    st = L.qb_sketch_onepass(ctypes.byref(d), int(seed) & (2 ** 64 - 1), col0, l, panel_rows, om.data_ptr(),
+                             g.data_ptr(), h.data_ptr(), ws.data_ptr(), ws.numel(), _stream_ptr(dev))
+    if st < 0:
+        raise QBError(st, "qb_sketch_onepass")
     return om, g, h
 
 

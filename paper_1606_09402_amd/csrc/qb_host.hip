@@ -1376,6 +1376,61 @@ int qb_sketch_dense(const qb_dense* A, uint64_t seed, int64_t col0, int64_t l, d
     return QB_OK;
 }
 
+// Single-pass form of the sketch sweep (Remark 4.2): A is streamed once, in panels of
+// panel_rows rows small enough to stay in the last-level cache; panel p gives
+// G_p = A_p Omega, and A_p^T G_p is added to H while A_p is still cached, so every element
+// of A leaves HBM once.  The H sum runs over the panels in order (fixed order).  The G_p
+// products are short (panel_rows x l outputs), so they split K over the workspace.
+static int64_t onepass_rows(const qb_dense* A, int64_t panel_rows) {
+    if (panel_rows > 0) return panel_rows < A->m ? panel_rows : A->m;
+    // default: panels of at most 96 MiB of A, a multiple of 128 rows
+    int64_t r = (int64_t(96) << 20) / (8 * (A->lda > 0 ? A->lda : 1));
+    r = (r / 128) * 128;
+    if (r < 128) r = 128;
+    return r < A->m ? r : A->m;
+}
+
+static int64_t onepass_ws_elems(int64_t rows, int64_t l) { return 32 * rows * l + 65536; }
+
+size_t qb_sketch_onepass_bytes(const qb_dense* A, int64_t l, int64_t panel_rows) {
+    if (check_dense(A) != QB_OK || A->dtype != QB_F64 || l < 1 || panel_rows < 0) return 0;
+    return sizeof(double) * onepass_ws_elems(onepass_rows(A, panel_rows), l);
+}
+
+int qb_sketch_onepass(const qb_dense* A, uint64_t seed, int64_t col0, int64_t l, int64_t panel_rows,
+                      double* om, double* g, double* h, void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (int st = check_dense(A)) return st;
+    if (A->dtype != QB_F64) return QB_ERR_UNSUPPORTED;
+    if (l < 1 || col0 < 0 || panel_rows < 0 || om == nullptr || g == nullptr || h == nullptr ||
+        ws == nullptr)
+        return QB_ERR_ARG;
+    const int64_t m = A->m, n = A->n, pr = onepass_rows(A, panel_rows);
+    const int64_t ws_elems = onepass_ws_elems(pr, l);
+    if (ws_bytes < sizeof(double) * static_cast<size_t>(ws_elems)) return QB_ERR_WORKSPACE;
+    const double* a = static_cast<const double*>(A->a);
+    QB_HIP(launch_gauss_fill(seed, 0, 0, 0, col0, n, l, om, l, stream));
+    for (int64_t p0 = 0; p0 < m; p0 += pr) {
+        const int64_t rows = pr < m - p0 ? pr : m - p0;
+        GemmDesc d{};   // G_p = A_p Omega
+        d.M = rows; d.N = l; d.K = n;
+        d.A = View{a + p0 * A->lda, A->lda, 1};
+        d.B = View{om, l, 1};
+        d.alpha = 1.0; d.beta = 0.0;
+        d.C = MutView{g + p0 * l, l, 1};
+        d.ws = static_cast<double*>(ws); d.ws_elems = ws_elems;
+        QB_HIP(gemm_f64(d, stream));
+        GemmDesc e{};   // H (+)= A_p^T G_p
+        e.M = n; e.N = l; e.K = rows;
+        e.A = View{a + p0 * A->lda, 1, A->lda};
+        e.B = View{g + p0 * l, l, 1};
+        e.alpha = 1.0; e.beta = p0 == 0 ? 0.0 : 1.0;
+        e.C0 = View{h, l, 1};
+        e.C = MutView{h, l, 1};
+        QB_HIP(gemm_f64(e, stream));
+    }
+    return QB_OK;
+}
+
 // Workspace of qb_sketch_lowp: the randQB_FP layout with one chunk of l columns (the
 // sketch buffers it uses are Omega_q^T, G_q^T, A_q^T and the column-norm partials).
 static bool sketch_lowp_layout(const qb_dense* A, int64_t l, Layout* L) {
