@@ -108,6 +108,8 @@ def main():
     ap.add_argument("--no-power", action="store_true")
     ap.add_argument("--no-trqrcp", action="store_true")
     ap.add_argument("--no-onepass", action="store_true")
+    ap.add_argument("--onepass-only", action="store_true",
+                    help="only one call of each sketch sweep (two-pass, single-pass) at l = 1024, for counters")
     ap.add_argument("--sparse-only", action="store_true",
                     help="run only the CSR block and print its JSON (for profiling runs)")
     ap.add_argument("--gen-device", default="cuda", choices=["cuda", "cpu"],
@@ -139,6 +141,15 @@ def main():
     A = wl.make(device=dev if args.gen_device == "cuda" else "cpu").to(dev)
     torch.cuda.synchronize()
     print(f"# generated {wl.name} on the GPU in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    if args.onepass_only:
+        ows = torch.empty(qb.qb_sketch_onepass_bytes_for(A, 1024), dtype=torch.uint8, device=dev)
+        torch.cuda.synchronize()
+        qb.qb_sketch_dense(A, seed, 0, 1024)
+        torch.cuda.synchronize()
+        qb.qb_sketch_onepass(A, seed, 0, 1024, ws=ows)
+        torch.cuda.synchronize()
+        print(json.dumps({"onepass_only": {"l": 1024, "calls": 1}}), flush=True)
+        return
     m, n = A.shape
     l_max = min(m, n)
     Qs = torch.empty((l_max, m), dtype=torch.float64, device=dev)
