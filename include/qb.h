@@ -20,7 +20,11 @@
  *
  * Conventions shared by every entry point
  *   - All matrix pointers are DEVICE pointers owned by the caller.  The library never
- *     allocates or frees them; scratch memory comes from the caller's workspace.
+ *     allocates or frees device memory: scratch memory comes from the caller's workspace.
+ *     Host-side read-backs go
+ *     to pageable memory of the calling thread.  A host thread's first call on a device
+ *     creates that thread's side stream and timing events for the device; later calls
+ *     reuse them (they live until the process ends).
  *   - All device work is ordered after earlier work on the caller's stream, and the call's
  *     results are complete on that stream when it returns (parts may run on private
  *     streams of default priority, joined to the caller's stream by events); calls that
@@ -119,7 +123,10 @@ typedef struct {
 
 typedef struct {
     double tol_rel;      /* stop when E < (tol_rel ||A||_F)^2 (strict), 0 <= tol_rel       */
-    int32_t b;           /* block size, 1 <= b <= 128                                        */
+    int32_t b;           /* block size, 1 <= b <= 128.  The b x b Cholesky
+                            factors and triangular inverses of every block are formed in one
+                            workgroup's registers and LDS, which bounds b; Section 5 uses
+                            b = 10 to 50.                                                   */
     int32_t power;       /* power-scheme parameter P of Algorithm 4 (steps 3-6), 0 <= P <= 16.
                             P > 0 is accepted by randQB_FP on binary64 A (dense or CSR) and
                             returns QB_ERR_UNSUPPORTED elsewhere.  Each chunk's Gaussian
@@ -171,9 +178,11 @@ QB_API size_t qb_workspace_bytes(int algo, int sparse, int64_t m, int64_t n, int
  * A->a is not read.  Returns 0 for invalid arguments or an unsupported combination. */
 QB_API size_t qb_dense_workspace_bytes(int algo, const qb_dense* A, const qb_params* p);
 
-/* randQB_FP (Algorithm 4, P = 0) on dense row-major A of dtype QB_F64 or QB_BF16.  ws
- * must hold at least qb_dense_workspace_bytes(QB_ALGO_FP, A, p) bytes of device memory
- * (256-byte aligned).  For QB_BF16 the relative tolerance is taken against ||A_q||_F. */
+/* randQB_FP (Algorithm 4) on dense row-major A of dtype QB_F64, QB_BF16 or QB_FP8E4M3
+ * (A->row_exp then gives the per-row power-of-two scales).  p->power > 0 (the power scheme
+ * of Algorithm 4 steps 3-6) is accepted for QB_F64 only.  ws must hold at least
+ * qb_dense_workspace_bytes(QB_ALGO_FP, A, p) bytes of device memory (256-byte aligned).  For
+ * the low-precision element types the relative tolerance is taken against ||A_q||_F. */
 QB_API int qb_fp_dense(const qb_dense* A, const qb_params* p, double* Q, int64_t ldq, double* B,
                 int64_t ldb, void* ws, size_t ws_bytes, hipStream_t stream, qb_info* info);
 
@@ -263,14 +272,19 @@ QB_API int qb_sumsq_dense(const qb_dense* A, double* out_host, void* ws, hipStre
 QB_API int qb_sketch_dense(const qb_dense* A, uint64_t seed, int64_t col0, int64_t l, double* om,
                     double* g, double* h, hipStream_t stream);
 
-/* Single-pass form of the same sweep (Remark 4.2) for binary64 A: A is streamed once in
- * panels of panel_rows rows (0: panels of at most 96 MiB, a multiple of 128 rows), small
- * enough to stay in the last-level cache; each panel A_p gives G_p = A_p Omega, and A_p^T G_p
- * is added to H while A_p is cached, so each element of A leaves HBM once.  om, g, h as in
- * qb_sketch_dense; H is summed over the panels in row order (a fixed order, so the result is
- * reproducible; it equals qb_sketch_dense's H up to rounding).  ws (caller-owned device
- * memory, qb_sketch_onepass_bytes bytes; 0 for invalid arguments) holds the split-K partials
- * of the panel products.  Enqueued on stream; does not synchronise. */
+/* Single-pass form of the same sweep (Remark 4.2) for binary64 A: A is streamed in panels
+ * of panel_rows rows (0: panels of at most 96 MiB of A, a multiple of 128 rows); each panel
+ * A_p gives G_p = A_p Omega, and A_p^T G_p is added to H right after, while A_p may still be
+ * in the last-level cache.  A leaves HBM once per panel only if the panel and the operands
+ * the two products stream beside it fit in that cache together, roughly
+ * 8 (panel_rows (n + l) + 2 n l) bytes within 256 MiB; for wider l the n x l operands
+ * Omega and H evict the panel and A is read about twice, as by qb_sketch_dense (measured
+ * at 20000 x 15000, l = 1024: about three times the algorithmic bytes, and slower than the
+ * two-pass sweep).  om, g, h as in qb_sketch_dense; H is summed over the panels in row
+ * order (a fixed order, so the result is reproducible; it equals qb_sketch_dense's H up to
+ * rounding).  ws (caller-owned device memory, qb_sketch_onepass_bytes bytes; 0 for invalid
+ * arguments) holds the split-K partials of the panel products.  Enqueued on stream; does
+ * not synchronise. */
 QB_API size_t qb_sketch_onepass_bytes(const qb_dense* A, int64_t l, int64_t panel_rows);
 QB_API int qb_sketch_onepass(const qb_dense* A, uint64_t seed, int64_t col0, int64_t l,
                              int64_t panel_rows, double* om, double* g, double* h, void* ws,
@@ -338,7 +352,6 @@ QB_API int qb_fixed_rank_bwd(const qb_batch* A, int64_t k, int32_t b, uint64_t s
                              void* dA, int64_t ldda, int64_t stride_da, void* ws, size_t ws_bytes,
                              hipStream_t stream);
 
-/* Human-readable name of a qb_status value (static storage). */
 /* Approximate truncated SVD from a QB factorisation (eq. (3) of the paper): the SVD of the
  * small factor, B = U~ diag(s) V~^T, turns A ~ QB into A ~ (Q U~) diag(s) V~^T; the leading
  * j columns of U = Q U~ and V = V~ with the leading j values of s approximate the rank-j SVD
@@ -363,6 +376,15 @@ QB_API int qb_svd_from_qb(int64_t m, int64_t n, int64_t k, const double* Q, int6
                           int64_t ldv, void* ws, size_t ws_bytes, hipStream_t stream,
                           int32_t* sweeps);
 
+/* Host-only self-check of the workspace layouts (no device work, no allocation): QB_OK if
+ * every region of the workspace that qb_{fp,ei}_{dense,csr} (oversample = 0, element type
+ * dtype) or qb_trqrcp_dense (oversample > 0: algo QB_ALGO_EI, sparse 0, QB_F64) would carve
+ * for this problem holds what the kernels writing it produce, QB_ERR_WORKSPACE if one is
+ * short, QB_ERR_ARG for invalid arguments. */
+QB_API int qb_layout_check(int algo, int sparse, int dtype, int64_t m, int64_t n, int64_t nnz,
+                           const qb_params* p, int32_t oversample);
+
+/* Human-readable name of a qb_status value (static storage). */
 QB_API const char* qb_status_string(int status);
 
 #ifdef __cplusplus

@@ -475,13 +475,25 @@ static hipError_t run_cfg(const GemmDesc& d, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Tile configuration for an M x N output: 0 tall-skinny (m x b panels), 1 small output with a
+// long reduction (split K), 2 the sketch sweep.
+static int shape_class(int64_t M, int64_t N) {
+    if (N <= 64 && M >= 4096) return 0;
+    if (N <= 64 || M <= 2048) return 1;
+    return 2;
+}
+
+int64_t gemm_f64_colsq_groups(int64_t M, int64_t N) {
+    return cdiv(M, shape_class(M, N) == 1 ? 64 : 128);
+}
+
 template <int AL, int BL>
 static hipError_t dispatch_shape(const GemmDesc& d, hipStream_t s) {
-    if (d.N <= 64 && d.M >= 4096)          // tall-skinny output (m x b panels)
-        return run_cfg<128, 64, 32, 4, 1, AL, BL, 2, 1>(d, s);
-    if (d.N <= 64 || d.M <= 2048)          // small output, long reduction (split-K)
-        return run_cfg<64, 64, 32, 2, 2, AL, BL, 2, 1>(d, s);
-    return run_cfg<128, 128, 32, 4, 2, AL, BL, 2, 2>(d, s);   // sketch sweep
+    switch (shape_class(d.M, d.N)) {
+        case 0: return run_cfg<128, 64, 32, 4, 1, AL, BL, 2, 1>(d, s);
+        case 1: return run_cfg<64, 64, 32, 2, 2, AL, BL, 2, 1>(d, s);
+        default: return run_cfg<128, 128, 32, 4, 2, AL, BL, 2, 2>(d, s);
+    }
 }
 
 hipError_t gemm_f64(const GemmDesc& d, hipStream_t s) {

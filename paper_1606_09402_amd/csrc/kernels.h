@@ -18,6 +18,8 @@ hipError_t launch_sumsq_vec(const double* x, int64_t len, double* scratch, doubl
 hipError_t launch_sum_partials(const double* partial, int64_t groups, int64_t stride, int64_t count,
                                double* out, hipStream_t s);
 hipError_t launch_sum_vector(const double* partial, int64_t count, double* out, hipStream_t s);
+// Partial sums the ||A||^2 launchers write into their scratch (dense, bfloat16, e4m3, vector).
+int64_t sumsq_partials();
 
 // gemm.hip -- FP64 MFMA GEMM.  out(i,j) = alpha sum_k Aop(i,k) Bop(k,j) + beta C0(i,j)
 struct GemmDesc {
@@ -34,6 +36,9 @@ struct GemmDesc {
     int max_split;       // 0 = automatic
 };
 hipError_t gemm_f64(const GemmDesc& d, hipStream_t s);
+// Row groups of the column sums of squares gemm_f64 writes for an M x N output (colsq):
+// one per output tile row, at most this many after a K split.
+int64_t gemm_f64_colsq_groups(int64_t M, int64_t N);
 
 // lowp.hip -- the low-precision (bfloat16 / e4m3-stored) form of the sketch sweep
 hipError_t launch_quant_transpose_omega(double* om, int64_t n, int64_t w, uint16_t* omT,

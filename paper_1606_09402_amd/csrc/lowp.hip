@@ -749,7 +749,7 @@ hipError_t launch_quant_transpose_omega(double* om, int64_t n, int64_t w, uint16
 
 hipError_t launch_sumsq_fp8(const uint8_t* a, const int32_t* row_exp, int64_t m, int64_t n,
                             int64_t lda, double* scratch, double* out, hipStream_t s) {
-    const int64_t g = m < 1024 ? m : 1024;
+    const int64_t g = m < sumsq_partials() ? m : sumsq_partials();
     const int vec = (reinterpret_cast<uintptr_t>(a) % 8 == 0) && (lda % 8 == 0);
     hipLaunchKernelGGL(sumsq_fp8_partial, dim3(static_cast<unsigned>(g)), dim3(256), 0, s, a, m, n, lda, vec,
                        row_exp, scratch);
@@ -760,7 +760,7 @@ hipError_t launch_sumsq_fp8(const uint8_t* a, const int32_t* row_exp, int64_t m,
 
 hipError_t launch_sumsq_bf16(const uint16_t* a, int64_t m, int64_t n, int64_t lda,
                              double* scratch, double* out, hipStream_t s) {
-    const int64_t g = m < 1024 ? m : 1024;
+    const int64_t g = m < sumsq_partials() ? m : sumsq_partials();
     const int vec = (reinterpret_cast<uintptr_t>(a) % 16 == 0) && (lda % 8 == 0);
     hipLaunchKernelGGL(sumsq_bf16_partial, dim3(static_cast<unsigned>(g)), dim3(256), 0, s, a, m,
                        n, lda, vec, scratch);

@@ -88,8 +88,10 @@ int64_t next_chunk(const qb_params* p, int64_t cap, int64_t k, int64_t w_prev, i
     return w < left ? w : left;
 }
 
+// split_cap >= 0 selects the allocation-free sizing: no partials for a side stream, and at most
+// split_cap elements of split-K partials (the products then take fewer K splits).
 Layout make_layout(int algo, int sparse, int dtype, int64_t m, int64_t n, int64_t nnz,
-                   const qb_params* p, int64_t ell = 0) {
+                   const qb_params* p, int64_t ell = 0, int64_t split_cap = -1) {
     Layout L{};
     const bool lowp = dtype == QB_BF16 || dtype == QB_FP8E4M3;
     const int64_t b = p->b;
@@ -110,6 +112,10 @@ Layout make_layout(int algo, int sparse, int dtype, int64_t m, int64_t n, int64_
     // dense randQB_FP: room for two K splits of the widest sketch GEMM (G, m x l~)
     if (algo == QB_ALGO_FP && !sparse && !lowp && L.split_elems < 2 * (m > n ? m : n) * lt)
         L.split_elems = 2 * (m > n ? m : n) * lt;
+    if (split_cap >= 0) {
+        if (L.split_elems > split_cap) L.split_elems = split_cap;
+        L.split2_elems = 0;
+    }
     // row-tile partials of the G column norms: dense GEMM tiles are >= 64 rows
     L.gpart_groups = sparse ? colsq_groups(m) : cdiv(m, 64);
     // per-block row sums of squares of B_i: partials from a GEMM epilogue over n rows
@@ -203,32 +209,72 @@ struct Op {
     SpmmPlan plan_a, plan_t;   // segment plans of CSR(A) and CSR(A^T)
 };
 
+// Streams and events that a host thread keeps per device across calls: the side stream of
+// the randQB_FP block loop with its two ordering events, and a pool of timing events.  They
+// are created on the thread's first call on that device and kept until the process ends,
+// so a call creates no stream or event once the pool has grown to the call's phase count.
+struct DevRes {
+    hipStream_t side = nullptr;
+    hipEvent_t ev_y = nullptr, ev_s = nullptr;
+    std::vector<hipEvent_t> pool;
+};
+
+constexpr int kMaxDevices = 64;
+
+DevRes* dev_res() {
+    thread_local DevRes* res[kMaxDevices] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    if (res[dev] == nullptr) {
+        DevRes* r = new DevRes();
+        // non-blocking, so that only the explicit events order it against the caller's
+        // stream (which may be the legacy default stream); default priority.  If it cannot
+        // be made, the products run on the caller's stream.
+        if (hipStreamCreateWithFlags(&r->side, hipStreamNonBlocking) != hipSuccess) r->side = nullptr;
+        if (r->side != nullptr && (hipEventCreateWithFlags(&r->ev_y, hipEventDisableTiming) != hipSuccess ||
+                                   hipEventCreateWithFlags(&r->ev_s, hipEventDisableTiming) != hipSuccess)) {
+            if (r->ev_y) (void)hipEventDestroy(r->ev_y);
+            (void)hipStreamDestroy(r->side);
+            r->side = nullptr;
+            r->ev_y = r->ev_s = nullptr;
+        }
+        (void)hipGetLastError();
+        res[dev] = r;
+    }
+    return res[dev];
+}
+
+// Phase timer: events recorded on the caller's stream at phase boundaries, taken from the
+// thread's pool (pool == nullptr: timing off, every mark is a no-op).
 struct Timer {
     hipStream_t s;
-    std::vector<hipEvent_t> ev;
+    std::vector<hipEvent_t>* pool;
+    size_t used = 0;
     std::vector<int> phase;
     bool ok = true;
-    explicit Timer(hipStream_t st) : s(st) {}
-    ~Timer() {
-        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
-    }
+    Timer(hipStream_t st, std::vector<hipEvent_t>* p) : s(st), pool(p) {}
     void mark(int ph) {   // start of phase ph (-1 = end of the previous phase)
-        hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) { ok = false; return; }
-        if (hipEventRecord(e, s) != hipSuccess) ok = false;
-        ev.push_back(e);
+        if (pool == nullptr) return;
+        if (used == pool->size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) { ok = false; return; }
+            pool->push_back(e);
+        }
+        if (hipEventRecord((*pool)[used], s) != hipSuccess) ok = false;
         phase.push_back(ph);
+        ++used;
     }
     // accumulate the time between consecutive marks into the phase of the earlier mark
     void collect(double* ms) {
-        for (size_t i = 0; i + 1 < ev.size(); ++i) {
+        if (pool == nullptr) return;
+        for (size_t i = 0; i + 1 < used; ++i) {
             float t = 0.f;
-            if (phase[i] >= 0 && hipEventElapsedTime(&t, ev[i], ev[i + 1]) == hipSuccess)
+            if (phase[i] >= 0 && hipEventElapsedTime(&t, (*pool)[i], (*pool)[i + 1]) == hipSuccess)
                 ms[phase[i]] += t;
         }
-        if (ev.size() >= 2) {
+        if (used >= 2) {
             float t = 0.f;
-            if (hipEventElapsedTime(&t, ev.front(), ev.back()) == hipSuccess) ms[5] = t;
+            if (hipEventElapsedTime(&t, (*pool)[0], (*pool)[used - 1]) == hipSuccess) ms[5] = t;
         }
     }
 };
@@ -650,30 +696,6 @@ void scan_rows(const double* hinfo, int bw, bool row_by_row, double eps2, double
     if (!row_by_row && Et < eps2) *stop = true;
 }
 
-// The second stream and its two events for the randQB_FP block loop, released on every
-// return path.  Non-blocking, so that only the explicit events order it against the caller's
-// stream (which may be the legacy default stream); default priority.  If it cannot be made,
-// the products run on the caller's stream.
-struct SideStream {
-    hipStream_t s = nullptr;
-    hipEvent_t ev_y = nullptr, ev_s = nullptr;
-    void make() {
-        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) s = nullptr;
-        if (s != nullptr && (hipEventCreateWithFlags(&ev_y, hipEventDisableTiming) != hipSuccess ||
-                             hipEventCreateWithFlags(&ev_s, hipEventDisableTiming) != hipSuccess))
-            release();
-        (void)hipGetLastError();
-    }
-    void release() {
-        if (ev_y) (void)hipEventDestroy(ev_y);
-        if (ev_s) (void)hipEventDestroy(ev_s);
-        if (s) (void)hipStreamDestroy(s);
-        s = nullptr;
-        ev_y = ev_s = nullptr;
-    }
-    ~SideStream() { release(); }
-};
-
 int check_params(const qb_params* p, int64_t m, int64_t n) {
     if (p == nullptr) return QB_ERR_ARG;
     if (p->power < 0 || p->power > kMaxPower) return QB_ERR_ARG;
@@ -687,21 +709,15 @@ int check_params(const qb_params* p, int64_t m, int64_t n) {
     return QB_OK;
 }
 
-thread_local double* t_pinned = nullptr;
+// Host buffer of the per-block read-back (pageable memory of the calling thread's stack):
+// 3 b doubles of decision data and a flag word.
+constexpr int kHostWords = 3 * kMaxB + 64;
 
-double* pinned_buffer() {
-    if (t_pinned == nullptr) {
-        void* p = nullptr;
-        if (hipHostMalloc(&p, sizeof(double) * (3 * kMaxB + 64), hipHostMallocDefault) != hipSuccess)
-            return nullptr;
-        t_pinned = static_cast<double*>(p);
-    }
-    return t_pinned;
-}
-
-// The common driver of the four entry points.
+// The common driver of the four entry points.  With Lfix set the call runs in the
+// allocation-free mode: the workspace layout is the given one (ws_bytes is not checked
+// against make_layout), and the call uses no side stream and no timing events.
 int run(int algo, Op& A, const qb_params* p, double* Q, int64_t ldq, double* B, int64_t ldb,
-        void* ws, size_t ws_bytes, hipStream_t s, qb_info* info) {
+        void* ws, size_t ws_bytes, hipStream_t s, qb_info* info, const Layout* Lfix = nullptr) {
     qb_info local{};
     qb_info* inf = info ? info : &local;
     memset(inf, 0, sizeof(*inf));
@@ -714,12 +730,12 @@ int run(int algo, Op& A, const qb_params* p, double* Q, int64_t ldq, double* B, 
     if (Q == nullptr || B == nullptr || ws == nullptr || ldq < A.m || ldb < A.n)
         return inf->status = QB_ERR_ARG;
     if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return inf->status = QB_ERR_ARG;
-    const Layout L = make_layout(algo, A.sparse, A.dtype, A.m, A.n, A.nnz, p);
+    const Layout L = Lfix != nullptr ? *Lfix : make_layout(algo, A.sparse, A.dtype, A.m, A.n, A.nnz, p);
     if (ws_bytes < L.total) return inf->status = QB_ERR_WORKSPACE;
-    double* host = pinned_buffer();
-    if (host == nullptr) return inf->status = QB_ERR_HIP;
-
-    Timer tm(s);
+    double host[kHostWords];
+    DevRes* res = Lfix != nullptr ? nullptr : dev_res();
+    Timer tm(s, res != nullptr ? &res->pool : nullptr);
+    const bool side_ok = algo == QB_ALGO_FP && res != nullptr && res->side != nullptr && L.split2_elems > 0;
     const int64_t m = A.m, n = A.n, b = p->b, lmax = p->l_max;
     char* wsb = static_cast<char*>(ws);
     double* scal = reinterpret_cast<double*>(wsb + L.scal);
@@ -742,9 +758,8 @@ int run(int algo, Op& A, const qb_params* p, double* Q, int64_t ldq, double* B, 
         QB_HIP(spmm_plan_build(A.rowptr, m, A.nnz, L.lt, wsb + L.plan_a, s, &A.plan_a));
         QB_HIP(spmm_plan_build(A.t_ptr, n, A.nnz, L.lt, wsb + L.plan_t, s, &A.plan_t));
     }
-    SideStream side;
-    if (algo == QB_ALGO_FP) side.make();
-    const Ctx x{A, p, Q, ldq, B, ldb, wsb, L, s, inf, &tm, host, side.s, side.ev_y, side.ev_s};
+    const Ctx x{A, p, Q, ldq, B, ldb, wsb, L, s, inf, &tm, host, side_ok ? res->side : nullptr,
+                side_ok ? res->ev_y : nullptr, side_ok ? res->ev_s : nullptr};
     QB_HIP(hipMemcpyAsync(host, scal, sizeof(double), hipMemcpyDeviceToHost, s));
     QB_HIP(hipStreamSynchronize(s));
     const double normA2 = host[0];
@@ -932,10 +947,9 @@ int qrcp_run(const qb_dense* Ad, const qb_params* p, int oversample, double* Q, 
     if (ell > qrcp_max_rows()) return inf->status = QB_ERR_ARG;
     const Layout L = make_layout(QB_ALGO_EI, 0, QB_F64, m, n, 0, p, ell);
     if (ws_bytes < L.total) return inf->status = QB_ERR_WORKSPACE;
-    double* host = pinned_buffer();
-    if (host == nullptr) return inf->status = QB_ERR_HIP;
-
-    Timer tm(s);
+    double host[kHostWords];
+    DevRes* res = dev_res();
+    Timer tm(s, res != nullptr ? &res->pool : nullptr);
     char* wsb = static_cast<char*>(ws);
     const Ctx x{A, p, Q, ldq, B, ldb, wsb, L, s, inf, &tm, host};
     double* scal = x.at<double>(L.scal);
@@ -1089,8 +1103,7 @@ int svd_from_qb(int64_t m, int64_t n, int64_t k, const double* Q, int64_t ldq, c
     if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return QB_ERR_ARG;
     const Layout L = svd_layout(m, n, k);
     if (ws_bytes < L.total) return QB_ERR_WORKSPACE;
-    double* host = pinned_buffer();
-    if (host == nullptr) return QB_ERR_HIP;
+    double host[kHostWords];
     char* wsb = static_cast<char*>(ws);
     Op none{};
     Ctx x{none, nullptr, nullptr, 0, nullptr, 0, wsb, L, s, nullptr, nullptr, host};
@@ -1191,15 +1204,14 @@ int check_coo(const qb_coo* A) {
 // synchronised.  ms (may be null) receives the device time of the conversion.
 int coo_convert(const qb_coo* A, const CooSplit& c, char* ws, hipStream_t s, int64_t* nnz_out,
                 double* ms) {
-    double* host = pinned_buffer();
-    if (host == nullptr) return QB_ERR_HIP;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    const bool timed = ms != nullptr && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
-    if (timed) QB_HIP(hipEventRecord(e0, s));
+    double host[2];
+    DevRes* res = ms != nullptr ? dev_res() : nullptr;
+    Timer tm(s, res != nullptr ? &res->pool : nullptr);
+    tm.mark(0);
     QB_HIP(coo_to_csr(A->row, A->col, A->val, A->m, A->n, A->nnz, ws + c.conv,
                       reinterpret_cast<int64_t*>(ws + c.rowptr), reinterpret_cast<int32_t*>(ws + c.colind),
                       reinterpret_cast<double*>(ws + c.val), s));
-    if (timed) QB_HIP(hipEventRecord(e1, s));
+    tm.mark(-1);
     const int64_t* nruns;
     const int* bad;
     coo_counts(A->m, A->n, A->nnz, ws + c.conv, &nruns, &bad);
@@ -1210,12 +1222,11 @@ int coo_convert(const qb_coo* A, const CooSplit& c, char* ws, hipStream_t s, int
     memcpy(&cnt, host, sizeof(cnt));
     int flag;
     memcpy(&flag, host + 1, sizeof(flag));
-    if (timed) {
-        float t = 0.f;
-        if (hipEventElapsedTime(&t, e0, e1) == hipSuccess) *ms = t;
+    if (ms != nullptr) {
+        double t[8] = {};
+        tm.collect(t);
+        *ms = t[0];
     }
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
     if (flag != 0) return QB_ERR_ARG;
     *nnz_out = cnt;
     return QB_OK;
@@ -1244,6 +1255,91 @@ int coo_run(int algo, const qb_coo* A, const qb_params* p, double* Q, int64_t ld
     const int r = run(algo, o, p, Q, ldq, B, ldb, wsb + c.run, ws_bytes - c.run, s, inf);
     inf->ms[7] = conv_ms;
     return r;
+}
+
+// ------------------------------------------------------------------ layout check
+
+// Whether every region of the workspace layout holds what its producers write (the extent of
+// a region runs to the next region's offset).  The producers' sizes come from the same
+// functions their launchers use.
+int layout_check(int algo, int sparse, int dtype, int64_t m, int64_t n, int64_t nnz, const qb_params* p,
+                 int ell) {
+    const Layout L = make_layout(algo, sparse, dtype, m, n, nnz, p, ell);
+    std::vector<size_t> offs = {L.red, L.scal, L.om, L.g, L.h, L.gpart, L.gnorm2, L.y, L.x2, L.s, L.w,
+                                L.z, L.d, L.gram, L.r1, L.r1i, L.rt, L.rti, L.ri, L.rii, L.tau,
+                                L.rowsq_part, L.rowsq, L.info, L.flags, L.split, L.split2, L.csc,
+                                L.plan_a, L.plan_t, L.omt, L.gqt, L.total};
+    if (ell > 0) offs.insert(offs.end(), {L.sk, L.skom, L.cola, L.colpart, L.qn, L.act, L.hh, L.bpiv,
+                                          L.g2p, L.rs, L.mm});
+    auto extent = [&](size_t off) {
+        size_t next = L.total;
+        for (size_t o : offs)
+            if (o > off && o < next) next = o;
+        return next - off;
+    };
+    bool ok = true;
+    auto need = [&](size_t off, double bytes) {
+        if ((off & 255) != 0 || static_cast<double>(extent(off)) < bytes) ok = false;
+    };
+    const bool lowp = dtype == QB_BF16 || dtype == QB_FP8E4M3;
+    const int64_t b = p->b, lt = L.lt, lmax = p->l_max;
+    const bool pw = p->power > 0;
+    const int64_t prow = pw && n > m ? n : m, pb = pw && b < kPowerBlock ? kPowerBlock : b;
+    const int64_t D = sizeof(double);
+    need(L.red, D * sumsq_partials());
+    need(L.scal, D);
+    need(L.om, D * n * lt);
+    need(L.g, D * m * (ell > 0 ? b : lt));
+    if (algo == QB_ALGO_FP) need(L.h, D * n * lt);
+    // column sums of squares of G (every chunk width w <= lt; EI: w = b)
+    for (int64_t w = 1; w <= lt; ++w) {
+        const int64_t groups = sparse ? colsq_groups(m) : lowp ? bf16_gemm_row_groups(m, w)
+                                                               : gemm_f64_colsq_groups(m, w);
+        need(L.gpart, D * groups * w);
+    }
+    need(L.gnorm2, D * lt);
+    need(L.y, D * prow * pb);
+    need(L.x2, D * prow * pb);
+    need(L.s, D * b * n);
+    need(L.w, D * lmax * b);
+    need(L.z, D * lmax * pb);
+    need(L.d, D * lmax * b);
+    for (size_t o : {L.gram, L.r1, L.r1i, L.rt, L.rti}) need(o, D * pb * pb);
+    need(L.ri, D * b * b);
+    need(L.rii, D * b * b);
+    need(L.tau, D * pb);
+    // row sums of squares of B_i: the B_i product (n x bw, K = bw for randQB_FP, K = m for
+    // randQB_EI) or, for CSR randQB_EI, the column reduction of A^T Q_i
+    for (int64_t bw = 1; bw <= b; ++bw) {
+        const int64_t groups = sparse && algo == QB_ALGO_EI ? colsq_groups(n) : gemm_f64_colsq_groups(n, bw);
+        need(L.rowsq_part, D * groups * bw);
+    }
+    need(L.rowsq, D * b);
+    need(L.info, D * 3 * b);
+    need(L.flags, sizeof(int) * 8);
+    if (sparse) {
+        need(L.csc, static_cast<double>(csc_layout(m, n, nnz).total));
+        need(L.plan_a, static_cast<double>(spmm_plan_bytes(m, nnz, lt)));
+        need(L.plan_t, static_cast<double>(spmm_plan_bytes(n, nnz, lt)));
+    }
+    if (lowp) {
+        need(L.omt, 2.0 * lt * L.ldn16);
+        need(L.gqt, 2.0 * lt * L.ldm16);
+    }
+    if (ell > 0) {
+        need(L.sk, D * n * ell);
+        need(L.skom, D * m * ell);
+        need(L.cola, D * n);
+        need(L.colpart, D * colsq_groups(m) * n);
+        need(L.qn, D * n);
+        need(L.act, sizeof(int) * n);
+        need(L.hh, D * (ell + 1));
+        need(L.bpiv, sizeof(int) * b);
+        need(L.g2p, D * b);
+        need(L.rs, D * b * b);
+        need(L.mm, D * b * b);
+    }
+    return ok ? QB_OK : QB_ERR_WORKSPACE;
 }
 
 }  // namespace
@@ -1276,6 +1372,14 @@ int qb_fp_dense(const qb_dense* A, const qb_params* p, double* Q, int64_t ldq, d
     }
     Op o = dense_op(A);
     return run(QB_ALGO_FP, o, p, Q, ldq, B, ldb, ws, ws_bytes, stream, info);
+}
+
+int qb_layout_check(int algo, int sparse, int dtype, int64_t m, int64_t n, int64_t nnz,
+                    const qb_params* p, int32_t oversample) {
+    if ((algo != QB_ALGO_FP && algo != QB_ALGO_EI) || m < 1 || n < 1 || nnz < 0) return QB_ERR_ARG;
+    if (check_params(p, m, n) != QB_OK || oversample < 0 || oversample > kMaxOversample) return QB_ERR_ARG;
+    const int ell = oversample > 0 ? p->b + oversample : 0;
+    return layout_check(algo, sparse != 0, dtype, m, n, nnz, p, ell);
 }
 
 int qb_ei_dense(const qb_dense* A, const qb_params* p, double* Q, int64_t ldq, double* B,
@@ -1376,10 +1480,10 @@ int qb_sketch_dense(const qb_dense* A, uint64_t seed, int64_t col0, int64_t l, d
     return QB_OK;
 }
 
-// Single-pass form of the sketch sweep (Remark 4.2): A is streamed once, in panels of
-// panel_rows rows small enough to stay in the last-level cache; panel p gives
-// G_p = A_p Omega, and A_p^T G_p is added to H while A_p is still cached, so every element
-// of A leaves HBM once.  The H sum runs over the panels in order (fixed order).  The G_p
+// Single-pass form of the sketch sweep (Remark 4.2): A is streamed in panels of panel_rows
+// rows; panel p gives G_p = A_p Omega, and A_p^T G_p is added to H right after, while A_p
+// may still be in the last-level cache (it stays there only if the panel and the n x l
+// operands fit in it together).  The H sum runs over the panels in order (fixed order).  The G_p
 // products are short (panel_rows x l outputs), so they split K over the workspace.
 static int64_t onepass_rows(const qb_dense* A, int64_t panel_rows) {
     if (panel_rows > 0) return panel_rows < A->m ? panel_rows : A->m;
@@ -1458,7 +1562,7 @@ int qb_sketch_lowp(const qb_dense* A, uint64_t seed, int64_t col0, int64_t l, do
     if (ws_bytes < L.total) return QB_ERR_WORKSPACE;
     char* wsb = static_cast<char*>(ws);
     Op o = dense_op(A);
-    Timer tm(stream);
+    Timer tm(stream, nullptr);
     const Ctx x{o, nullptr, nullptr, 0, nullptr, 0, wsb, L, stream, nullptr, &tm, nullptr};
     QB_HIP(launch_gauss_fill(seed, 0, 0, 0, col0, o.n, l, om, l, stream));
     return sketch_bf16(x, om, g, h, l, x.at<double>(L.gnorm2), false);
@@ -1519,8 +1623,7 @@ int qb_coo_to_csr(const qb_coo* A, int64_t* rowptr, int32_t* colind, double* val
         return QB_ERR_ARG;
     if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return QB_ERR_ARG;
     if (ws_bytes < coo_bytes(A->m, A->n, A->nnz)) return QB_ERR_WORKSPACE;
-    double* host = pinned_buffer();
-    if (host == nullptr) return QB_ERR_HIP;
+    double host[2];
     char* wsb = static_cast<char*>(ws);
     QB_HIP(coo_to_csr(A->row, A->col, A->val, A->m, A->n, A->nnz, wsb, rowptr, colind, val, stream));
     const int64_t* nruns;

@@ -105,6 +105,8 @@ hipError_t launch_sumsq_vec(const double* x, int64_t len, double* scratch, doubl
     return hipGetLastError();
 }
 
+int64_t sumsq_partials() { return kRedBlocks; }
+
 hipError_t launch_sum_vector(const double* partial, int64_t count, double* out, hipStream_t s) {
     hipLaunchKernelGGL(sum_vector_kernel, dim3(1), dim3(kRedThreads), 0, s, partial, count, out);
     return hipGetLastError();

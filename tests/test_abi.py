@@ -117,3 +117,4 @@ def test_trqrcp_argument_checks_without_gpu():
     assert L.qb_trqrcp_dense(ctypes.byref(d), ctypes.byref(p_pow), 8, *args) == -5
     d16 = qb.QbDense(100, 50, 50, 1, 0, 1 << 20)
     assert L.qb_trqrcp_dense(ctypes.byref(d16), ctypes.byref(p), 8, *args) == -5
+
