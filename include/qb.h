@@ -20,8 +20,8 @@
  *
  * Conventions shared by every entry point
  *   - All matrix pointers are DEVICE pointers owned by the caller.  The library never
- *     allocates or frees device memory: scratch memory comes from the caller's workspace.
- *     Host-side read-backs go
+ *     allocates or frees device memory: scratch memory comes from the caller's workspace
+ *     (qb_fp_dense_noalloc: from a static array of the library).  Host-side read-backs go
  *     to pageable memory of the calling thread.  A host thread's first call on a device
  *     creates that thread's side stream and timing events for the device; later calls
  *     reuse them (they live until the process ends).
@@ -185,6 +185,27 @@ QB_API size_t qb_dense_workspace_bytes(int algo, const qb_dense* A, const qb_par
  * the low-precision element types the relative tolerance is taken against ||A_q||_F. */
 QB_API int qb_fp_dense(const qb_dense* A, const qb_params* p, double* Q, int64_t ldq, double* B,
                 int64_t ldb, void* ws, size_t ws_bytes, hipStream_t stream, qb_info* info);
+
+/* Size of the device scratch array that qb_fp_dense_noalloc works in. */
+#define QB_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* qb_fp_dense for callers that cannot allocate memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): the same arguments without the
+ * workspace.  The call allocates nothing: its workspace is a static device array of
+ * QB_NOALLOC_SCRATCH_BYTES bytes inside the library (each device the library runs on holds
+ * one until the process ends); it creates no stream or event (everything runs on the
+ * caller's stream, and info->ms stays zero), and reads the per-block decision data back into
+ * pageable memory of the calling thread.  The first call on a device looks up that
+ * device's array address once.  Every call on a device shares that device's array, so
+ * calls that overlap on one device (several host threads or streams) race and must be
+ * serialised by the caller.  The layout is qb_fp_dense's with the split-K partials cut to
+ * what the array leaves, so the products may take fewer K splits: the results agree with
+ * qb_fp_dense's to rounding.  Returns QB_ERR_WORKSPACE, before any device work, when the
+ * problem's Omega / G / H chunks and block buffers do not fit in the array (for example,
+ * binary64 A with m, n about 1000 and a 50 b chunk fits; 4096 x 4096 with b = 64 does not);
+ * otherwise as qb_fp_dense. */
+QB_API int qb_fp_dense_noalloc(const qb_dense* A, const qb_params* p, double* Q, int64_t ldq,
+                               double* B, int64_t ldb, hipStream_t stream, qb_info* info);
 
 /* randQB_EI (Algorithm 2) on dense row-major binary64 A; EI's Omega_i is column block
  * i of the same Omega as randQB_FP uses. */

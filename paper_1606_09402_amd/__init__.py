@@ -95,6 +95,8 @@ def lib() -> ctypes.CDLL:
             f.argtypes = [P(QbDense), P(QbParams), _vp, _c_i64, _vp, _c_i64, _vp, ctypes.c_size_t, _vp,
                           P(QbInfo)]
             f.restype = ctypes.c_int
+        L.qb_fp_dense_noalloc.argtypes = [P(QbDense), P(QbParams), _vp, _c_i64, _vp, _c_i64, _vp, P(QbInfo)]
+        L.qb_fp_dense_noalloc.restype = ctypes.c_int
         for nm in ("qb_fp_csr", "qb_ei_csr"):
             f = getattr(L, nm)
             f.argtypes = [P(QbCsr), P(QbParams), _vp, _c_i64, _vp, _c_i64, _vp, ctypes.c_size_t, _vp,
@@ -280,6 +282,37 @@ def qb_fp_dense(A: torch.Tensor, tol: float, b: int, seed: int, l_max=None, l_ti
     d = _dense(A, row_exp)
     return _run("qb_fp_dense", QB_ALGO_FP, False, d, d.m, d.n, A.device, tol, b, l_max, l_tilde,
                 seed, row_by_row, Q_store, B_store, ws, power)
+
+
+def qb_fp_dense_noalloc(A: torch.Tensor, tol: float, b: int, seed: int, l_max=None, l_tilde: int = 0,
+                        row_by_row: bool = True, Q_store=None, B_store=None, power: int = 0,
+                        row_exp: torch.Tensor | None = None) -> QBResult:
+    """qb_fp_dense without a workspace: the library works in its static device scratch array
+    (QB_NOALLOC_SCRATCH_BYTES) and allocates nothing.  Pass Q_store / B_store to keep this
+    wrapper from allocating them."""
+    L = lib()
+    d = _dense(A, row_exp)
+    m, n, dev = d.m, d.n, A.device
+    l_max = min(m, n) if l_max is None else int(l_max)
+    p = _params(tol, b, l_max, l_tilde, seed, row_by_row, power)
+    if Q_store is None:
+        Q_store = torch.empty((l_max, m), dtype=torch.float64, device=dev)
+    if B_store is None:
+        B_store = torch.empty((l_max, n), dtype=torch.float64, device=dev)
+    if Q_store.shape[0] < l_max or Q_store.stride(1) != 1 or Q_store.stride(0) < m:
+        raise ValueError("Q_store must be at least l_max x m with unit column stride")
+    if B_store.shape[0] < l_max or B_store.stride(1) != 1 or B_store.stride(0) < n:
+        raise ValueError("B_store must be at least l_max x n with unit column stride")
+    info = QbInfo()
+    st = L.qb_fp_dense_noalloc(ctypes.byref(d), ctypes.byref(p), Q_store.data_ptr(), Q_store.stride(0),
+                               B_store.data_ptr(), B_store.stride(0), _stream_ptr(dev), ctypes.byref(info))
+    if st < 0:
+        raise QBError(st, "qb_fp_dense_noalloc")
+    r = int(info.rank)
+    return QBResult(Q=Q_store[:r].T, B=B_store[:r], rank=r, E=info.E, normA2=info.normA2, status=st,
+                    passes=info.passes, blocks=info.blocks, chunks=info.chunks,
+                    exhausted=info.exhausted, fallbacks=info.fallbacks, ms=list(info.ms),
+                    gemm_flops=list(info.gemm_flops), Q_store=Q_store, B_store=B_store)
 
 
 def qb_ei_dense(A: torch.Tensor, tol: float, b: int, seed: int, l_max=None, row_by_row: bool = True,

@@ -9,6 +9,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
 #include <vector>
 
 #include "kernels.h"
@@ -1342,6 +1343,45 @@ int layout_check(int algo, int sparse, int dtype, int64_t m, int64_t n, int64_t 
     return ok ? QB_OK : QB_ERR_WORKSPACE;
 }
 
+// ------------------------------------------------------------------ allocation-free entry
+
+// Scratch memory of qb_fp_dense_noalloc: a device array in the library's code object (each
+// device the library runs on holds its own copy until the process ends).  In host code the
+// name stands for a host-side shadow, never a device address: the device address is looked
+// up per device with hipGetSymbolAddress and only that pointer is handed to kernels.
+static __device__ __align__(256) char scratch[QB_NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// The current device's address of the scratch array, looked up on the first call on that
+// device (with it current) and kept.
+int scratch_ptr(void** out) {
+    int dev = 0;
+    QB_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return QB_ERR_ARG;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_dev[dev] == nullptr) {
+        void* ptr = nullptr;
+        QB_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (ptr == nullptr || (reinterpret_cast<uintptr_t>(ptr) & 255) != 0) return QB_ERR_HIP;
+        g_scratch_dev[dev] = ptr;
+    }
+    *out = g_scratch_dev[dev];
+    return QB_OK;
+}
+
+// Layout of the allocation-free mode inside the scratch array: make_layout's regions with the
+// split-K partials cut to the room the other regions leave.  false if they do not fit.
+bool noalloc_layout(const Op& A, const qb_params* p, Layout* L) {
+    const Layout base = make_layout(QB_ALGO_FP, 0, A.dtype, A.m, A.n, 0, p, 0, 0);
+    if (base.total > QB_NOALLOC_SCRATCH_BYTES) return false;
+    const int64_t room = static_cast<int64_t>(QB_NOALLOC_SCRATCH_BYTES - base.total) / 8 - 64;
+    if (room < 0) return false;
+    *L = make_layout(QB_ALGO_FP, 0, A.dtype, A.m, A.n, 0, p, 0, room);
+    return L->total <= QB_NOALLOC_SCRATCH_BYTES;
+}
+
 }  // namespace
 }  // namespace qb
 
@@ -1380,6 +1420,29 @@ int qb_layout_check(int algo, int sparse, int dtype, int64_t m, int64_t n, int64
     if (check_params(p, m, n) != QB_OK || oversample < 0 || oversample > kMaxOversample) return QB_ERR_ARG;
     const int ell = oversample > 0 ? p->b + oversample : 0;
     return layout_check(algo, sparse != 0, dtype, m, n, nnz, p, ell);
+}
+
+int qb_fp_dense_noalloc(const qb_dense* A, const qb_params* p, double* Q, int64_t ldq, double* B,
+                        int64_t ldb, hipStream_t stream, qb_info* info) {
+    int st = check_dense(A);
+    if (st == QB_OK && p == nullptr) st = QB_ERR_ARG;
+    if (st == QB_OK) st = check_params(p, A->m, A->n);
+    Op o{};
+    Layout L{};
+    if (st == QB_OK) {
+        o = dense_op(A);
+        if (!noalloc_layout(o, p, &L)) st = QB_ERR_WORKSPACE;
+    }
+    void* ws = nullptr;
+    if (st == QB_OK) st = scratch_ptr(&ws);
+    if (st != QB_OK) {
+        if (info) {
+            memset(info, 0, sizeof(*info));
+            info->status = st;
+        }
+        return st;
+    }
+    return run(QB_ALGO_FP, o, p, Q, ldq, B, ldb, ws, QB_NOALLOC_SCRATCH_BYTES, stream, info, &L);
 }
 
 int qb_ei_dense(const qb_dense* A, const qb_params* p, double* Q, int64_t ldq, double* B,
@@ -1440,16 +1503,16 @@ size_t qb_sumsq_workspace_bytes(void) { return sizeof(double) * 1040; }
 int qb_sumsq_dense(const qb_dense* A, double* out_host, void* ws, hipStream_t stream) {
     if (int st = check_dense(A)) return st;
     if (out_host == nullptr || ws == nullptr) return QB_ERR_ARG;
-    double* scratch = static_cast<double*>(ws);
-    double* res = scratch + 1024;
+    double* part = static_cast<double*>(ws);
+    double* res = part + 1024;
     if (A->dtype == QB_BF16)
-        QB_HIP(launch_sumsq_bf16(static_cast<const uint16_t*>(A->a), A->m, A->n, A->lda, scratch, res,
+        QB_HIP(launch_sumsq_bf16(static_cast<const uint16_t*>(A->a), A->m, A->n, A->lda, part, res,
                                  stream));
     else if (A->dtype == QB_FP8E4M3)
-        QB_HIP(launch_sumsq_fp8(static_cast<const uint8_t*>(A->a), A->row_exp, A->m, A->n, A->lda, scratch,
+        QB_HIP(launch_sumsq_fp8(static_cast<const uint8_t*>(A->a), A->row_exp, A->m, A->n, A->lda, part,
                                 res, stream));
     else
-        QB_HIP(launch_sumsq_dense(static_cast<const double*>(A->a), A->m, A->n, A->lda, scratch, res,
+        QB_HIP(launch_sumsq_dense(static_cast<const double*>(A->a), A->m, A->n, A->lda, part, res,
                                   stream));
     QB_HIP(hipMemcpyAsync(out_host, res, sizeof(double), hipMemcpyDeviceToHost, stream));
     QB_HIP(hipStreamSynchronize(stream));

@@ -118,3 +118,19 @@ def test_trqrcp_argument_checks_without_gpu():
     d16 = qb.QbDense(100, 50, 50, 1, 0, 1 << 20)
     assert L.qb_trqrcp_dense(ctypes.byref(d16), ctypes.byref(p), 8, *args) == -5
 
+
+def test_noalloc_entry_rejects_before_device_work():
+    """qb_fp_dense_noalloc checks its arguments and the scratch budget before any HIP call,
+    so these run without a GPU (the pointers are never dereferenced)."""
+    L = qb.lib()
+    d = qb.QbDense(4096, 4096, 4096, qb.QB_F64, 0, 16, None)
+    p = qb._params(1e-2, 64, 4096, 0, 1, True)
+    info = qb.QbInfo()
+    fake = ctypes.c_void_p(256)
+    st = L.qb_fp_dense_noalloc(ctypes.byref(d), ctypes.byref(p), fake, 4096, fake, 4096, None,
+                               ctypes.byref(info))
+    assert st == qb.QB_ERR_WORKSPACE and info.status == st
+    bad = qb._params(1e-2, 0, 4096, 0, 1, True)         # b = 0
+    assert L.qb_fp_dense_noalloc(ctypes.byref(d), ctypes.byref(bad), fake, 4096, fake, 4096, None,
+                                 None) == qb.QB_ERR_ARG
+    assert L.qb_fp_dense_noalloc(None, ctypes.byref(p), fake, 4096, fake, 4096, None, None) == qb.QB_ERR_ARG
