@@ -68,6 +68,10 @@ EXHAUST_REL = 2.0 ** -40
 UNIT_ROUNDOFF = 2.0 ** -53
 
 
+# power-of-two scale of Omega before its e4m3 rounding (the "e4m3" precision form)
+OMEGA_E4M3_SCALE = 2.0 ** 5
+
+
 def tol_floor(u: float = UNIT_ROUNDOFF, delta: float = 0.01) -> float:
     """Theorem 3: E is accurate to relative delta only if eps > sqrt(4u/delta) ||A||_F."""
     return float(np.sqrt(4.0 * u / delta))
@@ -230,12 +234,19 @@ def randqb_fp(A, tol_rel: float, b: int, seed: int, l_max=None, l_tilde: int = 0
     chunk's Omega is rounded to bfloat16 (Omega_q), G = A_q Omega_q is rounded to
     bfloat16 (G_q), and H = A_q^T G_q is formed from that same G_q.  The block loop uses
     Omega_q, G_q and H in binary64, so eq. (23) still yields B_i = Q_i^T A_q and
-    Theorem 1 holds for A_q with E starting from ||A_q||^2."""
+    Theorem 1 holds for A_q with E starting from ||A_q||^2.
+
+    precision = "e4m3" is the same form for a matrix stored in e4m3 with power-of-two row
+    scales (its values are bfloat16 values), whose G product runs on 8-bit operands:
+    Omega_q is the e4m3 rounding of 2^5 Omega, divided by 2^5 (|Omega| < 9 for the
+    generator's Gaussians, so 2^5 Omega stays inside the format's range and the division
+    is exact); G_q = bf16(A_q Omega_q), H = A_q^T G_q as above.  Any fixed Omega_q serves
+    as the sketch: Theorem 1 and eq. (23) hold for whatever matrix the block loop uses."""
     m, n, l_max = _check(A, tol_rel, b, l_max)
-    if precision not in ("f64", "bf16"):
-        raise ValueError("precision must be 'f64' or 'bf16'")
-    if precision == "bf16" and not lowp.is_bf16(A if not sp.issparse(A) else A.data):
-        raise ValueError("the precision form takes A already stored in bfloat16")
+    if precision not in ("f64", "bf16", "e4m3"):
+        raise ValueError("precision must be 'f64', 'bf16' or 'e4m3'")
+    if precision != "f64" and not lowp.is_bf16(A if not sp.issparse(A) else A.data):
+        raise ValueError("the precision form takes A already stored in bfloat16 or e4m3")
     if power < 0 or (power > 0 and precision != "f64"):
         raise ValueError("the power scheme takes power >= 0 and binary64")
     adaptive = l_tilde == -1
@@ -278,6 +289,9 @@ def randqb_fp(A, tol_rel: float, b: int, seed: int, l_max=None, l_tilde: int = 0
                 omegas.append(Om.copy())
             if precision == "bf16":
                 Om = lowp.round_bf16(Om)
+                G = lowp.round_bf16(np.asarray(A @ Om))
+            elif precision == "e4m3":
+                Om = lowp.round_e4m3(Om * OMEGA_E4M3_SCALE) / OMEGA_E4M3_SCALE
                 G = lowp.round_bf16(np.asarray(A @ Om))
             else:
                 G = A @ Om

@@ -74,6 +74,67 @@ def test_round_bf16_is_nearest_by_enumeration():
     assert not lowp.is_bf16(x)
 
 
+def test_round_e4m3_matches_binary32_to_e4m3_conversion():
+    # for binary32 inputs within the format's range a single RNE step to e4m3 is what
+    # torch's float32 -> float8_e4m3fn conversion does
+    g = np.random.default_rng(11)
+    x = np.concatenate([
+        g.standard_normal(50000) * np.exp(g.uniform(-14, 6, 50000)),
+        g.uniform(-448.0, 448.0, 2000),
+        g.uniform(-2.0 ** -6, 2.0 ** -6, 2000),                  # subnormals
+        np.array([0.0, -0.0, 448.0, -448.0, 2.0 ** -9, -(2.0 ** -6)]),
+    ]).astype(np.float32).astype(np.float64)
+    x = x[np.abs(x) <= 448.0]
+    ref = torch.from_numpy(x.astype(np.float32)).to(torch.float8_e4m3fn).double().numpy()
+    got = lowp.round_e4m3(x)
+    assert np.array_equal(got, ref)
+    assert np.array_equal(np.signbit(got), np.signbit(ref))
+
+
+def test_round_e4m3_ties_subnormals_and_range():
+    cases = {
+        1.0 + 1 / 16: 1.0,                     # tie between 1 and 1.125 -> even (1.0)
+        1.0 + 3 / 16: 1.25,                    # tie between 1.125 and 1.25 -> even (1.25)
+        1.0 + 1 / 16 + 2.0 ** -30: 1.125,      # just above the tie
+        -(1.0 + 1 / 16 + 2.0 ** -30): -1.125,
+        2.0 - 1 / 32: 2.0,                     # carry into the exponent
+        2.0 ** -10: 0.0,                       # half the smallest subnormal: tie -> 0
+        3 * 2.0 ** -10: 2.0 ** -8,             # tie between 1 and 2 quanta -> 2 quanta
+        2.0 ** -6 - 2.0 ** -11: 2.0 ** -6,     # rounds up into the normal range
+        7 * 2.0 ** -9: 7 * 2.0 ** -9,          # largest subnormal
+        448.0: 448.0,
+        456.0: 448.0,                          # below the midpoint 464 to the next binade step
+        464.0: 448.0,                          # the midpoint: tie to the even 448 (m = 6)
+    }
+    for x, want in cases.items():
+        got = float(lowp.round_e4m3(np.array([x]))[0])
+        assert got == want, (x, got, want)
+    assert np.isnan(lowp.round_e4m3(np.array([465.0]))[0])      # beyond the format
+    assert np.isnan(lowp.round_e4m3(np.array([np.inf]))[0])
+
+
+def test_round_e4m3_is_nearest_by_enumeration():
+    # every positive e4m3 value, from the definition of the format
+    vals = [m * 2.0 ** -9 for m in range(1, 8)]
+    for e in range(1, 16):
+        for m in range(8):
+            if e == 15 and m == 7:
+                continue                        # NaN encoding
+            vals.append(2.0 ** (e - 7) * (1 + m / 8))
+    vals = np.array(sorted(vals))
+    assert vals[-1] == 448.0 and len(vals) == 126
+    g = np.random.default_rng(5)
+    x = np.exp(g.uniform(np.log(2.0 ** -9), np.log(447.0), 20000))
+    got = lowp.round_e4m3(x)
+    idx = np.searchsorted(vals, x)
+    lo = vals[np.maximum(idx - 1, 0)]
+    hi = vals[np.minimum(idx, len(vals) - 1)]
+    nearest = np.where(x - lo < hi - x, lo, hi)
+    assert np.array_equal(got, nearest)
+    assert lowp.is_e4m3(got) and lowp.is_bf16(got)         # e4m3 values are bfloat16 values
+    assert not lowp.is_e4m3(x)
+
+
 # ------------------------------------------------------------------ precision form
 
 
@@ -134,3 +195,50 @@ def test_precision_form_rejects_unrounded_input():
     A64, _ = _bf16_matrix(100, 80, "poly2", 104)
     with pytest.raises(ValueError):
         R.randqb_fp(A64, 1e-2, 8, 1, precision="bf16")
+
+
+# ------------------------------------------------------------------ e4m3 form (8-bit G product)
+
+
+def _e4m3_matrix(m, n, kind, seed):
+    A64 = W.lowrank_dense(m, n, W.sigma_law(kind, min(m, n)), seed)
+    _, _, Aq = W.to_e4m3_rows(A64)
+    return A64.numpy(), Aq.numpy()
+
+
+def test_e4m3_form_indicator_is_exact_for_stored_matrix():
+    """Theorem 1 for the e4m3-stored A_q with Omega_q rounded to e4m3: eq. (23) with
+    H = A_q^T G_q still gives B = Q^T A_q, so E equals ||A_q - QB||^2."""
+    _, Aq = _e4m3_matrix(500, 400, "poly1.5", 111)
+    assert lowp.is_bf16(Aq)
+    res = R.randqb_fp(Aq, 5e-2, 32, W.SEED_OMEGA | 17, precision="e4m3")
+    assert res.status == R.QB_OK
+    nrm2 = R.sumsq(Aq)
+    assert abs(R.residual_sq(Aq, res.Q, res.B) - res.E) <= 1e-10 * nrm2
+    assert res.E < (5e-2) ** 2 * nrm2
+    assert np.linalg.norm(res.B - res.Q.T @ Aq) <= 1e-12 * np.sqrt(nrm2)
+    assert R.orth_loss_inf(res.Q) <= 1e-12
+
+
+def test_e4m3_form_omega_is_the_scaled_e4m3_rounding():
+    """One block of the e4m3 form spans qf(bf16(A_q Omega_q)) with Omega_q =
+    e4m3(2^5 Omega) / 2^5 -- and not the bfloat16 form's Omega_q."""
+    _, Aq = _e4m3_matrix(300, 200, "exp7", 112)
+    b, seed = 16, W.SEED_OMEGA | 18
+    res = R.randqb_fp(Aq, 1e-12, b, seed, l_max=b, l_tilde=b, precision="e4m3")
+    Om = R.omega(seed, 200, 0, b)
+    Om_q = lowp.round_e4m3(Om * 32.0) / 32.0
+    assert lowp.is_e4m3(Om_q * 32.0) and np.all(np.abs(Om * 32.0) < lowp.E4M3_MAX)
+    Q, _ = R.qr_pos(lowp.round_bf16(Aq @ Om_q))
+    assert np.allclose(np.abs(res.Q.T @ Q), np.eye(b), atol=1e-10)
+    Q_bf, _ = R.qr_pos(lowp.round_bf16(Aq @ lowp.round_bf16(Om)))
+    assert not np.allclose(np.abs(res.Q.T @ Q_bf), np.eye(b), atol=1e-6)
+
+
+def test_e4m3_form_generator_range():
+    """2^5 Omega fits the e4m3 range for every value the generator can produce: the
+    Box-Muller radius sqrt(-2 ln u1) with u1 >= 2^-53 is below 8.6."""
+    r_max = np.sqrt(-2.0 * np.log(2.0 ** -53))
+    assert r_max < 8.6 and 32.0 * r_max < lowp.E4M3_MAX
+    Om = R.omega(W.SEED_OMEGA | 19, 4096, 0, 64)
+    assert np.abs(Om).max() < r_max
