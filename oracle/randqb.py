@@ -111,6 +111,32 @@ def block_b(H_J, Y, Qk, Bk, W, R):
     return scipy.linalg.solve_triangular(R, S, trans="T", lower=False)
 
 
+def residual_sample(G_J, Om_J, Qk, Bk):
+    """The residual's sample (A - Q B) Omega_J = G_J - Q (B Omega_J) for the next block,
+    with G_J = A Omega_J; returns it and W = B Omega_J (B = Q^T A, so this samples
+    (I - Q Q^T) A without forming Q B)."""
+    W = Bk @ Om_J
+    return G_J - Qk @ W, W
+
+
+def orth_against(Y, Qk):
+    """An orthonormal basis Q_i of range(Y) orthogonal to range(Q): the Q factor of Y,
+    orthogonalised against Q once more and refactored (the re-orthogonalisation that
+    Algorithm 4 adds to Algorithm 3), with the triangular factor R of Y = Q_i R + Q (...)
+    (positive diagonal)."""
+    Qi, R = qr_pos(Y)
+    Qi, Rt = qr_pos(Qi - Qk @ (Qk.T @ Qi))
+    return Qi, Rt @ R
+
+
+def fp_block(G_J, Om_J, H_J, Qk, Bk):
+    """One block of randQB_FP from the sketches G = A Omega and H = A^T G alone: the new
+    basis block Q_i and B_i = Q_i^T A by eq. (23).  Returns (Q_i, B_i, R)."""
+    Y, W = residual_sample(G_J, Om_J, Qk, Bk)
+    Qi, R = orth_against(Y, Qk)
+    return Qi, block_b(H_J, Y, Qk, Bk, W, R), R
+
+
 def row_sumsq(Bi: np.ndarray) -> np.ndarray:
     return np.einsum("ij,ij->i", Bi, Bi)
 
@@ -303,13 +329,7 @@ def randqb_fp(A, tol_rel: float, b: int, seed: int, l_max=None, l_tilde: int = 0
             chunks += 1
         bw = min(b, chunk_hi - k)
         J = slice(k - chunk_lo, k - chunk_lo + bw)
-        Om_J, G_J, H_J = Om[:, J], G[:, J], H[:, J]
-        W = st.B @ Om_J                              # B Omega_i
-        Y = G_J - st.Q @ W                           # step 11 of Algorithm 4
-        Qi, R = qr_pos(Y)                            # step 12
-        Qi, Rt = qr_pos(Qi - st.Q @ (st.Q.T @ Qi))   # step 13 (re-orthogonalisation)
-        R = Rt @ R                                   # step 14
-        Bi = block_b(H_J, Y, st.Q, st.B, W, R)       # step 15, eq. (23)
+        Qi, Bi, R = fp_block(G[:, J], Om[:, J], H[:, J], st.Q, st.B)
         blocks += 1
         keep, E, stop, exh = _scan_rows(Bi, R, Gnorm[J], E, eps2, row_by_row)
         st.append(Qi[:, :keep], Bi[:keep])
@@ -343,14 +363,12 @@ def randqb_ei(A, tol_rel: float, b: int, seed: int, l_max=None,
     while st.k < l_max:
         k = st.k
         bw = min(b, l_max - k)
-        Om_i = omega(seed, n, k, bw)                 # step 4
+        Om_i = omega(seed, n, k, bw)
         G_i = np.asarray(A @ Om_i)                   # a pass over A
         gnorm = np.sqrt(np.einsum("ij,ij->j", G_i, G_i))
-        Y = G_i - st.Q @ (st.B @ Om_i)               # step 5
-        Qi, R = qr_pos(Y)
-        Qi, Rt = qr_pos(Qi - st.Q @ (st.Q.T @ Qi))   # step 6
-        R = Rt @ R
-        Bi = np.asarray((A.T @ Qi).T)                # step 7, a pass over A
+        Y, _ = residual_sample(G_i, Om_i, st.Q, st.B)
+        Qi, R = orth_against(Y, st.Q)
+        Bi = np.asarray((A.T @ Qi).T)                # B_i = Q_i^T A, a second pass over A
         passes += 2
         blocks += 1
         keep, E, stop, exh = _scan_rows(Bi, R, gnorm, E, eps2, row_by_row)
@@ -382,14 +400,11 @@ def randqb_fp_fixed(A, Om: np.ndarray, b: int, reorth: bool = True):
     l = Om.shape[1]
     for lo in range(0, l, b):
         J = slice(lo, min(l, lo + b))
-        W = B @ Om[:, J]
-        Y = G[:, J] - Q @ W
-        Qi, R = qr_pos(Y)
         if reorth:
-            Qi, Rt = qr_pos(Qi - Q @ (Q.T @ Qi))
-            R = Rt @ R
-            Bi = block_b(H[:, J], Y, Q, B, W, R)
-        else:   # Algorithm 3 step 9: B_i = R_i^{-T} (H_J^T - Omega_J^T B^T B)
+            Qi, Bi, _ = fp_block(G[:, J], Om[:, J], H[:, J], Q, B)
+        else:   # Algorithm 3: B_i = R_i^{-T} (H_J^T - Omega_J^T B^T B), no re-orthogonalisation
+            Y, W = residual_sample(G[:, J], Om[:, J], Q, B)
+            Qi, R = qr_pos(Y)
             Bi = scipy.linalg.solve_triangular(R, H[:, J].T - W.T @ B, trans="T", lower=False)
         Q = np.concatenate([Q, Qi], axis=1)
         B = np.concatenate([B, Bi], axis=0)
