@@ -85,10 +85,18 @@ typedef enum { QB_ALGO_FP = 0, QB_ALGO_EI = 1 } qb_algo;
  *   QB_FP8E4M3 8-bit storage (OCP e4m3fn: 4 exponent bits, bias 7, 3 stored significand
  *           bits, finite values up to 448) with a power-of-two scale per row:
  *           A_q(i, j) = 2^row_exp[i] * e4m3(a[i * lda + j]).  Every such value is a
- *           bfloat16 value, so the precision form above applies unchanged to A_q: the
- *           tiles are widened to bfloat16 on their way into LDS, the row scales enter the
- *           G epilogue (and the H operand) as exact power-of-two multiplications, and
- *           ||A_q||^2 is summed in binary64 from the scaled stored values.
+ *           bfloat16 value, and the precision form above applies to A_q with an 8-bit
+ *           Omega for the G product:
+ *             Omega_q = e4m3(2^5 Omega) / 2^5   (round to nearest even; 2^5 |Omega| < 448),
+ *             G_q     = bf16(A_q Omega_q)       (8-bit matrix cores, e4m3 x e4m3, binary32
+ *                                               accumulation -- each product is exact --
+ *                                               when n is a multiple of 64 and the rows of
+ *                                               A start 16-byte aligned, else the same
+ *                                               values on bfloat16 matrix cores),
+ *             H       = A_q^T G_q               (bfloat16 matrix cores, A_q widened on load);
+ *           the row scales enter the G epilogue (and the H operand) as exact power-of-two
+ *           multiplications, and ||A_q||^2 is summed in binary64 from the scaled stored
+ *           values.
  *   QB_F32  binary32 (the differentiation form's batches, qb_batch). */
 typedef enum { QB_F64 = 0, QB_BF16 = 1, QB_F32 = 2, QB_FP8E4M3 = 3 } qb_dtype;
 

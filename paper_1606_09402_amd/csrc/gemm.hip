@@ -36,6 +36,7 @@ struct GemmArgs {
     double* colsq;         // [tiles_m][N] partial column sums of squares, or nullptr
     int tiles_m, tiles_n;
     int vec_a, vec_b;      // 16-byte aligned rows: double2 loads allowed
+    const int* gate;       // if set and nonzero when the kernel starts, it does nothing
 };
 
 // Output element (row, col) inside a 16x16 f64 MFMA accumulator for lane l, slot r:
@@ -112,6 +113,7 @@ template <int BM, int BN, int BK, int WM, int WN, int AL, int BL, int OCC, int S
 __global__ void __launch_bounds__(64 * WM * WN, OCC) gemm_f64_kernel(const GemmArgs g) {
     using C = GemmCfg<BM, BN, BK, WM, WN, AL, BL>;
     static_assert(STAGES == 1 || STAGES == 2, "one or two LDS stages");
+    if (g.gate != nullptr && *g.gate != 0) return;
     constexpr int A_STAGE = C::A_ROWS * C::A_PITCH, B_STAGE = C::B_ROWS * C::B_PITCH;
     __shared__ __align__(16) double As[STAGES * A_STAGE];
     __shared__ __align__(16) double Bs[STAGES * B_STAGE];
@@ -442,6 +444,7 @@ static hipError_t run_cfg(const GemmDesc& d, hipStream_t s) {
     nsplit = static_cast<int>(cdiv(d.K, g.kchunk));
     if (nsplit < 1) nsplit = 1;
     g.P = d.ws;
+    g.gate = d.gate;
     g.colsq = nsplit == 1 ? d.colsq : nullptr;   // fused only without a split
     if (d.colsq_groups) *d.colsq_groups = g.tiles_m;
     dim3 grid(static_cast<unsigned>(tiles), static_cast<unsigned>(nsplit));
@@ -475,21 +478,24 @@ static hipError_t run_cfg(const GemmDesc& d, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Tile configuration for an M x N output: 0 tall-skinny (m x b panels), 1 small output with a
-// long reduction (split K), 2 the sketch sweep.
-static int shape_class(int64_t M, int64_t N) {
-    if (N <= 64 && M >= 4096) return 0;
+// Tile configuration for an M x N x K product: 0 tall-skinny (m x b panels) with at least
+// 512 row tiles of 128 or a long reduction, 1 small output with a long reduction (split K)
+// -- also the panels with fewer row tiles and a short reduction (the block loop's
+// G_J - Q W and Q_i - Q Z), which run faster in 64-row tiles (measured: 20000 x 64 x 896
+// in 77 us against 111 us, while 15000 x 64 x 20000 is slower) -- and 2 the sketch sweep.
+static int shape_class(int64_t M, int64_t N, int64_t K) {
+    if (N <= 64 && (M >= 512 * 128 || (M >= 4096 && K >= 4096))) return 0;
     if (N <= 64 || M <= 2048) return 1;
     return 2;
 }
 
 int64_t gemm_f64_colsq_groups(int64_t M, int64_t N) {
-    return cdiv(M, shape_class(M, N) == 1 ? 64 : 128);
+    return cdiv(M, N <= 64 || M <= 2048 ? 64 : 128);   // the most any K gives
 }
 
 template <int AL, int BL>
 static hipError_t dispatch_shape(const GemmDesc& d, hipStream_t s) {
-    switch (shape_class(d.M, d.N)) {
+    switch (shape_class(d.M, d.N, d.K)) {
         case 0: return run_cfg<128, 64, 32, 4, 1, AL, BL, 2, 1>(d, s);
         case 1: return run_cfg<64, 64, 32, 2, 2, AL, BL, 2, 1>(d, s);
         default: return run_cfg<128, 128, 32, 4, 2, AL, BL, 2, 2>(d, s);

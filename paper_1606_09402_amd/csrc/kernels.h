@@ -34,15 +34,28 @@ struct GemmDesc {
     double* ws;          // split-K scratch (nullptr: no split)
     int64_t ws_elems;
     int max_split;       // 0 = automatic
+    const int* gate;     // device flag: the product is skipped if it is nonzero at launch time
 };
 hipError_t gemm_f64(const GemmDesc& d, hipStream_t s);
-// Row groups of the column sums of squares gemm_f64 writes for an M x N output (colsq):
-// one per output tile row, at most this many after a K split.
+// Largest number of row groups of the column sums of squares gemm_f64 writes for an M x N
+// output (colsq): one per output tile row (the tile height depends on K as well).
 int64_t gemm_f64_colsq_groups(int64_t M, int64_t N);
 
 // lowp.hip -- the low-precision (bfloat16 / e4m3-stored) form of the sketch sweep
 hipError_t launch_quant_transpose_omega(double* om, int64_t n, int64_t w, uint16_t* omT,
                                         int64_t ldt, hipStream_t s);
+// The e4m3 form's Omega: omT8 (w x n bytes, ld ldt8) = e4m3(2^5 Omega)^T, omT (w x n bfloat16,
+// ld ldt) the same values / 2^5, om replaced by those values (binary64).
+hipError_t launch_quant_transpose_omega_e4m3(double* om, int64_t n, int64_t w, uint16_t* omT, int64_t ldt,
+                                             uint8_t* omT8, int64_t ldt8, hipStream_t s);
+// G = A_q Omega_q of the e4m3 form on 8-bit matrix cores (A: e4m3 bytes M x K with row
+// exponents, W: e4m3(2^5 Omega)^T, N x K bytes): the G epilogue of gemm_bf16.  gemm_f8_fits
+// tells whether the shape and alignment suit it (K a multiple of 64, 16-byte rows); *groups
+// receives the row groups written to colsq.
+bool gemm_f8_fits(int64_t K, const void* A, int64_t lda, const void* W, int64_t ldw);
+hipError_t gemm_f8(int64_t M, int64_t N, int64_t K, const uint8_t* A, int64_t lda, const int32_t* row_exp,
+                   const uint8_t* W, int64_t ldw, double* out, int64_t ldo, uint16_t* outT, int64_t ldt,
+                   double* colsq, int64_t* groups, hipStream_t s);
 hipError_t launch_sumsq_bf16(const uint16_t* a, int64_t m, int64_t n, int64_t lda,
                              double* scratch, double* out, hipStream_t s);
 hipError_t launch_sumsq_fp8(const uint8_t* a, const int32_t* row_exp, int64_t m, int64_t n,
@@ -69,8 +82,33 @@ hipError_t launch_upper_mul2(const double* A1, const double* B1, const double* A
 hipError_t launch_householder(double* X, int64_t m, int b, int64_t ldx, double* Q, int64_t ldq,
                               double* R, double* tau, hipStream_t s);
 hipError_t launch_gather_info(const double* rowsq, const double* R, const double* gcol, int b,
-                              double* info, hipStream_t s);
+                              const int* flag, double* info, hipStream_t s);
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s);
+
+// The stopping state of a randQB call, kept on the device so that blocks can be enqueued
+// ahead of the host's decision (the indicator of Theorem 1 decremented row by row, Section
+// 3.1, with the exhaustion guard).  skip = stop || halt gates the block products.
+struct ScanState {
+    double E;            // running indicator ||A||^2 - ||B||^2
+    int64_t k;           // rows accepted so far (the rank)
+    int stop;            // E fell below eps^2, or the guard fired
+    int exhausted;       // the guard fired
+    int halt;            // a CholeskyQR breakdown in the block that would start at row k
+    int skip;            // stop || halt
+    int blocks;          // blocks scanned
+    int pad;
+};
+// st = {E = *normA2, k = 0, rest 0}
+hipError_t launch_scan_init(const double* normA2, ScanState* st, hipStream_t s);
+// halt = skip = 0 and flags[0:8] = 0 (before a block is redone)
+hipError_t launch_scan_resume(ScanState* st, int* flags, hipStream_t s);
+// One block: if st is not stopped or halted and st->k == k_expect, a breakdown flag sets
+// halt; otherwise rows j = 0..bw-1 are taken while R_i(j,j) > exh_rel sqrt(g2[j]), each
+// lowering E by rowsq[j], stopping at the first E < eps2 (row_by_row) or after the block
+// (whole-block rule).  Records (k, E) after the block in khist / ehist[blocks].
+hipError_t launch_scan_block(const double* rowsq, const double* Ri, const double* g2, int bw, double eps2,
+                             int row_by_row, double exh_rel, const int* flags, ScanState* st,
+                             int64_t* khist, double* ehist, int64_t k_expect, hipStream_t s);
 hipError_t launch_fill_int(int* p, int n, int v, hipStream_t s);
 
 // spmm.hip -- CSR products and the CSR(A^T) build

@@ -23,6 +23,11 @@ namespace qb {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+
+// Power-of-two scale of Omega before its e4m3 rounding in the e4m3 form: the generator's
+// Gaussians stay below 9 in magnitude, so 2^5 Omega is inside the format's range (448).
+constexpr double kOmegaE4m3Scale = 32.0;
 
 // ------------------------------------------------------------------ rounding
 
@@ -125,6 +130,77 @@ quant_transpose_omega_kernel(double* __restrict__ om, int64_t n, int64_t w,
     for (int r = ty; r < 64; r += 4) {
         const int64_t j = c0 + r, i = r0 + tx;
         if (j < w && i < n) omT[j * ldt + i] = tile[tx][r];
+    }
+}
+
+// binary64 -> OCP e4m3fn byte, round to nearest, ties to even (finite inputs): 4 significant
+// bits for normal results (exponents 2^-6 .. 2^8), multiples of 2^-9 below 2^-6; a result
+// beyond 448 has no representation and gives the NaN byte.
+QB_DEV uint8_t f64_to_e4m3_rne(double x) {
+    const uint64_t u = static_cast<uint64_t>(__double_as_longlong(x));
+    const uint32_t sign = static_cast<uint32_t>((u >> 56) & 0x80u);
+    const int e64 = static_cast<int>((u >> 52) & 0x7FF);
+    const uint64_t mant = u & 0x000FFFFFFFFFFFFFull;
+    if (e64 == 0x7FF) return static_cast<uint8_t>(sign | 0x7Fu);
+    if (e64 == 0 && mant == 0) return static_cast<uint8_t>(sign);
+    int e = e64 - 1023 + 7;                    // e4m3 biased exponent of a normal result
+    const uint64_t sig = e64 == 0 ? mant : (mant | (1ull << 52));
+    int shift = 49;                            // keep 4 significant bits (1 + 3)
+    if (e <= 0) {                              // subnormal result
+        shift += 1 - e;
+        e = 0;
+    }
+    uint64_t q = 0;
+    if (shift < 64) {
+        q = sig >> shift;
+        const uint64_t rem = sig & ((1ull << shift) - 1), half = 1ull << (shift - 1);
+        if (rem > half || (rem == half && (q & 1))) ++q;
+    }
+    uint32_t bits;
+    if (e == 0) {
+        bits = static_cast<uint32_t>(q);       // q == 8 is the smallest normal, 0x08
+    } else {
+        if (q >= 16) { q >>= 1; ++e; }
+        if (e > 15 || (e == 15 && (q & 7) == 7)) return static_cast<uint8_t>(sign | 0x7Fu);
+        bits = (static_cast<uint32_t>(e) << 3) | static_cast<uint32_t>(q & 7);
+    }
+    return static_cast<uint8_t>(sign | bits);
+}
+
+// Value of an e4m3fn byte (not NaN) as binary64.
+QB_DEV double e4m3_to_f64(uint8_t v) {
+    const int e = (v >> 3) & 15, m = v & 7;
+    const double mag = e == 0 ? ldexp(static_cast<double>(m), -9) : ldexp(static_cast<double>(8 + m), e - 10);
+    return (v & 0x80) ? -mag : mag;
+}
+
+// The e4m3 form's Omega: Omega (n x w FP64) -> the bytes e4m3(2^5 Omega) transposed (w x n,
+// ld ldt8), the same values / 2^5 in bfloat16 transposed (w x n, ld ldt: exact, e4m3 values
+// are bfloat16 values), and Omega replaced by the dequantised e4m3(2^5 Omega) / 2^5.
+__global__ void __launch_bounds__(256)
+quant_transpose_omega_e4m3_kernel(double* __restrict__ om, int64_t n, int64_t w,
+                                  uint16_t* __restrict__ omT, int64_t ldt, uint8_t* __restrict__ omT8,
+                                  int64_t ldt8) {
+    __shared__ uint8_t tile[64][68];
+    const int64_t r0 = static_cast<int64_t>(blockIdx.y) * 64, c0 = static_cast<int64_t>(blockIdx.x) * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int r = ty; r < 64; r += 4) {
+        const int64_t i = r0 + r, j = c0 + tx;
+        uint8_t q = 0;
+        if (i < n && j < w) {
+            q = f64_to_e4m3_rne(om[i * w + j] * kOmegaE4m3Scale);
+            om[i * w + j] = e4m3_to_f64(q) / kOmegaE4m3Scale;
+        }
+        tile[r][tx] = q;
+    }
+    __syncthreads();
+    for (int r = ty; r < 64; r += 4) {
+        const int64_t j = c0 + r, i = r0 + tx;
+        if (j < w && i < n) {
+            const uint8_t q = tile[tx][r];
+            omT8[j * ldt8 + i] = q;
+            omT[j * ldt + i] = f64_to_bf16_rne(e4m3_to_f64(q) / kOmegaE4m3Scale);
+        }
     }
 }
 
@@ -737,6 +813,154 @@ __global__ void __launch_bounds__(64 * WM * WN, 1) gemm_bf16_dma_kernel(const Bf
     }
 }
 
+// ------------------------------------------------------------------ FP8 G product, LDS DMA
+
+// The G product of the e4m3 form on 8-bit matrix cores: out(i, j) = 2^(e_i - 5) sum_k
+// A8(i, k) W8(j, k), A8 the e4m3 bytes of A (M x K, K contiguous, row exponents e_i) and W8
+// the bytes e4m3(2^5 Omega)^T (N x K, K contiguous), on v_mfma_f32_32x32x64_f8f6f4 with both
+// operands e4m3 and binary32 accumulation (a product of two e4m3 values is exact in
+// binary32).  Tiles of BM x BN x 64 bytes move global -> LDS by DMA through a ring of STAGES
+// tiles as in gemm_bf16_dma_kernel; a 64-byte tile row has that kernel's chunk layout for
+// 32-deep bfloat16 rows (chunk c of row r at slot 4 r + (c ^ ((r >> 2) & 3))).  A lane's
+// operand of the tile's k-step is 32 bytes of its row, chunks 2 (lane / 32) and
+// 2 (lane / 32) + 1: the instruction pairs equal register bytes of the A and B operands with
+// the same k, so one k order shared by both operands gives the sum over the tile's 64 k
+// (checked on gfx950 against a host product of one instruction).  Epilogue as the bfloat16
+// kernels' e4m3 G epilogue: G_q = bf16(2^(e_i - 5) sums), the H operand 2^e_i G_q in bfloat16,
+// and the column sums of squares of G_q.  K must be a multiple of 64; rows beyond M (N)
+// re-read the last valid row and are never stored.
+template <int BM, int BN, int STAGES, int WM, int WN>
+__global__ void __launch_bounds__(64 * WM * WN, 1) gemm_f8_dma_kernel(const Bf16GemmArgs g) {
+    constexpr int NT = 64 * WM * WN, NW = NT / 64, BK = 64, CPR = 4;
+    constexpr int TM = BM / WM, TN = BN / WN, FM = TM / 32, FN = TN / 32;
+    constexpr int A_INSTR = BM * CPR / 64 / NW, B_INSTR = BN * CPR / 64 / NW;
+    constexpr int PER_TILE = A_INSTR + B_INSTR;           // DMA instructions per wave per tile
+    static_assert((BM * CPR) % (64 * NW) == 0 && (BN * CPR) % (64 * NW) == 0, "whole DMA instructions per wave");
+    __shared__ __align__(16) uint8_t As[STAGES][BM * BK];
+    __shared__ __align__(16) uint8_t Bs[STAGES][BN * BK];
+    __shared__ double red[WM][BN];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave / WN, wn = wave % WN;
+    const int logical = xcd_remap(blockIdx.x, gridDim.x);
+    int tile_m, tile_n;
+    group_tiles(logical, g.tiles_m, g.tiles_n, tile_m, tile_n);
+    const int64_t m0 = static_cast<int64_t>(tile_m) * BM, n0 = static_cast<int64_t>(tile_n) * BN;
+    const uint8_t* A8 = reinterpret_cast<const uint8_t*>(g.A);
+    const uint8_t* W8 = reinterpret_cast<const uint8_t*>(g.B);
+
+    f32x16 acc[FM][FN];
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) acc[a][b] = f32x16{};
+
+    auto slot_of = [](int r, int c) { return CPR * r + (c ^ ((r >> 2) & 3)); };
+    // one DMA instruction, as in gemm_bf16_dma_kernel (no register results; the kernel waits
+    // for its DMAs itself before each barrier)
+    auto dma16 = [](const uint8_t* src, const uint8_t* lds_dst) {
+        const uint32_t base = __builtin_amdgcn_readfirstlane(
+            static_cast<uint32_t>(reinterpret_cast<uintptr_t>((lds_ptr_t)lds_dst)));
+        asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off"
+                     :
+                     : "v"(src), "s"(base)
+                     : "memory", "m0");
+    };
+    auto issue = [&](int st, int64_t k0) {
+#pragma unroll
+        for (int j = 0; j < A_INSTR; ++j) {
+            const int s0 = (wave * A_INSTR + j) * 64;
+            const int sl = s0 + lane, r = sl / CPR, c = (sl % CPR) ^ ((r >> 2) & 3);
+            const int64_t gi = m0 + r < g.M ? m0 + r : g.M - 1;
+            dma16(A8 + gi * g.lda + k0 + 16 * c, &As[st][s0 * 16]);
+        }
+#pragma unroll
+        for (int j = 0; j < B_INSTR; ++j) {
+            const int s0 = (wave * B_INSTR + j) * 64;
+            const int sl = s0 + lane, r = sl / CPR, c = (sl % CPR) ^ ((r >> 2) & 3);
+            const int64_t gj = n0 + r < g.N ? n0 + r : g.N - 1;
+            dma16(W8 + gj * g.ldb + k0 + 16 * c, &Bs[st][s0 * 16]);
+        }
+    };
+    const int wm0 = wm * TM, wn0 = wn * TN;
+    const int lr = lane & 31, lch = lane >> 5;
+    auto operand = [&](const uint8_t* tile, int r) {
+        const uint4 lo = *reinterpret_cast<const uint4*>(tile + 16 * slot_of(r, 2 * lch));
+        const uint4 hi = *reinterpret_cast<const uint4*>(tile + 16 * slot_of(r, 2 * lch + 1));
+        return i32x8{static_cast<int>(lo.x), static_cast<int>(lo.y), static_cast<int>(lo.z), static_cast<int>(lo.w),
+                     static_cast<int>(hi.x), static_cast<int>(hi.y), static_cast<int>(hi.z), static_cast<int>(hi.w)};
+    };
+    auto compute = [&](int st) {
+        i32x8 a[FM], b[FN];
+#pragma unroll
+        for (int fm = 0; fm < FM; ++fm) a[fm] = operand(&As[st][0], wm0 + fm * 32 + lr);
+#pragma unroll
+        for (int fn = 0; fn < FN; ++fn) b[fn] = operand(&Bs[st][0], wn0 + fn * 32 + lr);
+#pragma unroll
+        for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+            for (int fn = 0; fn < FN; ++fn)
+                acc[fm][fn] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a[fm], b[fn], acc[fm][fn], 0, 0, 0, 0,
+                                                                              0, 0);
+    };
+
+    const int64_t T = g.K / BK;   // K tiles
+    if (T > 0) {
+#pragma unroll
+        for (int p = 0; p < STAGES - 1; ++p)
+            if (p < T) issue(p, static_cast<int64_t>(p) * BK);
+        for (int64_t t = 0; t < T; ++t) {
+            const int64_t later = T - 1 - t < STAGES - 2 ? T - 1 - t : STAGES - 2;
+            if (later >= STAGES - 2) __builtin_amdgcn_s_waitcnt(vmcnt_imm((STAGES - 2) * PER_TILE));
+            else if (later == 1) __builtin_amdgcn_s_waitcnt(vmcnt_imm(PER_TILE));
+            else __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+            asm volatile("" ::: "memory");
+            __builtin_amdgcn_s_barrier();
+            asm volatile("" ::: "memory");
+            if (t + STAGES - 1 < T) issue(static_cast<int>((t + STAGES - 1) % STAGES), (t + STAGES - 1) * BK);
+            compute(static_cast<int>(t % STAGES));
+        }
+        __syncthreads();
+    }
+
+    double csq[FN];
+#pragma unroll
+    for (int fn = 0; fn < FN; ++fn) csq[fn] = 0.0;
+#pragma unroll
+    for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+        for (int fn = 0; fn < FN; ++fn)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t i = m0 + wm0 + fm * 32 + acc32_row(lane, r);
+                const int64_t j = n0 + wn0 + fn * 32 + (lane & 31);
+                if (i < g.M && j < g.N) {
+                    const int e = g.row_exp[i];
+                    const uint16_t h = f32_to_bf16_rne(ldexpf(acc[fm][fn][r], e - 5));
+                    const double v = bf16_to_f64(h);
+                    g.out[i * g.ldo + j] = v;
+                    g.outT[j * g.ldt + i] =
+                        static_cast<uint16_t>(__float_as_uint(ldexpf(__uint_as_float(uint32_t(h) << 16), e)) >> 16);
+                    csq[fn] += v * v;
+                }
+            }
+    if (g.colsq != nullptr) {
+#pragma unroll
+        for (int fn = 0; fn < FN; ++fn) {
+            double v = csq[fn];
+            v += __shfl_xor(v, 32, 64);
+            if (lane < 32) red[wm][wn0 + fn * 32 + lane] = v;
+        }
+        __syncthreads();
+        for (int j = tid; j < BN; j += NT) {
+            double t = 0.0;
+#pragma unroll
+            for (int w = 0; w < WM; ++w) t += red[w][j];
+            if (n0 + j < g.N) g.colsq[static_cast<int64_t>(tile_m) * g.N + n0 + j] = t;
+        }
+    }
+}
+
 // ------------------------------------------------------------------ host
 
 hipError_t launch_quant_transpose_omega(double* om, int64_t n, int64_t w, uint16_t* omT,
@@ -744,6 +968,39 @@ hipError_t launch_quant_transpose_omega(double* om, int64_t n, int64_t w, uint16
     if (n <= 0 || w <= 0) return hipSuccess;
     dim3 grid(static_cast<unsigned>(cdiv(w, 64)), static_cast<unsigned>(cdiv(n, 64)));
     hipLaunchKernelGGL(quant_transpose_omega_kernel, grid, dim3(256), 0, s, om, n, w, omT, ldt);
+    return hipGetLastError();
+}
+
+hipError_t launch_quant_transpose_omega_e4m3(double* om, int64_t n, int64_t w, uint16_t* omT, int64_t ldt,
+                                             uint8_t* omT8, int64_t ldt8, hipStream_t s) {
+    if (n <= 0 || w <= 0) return hipSuccess;
+    dim3 grid(static_cast<unsigned>(cdiv(w, 64)), static_cast<unsigned>(cdiv(n, 64)));
+    hipLaunchKernelGGL(quant_transpose_omega_e4m3_kernel, grid, dim3(256), 0, s, om, n, w, omT, ldt, omT8, ldt8);
+    return hipGetLastError();
+}
+
+bool gemm_f8_fits(int64_t K, const void* A, int64_t lda, const void* W, int64_t ldw) {
+    return K % 64 == 0 && lda % 16 == 0 && ldw % 16 == 0 && reinterpret_cast<uintptr_t>(A) % 16 == 0 &&
+           reinterpret_cast<uintptr_t>(W) % 16 == 0;
+}
+
+hipError_t gemm_f8(int64_t M, int64_t N, int64_t K, const uint8_t* A, int64_t lda, const int32_t* row_exp,
+                   const uint8_t* W, int64_t ldw, double* out, int64_t ldo, uint16_t* outT, int64_t ldt,
+                   double* colsq, int64_t* groups, hipStream_t s) {
+    *groups = 0;
+    if (M <= 0 || N <= 0) return hipSuccess;
+    if (!gemm_f8_fits(K, A, lda, W, ldw) || row_exp == nullptr || outT == nullptr) return hipErrorInvalidValue;
+    Bf16GemmArgs g{};
+    g.M = M; g.N = N; g.K = K;
+    g.A = reinterpret_cast<const uint16_t*>(A); g.lda = lda;
+    g.B = reinterpret_cast<const uint16_t*>(W); g.ldb = ldw;
+    g.out = out; g.ldo = ldo; g.outT = outT; g.ldt = ldt; g.colsq = colsq; g.row_exp = row_exp;
+    constexpr int kTile = 256;
+    g.tiles_m = static_cast<int>(cdiv(M, kTile));
+    g.tiles_n = static_cast<int>(cdiv(N, kTile));
+    *groups = g.tiles_m;
+    const dim3 grid(static_cast<unsigned>(static_cast<int64_t>(g.tiles_m) * g.tiles_n));
+    hipLaunchKernelGGL((gemm_f8_dma_kernel<256, 256, 4, 4, 2>), grid, dim3(512), 0, s, g);
     return hipGetLastError();
 }
 

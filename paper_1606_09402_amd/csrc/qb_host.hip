@@ -25,6 +25,7 @@ constexpr double kUnitRoundoff = 0x1p-53;
 constexpr int64_t kGramSplitElems = 1 << 22;
 constexpr int kMaxPower = 16;               // largest power-scheme parameter P accepted
 constexpr int kPowerBlock = 128;            // column block of the power-scheme orth()
+constexpr int kLookahead = 4;               // blocks enqueued ahead of the stopping decision
 constexpr int kMaxOversample = 128;         // trQRCP sketch rows beyond b
 constexpr uint32_t kSketchStream = 1;       // generator stream of trQRCP's sketch (randQB: 0)
 
@@ -42,12 +43,16 @@ struct Layout {
     size_t red, scal, om, g, h, gpart, gnorm2, y, x2, s, w, z, d, gram, r1, r1i, rt, rti, ri, rii, tau,
         rowsq_part, rowsq, info, flags, split, csc, plan_a, plan_t, omt, gqt, total;
     size_t split2;          // split-K partials of the products issued on the side stream
+    size_t scan, khist, ehist;   // device stopping state and the (k, E) after each block
+    int64_t nhist;
     // trQRCP: sketch St (n x l), its Gaussian (m x l), ||A(:, j)||^2 and its partials, the
     // remaining sketch norms, active flags, reflector, block pivots, their ||A(:, p)||^2,
     // R~_11 and R~_11 R_i^{-1}
     size_t sk, skom, cola, colpart, qn, act, hh, bpiv, g2p, rs, mm;
     int64_t lt, split_elems, split2_elems, gpart_groups;
     int64_t ldm16, ldn16;   // row strides (elements) of the bfloat16 copies: m, n rounded to 8
+    size_t omt8;            // e4m3 form: e4m3(2^5 Omega)^T bytes (l~ x ldn8)
+    int64_t ldn8;           // its row stride: n rounded to 16
 };
 
 // Largest chunk of Omega columns: l_tilde, or the paper's min(50 b, l_max) for 0 and for
@@ -157,8 +162,13 @@ Layout make_layout(int algo, int sparse, int dtype, int64_t m, int64_t n, int64_
     L.tau = take(sizeof(double) * pb);
     L.rowsq_part = take(sizeof(double) * nb_part * b);
     L.rowsq = take(sizeof(double) * b);
-    L.info = take(sizeof(double) * 3 * b);
+    L.info = take(sizeof(double) * (3 * b + 1));
     L.flags = take(sizeof(int) * 8);
+    // blocks of a call: at most one per b rows plus one short block per chunk
+    L.nhist = 2 * cdiv(lmax, b) + 8;
+    L.scan = take(sizeof(ScanState));
+    L.khist = take(sizeof(int64_t) * L.nhist);
+    L.ehist = take(sizeof(double) * L.nhist);
     L.split = take(sizeof(double) * L.split_elems);
     L.split2 = take(sizeof(double) * L.split2_elems);
     L.csc = sparse ? take(csc_layout(m, n, nnz).total) : take(0);
@@ -171,6 +181,8 @@ Layout make_layout(int algo, int sparse, int dtype, int64_t m, int64_t n, int64_
     L.ldn16 = round_up(n, 8);
     L.omt = lowp ? take(sizeof(uint16_t) * lt * L.ldn16) : take(0);
     L.gqt = lowp ? take(sizeof(uint16_t) * lt * L.ldm16) : take(0);
+    L.ldn8 = round_up(n, 16);
+    L.omt8 = dtype == QB_FP8E4M3 ? take(lt * L.ldn8) : take(0);
     if (ell > 0) {
         L.sk = take(sizeof(double) * n * ell);
         L.skom = take(sizeof(double) * m * ell);
@@ -295,6 +307,7 @@ struct Ctx {
     double* host_info;   // 3 b doubles + flags
     hipStream_t side = nullptr;   // randQB_FP: stream of the D, S products (or none)
     hipEvent_t ev_y = nullptr, ev_s = nullptr;
+    const int* gate = nullptr;    // device flag that skips the block products (stopped call)
     template <class T>
     T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
 };
@@ -305,6 +318,7 @@ GemmDesc gdesc(int64_t M, int64_t N, int64_t K, View a, View b, double alpha, do
     d.M = M; d.N = N; d.K = K; d.A = a; d.B = b; d.alpha = alpha; d.beta = beta; d.C0 = c0; d.C = c;
     d.colsq = nullptr; d.colsq_groups = nullptr;
     d.ws = x.at<double>(x.L.split); d.ws_elems = x.L.split_elems; d.max_split = 0;
+    d.gate = x.gate;
     return d;
 }
 
@@ -344,22 +358,34 @@ int apply_At(const Ctx& x, const double* G, int64_t ldg, double* H, int64_t ldh,
 }
 
 // The low-precision sketch of a chunk: Omega (n x w, ld w, binary64 on entry) is replaced
-// by its bfloat16 rounding Omega_q (and copied transposed in bfloat16), G = bf16(A_q Omega_q)
-// with its column sums of squares, H = A_q^T G_q reading A_q in place (bfloat16, or e4m3
-// with power-of-two row scales).
+// by its rounding Omega_q -- bfloat16, or for e4m3-stored A the e4m3 rounding of 2^5 Omega
+// divided by 2^5 -- (and copied transposed in bfloat16, and in e4m3 bytes), G = bf16(A_q
+// Omega_q) with its column sums of squares (on 8-bit matrix cores for e4m3 A when the shape
+// allows, else on bfloat16 ones: the products are exact either way), H = A_q^T G_q reading
+// A_q in place (bfloat16, or e4m3 with power-of-two row scales).
 int sketch_bf16(const Ctx& x, double* Om, double* G, double* H, int64_t w, double* gnorm2,
                 bool time_phases) {
     const Op& A = x.A;
     uint16_t* omt = x.at<uint16_t>(x.L.omt);
     uint16_t* gqt = x.at<uint16_t>(x.L.gqt);
     double* gpart = x.at<double>(x.L.gpart);
-    QB_HIP(launch_quant_transpose_omega(Om, A.n, w, omt, x.L.ldn16, x.s));
-    if (time_phases) x.tm->mark(2);
     const bool f8 = A.dtype == QB_FP8E4M3;
+    uint8_t* omt8 = f8 ? x.at<uint8_t>(x.L.omt8) : nullptr;
+    if (f8)
+        QB_HIP(launch_quant_transpose_omega_e4m3(Om, A.n, w, omt, x.L.ldn16, omt8, x.L.ldn8, x.s));
+    else
+        QB_HIP(launch_quant_transpose_omega(Om, A.n, w, omt, x.L.ldn16, x.s));
+    if (time_phases) x.tm->mark(2);
     const void* a = f8 ? static_cast<const void*>(A.a8) : static_cast<const void*>(A.aq);
-    QB_HIP(gemm_bf16(A.m, w, A.n, a, A.lda, false, f8, A.row_exp, omt, x.L.ldn16, G, w, gqt, x.L.ldm16,
-                     gpart, x.s));
-    QB_HIP(launch_sum_partials(gpart, bf16_gemm_row_groups(A.m, w), w, w, gnorm2, x.s));
+    int64_t groups = bf16_gemm_row_groups(A.m, w);
+    if (f8 && gemm_f8_fits(A.n, A.a8, A.lda, omt8, x.L.ldn8)) {
+        QB_HIP(gemm_f8(A.m, w, A.n, A.a8, A.lda, A.row_exp, omt8, x.L.ldn8, G, w, gqt, x.L.ldm16, gpart, &groups,
+                       x.s));
+    } else {
+        QB_HIP(gemm_bf16(A.m, w, A.n, a, A.lda, false, f8, A.row_exp, omt, x.L.ldn16, G, w, gqt, x.L.ldm16,
+                         gpart, x.s));
+    }
+    QB_HIP(launch_sum_partials(gpart, groups, w, w, gnorm2, x.s));
     if (time_phases) x.tm->mark(3);
     QB_HIP(gemm_bf16(A.n, w, A.m, a, A.lda, true, f8, nullptr, gqt, x.L.ldm16, H, w, nullptr, 0, nullptr,
                      x.s));
@@ -657,13 +683,11 @@ int power_rounds(const Ctx& x, int64_t k, int64_t w, double*& Om, double*& H, do
 // *breakdown tells whether CholeskyQR failed in this block.
 int fetch_block(const Ctx& x, int bw, const double* gnorm2_j, bool* breakdown) {
     double* info = x.at<double>(x.L.info);
-    QB_HIP(launch_gather_info(x.at<double>(x.L.rowsq), x.at<double>(x.L.ri), gnorm2_j, bw, info,
-                              x.s));
-    QB_HIP(hipMemcpyAsync(x.host_info, info, sizeof(double) * 3 * bw, hipMemcpyDeviceToHost, x.s));
-    int* hflag = reinterpret_cast<int*>(x.host_info + 3 * kMaxB);
-    QB_HIP(hipMemcpyAsync(hflag, x.at<int>(x.L.flags), sizeof(int), hipMemcpyDeviceToHost, x.s));
+    QB_HIP(launch_gather_info(x.at<double>(x.L.rowsq), x.at<double>(x.L.ri), gnorm2_j, bw,
+                              x.at<int>(x.L.flags), info, x.s));
+    QB_HIP(hipMemcpyAsync(x.host_info, info, sizeof(double) * (3 * bw + 1), hipMemcpyDeviceToHost, x.s));
     QB_HIP(hipStreamSynchronize(x.s));
-    *breakdown = *hflag != 0;
+    *breakdown = x.host_info[3 * bw] != 0.0;
     return QB_OK;
 }
 
@@ -759,8 +783,9 @@ int run(int algo, Op& A, const qb_params* p, double* Q, int64_t ldq, double* B, 
         QB_HIP(spmm_plan_build(A.rowptr, m, A.nnz, L.lt, wsb + L.plan_a, s, &A.plan_a));
         QB_HIP(spmm_plan_build(A.t_ptr, n, A.nnz, L.lt, wsb + L.plan_t, s, &A.plan_t));
     }
+    ScanState* scan = reinterpret_cast<ScanState*>(wsb + L.scan);
     const Ctx x{A, p, Q, ldq, B, ldb, wsb, L, s, inf, &tm, host, side_ok ? res->side : nullptr,
-                side_ok ? res->ev_y : nullptr, side_ok ? res->ev_s : nullptr};
+                side_ok ? res->ev_y : nullptr, side_ok ? res->ev_s : nullptr, &scan->skip};
     QB_HIP(hipMemcpyAsync(host, scal, sizeof(double), hipMemcpyDeviceToHost, s));
     QB_HIP(hipStreamSynchronize(s));
     const double normA2 = host[0];
@@ -775,8 +800,12 @@ int run(int algo, Op& A, const qb_params* p, double* Q, int64_t ldq, double* B, 
     double E = normA2;
     int64_t k = 0;
     bool exhausted = false;
+    int scanned = 0;
     if (!(normA2 == 0.0 || E < eps2)) {
         QB_HIP(launch_fill_int(x.at<int>(L.flags), 8, 0, s));
+        QB_HIP(launch_scan_init(scal, scan, s));
+        int64_t* khist = x.at<int64_t>(L.khist);
+        double* ehist = x.at<double>(L.ehist);
         int64_t chunk_lo = 0, chunk_hi = 0;
         int64_t k_half = 0;       // block end where the current chunk's second half starts
         double e_half = E;        // the indicator there
@@ -785,89 +814,129 @@ int run(int algo, Op& A, const qb_params* p, double* Q, int64_t ldq, double* B, 
         double* H = x.at<double>(L.h);
         double* gnorm2 = x.at<double>(L.gnorm2);
         bool stop = false;
+        bool redo_hh = false;     // the block at row k broke down in CholeskyQR: redo it by Householder
+        double dec = 0.0;         // the indicator's drop per block over the last run of blocks
         while (k < lmax && !stop) {
-            int64_t bw;
-            const double *GJ, *OmJ, *HJ = nullptr, *g2J;
-            int64_t ldj;
-            if (algo == QB_ALGO_FP) {
-                if (k == chunk_hi) {   // draw the next chunk of Omega; G = A Omega, H = A^T G
-                    const int64_t w = next_chunk(p, L.lt, k, chunk_hi - chunk_lo, chunk_hi - k_half,
-                                                 e_half, E, eps2);
-                    chunk_lo = k;
-                    chunk_hi = k + w;
-                    k_half = chunk_lo + b * (cdiv(w, b) / 2);
-                    e_half = E;
-                    tm.mark(1);
-                    QB_HIP(launch_gauss_fill(p->seed, 0, 0, 0, chunk_lo, n, w, Om, w, s));
-                    if (p->power > 0) {
-                        tm.mark(6);
-                        if (int e = power_rounds(x, k, w, Om, H, G, gnorm2)) return inf->status = e;
-                        inf->passes += 2 * p->power;
-                    }
-                    if (A.dtype == QB_BF16 || A.dtype == QB_FP8E4M3) {
-                        if (int e = sketch_bf16(x, Om, G, H, w, gnorm2, true)) return inf->status = e;
-                    } else {
-                        tm.mark(2);
-                        if (int e = apply_A(x, Om, w, G, w, w, gnorm2)) return inf->status = e;
-                        tm.mark(3);
-                        if (int e = apply_At(x, G, w, H, w, w)) return inf->status = e;
-                    }
-                    tm.mark(4);
-                    inf->passes += 2;
-                    inf->chunks += 1;
-                    inf->gemm_flops[0] += 2.0 * m * n * w;
-                    inf->gemm_flops[1] += 2.0 * m * n * w;
-                }
-                bw = b < chunk_hi - k ? b : chunk_hi - k;
-                ldj = chunk_hi - chunk_lo;
-                const int64_t J0 = k - chunk_lo;
-                GJ = G + J0;
-                OmJ = Om + J0;
-                HJ = H + J0;
-                g2J = gnorm2 + J0;
-            } else {
-                bw = b < lmax - k ? b : lmax - k;
-                ldj = bw;
+            if (algo == QB_ALGO_FP && k == chunk_hi) {
+                // draw the next chunk of Omega; G = A Omega, H = A^T G
+                const int64_t w = next_chunk(p, L.lt, k, chunk_hi - chunk_lo, chunk_hi - k_half, e_half, E,
+                                             eps2);
+                chunk_lo = k;
+                chunk_hi = k + w;
+                k_half = chunk_lo + b * (cdiv(w, b) / 2);
+                e_half = E;
                 tm.mark(1);
-                QB_HIP(launch_gauss_fill(p->seed, 0, 0, 0, k, n, bw, Om, bw, s));
-                tm.mark(2);
-                if (int e = apply_A(x, Om, bw, G, bw, bw, gnorm2)) return inf->status = e;
+                QB_HIP(launch_gauss_fill(p->seed, 0, 0, 0, chunk_lo, n, w, Om, w, s));
+                if (p->power > 0) {
+                    tm.mark(6);
+                    if (int e = power_rounds(x, k, w, Om, H, G, gnorm2)) return inf->status = e;
+                    inf->passes += 2 * p->power;
+                }
+                if (A.dtype == QB_BF16 || A.dtype == QB_FP8E4M3) {
+                    if (int e = sketch_bf16(x, Om, G, H, w, gnorm2, true)) return inf->status = e;
+                } else {
+                    tm.mark(2);
+                    if (int e = apply_A(x, Om, w, G, w, w, gnorm2)) return inf->status = e;
+                    tm.mark(3);
+                    if (int e = apply_At(x, G, w, H, w, w)) return inf->status = e;
+                }
                 tm.mark(4);
                 inf->passes += 2;
-                inf->gemm_flops[0] += 2.0 * m * n * bw;
-                inf->gemm_flops[1] += 2.0 * m * n * bw;
-                GJ = G;
-                OmJ = Om;
-                g2J = gnorm2;
+                inf->chunks += 1;
+                inf->gemm_flops[0] += 2.0 * m * n * w;
+                inf->gemm_flops[1] += 2.0 * m * n * w;
             }
-            const int bwi = static_cast<int>(bw);
-            bool breakdown = false;
-            for (int attempt = 0; attempt < 2; ++attempt) {
-                const bool use_hh = attempt == 1;
-                if (use_hh) {
-                    QB_HIP(launch_fill_int(x.at<int>(L.flags), 8, 0, s));
-                    inf->fallbacks += 1;
+            // Blocks are enqueued ahead of the stopping decision, which the device takes
+            // (scan_block) and the host reads back once per run of blocks.  A run never
+            // crosses a chunk end, and holds about as many blocks as the last drop of the
+            // indicator per block says cannot reach eps^2 (at most kLookahead), so that few
+            // blocks run past the stop; the products of blocks past it are skipped by the gate.
+            // randQB_EI runs one block at a time: a block redone after a CholeskyQR breakdown
+            // reuses its A Omega_i, which the next block's product would overwrite.
+            const int64_t k_end = algo == QB_ALGO_FP ? chunk_hi : lmax;
+            int nrun = 1;
+            if (algo == QB_ALGO_FP && !redo_hh && dec > 0.0) {
+                const double r = floor((E - eps2) / dec);
+                nrun = r >= kLookahead ? kLookahead : (r >= 1.0 ? static_cast<int>(r) : 1);
+            }
+            int64_t ks = k;
+            for (int t = 0; t < nrun && ks < k_end; ++t) {
+                const int64_t bw = b < k_end - ks ? b : k_end - ks;
+                const int bwi = static_cast<int>(bw);
+                const double *GJ, *OmJ, *HJ = nullptr, *g2J;
+                int64_t ldj;
+                if (algo == QB_ALGO_FP) {
+                    ldj = chunk_hi - chunk_lo;
+                    const int64_t J0 = ks - chunk_lo;
+                    GJ = G + J0;
+                    OmJ = Om + J0;
+                    HJ = H + J0;
+                    g2J = gnorm2 + J0;
+                } else {
+                    ldj = bw;
+                    if (!(t == 0 && redo_hh)) {   // a redone block keeps its A Omega_i
+                        tm.mark(1);
+                        QB_HIP(launch_gauss_fill(p->seed, 0, 0, 0, ks, n, bw, Om, bw, s));
+                        tm.mark(2);
+                        if (int e = apply_A(x, Om, bw, G, bw, bw, gnorm2)) return inf->status = e;
+                        tm.mark(4);
+                    }
+                    GJ = G;
+                    OmJ = Om;
+                    g2J = gnorm2;
                 }
-                if (int e = orth_block(x, k, bwi, GJ, ldj, OmJ, ldj, use_hh,
-                                       algo == QB_ALGO_FP ? HJ : nullptr, ldj))
+                const bool use_hh = t == 0 && redo_hh;
+                if (use_hh) QB_HIP(launch_scan_resume(scan, x.at<int>(L.flags), s));
+                if (int e = orth_block(x, ks, bwi, GJ, ldj, OmJ, ldj, use_hh, algo == QB_ALGO_FP ? HJ : nullptr, ldj))
                     return inf->status = e;
                 if (algo == QB_ALGO_FP) {
-                    if (int e = fp_block_b(x, k, bwi)) return inf->status = e;
+                    if (int e = fp_block_b(x, ks, bwi)) return inf->status = e;
                 } else {
                     tm.mark(3);
-                    if (int e = ei_block_b(x, k, bwi)) return inf->status = e;
+                    if (int e = ei_block_b(x, ks, bwi)) return inf->status = e;
                     tm.mark(4);
                 }
-                if (int e = fetch_block(x, bwi, g2J, &breakdown)) return inf->status = e;
-                if (!breakdown) break;
+                QB_HIP(launch_scan_block(x.at<double>(L.rowsq), x.at<double>(L.ri), g2J, bwi, eps2,
+                                         p->row_by_row != 0, kExhaustRel, x.at<int>(L.flags), scan, khist, ehist,
+                                         ks, s));
+                ks += bw;
             }
-            inf->blocks += 1;
-            int keep = 0;
-            bool exh = false;
-            scan_rows(host, bwi, p->row_by_row != 0, eps2, &E, &keep, &stop, &exh);
-            k += keep;
-            if (k == k_half) e_half = E;
-            if (exh) exhausted = true;
+            ScanState hs;
+            QB_HIP(hipMemcpyAsync(&hs, scan, sizeof(ScanState), hipMemcpyDeviceToHost, s));
+            QB_HIP(hipStreamSynchronize(s));
+            if (hs.blocks > scanned) {
+                // indicator drop per block over the blocks of this run
+                const int first = scanned;
+                dec = (E - hs.E) / static_cast<double>(hs.blocks - first);
+                if (algo == QB_ALGO_FP && k < k_half && hs.k >= k_half) {
+                    // the indicator at the end of the block that ends at k_half
+                    const int nb = hs.blocks - first;
+                    int64_t kh[2 * kLookahead];
+                    double eh[2 * kLookahead];
+                    QB_HIP(hipMemcpyAsync(kh, khist + first, sizeof(int64_t) * nb, hipMemcpyDeviceToHost, s));
+                    QB_HIP(hipMemcpyAsync(eh, ehist + first, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+                    QB_HIP(hipStreamSynchronize(s));
+                    for (int i = 0; i < nb; ++i)
+                        if (kh[i] == k_half) e_half = eh[i];
+                }
+                scanned = hs.blocks;
+            }
+            k = hs.k;
+            E = hs.E;
+            stop = hs.stop != 0;
+            exhausted = hs.exhausted != 0;
+            redo_hh = hs.halt != 0;
+            if (redo_hh) inf->fallbacks += 1;
+        }
+        inf->blocks = scanned;
+        if (algo == QB_ALGO_EI) {
+            inf->passes = 2 * scanned;
+            inf->gemm_flops[0] = inf->gemm_flops[1] = 0.0;
+            for (int i = 0; i < scanned; ++i) {
+                const double bwd = static_cast<double>(b < lmax - static_cast<int64_t>(i) * b ? b : lmax - i * b);
+                inf->gemm_flops[0] += 2.0 * m * n * bwd;
+                inf->gemm_flops[1] += 2.0 * m * n * bwd;
+            }
         }
     }
     tm.mark(-1);
@@ -1268,8 +1337,9 @@ int layout_check(int algo, int sparse, int dtype, int64_t m, int64_t n, int64_t 
     const Layout L = make_layout(algo, sparse, dtype, m, n, nnz, p, ell);
     std::vector<size_t> offs = {L.red, L.scal, L.om, L.g, L.h, L.gpart, L.gnorm2, L.y, L.x2, L.s, L.w,
                                 L.z, L.d, L.gram, L.r1, L.r1i, L.rt, L.rti, L.ri, L.rii, L.tau,
-                                L.rowsq_part, L.rowsq, L.info, L.flags, L.split, L.split2, L.csc,
-                                L.plan_a, L.plan_t, L.omt, L.gqt, L.total};
+                                L.rowsq_part, L.rowsq, L.info, L.flags, L.scan, L.khist, L.ehist,
+                                L.split, L.split2, L.csc,
+                                L.plan_a, L.plan_t, L.omt, L.gqt, L.omt8, L.total};
     if (ell > 0) offs.insert(offs.end(), {L.sk, L.skom, L.cola, L.colpart, L.qn, L.act, L.hh, L.bpiv,
                                           L.g2p, L.rs, L.mm});
     auto extent = [&](size_t off) {
@@ -1316,8 +1386,14 @@ int layout_check(int algo, int sparse, int dtype, int64_t m, int64_t n, int64_t 
         need(L.rowsq_part, D * groups * bw);
     }
     need(L.rowsq, D * b);
-    need(L.info, D * 3 * b);
+    need(L.info, D * (3 * b + 1));
     need(L.flags, sizeof(int) * 8);
+    need(L.scan, sizeof(ScanState));
+    // scanned blocks: every block but the last keeps at least one row; randQB_FP chunks are
+    // multiples of b except the last, so at most cdiv(l_max, b) + chunks blocks, chunks
+    // being at most cdiv(l_max, b)
+    need(L.khist, 8.0 * (2 * cdiv(lmax, b) + 1));
+    need(L.ehist, D * (2 * cdiv(lmax, b) + 1));
     if (sparse) {
         need(L.csc, static_cast<double>(csc_layout(m, n, nnz).total));
         need(L.plan_a, static_cast<double>(spmm_plan_bytes(m, nnz, lt)));
@@ -1327,6 +1403,7 @@ int layout_check(int algo, int sparse, int dtype, int64_t m, int64_t n, int64_t 
         need(L.omt, 2.0 * lt * L.ldn16);
         need(L.gqt, 2.0 * lt * L.ldm16);
     }
+    if (dtype == QB_FP8E4M3) need(L.omt8, 1.0 * lt * L.ldn8);
     if (ell > 0) {
         need(L.sk, D * n * ell);
         need(L.skom, D * m * ell);

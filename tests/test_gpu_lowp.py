@@ -233,11 +233,19 @@ def test_fp_bf16_full_size(qb):
 
 # ------------------------------------------------------------------ e4m3 storage
 #
-# A stored in OCP e4m3fn with a power-of-two scale per row: A_q(i, j) = 2^e_i e4m3(...).
-# Every such value is a bfloat16 value, so the oracle's precision form applies to A_q
-# unchanged and the tolerances above carry over.  The storage error (2.6e-2 of ||A||
-# for these matrices) lies above tol 1e-2; the method is run at tol 5e-2, where the true
-# error against the binary64 matrix still meets tol.
+# A stored in OCP e4m3fn with a power-of-two scale per row: A_q(i, j) = 2^e_i e4m3(...),
+# every value a bfloat16 value.  The G product runs on 8-bit operands: Omega_q is the e4m3
+# rounding of 2^5 Omega divided by 2^5 (the oracle's precision form "e4m3"), and each
+# product of two e4m3 values is exact in binary32, so G_q = bf16(fl32(A_q Omega_q)) obeys
+# the bounds above with Omega_q in place of the bfloat16 one; H is the bfloat16 form's.
+# Shapes whose K is a multiple of 64 (with 16-byte rows) take the 8-bit matrix cores, the
+# others the bfloat16 ones on the same e4m3 values.  The storage error (2.6e-2 of ||A|| for
+# these matrices) lies above tol 1e-2; the method is run at tol 5e-2, where the true error
+# against the binary64 matrix still meets tol.
+
+
+def _omega_e4m3(seed, n, l, col0):
+    return OL.round_e4m3(ORNG.gaussian_matrix(seed, n, l, 0, col0) * R.OMEGA_E4M3_SCALE) / R.OMEGA_E4M3_SCALE
 
 
 def _fp8_pair(m, n, kind, seed):
@@ -256,13 +264,14 @@ def test_sumsq_fp8(qb, m, n):
 
 
 @pytest.mark.parametrize("m,n,l,col0", [
-    (700, 530, 200, 64),
-    (1024, 768, 256, 0),
-    (4096, 256, 128, 128),
+    (700, 530, 200, 64),       # K = 530: G on the bfloat16 matrix cores (e4m3 Omega_q values)
+    (1024, 768, 256, 0),       # G on 8-bit matrix cores, a few 256 x 256 tiles
+    (4096, 256, 128, 128),     # 8-bit G, four K tiles of 64
+    (300, 128, 33, 5),         # 8-bit G, one partial tile in each direction
     (2048, 16384, 1024, 0),    # H with 256 tiles: e4m3 A read in place by transposed byte reads
     (2048, 16368, 1000, 64),   # the same with ragged H rows (16368 = 16 x 1023) and columns
     (2048, 16380, 1000, 64),   # H rows not a multiple of 16: the register-staged kernel
-    (16384, 2048, 1024, 0),    # G with 256 tiles: e4m3 A rows moved by DMA, row scales in the epilogue
+    (16384, 2048, 1024, 0),    # G with 256 tiles on 8-bit matrix cores, row scales in the epilogue
     (16300, 2048, 1000, 64),   # the same with ragged G rows and columns
 ])
 def test_sketch_fp8(qb, m, n, l, col0):
@@ -272,7 +281,7 @@ def test_sketch_fp8(qb, m, n, l, col0):
     torch.cuda.synchronize()
     A = Aq.numpy()
     om, g, h = om.cpu().numpy(), g.cpu().numpy(), h.cpu().numpy()
-    om_ref = OL.round_bf16(ORNG.gaussian_matrix(SEED, n, l, 0, col0))
+    om_ref = _omega_e4m3(SEED, n, l, col0)
     assert np.array_equal(om.view(np.int64), om_ref.view(np.int64))
     assert OL.is_bf16(g)
     exact = A @ om_ref
@@ -290,6 +299,54 @@ def test_fp_fp8_vs_oracle(qb, m, n, b, l_tilde):
     tol = 5e-2
     _log(f"fp e4m3 {m}x{n} b={b} tol={tol} l_tilde={l_tilde}")
     A64, A8, e, Aq = _fp8_pair(m, n, "poly1.5", 33)
-    ora = R.randqb_fp(Aq.numpy(), tol, b, SEED, l_tilde=l_tilde, precision="bf16")
+    ora = R.randqb_fp(Aq.numpy(), tol, b, SEED, l_tilde=l_tilde, precision="e4m3")
     res = qb.qb_fp_dense(A8.cuda(), tol, b, SEED, l_tilde=l_tilde, row_exp=e.cuda())
     _check_method(res, ora, A64.cuda(), Aq.cuda(), tol, f"e4m3 {m}x{n}")
+
+
+def test_fp_fp8_full_size(qb):
+    """The 32768 x 32768 e4m3 run of the benchmark (tol 5e-2, adaptive schedule) at full
+    size: sampled rows of Omega_q and G_q of the first chunk against the oracle's formulas
+    (8-bit G product), then the properties that hold at any size for the whole run."""
+    wl = W.C4
+    tol = 5e-2
+    dev = torch.device("cuda")
+    _log("generating the 32768 x 32768 matrix on the GPU")
+    A64 = wl.make(device=dev)
+    A8, e, Aq = W.to_e4m3_rows(A64)
+    torch.cuda.synchronize()
+    l = 8 * wl.b
+    om, g, h = qb.qb_sketch_lowp(A8, SEED, 0, l, row_exp=e)
+    torch.cuda.synchronize()
+    rows = np.array([0, 1, 4095, 12345, 20000, 32767])
+    om_rows = om[torch.as_tensor(rows, device=dev)].cpu().numpy()
+    for i, r in enumerate(rows):
+        ref = OL.round_e4m3(ORNG.gaussian_matrix(SEED, 1, l, int(r), 0) * R.OMEGA_E4M3_SCALE) / R.OMEGA_E4M3_SCALE
+        assert np.array_equal(om_rows[i:i + 1].view(np.int64), ref.view(np.int64))
+    omq = om.cpu().numpy()
+    gam = _gamma(wl.n)
+    for r in rows:
+        a = Aq[int(r)].cpu().numpy()
+        exact = a @ omq
+        S = np.abs(a) @ np.abs(omq)
+        gg = g[int(r)].cpu().numpy()
+        assert OL.is_bf16(gg)
+        assert np.all(np.abs(gg - exact) <= U16 * (np.abs(exact) + gam * S) + gam * S)
+    del om, g, h
+    res = qb.qb_fp_dense(A8, tol, wl.b, SEED, l_tilde=-1, row_exp=e)
+    nrm2 = R.sumsq(Aq.cpu().numpy())
+    Q, B = res.Q, res.B
+    eps2 = tol ** 2 * nrm2
+    direct = float(torch.linalg.matrix_norm(Aq - Q @ B) ** 2)
+    true_rel = float(torch.linalg.matrix_norm(A64 - Q @ B) / torch.linalg.matrix_norm(A64))
+    orth = float(torch.linalg.matrix_norm(Q.T @ Q - torch.eye(res.rank, dtype=Q.dtype, device=dev),
+                                          ord=float("inf")))
+    opt = R.svd_optimal_rank(wl.sigma(), tol)
+    _log(f"full size e4m3: rank {res.rank} (svd-optimal of A {opt}); E/eps2 {res.E / eps2:.4f}; "
+         f"direct/eps2 {direct / eps2:.4f}; true rel {true_rel:.4e}; orth {orth:.2e}; ms {res.ms}")
+    assert abs(res.normA2 - nrm2) <= 1e-13 * nrm2
+    assert res.status == 0 and res.E < eps2
+    assert abs(direct - res.E) <= 0.05 * eps2
+    assert orth <= 1e-12
+    assert true_rel <= tol
+    assert opt - 2 <= res.rank <= int(1.3 * opt) + wl.b
