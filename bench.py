@@ -23,13 +23,19 @@ Prints one JSON line.  value = median time-to-tolerance in seconds (lower is bet
 roofline: the dominant kernel (the larger of the two FP64 MFMA sketch GEMMs, G = A Omega
 or H = A^T G) -- algorithmic flops 2 m n l~ per launch over its average launch time,
 measured with HIP events recorded by the library on the stream the GEMM runs on;
-MI355X FP64 matrix peak 78.6 TFLOP/s.  cpu_baseline: the FP64 oracle (NumPy/OpenBLAS)
-on the same workload, run once on the host cores.
+MI355X FP64 matrix peak 78.6 TFLOP/s.  Its traffic (HBM bytes per launch) and MFMA busy
+percentage come from three rocprofv3 counter passes (FETCH_SIZE, WRITE_SIZE, MfmaUtil) over
+one call of the same workload in a child process, each counter scaled by what it reads for a
+library kernel of exactly 1 GiB of traffic (skip with --no-counters).  cpu_baseline: the
+FP64 oracle (NumPy/OpenBLAS) on the same workload on the host cores, median of 5 runs, with
+the oracle's times on the other workloads beside it.
 """
 from __future__ import annotations
 
 import argparse
 import json
+
+import numpy as np
 import os
 import statistics
 import sys
@@ -39,15 +45,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6
-# HBM bytes per launch of the sketch GEMMs of the adaptive schedule (chunks of 512 and
-# 1024 columns on the headline workload; mean of the two launches of each product):
-# rocprofv3 FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 in KiB, the scales being what the two
-# counters read for a plain 1 GiB device copy.  Measured for the current gemm_f64_kernel;
-# profiles/gemm_f64_sketch_dense_20000x15000_b64_tol1e-3.md.
-G_TRAFFIC_BYTES = int((2 * (2073048.0 + 3891728.6) / 2 + (160000.0 + 161256.0) / 2) * 1024)
-H_TRAFFIC_BYTES = int((2 * (2345455.8 + 4577801.8) / 2 + (300000.0 + 480000.0) / 2) * 1024)
 FP32_PEAK_TFLOPS = 157.3
 BF16_PEAK_TFLOPS = 2500.0
+FP8_PEAK_TFLOPS = 5000.0
 HBM_PEAK_GBPS = 8000.0
 
 
@@ -112,6 +112,12 @@ def main():
                     help="only one call of each sketch sweep (two-pass, single-pass) at l = 1024, for counters")
     ap.add_argument("--sparse-only", action="store_true",
                     help="run only the CSR block and print its JSON (for profiling runs)")
+    ap.add_argument("--precision-only", action="store_true",
+                    help="run only the precision-form block and print its JSON (for profiling runs)")
+    ap.add_argument("--no-counters", action="store_true",
+                    help="skip the rocprofv3 counter passes (HBM traffic, MFMA busy) of the dominant kernel")
+    ap.add_argument("--counter-probe", action="store_true",
+                    help=argparse.SUPPRESS)   # the program the counter passes run
     ap.add_argument("--gen-device", default="cuda", choices=["cuda", "cpu"],
                     help="where the seeded test matrix is generated (cpu keeps the GPU QR of the "
                          "generator out of counter-collection runs)")
@@ -131,8 +137,15 @@ def main():
     import paper_1606_09402_amd as qb
     import workloads as W
 
+    if args.counter_probe:
+        counter_probe(qb, W, torch, args.l_tilde)
+        return
     if args.sparse_only:
         print(json.dumps({"sparse": sparse_block(qb, W, torch)}), flush=True)
+        return
+    if args.precision_only:
+        print(json.dumps({"precision": precision_block(qb, W, torch, max(1, min(args.steps, 5)), args.l_tilde,
+                                                       args.gen_device)}), flush=True)
         return
     wl = W.C2
     seed = W.SEED_OMEGA | 2
@@ -252,10 +265,23 @@ def main():
         "svd_from_qb": svd_entry,
         "roofline": {"bound": "mfma", "kernel": dom_name, "achieved": round(achieved, 3),
                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
-                     "traffic": (G_TRAFFIC_BYTES if dom_name.startswith("gemm_f64 G") else H_TRAFFIC_BYTES)
-                     if args.l_tilde == -1 and r.chunks == 2 else None},
+                     "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None},
     }
+    if not args.no_counters:
+        # HBM bytes and MFMA busy of the same kernel, from rocprofv3 counter passes over one
+        # call of the same workload run as a child process (measure_counters)
+        cnt = measure_counters(args.l_tilde)
+        out["counters"] = cnt
+        key = "H" if dom_name.startswith("gemm_f64 H") else "G"
+        # algorithmic bytes per launch, 8 (m n + (m + n) w) for the mean chunk width w
+        w_mean = r.gemm_flops[0] / (2.0 * m * n) / max(1, r.chunks)
+        alg = 8.0 * (m * n + (m + n) * w_mean)
+        cnt["algorithmic_bytes_per_launch"] = int(alg)
+        if cnt.get("traffic_bytes", {}).get(key) is not None:
+            out["roofline"]["traffic"] = int(cnt["traffic_bytes"][key])
+            out["roofline"]["traffic_over_algorithmic"] = round(cnt["traffic_bytes"][key] / alg, 3)
+        if cnt.get("mfma_util_pct", {}).get(key) is not None:
+            out["roofline"]["mfma_busy_pct"] = cnt["mfma_util_pct"][key]
     if args.l_tilde != 0:   # the paper's fixed l~ = 50 b beside the headline schedule
         fp(0)
         pt = []
@@ -289,6 +315,30 @@ def main():
                                       "block_loop": rq.ms[4], "total": rq.ms[5]}}
         print(f"# power 1: {statistics.median(pw) * 1e3:.1f} ms rank {rq.rank} passes {rq.passes}",
               file=sys.stderr, flush=True)
+    # the 1000 x 800 matrix (sigma_j = j^-2, b = 20, tol 1e-2): latency-bound, wall time only
+    c1 = W.C1.make().to(dev)
+    s1 = W.SEED_OMEGA | 1
+    c1_ws = torch.empty(max(qb.qb_workspace_bytes(qb.QB_ALGO_FP, False, W.C1.m, W.C1.n, 0, W.C1.tol, W.C1.b,
+                                                  min(W.C1.m, W.C1.n)),
+                            qb.qb_workspace_bytes(qb.QB_ALGO_EI, False, W.C1.m, W.C1.n, 0, W.C1.tol, W.C1.b,
+                                                  min(W.C1.m, W.C1.n))), dtype=torch.uint8, device=dev)
+    c1_out = {"workload": W.C1.name}
+    for nm, fn in (("fp", lambda: qb.qb_fp_dense(c1, W.C1.tol, W.C1.b, s1, ws=c1_ws)),
+                   ("ei", lambda: qb.qb_ei_dense(c1, W.C1.tol, W.C1.b, s1, ws=c1_ws))):
+        fn()
+        torch.cuda.synchronize()
+        tt = []
+        for _ in range(20):
+            t = time.perf_counter()
+            rc1 = fn()
+            torch.cuda.synchronize()
+            tt.append(time.perf_counter() - t)
+        c1_out[nm] = {"time_to_tol_s": round(statistics.median(tt), 6), "rank": rc1.rank,
+                      "E_rel": (max(rc1.E, 0.0) / rc1.normA2) ** 0.5, "passes": rc1.passes, "runs": 20}
+    out["c1"] = c1_out
+    print(f"# 1000x800: fp {c1_out['fp']['time_to_tol_s'] * 1e3:.2f} ms, ei {c1_out['ei']['time_to_tol_s'] * 1e3:.2f} ms",
+          file=sys.stderr, flush=True)
+    del c1, c1_ws
     if not args.no_ei:
         ei()
         torch.cuda.synchronize()
@@ -414,6 +464,22 @@ def precision_block(qb, W, torch, steps, l_tilde, gen_device="cuda"):
         peak = FP64_PEAK_TFLOPS if name.startswith("f64") else BF16_PEAK_TFLOPS
         dom_ms = max(g_ms, h_ms)
         achieved = per_launch / (dom_ms * 1e-3) / 1e12
+        gemms = None
+        if name == "fp8_e4m3":
+            # G on the 8-bit matrix cores (e4m3 x e4m3, 5.0 PFLOP/s dense), H on bfloat16 ones
+            gemms = {"G": {"kernel": "gemm_f8 (MFMA 32x32x64 f8f6f4, e4m3 A and Omega_q, FP32 acc)",
+                           "ms_per_launch": g_ms, "tflops": round(per_launch / (g_ms * 1e-3) / 1e12, 2),
+                           "peak_tflops": FP8_PEAK_TFLOPS,
+                           "frac": round(per_launch / (g_ms * 1e-3) / 1e12 / FP8_PEAK_TFLOPS, 4)},
+                     "H": {"kernel": "gemm_bf16 (MFMA 32x32x16 bf16, e4m3 A widened on load)",
+                           "ms_per_launch": h_ms, "tflops": round(per_launch / (h_ms * 1e-3) / 1e12, 2),
+                           "peak_tflops": BF16_PEAK_TFLOPS,
+                           "frac": round(per_launch / (h_ms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS, 4)}}
+        elif name == "bf16":
+            gemms = {k: {"ms_per_launch": t_, "tflops": round(per_launch / (t_ * 1e-3) / 1e12, 2),
+                         "peak_tflops": BF16_PEAK_TFLOPS,
+                         "frac": round(per_launch / (t_ * 1e-3) / 1e12 / BF16_PEAK_TFLOPS, 4)}
+                     for k, t_ in (("G", g_ms), ("H", h_ms))}
         res[name] = {"tol": tol, "time_to_tol_s": round(statistics.median(ts), 6), "rank": r.rank,
                      "true_rel_err": true_rel, "E_rel": (max(r.E, 0.0) / r.normA2) ** 0.5,
                      "passes": r.passes, "chunks": r.chunks,
@@ -421,10 +487,14 @@ def precision_block(qb, W, torch, steps, l_tilde, gen_device="cuda"):
                                   "block_loop": r.ms[4], "total": r.ms[5]},
                      "sketch_gemm": {"kernel": "gemm_f64 (MFMA 16x16x4 f64)" if name.startswith("f64")
                                      else "gemm_bf16 (MFMA 32x32x16 bf16, FP32 acc)"
-                                     + (", e4m3 A widened on load" if name == "fp8_e4m3" else ""),
+                                     if name == "bf16" else "G: gemm_f8 (MFMA 32x32x64 e4m3), "
+                                     "H: gemm_bf16 (e4m3 A widened on load); rate of the slower launch "
+                                     "against the BF16 peak",
                                      "G_ms_per_launch": g_ms, "H_ms_per_launch": h_ms,
                                      "achieved_tflops": round(achieved, 2), "peak_tflops": peak,
                                      "frac": round(achieved / peak, 4)}}
+        if gemms is not None:
+            res[name]["sketch_gemms"] = gemms
         print(f"# precision {name}: {statistics.median(ts) * 1e3:.2f} ms rank {r.rank} "
               f"true rel {true_rel:.4e}", file=sys.stderr, flush=True)
     res["workload"] = wl.name
@@ -572,10 +642,131 @@ def sparse_block(qb, W, torch, steps=1):
     return res
 
 
-def cpu_baseline(A, wl, seed, l_tilde):
-    """The FP64 oracle's randQB_FP on the same matrix and schedule, once, on the host cores."""
-    import numpy as np
+def counter_probe(qb, W, torch, l_tilde):
+    """The program the counter passes run (bench.py --counter-probe): two calibration kernels
+    of known traffic -- ||X||^2 of a 1 GiB matrix (sumsq_dense_partial reads exactly 2^30
+    bytes) and 2^27 Gaussian entries (gauss_fill_kernel writes exactly 2^30 bytes) -- then the
+    headline randQB_FP call twice (warm-up, measured) on the same matrix, generated on the
+    host so that no library QR of the generator runs under the counters."""
+    dev = torch.device("cuda:0")
+    X = torch.full((8192, 16384), 0.5, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    qb.qb_sumsq_dense(X)
+    del X
+    g = qb.qb_gaussian_fill(1, 8192, 16384)
+    torch.cuda.synchronize()
+    del g
+    wl = W.C2
+    seed = W.SEED_OMEGA | 2
+    A = wl.make(device="cpu").to(dev)
+    m, n = A.shape
+    l_max = min(m, n)
+    for _ in range(2):
+        qb.qb_fp_dense(A, wl.tol, wl.b, seed, l_max=l_max, l_tilde=l_tilde)
+        torch.cuda.synchronize()
 
+
+def _read_counters(csv_path):
+    """rocprofv3 counter-collection CSV -> list of (dispatch id, kernel name, counter, value)."""
+    import csv
+    out = []
+    with open(csv_path) as f:
+        for row in csv.DictReader(f):
+            out.append((int(row["Dispatch_Id"]), row["Kernel_Name"], row["Counter_Name"], float(row["Counter_Value"])))
+    out.sort()
+    return out
+
+
+def measure_counters(l_tilde, timeout=300):
+    """Counter passes over counter_probe (each its own rocprofv3 run: FETCH_SIZE, WRITE_SIZE,
+    then the MfmaUtil metric): the dominant sketch GEMMs' HBM bytes per launch of the measured
+    call (each counter scaled by what it reads for its calibration kernel of exactly 1 GiB)
+    and their MFMA busy percentage.  Returns {} fields as None when a pass fails."""
+    import glob
+    import shutil
+    import subprocess
+    import tempfile
+
+    res = {"traffic_bytes": {"G": None, "H": None}, "mfma_util_pct": {"G": None, "H": None}, "passes": {}}
+    tmp = tempfile.mkdtemp(prefix="qb_counters_", dir="/tmp")
+    env = dict(os.environ, TMPDIR="/tmp")
+    prof = shutil.which("rocprofv3") or "/opt/rocm/bin/rocprofv3"
+    per = {}
+    for name in ("FETCH_SIZE", "WRITE_SIZE", "MfmaUtil"):
+        d = os.path.join(tmp, name)
+        cmd = [prof, "--pmc", name, "--output-format", "csv", "-d", d, "-o", "run", "--",
+               sys.executable, os.path.join(ROOT, "bench.py"), "--counter-probe", "--l-tilde", str(l_tilde)]
+        print(f"# counters: {name} pass ...", file=sys.stderr, flush=True)
+        try:
+            r = subprocess.run(cmd, cwd="/tmp", env=env, stdout=subprocess.DEVNULL, stderr=subprocess.PIPE,
+                               timeout=timeout)
+            rc = r.returncode
+        except subprocess.TimeoutExpired:
+            rc = "timeout"
+        files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        res["passes"][name] = {"rc": rc, "csv": bool(files)}
+        if files:
+            per[name] = _read_counters(files[0])
+    # the sketch GEMMs: gemm_f64_kernel<128, 128, ...> with A layout 0 (G = A Omega) or
+    # 1 (H = A^T G); the measured call's launches are the last half of each
+    def launches(rows, counter, al):
+        tag = f"gemm_f64_kernel<128, 128, 32, 4, 2, {al}, 0"
+        vals = [v for _, k, c, v in rows if c == counter and tag in k]
+        return vals[len(vals) // 2:]
+
+    def first(rows, counter, kname):
+        for _, k, c, v in rows:
+            if c == counter and kname in k:
+                return v
+        return None
+
+    try:
+        fetch, write = per.get("FETCH_SIZE"), per.get("WRITE_SIZE")
+        if fetch and write:
+            cal_f = first(fetch, "FETCH_SIZE", "sumsq_dense_partial")
+            cal_w = first(write, "WRITE_SIZE", "gauss_fill_kernel")
+            f_scale = 2.0 ** 30 / (cal_f * 1024.0)
+            w_scale = 2.0 ** 30 / (cal_w * 1024.0)
+            res["scale"] = {"FETCH_SIZE": round(f_scale, 4), "WRITE_SIZE": round(w_scale, 4)}
+            for key, al in (("G", 0), ("H", 1)):
+                fl, wr = launches(fetch, "FETCH_SIZE", al), launches(write, "WRITE_SIZE", al)
+                if fl and wr and len(fl) == len(wr):
+                    res["traffic_bytes"][key] = float(np.mean([a * 1024 * f_scale + b * 1024 * w_scale
+                                                               for a, b in zip(fl, wr)]))
+                    res["launches"] = len(fl)
+        mf = per.get("MfmaUtil")
+        if mf:
+            for key, al in (("G", 0), ("H", 1)):
+                u = launches(mf, "MfmaUtil", al)
+                if u:
+                    res["mfma_util_pct"][key] = round(float(np.mean(u)), 2)
+    except Exception as e:  # a malformed file leaves the fields at None
+        res["error"] = repr(e)
+    shutil.rmtree(tmp, ignore_errors=True)
+    return res
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(A, wl, seed, l_tilde, runs=5):
+    """The FP64 oracle's randQB_FP on the same matrix and schedule on the host cores: the
+    median of `runs` runs (matrix generation excluded), with the host's core count and CPU
+    model, and the oracle's times on the other workloads' instances (randQB_FP and randQB_EI
+    on the 1000 x 800 matrix, the 4096 x 4096 precision-form parity instance in bfloat16,
+    and a bounded sample of the CSR workload)."""
+    import numpy as np
+    import torch
+
+    import workloads as W
     from oracle import randqb as R
     try:
         from threadpoolctl import threadpool_info
@@ -584,14 +775,48 @@ def cpu_baseline(A, wl, seed, l_tilde):
         threads = os.cpu_count() or 1
     An = A.cpu().numpy()
     print("# cpu baseline: oracle randQB_FP on the full workload ...", file=sys.stderr, flush=True)
+    ts = []
+    for _ in range(runs):
+        t = time.perf_counter()
+        ora = R.randqb_fp(An, wl.tol, wl.b, seed, l_tilde=l_tilde)
+        ts.append(time.perf_counter() - t)
+    dt = statistics.median(ts)
+    print(f"# cpu baseline: median {dt:.2f} s of {runs} (rank {ora.rank})", file=sys.stderr, flush=True)
+    others = {}
+    # 1000 x 800 (sigma_j = j^-2, b = 20, tol 1e-2): randQB_FP and randQB_EI
+    c1 = W.C1.make().numpy()
+    s1 = W.SEED_OMEGA | 1
+    for name, fn in (("fp", lambda: R.randqb_fp(c1, W.C1.tol, W.C1.b, s1)),
+                     ("ei", lambda: R.randqb_ei(c1, W.C1.tol, W.C1.b, s1))):
+        tt = []
+        for _ in range(runs):
+            t = time.perf_counter()
+            r = fn()
+            tt.append(time.perf_counter() - t)
+        others[f"{W.C1.name}_{name}"] = {"median_s": round(statistics.median(tt), 4), "rank": r.rank,
+                                          "E_rel": (max(r.E, 0.0) / r.normA2) ** 0.5}
+    # precision-form parity instance, 4096 x 4096 bfloat16 (paper chunk rule)
+    c4 = W.to_bf16(W.C4_SMALL.make()).double().numpy()
+    tt = []
+    for _ in range(3):
+        t = time.perf_counter()
+        r = R.randqb_fp(c4, W.C4_SMALL.tol, W.C4_SMALL.b, W.SEED_OMEGA | 4, precision="bf16")
+        tt.append(time.perf_counter() - t)
+    others[f"{W.C4_SMALL.name}_bf16"] = {"median_s": round(statistics.median(tt), 4), "rank": r.rank, "runs": 3}
+    # CSR workload, bounded sample: the first 250 rows of the factorisation (one chunk of 250
+    # columns, l_max = 250), once; SciPy's sparse products are single-threaded
+    csr = W.C3.make().to_scipy()
     t = time.perf_counter()
-    ora = R.randqb_fp(An, wl.tol, wl.b, seed, l_tilde=l_tilde)
-    dt = time.perf_counter() - t
-    print(f"# cpu baseline: {dt:.1f} s rank {ora.rank}", file=sys.stderr, flush=True)
+    r = R.randqb_fp(csr, W.C3.tol, W.C3.b, W.SEED_OMEGA | 3, l_max=250, l_tilde=250)
+    others[f"{W.C3.name}_sample"] = {"time_s": round(time.perf_counter() - t, 3), "rank": r.rank,
+                                      "sample": "l_max = 250 (one chunk of 250 columns, 5 blocks), "
+                                                "not converged; SciPy sparse products single-threaded"}
+    print(f"# cpu baseline others: {json.dumps(others)}", file=sys.stderr, flush=True)
     return {"value": round(dt, 3), "unit": "s", "cores": threads, "kind": "oracle",
-            "sample": f"full {wl.name} workload, one randQB_FP call with the same chunk schedule "
-                      "(NumPy/OpenBLAS FP64)",
-            "rank": ora.rank}
+            "sample": f"full {wl.name} workload, randQB_FP with the same chunk schedule "
+                      f"(NumPy/OpenBLAS FP64), median of {runs} runs",
+            "runs_s": [round(x, 3) for x in ts], "rank": ora.rank, "nproc": os.cpu_count(),
+            "cpu_model": _cpu_model(), "others": others}
 
 
 if __name__ == "__main__":

@@ -28,8 +28,11 @@
  *   - All device work is ordered after earlier work on the caller's stream, and the call's
  *     results are complete on that stream when it returns (parts may run on private
  *     streams of default priority, joined to the caller's stream by events); calls that
- *     return a rank synchronise that stream before returning (the rank is decided on the
- *     host, one b-vector copy per block).
+ *     return a rank synchronise that stream before returning.  For randQB_FP and randQB_EI
+ *     the stopping rule runs on the device; the host reads its state back once per run of
+ *     up to 4 blocks (randQB_FP) or once per block (randQB_EI), so blocks past the stop may
+ *     have been enqueued: their products are skipped on the device, and what they leave
+ *     lies outside [0, rank).
  *   - Dense A is row-major: A(i, j) at a[i * lda + j], lda >= n.
  *   - Q is column-major m x l_max: Q(i, j) at Q[j * ldq + i], ldq >= m.
  *   - B is row-major l_max x n: B(i, j) at B[i * ldb + j], ldb >= n.

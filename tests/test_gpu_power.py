@@ -148,3 +148,41 @@ def test_power_csr_full_size_properties(qb):
     assert orth <= 1e-11
     assert dB <= 1e-9 * nB
     assert res.passes == 4 * res.chunks
+
+
+@pytest.mark.parametrize("algo", ["fp_paper_rule", "ei"])
+def test_csr_full_size_p0_properties(qb, algo):
+    """The 500000 x 200000 CSR workload at P = 0 as the benchmark times it (l_max 16384;
+    randQB_FP with the paper's l~ = 50 b, and randQB_EI), where the rank reaches about 14000
+    and the drift of eq. (23) that Remark 4.1 describes is largest: Q^T Q = I, B = Q^T A on 64
+    sampled columns (with Q orthonormal this makes E = ||A||^2 - ||B||^2 the squared
+    residual, Theorem 1), E below eps^2, and the pass count (2 per chunk for randQB_FP, 2 per
+    block for randQB_EI)."""
+    wl = W.C3
+    seed = W.SEED_OMEGA | 3
+    csr = wl.make()
+    rp, ci, va = _csr_dev(csr)
+    _log(f"C3 P=0 {algo}")
+    if algo == "ei":
+        res = qb.qb_ei_csr(csr.m, csr.n, rp, ci, va, wl.tol, wl.b, seed, l_max=16384)
+    else:
+        res = qb.qb_fp_csr(csr.m, csr.n, rp, ci, va, wl.tol, wl.b, seed, l_max=16384, l_tilde=0)
+    k = res.rank
+    Q, B = res.Q, res.B
+    orth = float((Q.T @ Q - torch.eye(k, dtype=torch.float64, device="cuda")).abs().max())
+    cols = np.random.default_rng(92).choice(csr.n, 64, replace=False)
+    S = csr.to_scipy().tocsc()
+    Acols = torch.tensor(S[:, cols].toarray(), device="cuda")
+    tc = torch.tensor(cols, device="cuda")
+    dB = float(torch.linalg.matrix_norm(B[:, tc] - Q.T @ Acols))
+    nB = float(torch.linalg.matrix_norm(B[:, tc]))
+    _log(f"C3 P=0 {algo}: rank {k} E_rel {np.sqrt(max(res.E, 0) / res.normA2):.4f} orth {orth:.2e} "
+         f"|B - Q^T A|/|B| on sampled columns {dB / nB:.2e} passes {res.passes} blocks {res.blocks}")
+    assert res.status == qb.QB_OK and res.E < (wl.tol ** 2) * res.normA2
+    assert 10000 <= k <= 16384
+    assert orth <= 1e-11
+    assert dB <= 1e-9 * nB
+    if algo == "ei":
+        assert res.passes == 2 * res.blocks
+    else:
+        assert res.passes == 2 * res.chunks
