@@ -20,7 +20,7 @@ LIBDIR = os.path.join(PKG, "_lib")
 OBJDIR = os.path.join(ROOT, "_build")
 LIBNAME = "libqb.so"
 
-SOURCES = ["rng.hip", "reduce.hip", "gemm.hip", "lowp.hip", "panel.hip", "spmm.hip", "qb_host.hip",
+SOURCES = ["rng.hip", "reduce.hip", "gemm.hip", "tsgemm.hip", "lowp.hip", "panel.hip", "spmm.hip", "qb_host.hip",
            "diff.hip", "svd.hip", "coo.hip", "qrcp.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -33,7 +33,10 @@ COMMON = [
     "-I", os.path.join(ROOT, "include"),
 ]
 # the Gaussian generator must not fuse multiply-adds (bit-specified sequence)
-PER_FILE = {"rng.hip": ["-ffp-contract=off"]}
+PER_FILE = {"rng.hip": ["-ffp-contract=off"],
+            # the register-fed narrow products keep their accumulators in ordinary VGPRs
+            # (otherwise the loop copies them between register files every iteration)
+            "tsgemm.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form", "-Wno-inline-asm"]}
 
 
 def _compile(src: str) -> str:

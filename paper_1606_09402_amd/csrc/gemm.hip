@@ -396,6 +396,21 @@ scale_copy_kernel(int64_t M, int64_t N, double beta, const double* C0, int64_t c
 
 // ------------------------------------------------------------------------------ host
 
+hipError_t launch_splitk_reduce(const GemmDesc& d, int nsplit, hipStream_t s) {
+    const int64_t tot = d.M * d.N;
+    if (nsplit >= 2 * kRedLanes && tot <= (int64_t(1) << 18)) {
+        // few outputs, long reduction: spread each element over kRedLanes threads
+        hipLaunchKernelGGL(splitk_reduce_wide_kernel, dim3(static_cast<unsigned>(cdiv(tot, 256 / kRedLanes))),
+                           dim3(256), 0, s, d.ws, nsplit, d.M, d.N, d.alpha, d.beta, d.C0.p, d.C0.si,
+                           d.C0.sj, d.C.p, d.C.si, d.C.sj);
+    } else {
+        hipLaunchKernelGGL(splitk_reduce_kernel, dim3(static_cast<unsigned>(cdiv(tot, 256))), dim3(256), 0,
+                           s, d.ws, nsplit, d.M, d.N, d.alpha, d.beta, d.C0.p, d.C0.si, d.C0.sj, d.C.p,
+                           d.C.si, d.C.sj);
+    }
+    return hipGetLastError();
+}
+
 
 template <int BM, int BN, int BK, int WM, int WN, int AL, int BL, int OCC, int STAGES>
 static hipError_t run_cfg(const GemmDesc& d, hipStream_t s) {
@@ -451,18 +466,8 @@ static hipError_t run_cfg(const GemmDesc& d, hipStream_t s) {
     hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, WM, WN, AL, BL, OCC, STAGES>), grid, dim3(64 * WM * WN), 0,
                        s, g);
     if (nsplit > 1) {
-        const int64_t tot = d.M * d.N;
-        if (nsplit >= 2 * kRedLanes && tot <= (int64_t(1) << 18)) {
-            // few outputs, long reduction: spread each element over kRedLanes threads
-            hipLaunchKernelGGL(splitk_reduce_wide_kernel,
-                               dim3(static_cast<unsigned>(cdiv(tot, 256 / kRedLanes))), dim3(256), 0,
-                               s, d.ws, nsplit, d.M, d.N, d.alpha, d.beta, d.C0.p, d.C0.si,
-                               d.C0.sj, d.C.p, d.C.si, d.C.sj);
-        } else {
-            hipLaunchKernelGGL(splitk_reduce_kernel, dim3(static_cast<unsigned>(cdiv(tot, 256))),
-                               dim3(256), 0, s, d.ws, nsplit, d.M, d.N, d.alpha, d.beta, d.C0.p,
-                               d.C0.si, d.C0.sj, d.C.p, d.C.si, d.C.sj);
-        }
+        const hipError_t e = launch_splitk_reduce(d, nsplit, s);
+        if (e != hipSuccess) return e;
         if (d.colsq != nullptr) {
             // at most tiles_m groups of rows, so the caller's [tiles_m][N] buffer fits
             const int64_t groups = g.tiles_m < 256 ? g.tiles_m : 256;
@@ -513,6 +518,22 @@ hipError_t gemm_f64(const GemmDesc& d, hipStream_t s) {
         hipLaunchKernelGGL(scale_copy_kernel, dim3(static_cast<unsigned>(cdiv(tot, 256))), dim3(256),
                            0, s, d.M, d.N, d.beta, d.C0.p, d.C0.si, d.C0.sj, d.C.p, d.C.si, d.C.sj);
         return hipGetLastError();
+    }
+    // narrow products (the block loop's m x b and n x b panels) on the register-fed kernels of
+    // tsgemm.hip where they were measured faster: the panel form (column-major A) for
+    // reductions of 132 .. 16384, and the reduction form (k-contiguous A, column-major B) for
+    // reductions of 100000 and more.  Shorter reductions and wider outputs stay on the
+    // LDS-tiled kernel below.
+    if (d.colsq == nullptr && d.N <= 64 && d.K > 128) {
+        if (d.A.si == 1 && d.K <= 16384 && ts_panel_dma_fits(d)) return ts_panel_dma(d, 2, 4, 4, 1, s, 1);
+        if (d.A.sj == 1 && d.B.si == 1 && d.K >= 100000 && ts_red_fits(d)) {
+            // about 1024 workgroups (one per CU resident at a time), within the split buffer
+            const int64_t tiles = cdiv(d.M, 64);
+            int64_t ns = cdiv(1024, tiles);
+            if (ns > 256) ns = 256;
+            while (ns > 1 && (d.ws == nullptr || ns * d.M * d.N > d.ws_elems)) --ns;
+            return ts_red(d, 4, 4, static_cast<int>(ns), s);
+        }
     }
     const int al = d.A.sj == 1 ? 0 : 1;
     const int bl = d.B.sj == 1 ? 0 : 1;

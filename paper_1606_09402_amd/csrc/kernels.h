@@ -37,6 +37,22 @@ struct GemmDesc {
     const int* gate;     // device flag: the product is skipped if it is nonzero at launch time
 };
 hipError_t gemm_f64(const GemmDesc& d, hipStream_t s);
+// Fixed-order sum of nsplit partials d.ws[split][M][N] into d.C with the alpha / beta epilogue.
+hipError_t launch_splitk_reduce(const GemmDesc& d, int nsplit, hipStream_t s);
+
+// tsgemm.hip -- narrow products (N <= 64) with MFMA operands loaded from global memory.
+// Panel form: A column-major (d.A.si == 1); reduction form: A with k contiguous (d.A.sj == 1)
+// and B contiguous in k or j.  fm: 16-row blocks per output tile; waves: workgroup waves
+// sharing the reduction; nsplit: reduction splits over workgroups (partials in d.ws).
+// hipErrorNotSupported when the operands do not fit the form.
+bool ts_panel_fits(const GemmDesc& d);
+bool ts_red_fits(const GemmDesc& d);
+hipError_t ts_panel(const GemmDesc& d, int fm, int waves, int nsplit, hipStream_t s);
+hipError_t ts_red(const GemmDesc& d, int fm, int waves, int nsplit, hipStream_t s);
+// Panel form through per-wave LDS DMA rings of `depth` steps (full row tiles; B row-major).
+bool ts_panel_dma_fits(const GemmDesc& d);
+hipError_t ts_panel_dma(const GemmDesc& d, int fm, int waves, int depth, int nsplit, hipStream_t s, int nt = 0);
+
 // Largest number of row groups of the column sums of squares gemm_f64 writes for an M x N
 // output (colsq): one per output tile row (the tile height depends on K as well).
 int64_t gemm_f64_colsq_groups(int64_t M, int64_t N);
