@@ -367,13 +367,17 @@ typedef struct {
 QB_API size_t qb_fixed_rank_workspace_bytes(const qb_batch* A, int64_t k, int32_t b);
 
 /* Forward.  Q: per matrix m x k row-major (row stride ldq >= k, batch stride stride_q);
- * B: per matrix k x n row-major (ldb >= n, stride_b).  Synchronises the stream.  Returns
- * QB_NOT_CONVERGED (a warning) if CholeskyQR met a pivot below 1e-6 (binary32) or 1e-12
- * (binary64) of the largest Gram diagonal in some block: A Omega is then numerically
- * rank deficient at rank k and Q, B are unreliable. */
+ * B: per matrix k x n row-major (ldb >= n, stride_b).  A CholeskyQR pivot below 1e-6
+ * (binary32) or 1e-12 (binary64) of the largest Gram diagonal in some block means that
+ * A Omega is numerically rank deficient at rank k and Q, B are unreliable; it is reported
+ * through breakdown:
+ *   breakdown  device int32, or NULL.  Non-NULL: the call is only enqueued (no host wait) and
+ *              *breakdown is set, in stream order, to 1 after such a pivot and 0 otherwise.
+ *              NULL: the call synchronises the stream and returns QB_NOT_CONVERGED (a
+ *              warning) after such a pivot. */
 QB_API int qb_fixed_rank_fwd(const qb_batch* A, int64_t k, int32_t b, uint64_t seed, void* Q,
                              int64_t ldq, int64_t stride_q, void* B, int64_t ldb, int64_t stride_b,
-                             void* ws, size_t ws_bytes, hipStream_t stream);
+                             void* ws, size_t ws_bytes, int32_t* breakdown, hipStream_t stream);
 
 /* Backward: dA = dL/dA (per matrix m x n row-major, ldda >= n) from the forward's Q and
  * the adjoints dQ (m x k, may be NULL for zero) and dB (k x n, may be NULL).  dA is

@@ -119,7 +119,7 @@ def lib() -> ctypes.CDLL:
         L.qb_fixed_rank_workspace_bytes.argtypes = [P(QbBatch), _c_i64, _c_i32]
         L.qb_fixed_rank_workspace_bytes.restype = ctypes.c_size_t
         L.qb_fixed_rank_fwd.argtypes = [P(QbBatch), _c_i64, _c_i32, ctypes.c_uint64, _vp, _c_i64, _c_i64,
-                                        _vp, _c_i64, _c_i64, _vp, ctypes.c_size_t, _vp]
+                                        _vp, _c_i64, _c_i64, _vp, ctypes.c_size_t, _vp, _vp]
         L.qb_fixed_rank_fwd.restype = ctypes.c_int
         L.qb_fixed_rank_bwd.argtypes = [P(QbBatch), _c_i64, _c_i32, ctypes.c_uint64, _vp, _c_i64, _c_i64,
                                         _vp, _c_i64, _c_i64, _vp, _c_i64, _c_i64, _vp, _c_i64, _c_i64,
@@ -600,16 +600,25 @@ def _ws_for(A, k, b, ws):
     return ws, need
 
 
-def qb_fixed_rank_fwd(A: torch.Tensor, k: int, b: int, seed: int, ws=None):
-    """Fixed-rank randQB_FP of every matrix of A (batch, m, n): (Q (batch, m, k), B (batch, k, n))."""
+def qb_fixed_rank_fwd(A: torch.Tensor, k: int, b: int, seed: int, ws=None, breakdown=None):
+    """Fixed-rank randQB_FP of every matrix of A (batch, m, n): (Q (batch, m, k), B (batch, k, n)).
+
+    breakdown: None (the call waits for the stream and raises on a CholeskyQR breakdown) or an
+    int32 GPU tensor of one element that receives the breakdown flag in stream order (no wait;
+    the caller checks it)."""
     d = _batch(A)
     ws, need = _ws_for(A, k, b, ws)
     bt, m, n = A.shape
     Q = torch.empty((bt, m, k), dtype=A.dtype, device=A.device)
     B = torch.empty((bt, k, n), dtype=A.dtype, device=A.device)
+    flag = None
+    if breakdown is not None:
+        if breakdown.dtype != torch.int32 or not breakdown.is_cuda or breakdown.numel() < 1:
+            raise ValueError("breakdown must be an int32 GPU tensor")
+        flag = breakdown.data_ptr()
     st = lib().qb_fixed_rank_fwd(ctypes.byref(d), int(k), int(b), int(seed) & (2 ** 64 - 1), Q.data_ptr(),
                                  Q.stride(1), Q.stride(0), B.data_ptr(), B.stride(1), B.stride(0),
-                                 ws.data_ptr(), ws.numel(), _stream_ptr(A.device))
+                                 ws.data_ptr(), ws.numel(), flag, _stream_ptr(A.device))
     if st < 0 or st == QB_NOT_CONVERGED:
         raise QBError(st, "qb_fixed_rank_fwd")
     return Q, B

@@ -18,6 +18,8 @@
 // Every product runs on one batched MFMA GEMM templated on the element type (binary32
 // for speed, binary64 for checking the adjoint to round-off); the b x b Cholesky factors
 // and the k x k triangular inverse are one workgroup per matrix.
+#include <type_traits>
+
 #include "kernels.h"
 
 namespace qb {
@@ -174,6 +176,179 @@ __global__ void __launch_bounds__(256) bgemm_kernel(const BGemm<T> g) {
             }
 }
 
+// The same product for large tiles: BM x BN per workgroup of WM x WN waves, BK-deep K tiles
+// moved global -> registers -> LDS through two LDS stages (tile t + 1 is loaded while tile
+// t is multiplied; one barrier per tile), with 16-byte loads along the contiguous index of
+// each operand when the host found it aligned (vec), scalar checked loads otherwise and in
+// edge tiles.  Each operand keeps its global orientation in LDS: an operand contiguous in k
+// (AKF / BKF) as rows of BK + 4 elements, one contiguous in i (j) as BK rows of BM + 16 (BN +
+// 16) elements; both pitches make the 16 x 4 operand reads of an MFMA and the 16-byte
+// stores free of bank conflicts.
+template <typename T, int BM, int BN, int BK, int WM, int WN, bool AKF, bool BKF>
+__global__ void __launch_bounds__(64 * WM * WN) bgemm2_kernel(const BGemm<T> g, int vec_a, int vec_b) {
+    constexpr int NT = 64 * WM * WN, TM = BM / WM, TN = BN / WN, FM = TM / 16, FN = TN / 16;
+    constexpr int VE = 16 / sizeof(T);                       // elements per 16-byte load
+    constexpr int PK = BK + 16 / sizeof(T) * (sizeof(T) == 4 ? 1 : 1);   // k-contiguous row pitch
+    constexpr int PA = BM + 64 / sizeof(T), PB = BN + 64 / sizeof(T);    // i / j-contiguous pitches
+    constexpr int A_SZ = AKF ? BM * PK : BK * PA, B_SZ = BKF ? BN * PK : BK * PB;
+    constexpr int LA = BM * BK / NT, LB = BN * BK / NT;      // elements per thread per tile
+    static_assert(LA % VE == 0 && LB % VE == 0 && BK % 4 == 0 && BK % VE == 0, "tile shape");
+    using V = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+    __shared__ __align__(16) T As[2][A_SZ];
+    __shared__ __align__(16) T Bs[2][B_SZ];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave / WN, wn = wave % WN;
+    const int li = lane & 15, lk = lane >> 4;
+    const int64_t z = blockIdx.z;
+    const int tile_m = blockIdx.x / g.tiles_n, tile_n = blockIdx.x % g.tiles_n;
+    const int64_t m0 = static_cast<int64_t>(tile_m) * BM, n0 = static_cast<int64_t>(tile_n) * BN;
+    const T* A = g.A + z * g.a_sz;
+    const T* B = g.B + z * g.b_sz;
+    const bool full = m0 + BM <= g.M && n0 + BN <= g.N;
+    const bool va = vec_a && full, vb = vec_b && full;
+
+    // element e (a multiple of VE) of the thread's share: (kk, ii) of A, (kk, jj) of B, the VE
+    // elements e .. e + VE - 1 running along the operand's contiguous index
+    auto a_of = [](int e, int& kk, int& ii) {
+        if (AKF) { kk = e % BK; ii = e / BK; } else { kk = e / BM; ii = e % BM; }
+    };
+    auto b_of = [](int e, int& kk, int& jj) {
+        if (BKF) { kk = e % BK; jj = e / BK; } else { kk = e / BN; jj = e % BN; }
+    };
+    T ra[LA], rb[LB];
+    auto load = [&](int64_t k0, int64_t ke) {
+        const bool kin = k0 + BK <= ke;
+#pragma unroll
+        for (int p = 0; p < LA / VE; ++p) {
+            int kk, ii;
+            a_of((tid + p * NT) * VE, kk, ii);
+            if (va && kin) {
+                const V x = *reinterpret_cast<const V*>(A + (m0 + ii) * g.a_si + (k0 + kk) * g.a_sk);
+                const T* xs = reinterpret_cast<const T*>(&x);
+#pragma unroll
+                for (int q = 0; q < VE; ++q) ra[p * VE + q] = xs[q];
+            } else {
+#pragma unroll
+                for (int q = 0; q < VE; ++q) {
+                    const int64_t i = m0 + ii + (AKF ? 0 : q), k = k0 + kk + (AKF ? q : 0);
+                    ra[p * VE + q] = (i < g.M && k < ke) ? A[i * g.a_si + k * g.a_sk] : T(0);
+                }
+            }
+        }
+#pragma unroll
+        for (int p = 0; p < LB / VE; ++p) {
+            int kk, jj;
+            b_of((tid + p * NT) * VE, kk, jj);
+            if (vb && kin) {
+                const V x = *reinterpret_cast<const V*>(B + (k0 + kk) * g.b_sk + (n0 + jj) * g.b_sj);
+                const T* xs = reinterpret_cast<const T*>(&x);
+#pragma unroll
+                for (int q = 0; q < VE; ++q) rb[p * VE + q] = xs[q];
+            } else {
+#pragma unroll
+                for (int q = 0; q < VE; ++q) {
+                    const int64_t j = n0 + jj + (BKF ? 0 : q), k = k0 + kk + (BKF ? q : 0);
+                    rb[p * VE + q] = (j < g.N && k < ke) ? B[k * g.b_sk + j * g.b_sj] : T(0);
+                }
+            }
+        }
+    };
+    auto store = [&](int st) {
+#pragma unroll
+        for (int p = 0; p < LA / VE; ++p) {
+            int kk, ii;
+            a_of((tid + p * NT) * VE, kk, ii);
+            T* d = &As[st][AKF ? ii * PK + kk : kk * PA + ii];
+            *reinterpret_cast<V*>(d) = *reinterpret_cast<const V*>(&ra[p * VE]);
+        }
+#pragma unroll
+        for (int p = 0; p < LB / VE; ++p) {
+            int kk, jj;
+            b_of((tid + p * NT) * VE, kk, jj);
+            T* d = &Bs[st][BKF ? jj * PK + kk : kk * PB + jj];
+            *reinterpret_cast<V*>(d) = *reinterpret_cast<const V*>(&rb[p * VE]);
+        }
+    };
+
+    using Acc = typename Mfma<T>::acc_t;
+    Acc acc[FM][FN];
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) acc[a][b] = Acc{};
+    const int wm0 = wm * TM, wn0 = wn * TN;
+    auto compute = [&](int st) {
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+            T a[FM], b[FN];
+#pragma unroll
+            for (int fm = 0; fm < FM; ++fm) {
+                const int i = wm0 + fm * 16 + li;
+                a[fm] = AKF ? As[st][i * PK + kk + lk] : As[st][(kk + lk) * PA + i];
+            }
+#pragma unroll
+            for (int fn = 0; fn < FN; ++fn) {
+                const int j = wn0 + fn * 16 + li;
+                b[fn] = BKF ? Bs[st][j * PK + kk + lk] : Bs[st][(kk + lk) * PB + j];
+            }
+#pragma unroll
+            for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+                for (int fn = 0; fn < FN; ++fn) acc[fm][fn] = Mfma<T>::op(a[fm], b[fn], acc[fm][fn]);
+        }
+    };
+
+    const int64_t kb = static_cast<int64_t>(blockIdx.y) * g.kchunk;
+    const int64_t ke = kb + g.kchunk < g.K ? kb + g.kchunk : g.K;
+    int st = 0;
+    if (kb < ke) {
+        load(kb, ke);
+        store(0);
+        __syncthreads();
+        for (int64_t k0 = kb; k0 < ke; k0 += BK) {
+            const bool more = k0 + BK < ke;
+            if (more) load(k0 + BK, ke);
+            compute(st);
+            if (more) store(st ^ 1);
+            __syncthreads();
+            st ^= 1;
+        }
+    }
+
+    T* out;
+    int64_t osi, osj;
+    const bool split = gridDim.y > 1;
+    if (split) {
+        out = g.P + (static_cast<int64_t>(blockIdx.y) * gridDim.z + z) * g.M * g.N;
+        osi = g.N;
+        osj = 1;
+    } else {
+        out = g.C + z * g.c_sz;
+        osi = g.c_si;
+        osj = g.c_sj;
+    }
+    const T* C0 = g.C0 + z * g.c0_sz;
+#pragma unroll
+    for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+        for (int fn = 0; fn < FN; ++fn)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t i = m0 + wm0 + fm * 16 + Mfma<T>::row(lane, r);
+                const int64_t j = n0 + wn0 + fn * 16 + li;
+                if (i < g.M && j < g.N) {
+                    if (split) {
+                        out[i * osi + j] = acc[fm][fn][r];
+                    } else {
+                        T v = g.alpha * acc[fm][fn][r];
+                        if (g.beta != T(0)) v += g.beta * C0[i * g.c0_si + j * g.c0_sj];
+                        out[i * osi + j * osj] = v;
+                    }
+                }
+            }
+}
+
 // Fixed-order sum of the K splits with the alpha / beta epilogue.
 template <typename T>
 __global__ void __launch_bounds__(256)
@@ -222,10 +397,12 @@ hipError_t bgemm(int64_t batch, int64_t M, int64_t N, int64_t K, BV<T> a, BV<T> 
     g.C0 = c0.p; g.c0_si = c0.si; g.c0_sj = c0.sj; g.c0_sz = c0.sz;
     g.C = c.p; g.c_si = c.si; g.c_sj = c.sj; g.c_sz = c.sz;
     if (batch > 65535) return hipErrorInvalidValue;
-    // 64 x 64 tiles; 128 x 64 for tall outputs with few tiles per matrix
-    const bool tall = M >= 1024 && N <= 64;
-    g.tiles_n = static_cast<int>(cdiv(N, 64));
-    const int64_t tiles = cdiv(M, tall ? 128 : 64) * g.tiles_n;
+    // 128 x 128 tiles (two LDS stages) for outputs of at least 128 x 128 with a reduction
+    // of at least 128; else 64 x 64 tiles, 128 x 64 for tall outputs with few tiles per matrix
+    const bool big = M >= 128 && N >= 128 && K >= 128;
+    const bool tall = !big && M >= 1024 && N <= 64;
+    g.tiles_n = static_cast<int>(cdiv(N, big ? 128 : 64));
+    const int64_t tiles = cdiv(M, big || tall ? 128 : 64) * g.tiles_n;
     // few workgroups and a long reduction (Gram matrices, Q^T X): split K over about 2048
     // workgroups in chunks of at least 128
     int64_t nsplit = 1;
@@ -239,10 +416,24 @@ hipError_t bgemm(int64_t batch, int64_t M, int64_t N, int64_t K, BV<T> a, BV<T> 
     if (nsplit < 1) nsplit = 1;
     g.P = sw.p;
     dim3 grid(static_cast<unsigned>(tiles), static_cast<unsigned>(nsplit), static_cast<unsigned>(batch));
-    if (tall)
+    if (big) {
+        // 16-byte loads when the operand's contiguous index is aligned in every matrix
+        constexpr int64_t VE = 16 / sizeof(T);
+        auto aligned = [&](const T* p, int64_t s1, int64_t s2, int64_t sz) {
+            return reinterpret_cast<uintptr_t>(p) % 16 == 0 && s1 % VE == 0 && s2 % VE == 0 && sz % VE == 0;
+        };
+        const bool akf = g.a_sk == 1, bkf = g.b_sk == 1 && g.b_sj != 1;
+        const int va = akf ? aligned(g.A, g.a_si, 0, g.a_sz) : g.a_si == 1 && aligned(g.A, g.a_sk, 0, g.a_sz);
+        const int vb = bkf ? aligned(g.B, g.b_sj, 0, g.b_sz) : g.b_sj == 1 && aligned(g.B, g.b_sk, 0, g.b_sz);
+        if (akf && bkf) hipLaunchKernelGGL((bgemm2_kernel<T, 128, 128, 32, 4, 2, true, true>), grid, dim3(512), 0, s, g, va, vb);
+        else if (akf) hipLaunchKernelGGL((bgemm2_kernel<T, 128, 128, 32, 4, 2, true, false>), grid, dim3(512), 0, s, g, va, vb);
+        else if (bkf) hipLaunchKernelGGL((bgemm2_kernel<T, 128, 128, 32, 4, 2, false, true>), grid, dim3(512), 0, s, g, va, vb);
+        else hipLaunchKernelGGL((bgemm2_kernel<T, 128, 128, 32, 4, 2, false, false>), grid, dim3(512), 0, s, g, va, vb);
+    } else if (tall) {
         hipLaunchKernelGGL((bgemm_kernel<T, 128, 64, 16>), grid, dim3(256), 0, s, g);
-    else
+    } else {
         hipLaunchKernelGGL((bgemm_kernel<T, 64, 64, 16>), grid, dim3(256), 0, s, g);
+    }
     if (nsplit > 1) {
         const int64_t tot = batch * M * N;
         hipLaunchKernelGGL((bgemm_splitk_reduce<T>), dim3(static_cast<unsigned>(cdiv(tot, 256))), dim3(256), 0, s,
@@ -510,7 +701,8 @@ int cholqr_b(int64_t batch, int64_t m, int b, const T* X, int64_t xsz, T* Qout, 
 
 template <typename T>
 int fixed_fwd(const qb_batch* Ab, int64_t k, int b, uint64_t seed, T* Q, int64_t ldq, int64_t sq, T* B,
-              int64_t ldb, int64_t sb, char* ws, const DiffLayout& L, hipStream_t s, int* host_flag) {
+              int64_t ldb, int64_t sb, char* ws, const DiffLayout& L, hipStream_t s, int* host_flag,
+              int32_t* dev_flag) {
     const int64_t bt = Ab->batch, m = Ab->m, n = Ab->n;
     const T* A = static_cast<const T*>(Ab->a);
     const int64_t lda = Ab->lda, sa = Ab->stride_a;
@@ -559,6 +751,10 @@ int fixed_fwd(const qb_batch* Ab, int64_t k, int b, uint64_t seed, T* Q, int64_t
         // B_i^T = S^T R_i^{-1}, written transposed into rows j0.. of B
         QB_DHIP(bgemm<T>(bt, n, b, b, BV<T>{S, b, 1, n * b}, BV<T>{Rii, b, 1, bb}, T(1), T(0), none,
                          BMV<T>{B + j0 * ldb, 1, ldb, sb}, s, SW));
+    }
+    if (dev_flag != nullptr) {   // stream-ordered report, no host wait
+        QB_DHIP(hipMemcpyAsync(dev_flag, flag, sizeof(int), hipMemcpyDeviceToDevice, s));
+        return QB_OK;
     }
     QB_DHIP(hipMemcpyAsync(host_flag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
     QB_DHIP(hipStreamSynchronize(s));
@@ -642,7 +838,7 @@ size_t qb_fixed_rank_workspace_bytes(const qb_batch* A, int64_t k, int32_t b) {
 
 int qb_fixed_rank_fwd(const qb_batch* A, int64_t k, int32_t b, uint64_t seed, void* Q, int64_t ldq,
                       int64_t stride_q, void* B, int64_t ldb, int64_t stride_b, void* ws,
-                      size_t ws_bytes, hipStream_t stream) {
+                      size_t ws_bytes, int32_t* breakdown, hipStream_t stream) {
     if (int st = check_batch(A, k, b)) return st;
     if (Q == nullptr || B == nullptr || ws == nullptr || ldq < k || ldb < A->n) return QB_ERR_ARG;
     if (A->batch > 1 && (stride_q < A->m * ldq || stride_b < k * ldb)) return QB_ERR_ARG;
@@ -654,11 +850,11 @@ int qb_fixed_rank_fwd(const qb_batch* A, int64_t k, int32_t b, uint64_t seed, vo
     if (A->dtype == QB_F32) {
         const DiffLayout L = diff_layout<float>(A->batch, A->m, A->n, k, b);
         st = fixed_fwd<float>(A, k, b, seed, static_cast<float*>(Q), ldq, stride_q, static_cast<float*>(B),
-                              ldb, stride_b, w, L, stream, &flag);
+                              ldb, stride_b, w, L, stream, &flag, breakdown);
     } else {
         const DiffLayout L = diff_layout<double>(A->batch, A->m, A->n, k, b);
         st = fixed_fwd<double>(A, k, b, seed, static_cast<double*>(Q), ldq, stride_q,
-                               static_cast<double*>(B), ldb, stride_b, w, L, stream, &flag);
+                               static_cast<double*>(B), ldb, stride_b, w, L, stream, &flag, breakdown);
     }
     if (st != QB_OK) return st;
     return flag ? QB_NOT_CONVERGED : QB_OK;

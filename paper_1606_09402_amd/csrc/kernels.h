@@ -135,6 +135,7 @@ hipError_t launch_spmm_csr(const int64_t* rowptr, const int32_t* colind, const d
 // 512 nonzeros, long rows reduced in segment order); built once per matrix per call.
 struct SpmmPlan {
     int64_t rows, smax, wmax;
+    int64_t nnz;
     int64_t* seg_off;    // rows + 1: exclusive prefix of segments per row (last = total)
     int64_t* mseg_off;   // rows + 1: exclusive prefix of the segments of multi-segment rows
     int32_t* seg_row;    // smax: row of each segment

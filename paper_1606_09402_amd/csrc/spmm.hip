@@ -72,7 +72,9 @@ __global__ void plan_fill_kernel(const int64_t* __restrict__ seg_off, int64_t ro
 }
 
 // Wavefront per segment: its nonzeros times the rows of X for the 256 columns of this
-// pass; a row with one segment is written to G, the segments of a longer row to P.
+// pass (4 per lane); a row with one segment is written to G, the segments of a longer row
+// to P.  Used for short rows, where the index loads of a segment dominate and wide passes
+// amortise them.
 __global__ void __launch_bounds__(kSpmmThreads)
 spmm_seg_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
                 const double* __restrict__ val, int64_t rows, const int64_t* __restrict__ seg_off,
@@ -102,6 +104,57 @@ spmm_seg_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ 
 #pragma unroll
     for (int t = 0; t < 4; ++t)
         if (ok[t]) out[64 * t] = acc[t];
+}
+
+// Wavefront per segment, over one slab of kSlab = 32 dense columns: the two half-waves take
+// alternate nonzeros of the segment (lane l: column c0 + l mod 32 of nonzeros e0 + l / 32,
+// + 2, ...), each keeping kUnroll gathers of X rows in flight, and are added at the end.  A
+// slab of X (32 columns of every row) is at most 128 MB for the matrices of this library's
+// sparse workload, so the slab in use stays resident in the last-level cache while its
+// segments are processed (all segments of a slab are dispatched before the next slab's); the
+// CSR arrays are re-read once per slab.  A row with one segment is written to G, the
+// segments of a longer row to P.
+constexpr int kSlab = 32;
+constexpr int kUnroll = 4;
+constexpr int64_t kLongRow = 16;
+__global__ void __launch_bounds__(kSpmmThreads)
+spmm_seg32_kernel(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
+                  const double* __restrict__ val, int64_t rows, const int64_t* __restrict__ seg_off,
+                  const int64_t* __restrict__ mseg_off, const int32_t* __restrict__ seg_row,
+                  const double* __restrict__ X, int64_t ldx, double* __restrict__ G, int64_t ldg,
+                  double* __restrict__ P, int64_t w) {
+    const int lane = threadIdx.x & 63, half = lane >> 5;
+    // the segment index is the same for the whole wave
+    const int64_t sg = static_cast<int64_t>(blockIdx.x) * (kSpmmThreads / 64) +
+                       __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (sg >= seg_off[rows]) return;
+    const int64_t row = seg_row[sg];
+    const int64_t q = sg - seg_off[row], ns = seg_off[row + 1] - seg_off[row];
+    const int64_t c = static_cast<int64_t>(blockIdx.y) * kSlab + (lane & 31);
+    const bool ok = c < w;
+    const int64_t cc = ok ? c : w - 1;   // columns past w re-read the last one (never stored)
+    const int64_t e0 = rowptr[row] + q * kSeg;
+    const int64_t e1 = e0 + kSeg < rowptr[row + 1] ? e0 + kSeg : rowptr[row + 1];
+    const double* xc = X + cc;
+    double acc = 0.0;
+    int64_t e = e0 + half;
+    for (; e + 2 * (kUnroll - 1) < e1; e += 2 * kUnroll) {
+        double v[kUnroll], x[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            v[u] = val[e + 2 * u];
+            x[u] = xc[static_cast<int64_t>(colind[e + 2 * u]) * ldx];
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) acc += v[u] * x[u];
+    }
+    for (; e < e1; e += 2) acc += val[e] * xc[static_cast<int64_t>(colind[e]) * ldx];
+    // even-indexed nonzeros (lanes 0..31) plus odd-indexed ones (lanes 32..63)
+    const double other = __shfl_down(acc, 32, 64);
+    if (half != 0 || !ok) return;
+    acc += other;
+    if (ns == 1) G[row * ldg + c] = acc;
+    else P[(mseg_off[row] + q) * w + c] = acc;
 }
 
 // Rows with several segments: G row = sum of the segment partials in segment order.
@@ -222,6 +275,7 @@ hipError_t spmm_plan_build(const int64_t* rowptr, int64_t rows, int64_t nnz, int
     int64_t* cnt_s = reinterpret_cast<int64_t*>(take(sizeof(int64_t) * (rows + 1)));
     int64_t* cnt_m = reinterpret_cast<int64_t*>(take(sizeof(int64_t) * (rows + 1)));
     plan->rows = rows;
+    plan->nnz = nnz;
     plan->smax = rows + nnz / kSeg + 1;
     plan->seg_off = reinterpret_cast<int64_t*>(take(sizeof(int64_t) * (rows + 1)));
     plan->mseg_off = reinterpret_cast<int64_t*>(take(sizeof(int64_t) * (rows + 1)));
@@ -249,11 +303,17 @@ hipError_t launch_spmm_plan(const SpmmPlan& plan, const int64_t* rowptr, const i
                             int64_t w, hipStream_t s) {
     if (plan.rows <= 0 || w <= 0) return hipSuccess;
     if (w > plan.wmax) return hipErrorInvalidValue;
-    const unsigned slabs = static_cast<unsigned>(cdiv(w, kSpmmCols));
-    dim3 grid(static_cast<unsigned>(cdiv(plan.smax, kSpmmThreads / 64)), slabs);
-    hipLaunchKernelGGL(spmm_seg_kernel, grid, dim3(kSpmmThreads), 0, s, rowptr, colind, val, plan.rows,
-                       plan.seg_off, plan.mseg_off, plan.seg_row, X, ldx, G, ldg, plan.P, w);
-    dim3 rgrid(static_cast<unsigned>(cdiv(plan.rows, kSpmmThreads / 64)), slabs);
+    if (plan.nnz >= kLongRow * plan.rows) {
+        dim3 grid(static_cast<unsigned>(cdiv(plan.smax, kSpmmThreads / 64)), static_cast<unsigned>(cdiv(w, kSlab)));
+        hipLaunchKernelGGL(spmm_seg32_kernel, grid, dim3(kSpmmThreads), 0, s, rowptr, colind, val, plan.rows,
+                           plan.seg_off, plan.mseg_off, plan.seg_row, X, ldx, G, ldg, plan.P, w);
+    } else {
+        dim3 grid(static_cast<unsigned>(cdiv(plan.smax, kSpmmThreads / 64)),
+                  static_cast<unsigned>(cdiv(w, kSpmmCols)));
+        hipLaunchKernelGGL(spmm_seg_kernel, grid, dim3(kSpmmThreads), 0, s, rowptr, colind, val, plan.rows,
+                           plan.seg_off, plan.mseg_off, plan.seg_row, X, ldx, G, ldg, plan.P, w);
+    }
+    dim3 rgrid(static_cast<unsigned>(cdiv(plan.rows, kSpmmThreads / 64)), static_cast<unsigned>(cdiv(w, kSpmmCols)));
     hipLaunchKernelGGL(spmm_seg_reduce_kernel, rgrid, dim3(kSpmmThreads), 0, s, plan.rows, plan.seg_off,
                        plan.mseg_off, plan.P, G, ldg, w);
     return hipGetLastError();

@@ -38,7 +38,9 @@ def _batch(m, n, kind, count, seed, dtype=torch.float64):
     return torch.stack([W.lowrank_dense(m, n, sig, seed + 7 * z) for z in range(count)]).to(dtype)
 
 
-@pytest.mark.parametrize("m,n,k,b,count", [(96, 64, 32, 16, 1), (300, 200, 48, 16, 3), (257, 190, 60, 20, 2)])
+# (300, 260, 128, 32, 2): the 128 x 128-tile products with a ragged row tile and K tail
+@pytest.mark.parametrize("m,n,k,b,count", [(96, 64, 32, 16, 1), (300, 200, 48, 16, 3), (257, 190, 60, 20, 2),
+                                           (300, 260, 128, 32, 2)])
 def test_fixed_rank_forward_f64(qb, m, n, k, b, count):
     _log(f"fixed-rank forward f64 {count} x {m}x{n} k={k} b={b}")
     A = _batch(m, n, "exp40", count, 401)
@@ -53,7 +55,7 @@ def test_fixed_rank_forward_f64(qb, m, n, k, b, count):
         assert np.max(np.abs(Q[z].T @ Q[z] - np.eye(k))) <= 1e-12
 
 
-@pytest.mark.parametrize("m,n,k,b,count", [(96, 64, 32, 16, 1), (300, 200, 48, 16, 3)])
+@pytest.mark.parametrize("m,n,k,b,count", [(96, 64, 32, 16, 1), (300, 200, 48, 16, 3), (300, 260, 128, 32, 2)])
 def test_fixed_rank_backward_f64(qb, m, n, k, b, count):
     _log(f"fixed-rank backward f64 {count} x {m}x{n} k={k} b={b}")
     A = _batch(m, n, "exp40", count, 402)
@@ -71,6 +73,27 @@ def test_fixed_rank_backward_f64(qb, m, n, k, b, count):
     dA_q = qb.qb_fixed_rank_bwd(Ad, k, b, SEED, Q, dQ.cuda(), None).cpu().numpy()
     dA_b = qb.qb_fixed_rank_bwd(Ad, k, b, SEED, Q, None, dB.cuda()).cpu().numpy()
     assert np.allclose(dA_q + dA_b, dA, atol=1e-12 * np.linalg.norm(dA))
+
+
+def test_breakdown_flag_without_host_wait(qb):
+    """The forward with a device breakdown flag: same Q, B bits as the waiting call and flag 0
+    on a full-rank batch; flag 1 (and the waiting call's QB_NOT_CONVERGED) when A Omega is
+    rank deficient at rank k (A of rank 10, k = 32)."""
+    A = _batch(300, 200, "exp40", 3, 404).cuda()
+    flag = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+    Q1, B1 = qb.qb_fixed_rank_fwd(A, 48, 16, SEED, breakdown=flag)
+    Q0, B0 = qb.qb_fixed_rank_fwd(A, 48, 16, SEED)
+    torch.cuda.synchronize()
+    assert flag.item() == 0
+    assert torch.equal(Q0, Q1) and torch.equal(B0, B1)
+    rs = np.random.default_rng(13)
+    low = torch.tensor(rs.standard_normal((1, 200, 10)) @ rs.standard_normal((1, 10, 120))).cuda()
+    flag.fill_(-1)
+    qb.qb_fixed_rank_fwd(low, 32, 16, SEED, breakdown=flag)
+    torch.cuda.synchronize()
+    assert flag.item() == 1
+    with pytest.raises(qb.QBError):
+        qb.qb_fixed_rank_fwd(low, 32, 16, SEED)
 
 
 def _gpu_loss_grad(qb, A, k, b):
