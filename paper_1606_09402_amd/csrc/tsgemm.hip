@@ -274,12 +274,18 @@ QB_DEV void ts_dma16_nt(const double* base, uint32_t off, uint32_t lds) {
                  : "memory", "m0");
 }
 
-template <int FM, int D>
+// VC: N = 16 FNM + 2 with the last two columns on the vector ALU -- lane l accumulates
+// C(r0 + l mod 32, 16 FNM + l / 32) from the A and B tiles already in LDS -- instead of a
+// fourth MFMA column block that would be seven-eighths padding (FM == 2; accf[FM * 16]).
+template <int FM, int D, int FNM, bool VC>
 QB_DEV void ts_panel_dma_body(const TsArgs& g, int64_t r0, int64_t kw, int64_t nst, int64_t ke,
-                              uint32_t ring, const char* ring_ptr, double (&accf)[FM * 16]) {
+                              uint32_t ring, const char* ring_ptr, double (&accf)[FM * 16 + 1]) {
     using L = PanelDma<FM>;
     static_assert(FM == 2 || FM == 4, "DMA panel tiles");
+    static_assert(!VC || (FM == 2 && FNM < 4), "vector-ALU columns need 32-row tiles");
     const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+    const int vr = lane & 31, vc = 16 * FNM + (lane >> 5);   // this lane's vector-ALU output
+    double accv = 0.0;
     const int64_t nfull = nst > 0 && kw + 4 * nst > ke ? nst - 1 : nst;
     // per-lane DMA source offsets (bytes) from A(r0, kcol) and B(kcol, 0)
     uint32_t aoff[FM / 2], boff[2];
@@ -328,12 +334,23 @@ QB_DEV void ts_panel_dma_body(const TsArgs& g, int64_t r0, int64_t kw, int64_t n
             av[2 * h + 1] = x.y;
         }
 #pragma unroll
-        for (int fn = 0; fn < 4; ++fn)
+        for (int fn = 0; fn < FNM; ++fn)
             bv[fn] = *reinterpret_cast<const double*>(st + L::A_BYTES + 8 * (lk * 64 + 16 * fn + li));
 #pragma unroll
-        for (int fn = 0; fn < 4; ++fn)
+        for (int fn = 0; fn < FNM; ++fn)
 #pragma unroll
             for (int f = 0; f < FM; ++f) acc[f][fn] = ts_mfma(av[f], bv[fn], acc[f][fn]);
+        if constexpr (VC) {
+            // A(vr, k) sits at byte 256 k + 8 vr of the 32-row stage, B(k, vc) at row k of B's
+            double xa[4], xb[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                xa[k] = *reinterpret_cast<const double*>(st + 256 * k + 8 * vr);
+                xb[k] = *reinterpret_cast<const double*>(st + L::A_BYTES + 8 * (k * 64 + vc));
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) accv = fma(xa[k], xb[k], accv);
+        }
         asm volatile("" ::: "memory");
         // the slot of step t - 1 is free: its operands were consumed by the MFMAs above's
         // predecessors (their LDS reads completed before those MFMAs issued)
@@ -348,14 +365,19 @@ QB_DEV void ts_panel_dma_body(const TsArgs& g, int64_t r0, int64_t kw, int64_t n
 #pragma unroll
         for (int e = 0; e < FM; ++e) av[e] = g.A[kc * g.lda + il + e];
 #pragma unroll
-        for (int fn = 0; fn < 4; ++fn) {
+        for (int fn = 0; fn < FNM; ++fn) {
             const int64_t j = 16 * fn + li < g.N ? 16 * fn + li : g.N - 1;
             bv[fn] = v ? g.B[kc * g.bsk + j] : 0.0;
         }
 #pragma unroll
-        for (int fn = 0; fn < 4; ++fn)
+        for (int fn = 0; fn < FNM; ++fn)
 #pragma unroll
             for (int f = 0; f < FM; ++f) acc[f][fn] = ts_mfma(av[f], bv[fn], acc[f][fn]);
+        if constexpr (VC) {
+            const int64_t k0 = kw + 4 * nfull;
+            for (int k = 0; k < 4; ++k)
+                if (k0 + k < ke) accv = fma(g.A[(k0 + k) * g.lda + r0 + vr], g.B[(k0 + k) * g.bsk + vc], accv);
+        }
     }
 #pragma unroll
     for (int f = 0; f < FM; ++f)
@@ -363,12 +385,13 @@ QB_DEV void ts_panel_dma_body(const TsArgs& g, int64_t r0, int64_t kw, int64_t n
         for (int fn = 0; fn < 4; ++fn)
 #pragma unroll
             for (int r = 0; r < 4; ++r) accf[(f * 4 + fn) * 4 + r] = acc[f][fn][r];
+    accf[FM * 16] = accv;
 }
 
-template <int FM, int WK, int D>
+template <int FM, int WK, int D, int FNM, bool VC>
 __global__ void __launch_bounds__(64 * WK) ts_panel_dma_kernel(const TsArgs g) {
     if (g.gate != nullptr && *g.gate != 0) return;
-    constexpr int NACC = FM * 16;
+    constexpr int NACC = FM * 16 + 1;
     constexpr int RING = WK * D * PanelDma<FM>::STAGE;
     constexpr int RED = (WK > 1 ? WK - 1 : 0) * NACC * 64 * 8;
     __shared__ __align__(16) char lds[RING > RED ? RING : RED];
@@ -385,13 +408,20 @@ __global__ void __launch_bounds__(64 * WK) ts_panel_dma_kernel(const TsArgs g) {
     const char* ring_ptr = lds + wave * D * PanelDma<FM>::STAGE;
     const uint32_t ring = __builtin_amdgcn_readfirstlane(
         static_cast<uint32_t>(reinterpret_cast<uintptr_t>((ts_lds_ptr)ring_ptr)));
-    if (r0 + 16 * FM <= g.M)
-        ts_panel_dma_body<FM, D>(g, r0, kb + 4 * t0, t1 - t0, ke, ring, ring_ptr, acc);
-    else
-        ts_panel_body<FM, WK, 2, true>(g, r0, kb + 4 * t0, t1 - t0, ke, acc);   // the one edge tile
+    const bool full = r0 + 16 * FM <= g.M;
+    if (full) {
+        ts_panel_dma_body<FM, D, FNM, VC>(g, r0, kb + 4 * t0, t1 - t0, ke, ring, ring_ptr, acc);
+    } else {   // the one edge tile: every column on MFMA
+        double a16[FM * 16];
+        ts_panel_body<FM, WK, 2, true>(g, r0, kb + 4 * t0, t1 - t0, ke, a16);
+#pragma unroll
+        for (int x = 0; x < FM * 16; ++x) acc[x] = a16[x];
+        acc[FM * 16] = 0.0;
+    }
     if (WK > 1) __syncthreads();   // every wave is done with its ring before it is reused
     ts_wave_reduce<NACC, WK>(reinterpret_cast<double*>(lds), acc, wave, lane);
     if (wave != 0) return;
+    const int64_t jmfma = VC && full ? 16 * FNM : g.N;   // columns written from the MFMA tiles
 #pragma unroll
     for (int f = 0; f < FM; ++f)
 #pragma unroll
@@ -400,8 +430,9 @@ __global__ void __launch_bounds__(64 * WK) ts_panel_dma_kernel(const TsArgs g) {
             for (int r = 0; r < 4; ++r) {
                 const int64_t i = r0 + FM * ((r << 2) + lk) + f;
                 const int64_t j = 16 * fn + li;
-                if (i < g.M && j < g.N) ts_store(g, split, i, j, acc[(f * 4 + fn) * 4 + r]);
+                if (i < g.M && j < jmfma) ts_store(g, split, i, j, acc[(f * 4 + fn) * 4 + r]);
             }
+    if (VC && full) ts_store(g, split, r0 + (lane & 31), 16 * FNM + (lane >> 5), acc[FM * 16]);
 }
 
 // ------------------------------------------------------------------ reduction form
@@ -595,8 +626,14 @@ static hipError_t launch_panel_dma(TsArgs g, int nsplit, hipStream_t s) {
     g.tiles = static_cast<int>(cdiv(g.M, 16 * FM));
     g.kchunk = cdiv(cdiv(g.K, nsplit), 4) * 4;
     g.nsplit = static_cast<int>(cdiv(g.K, g.kchunk));
-    hipLaunchKernelGGL((ts_panel_dma_kernel<FM, WK, D>), dim3(static_cast<unsigned>(g.tiles * g.nsplit)),
-                       dim3(64 * WK), 0, s, g);
+    const dim3 grid(static_cast<unsigned>(g.tiles * g.nsplit));
+    if constexpr (FM == 2) {
+        if (g.N == 50) {   // 48 columns on MFMA, two on the vector ALU
+            hipLaunchKernelGGL((ts_panel_dma_kernel<FM, WK, D, 3, true>), grid, dim3(64 * WK), 0, s, g);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((ts_panel_dma_kernel<FM, WK, D, 4, false>), grid, dim3(64 * WK), 0, s, g);
     return hipGetLastError();
 }
 
