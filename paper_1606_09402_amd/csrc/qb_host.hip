@@ -816,6 +816,7 @@ int run(int algo, Op& A, const qb_params* p, double* Q, int64_t ldq, double* B, 
         bool stop = false;
         bool redo_hh = false;     // the block at row k broke down in CholeskyQR: redo it by Householder
         double dec = 0.0;         // the indicator's drop per block over the last run of blocks
+        double ratio = 0.0;       // and its ratio per block (geometric mean)
         while (k < lmax && !stop) {
             if (algo == QB_ALGO_FP && k == chunk_hi) {
                 // draw the next chunk of Omega; G = A Omega, H = A^T G
@@ -848,16 +849,24 @@ int run(int algo, Op& A, const qb_params* p, double* Q, int64_t ldq, double* B, 
             }
             // Blocks are enqueued ahead of the stopping decision, which the device takes
             // (scan_block) and the host reads back once per run of blocks.  A run never
-            // crosses a chunk end, and holds about as many blocks as the last drop of the
-            // indicator per block says cannot reach eps^2 (at most kLookahead), so that few
-            // blocks run past the stop; the products of blocks past it are skipped by the gate.
+            // crosses a chunk end, and holds (at most kLookahead) as many blocks as the last
+            // run's indicator says are still needed: block t of the run is needed unless the
+            // indicator is below eps^2 after t blocks, predicted both with the last run's
+            // drop per block (linear decay) and with its ratio per block (geometric decay,
+            // the rule for a geometrically decaying spectrum, where the linear prediction
+            // would allow one block per run), the larger of the two.  Few blocks run past
+            // the stop; their products are skipped by the gate.
             // randQB_EI runs one block at a time: a block redone after a CholeskyQR breakdown
             // reuses its A Omega_i, which the next block's product would overwrite.
             const int64_t k_end = algo == QB_ALGO_FP ? chunk_hi : lmax;
             int nrun = 1;
             if (algo == QB_ALGO_FP && !redo_hh && dec > 0.0) {
-                const double r = floor((E - eps2) / dec);
-                nrun = r >= kLookahead ? kLookahead : (r >= 1.0 ? static_cast<int>(r) : 1);
+                double t = floor((E - eps2) / dec) + 1.0;
+                if (ratio > 0.0 && ratio < 1.0 && E > eps2) {
+                    const double tg = floor(log(E / eps2) / log(1.0 / ratio)) + 1.0;
+                    if (tg > t) t = tg;
+                }
+                nrun = t >= kLookahead ? kLookahead : (t >= 1.0 ? static_cast<int>(t) : 1);
             }
             int64_t ks = k;
             for (int t = 0; t < nrun && ks < k_end; ++t) {
@@ -908,6 +917,7 @@ int run(int algo, Op& A, const qb_params* p, double* Q, int64_t ldq, double* B, 
                 // indicator drop per block over the blocks of this run
                 const int first = scanned;
                 dec = (E - hs.E) / static_cast<double>(hs.blocks - first);
+                ratio = E > 0.0 && hs.E > 0.0 ? pow(hs.E / E, 1.0 / static_cast<double>(hs.blocks - first)) : 0.0;
                 if (algo == QB_ALGO_FP && k < k_half && hs.k >= k_half) {
                     // the indicator at the end of the block that ends at k_half
                     const int nb = hs.blocks - first;
