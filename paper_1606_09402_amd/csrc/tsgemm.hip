@@ -442,9 +442,13 @@ __global__ void __launch_bounds__(64 * WK) ts_panel_dma_kernel(const TsArgs g) {
 // rows; its reduction range (one split) is cut into groups of 16 indices shared out to its WV
 // waves in contiguous runs.  Each lane loads, per group, 4 consecutive reduction indices of its
 // FM rows of A and of its 4 columns of B; D groups are kept in flight.
-template <int FM, int D, bool BK1>
+// VC: N = 16 FNM + 2 with the last two columns on the vector ALU: lane (i, q) multiplies its
+// rows' A values by the B values of those two columns, which lanes (0, q) and (1, q) already
+// hold in their fourth column block (exchanged by a lane permute), and the four partial sums
+// of a row are added across q at the end (accf[FM * 16 + 2 f + c]).
+template <int FM, int D, bool BK1, int FNM, bool VC>
 QB_DEV void ts_red_body(const TsArgs& g, int64_t i0, int64_t kw, int64_t ngr, int64_t ke,
-                        double (&accf)[FM * 16]) {
+                        double (&accf)[FM * 16 + (VC ? 2 * FM : 0)]) {
     const int lane = threadIdx.x & 63, li = lane & 15, lq = lane >> 4;
     // groups [0, nfull) lie inside the reduction range; a last group that crosses ke is done
     // apart with masked loads
@@ -500,13 +504,28 @@ QB_DEV void ts_red_body(const TsArgs& g, int64_t i0, int64_t kw, int64_t ngr, in
     for (int f = 0; f < FM; ++f)
 #pragma unroll
         for (int fn = 0; fn < 4; ++fn) acc[f][fn] = v4d{0.0, 0.0, 0.0, 0.0};
+    double pv[FM][2];
+#pragma unroll
+    for (int f = 0; f < FM; ++f) pv[f][0] = pv[f][1] = 0.0;
     auto group = [&](const double (&av)[FM][4], const double (&bv)[4][4]) {
 #pragma unroll
         for (int s = 0; s < 4; ++s)
 #pragma unroll
-            for (int fn = 0; fn < 4; ++fn)
+            for (int fn = 0; fn < FNM; ++fn)
 #pragma unroll
                 for (int f = 0; f < FM; ++f) acc[f][fn] = ts_mfma(av[f][s], bv[fn][s], acc[f][fn]);
+        if constexpr (VC) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const double x0 = __shfl(bv[FNM][s], (lane & 48) | 0, 64);
+                const double x1 = __shfl(bv[FNM][s], (lane & 48) | 1, 64);
+#pragma unroll
+                for (int f = 0; f < FM; ++f) {
+                    pv[f][0] = fma(av[f][s], x0, pv[f][0]);
+                    pv[f][1] = fma(av[f][s], x1, pv[f][1]);
+                }
+            }
+        }
     };
     if (nfull > 0) {
         auto k0 = [&](int64_t u) { return kw + 16 * (u < nfull ? u : nfull - 1); };
@@ -561,12 +580,23 @@ QB_DEV void ts_red_body(const TsArgs& g, int64_t i0, int64_t kw, int64_t ngr, in
         for (int fn = 0; fn < 4; ++fn)
 #pragma unroll
             for (int r = 0; r < 4; ++r) accf[(f * 4 + fn) * 4 + r] = acc[f][fn][r];
+    if constexpr (VC) {
+#pragma unroll
+        for (int f = 0; f < FM; ++f)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                double v = pv[f][c];
+                v += __shfl_xor(v, 16, 64);
+                v += __shfl_xor(v, 32, 64);
+                accf[FM * 16 + 2 * f + c] = v;
+            }
+    }
 }
 
-template <int FM, int WV, int D, bool BK1>
+template <int FM, int WV, int D, bool BK1, int FNM, bool VC>
 __global__ void __launch_bounds__(64 * WV) ts_red_kernel(const TsArgs g) {
     if (g.gate != nullptr && *g.gate != 0) return;
-    constexpr int NACC = FM * 16;
+    constexpr int NACC = FM * 16 + (VC ? 2 * FM : 0);
     __shared__ double red[(WV > 1 ? WV - 1 : 1) * NACC * 64];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
@@ -581,9 +611,10 @@ __global__ void __launch_bounds__(64 * WV) ts_red_kernel(const TsArgs g) {
     const int64_t groups = (ke - kb + 15) / 16;
     const int64_t u0 = groups * wave / WV, u1 = groups * (wave + 1) / WV;
     double acc[NACC];
-    ts_red_body<FM, D, BK1>(g, i0, kb + 16 * u0, u1 - u0, ke, acc);
+    ts_red_body<FM, D, BK1, FNM, VC>(g, i0, kb + 16 * u0, u1 - u0, ke, acc);
     ts_wave_reduce<NACC, WV>(red, acc, wave, lane);
     if (wave != 0) return;
+    const int64_t jmfma = VC ? 16 * FNM : g.N;   // columns written from the MFMA tiles
 #pragma unroll
     for (int f = 0; f < FM; ++f)
 #pragma unroll
@@ -592,8 +623,19 @@ __global__ void __launch_bounds__(64 * WV) ts_red_kernel(const TsArgs g) {
             for (int r = 0; r < 4; ++r) {
                 const int64_t i = i0 + 16 * f + (r << 2) + lq;
                 const int64_t j = 16 * fn + li;
-                if (i < g.M && j < g.N) ts_store(g, split, i, j, acc[(f * 4 + fn) * 4 + r]);
+                if (i < g.M && j < jmfma) ts_store(g, split, i, j, acc[(f * 4 + fn) * 4 + r]);
             }
+    if constexpr (VC) {
+        if (lq == 0) {
+#pragma unroll
+            for (int f = 0; f < FM; ++f)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const int64_t i = i0 + 16 * f + li, j = 16 * FNM + c;
+                    if (i < g.M && j < g.N) ts_store(g, split, i, j, acc[FM * 16 + 2 * f + c]);
+                }
+        }
+    }
 }
 
 // ------------------------------------------------------------------ host
@@ -642,8 +684,14 @@ static hipError_t launch_red(TsArgs g, int nsplit, hipStream_t s) {
     g.tiles = static_cast<int>(cdiv(g.M, 16 * FM));
     g.kchunk = cdiv(cdiv(g.K, nsplit), 16) * 16;
     g.nsplit = static_cast<int>(cdiv(g.K, g.kchunk));
-    hipLaunchKernelGGL((ts_red_kernel<FM, WV, D, BK1>), dim3(static_cast<unsigned>(g.tiles * g.nsplit)),
-                       dim3(64 * WV), 0, s, g);
+    const dim3 grid(static_cast<unsigned>(g.tiles * g.nsplit));
+    if constexpr (FM == 4) {
+        if (g.N == 50) {   // 48 columns on MFMA, two on the vector ALU
+            hipLaunchKernelGGL((ts_red_kernel<FM, WV, D, BK1, 3, true>), grid, dim3(64 * WV), 0, s, g);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((ts_red_kernel<FM, WV, D, BK1, 4, false>), grid, dim3(64 * WV), 0, s, g);
     return hipGetLastError();
 }
 
