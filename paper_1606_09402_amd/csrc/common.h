@@ -25,6 +25,33 @@ struct MutView {
     int64_t si, sj;
 };
 
+// sqrt(x) and 1 / sqrt(x) for a positive normal x: the hardware reciprocal square root
+// (about 23 correct bits) refined by two coupled Newton steps of Goldschmidt's iteration,
+// g -> sqrt(x) and h -> 1 / (2 sqrt(x)), each step doubling the correct bits.  One short
+// dependent chain gives both values (no separate division for 1 / R(j, j)).
+QB_DEV void sqrt_and_rsqrt(double x, double& g, double& ir) {
+    const double y = __builtin_amdgcn_rsq(x);
+    g = x * y;
+    double h = 0.5 * y;
+    double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    ir = 2.0 * h;
+}
+
+// 1 / x for a normal x: the hardware reciprocal refined by two Newton steps (each step
+// doubles the correct bits).
+QB_DEV double rcp_refined(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a contiguous range
 // of logical tiles so that tiles sharing an operand row-slab share one L2.
 QB_DEV int xcd_remap(int wg, int nwg) {

@@ -177,10 +177,14 @@ hipError_t launch_qrcp_rs(const double* St, int l, const int* piv, int bw, doubl
 hipError_t launch_gather_cols(const double* X, int64_t ldx, int64_t rows, const int* piv, int bw,
                               double* Y, int64_t ldy, hipStream_t s);
 
-// svd.hip -- one-sided Jacobi SVD of a k x k factor (circle ordering) and its outputs
-int jacobi_players(int k);
-hipError_t launch_jacobi_round(double* X, double* W, int k, int64_t ld, int round, double tol,
-                               int* flag, hipStream_t s);
+// svd.hip -- block one-sided Jacobi SVD of a k x k factor (circle ordering over blocks of
+// 32 columns) and its outputs
+int jacobi_rounds(int k);
+size_t jacobi_part_elems(int k);
+size_t jacobi_rot_elems(int k);
+hipError_t launch_jacobi_block_round(double* X, double* W, int k, int64_t ld, int round, double tol_r,
+                                     double tol_c, int inner, double* part, double* V, int* skip,
+                                     int* flag, hipStream_t s);
 hipError_t launch_svd_finish(const double* X, const double* W, int k, int64_t ld, double* sig,
                              int* pos, double* s_out, double* Ut, double* Ws, hipStream_t s);
 hipError_t launch_sign_rule(double* V, int64_t n, int64_t ldv, double* Ut, int k, int64_t ldu,

@@ -152,23 +152,6 @@ QB_DEV double readlane_d(double x, int lane) {
     return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
 }
 
-// sqrt(x) and 1 / sqrt(x) for a positive normal x: the hardware reciprocal square root
-// (about 23 correct bits) refined by two coupled Newton steps of Goldschmidt's iteration,
-// g -> sqrt(x) and h -> 1 / (2 sqrt(x)), each step doubling the correct bits.  One short
-// dependent chain gives both values (no separate division for 1 / R(j, j)).
-QB_DEV void sqrt_and_rsqrt(double x, double& g, double& ir) {
-    const double y = __builtin_amdgcn_rsq(x);
-    g = x * y;
-    double h = 0.5 * y;
-    double r = fma(-g, h, 0.5);
-    g = fma(g, r, g);
-    h = fma(h, r, h);
-    r = fma(-g, h, 0.5);
-    g = fma(g, r, g);
-    h = fma(h, r, h);
-    ir = 2.0 * h;
-}
-
 // Gram (b x b, row-major, only the upper triangle is read) -> R upper (row-major, zero below
 // the diagonal) with Gram = R^T R, and Rinv = R^{-1}; flag[0] = 1 if some pivot is not above
 // tau * max_i Gram(i, i).  One workgroup of 256 threads.  The matrix, padded with the

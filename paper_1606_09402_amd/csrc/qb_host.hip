@@ -1133,9 +1133,10 @@ int qrcp_run(const qb_dense* Ad, const qb_params* p, int oversample, double* Q, 
 }
 
 // Workspace of the SVD from QB: P (n x k, the orthonormalised B^T), T / X (k x k), the
-// rotations W, the sorted Ut and Ws (k x k each), the values and their order, and the
-// buffers of orth_panel (128-column panels of n rows, k x 128 projections, 128 x 128
-// factors, split-K partials).
+// rotations W, the sorted Ut and Ws (k x k each), the values and their order, the block
+// Jacobi's partial Gram matrices, pair rotations and skip flags, and the buffers of
+// orth_panel (128-column panels of n rows, k x 128 projections, 128 x 128 factors, split-K
+// partials).
 Layout svd_layout(int64_t m, int64_t n, int64_t k) {
     Layout L{};
     const int64_t pb = kPowerBlock;
@@ -1154,6 +1155,9 @@ Layout svd_layout(int64_t m, int64_t n, int64_t k) {
     L.d = take(sizeof(double) * k * k);    // Ws
     L.gnorm2 = take(sizeof(double) * k);   // column norms
     L.info = take(sizeof(int) * k);        // order
+    L.w = take(sizeof(double) * jacobi_part_elems(static_cast<int>(k)));   // pair Gram partials
+    L.ri = take(sizeof(double) * jacobi_rot_elems(static_cast<int>(k)));   // pair rotations
+    L.rowsq = take(sizeof(int) * (jacobi_rot_elems(static_cast<int>(k)) + 1));   // skip flags
     L.y = take(sizeof(double) * n * pb);
     L.x2 = take(sizeof(double) * n * pb);
     L.z = take(sizeof(double) * k * pb);
@@ -1171,6 +1175,7 @@ Layout svd_layout(int64_t m, int64_t n, int64_t k) {
 }
 
 constexpr int kMaxSweeps = 40;
+constexpr int kJacobiInner = 1;   // two-sided Jacobi sweeps on each pair's Gram matrix per round
 
 int svd_from_qb(int64_t m, int64_t n, int64_t k, const double* Q, int64_t ldq, const double* B,
                 int64_t ldb, double* U, int64_t ldu, double* sv, double* V, int64_t ldv, void* ws,
@@ -1212,16 +1217,26 @@ int svd_from_qb(int64_t m, int64_t n, int64_t k, const double* Q, int64_t ldq, c
                            MutView{T, k, 1}, x);
         QB_HIP(gemm_f64(d, s));
     }
-    // one-sided Jacobi on X = T^T (column-major: the same storage as row-major T)
+    // block one-sided Jacobi on X = T^T (column-major: the same storage as row-major T).
+    // Pairs rotate at cosines above tol = 16 sqrt(k) u, and the sweeps end after one in
+    // which none did.  (The usual one-sided threshold is sqrt(k) u; a block rotation
+    // applied as one product of 2 kJb columns leaves cosines of a few u sqrt(2 kJb) of its
+    // own, so the threshold sits above that floor.)
     QB_HIP(launch_identity(W, ki, k, s));
-    const double tol = sqrt(static_cast<double>(k)) * kUnitRoundoff;
-    const int rounds = jacobi_players(ki) - 1;
+    const double tol_r = 16.0 * sqrt(static_cast<double>(k)) * kUnitRoundoff;
+    const double tol_c = tol_r;
+    const int rounds = jacobi_rounds(ki);
+    double* jpart = x.at<double>(L.w);
+    double* jrot = x.at<double>(L.ri);
+    int* jskip = x.at<int>(L.rowsq);
     int st = QB_NOT_CONVERGED;
     int sweeps = 0;
     int* hflag = reinterpret_cast<int*>(host + 3 * kMaxB);
     while (sweeps < kMaxSweeps) {
         QB_HIP(launch_fill_int(flags + 1, 1, 0, s));
-        for (int r = 0; r < rounds; ++r) QB_HIP(launch_jacobi_round(T, W, ki, k, r, tol, flags + 1, s));
+        for (int r = 0; r < rounds; ++r)
+            QB_HIP(launch_jacobi_block_round(T, W, ki, k, r, tol_r, tol_c, kJacobiInner, jpart, jrot, jskip,
+                                             flags + 1, s));
         ++sweeps;
         QB_HIP(hipMemcpyAsync(hflag, flags + 1, sizeof(int), hipMemcpyDeviceToHost, s));
         QB_HIP(hipStreamSynchronize(s));

@@ -3,15 +3,15 @@
 // a one-sided Jacobi SVD of the k x k factor X = T^T.  One-sided Jacobi (Hestenes) rotates
 // pairs of columns of X until all are mutually orthogonal: the column norms are then the
 // singular values, the normalised columns the left singular vectors, and the accumulated
-// rotations W the right singular vectors of X.  Rounds follow the circle ordering, so the
-// k/2 pairs of a round are disjoint and run as one launch, a workgroup per pair.  Every
-// sum is taken in a fixed order (bit-reproducible results).
+// rotations W the right singular vectors of X.  The method works on blocks of columns
+// (below): a round of the circle ordering over the blocks is three launches, whatever the
+// block width, instead of one launch per round over single columns.  Every sum is taken in
+// a fixed order (bit-reproducible results).
 #include "kernels.h"
 
 namespace qb {
 
 constexpr int kSvdThreads = 256;
-constexpr int kRegK = 8;   // columns of up to kRegK * 256 rows are held in registers
 
 // Fixed-order sum over the workgroup of three values at once.
 QB_DEV void block_sum3(double& a, double& b, double& c, double (*sh)[kSvdThreads / 64]) {
@@ -46,85 +46,352 @@ QB_DEV void circle_pair(int np, int r, int p, int& a, int& b) {
     b = 1 + (r + m - 1 - p) % m;
 }
 
-// One round: workgroup p rotates its pair of columns of X (and of W) when their cosine
-// exceeds tol; flag is set to 1 if any pair rotated.
+// Block form.  The columns of X are cut into blocks of kJb (the last one ragged; an odd
+// count gets an empty dummy block), and the circle ordering runs over the blocks: a round
+// pairs them into disjoint pairs of 2 kJb columns.  For each pair the round forms the Gram
+// matrix of its columns (pair_gram_kernel, split over the rows, partial sums added in split
+// order), finds the rotations that diagonalise it by cyclic two-sided Jacobi in LDS
+// (pair_eig_kernel: the rotation of columns p, q is the one the column pair itself would
+// get, read off the Gram entries), and applies their product V to the pair's columns of X
+// and of W (pair_apply_kernel).  The Gram matrix is formed afresh from X in every round, so
+// its rounding does not accumulate; the pair test of the next sweep measures the cosine of
+// each column pair from fresh dot products, as the scalar method does.
+constexpr int kJb = 32;            // columns per block
+constexpr int kJp = 2 * kJb;       // columns per pair of blocks
+constexpr int kJrows = 64;         // rows per LDS tile (Gram and apply)
+constexpr int kGramTiles = 2;      // tiles per Gram split
+
+// Column of X that slot j (0 .. kJp-1) of the pair of blocks (a, b) holds, or -1.
+QB_DEV int pair_col(int a, int b, int nb, int j, int k) {
+    const int blk = j < kJb ? a : b;
+    if (blk >= nb) return -1;
+    const int c = blk * kJb + (j & (kJb - 1));
+    return c < k ? c : -1;
+}
+
+// The pair's tile of rows [r0, r0 + kJrows): element (row r, slot j) of X, zero outside X
+// or for an empty slot, stored at xs[j * SJ + r * SR] in LDS.  Thread t holds row
+// r0 + (t mod 64) of slots t / 64 + 4 q; its 16 loads are all issued before the first
+// LDS store.
+template <int SJ, int SR>
+QB_DEV void stage_pair_tile(const double* __restrict__ X, int k, int64_t ld, int a, int b, int nb, int r0,
+                            double* xs) {
+    constexpr int kPer = kJp * kJrows / kSvdThreads;
+    const int r = static_cast<int>(threadIdx.x) & (kJrows - 1);
+    const int j0 = static_cast<int>(threadIdx.x) / kJrows;
+    const int row = r0 + r;
+    double v[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int c = pair_col(a, b, nb, j0 + q * (kSvdThreads / kJrows), k);
+        v[q] = (c >= 0 && row < k) ? X[static_cast<int64_t>(c) * ld + row] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) xs[(j0 + q * (kSvdThreads / kJrows)) * SJ + r * SR] = v[q];
+}
+
+// Partial Gram matrix of rows [R y, R (y + 1)), R = kGramTiles kJrows, of the pair's columns:
+// part[(pair * nsplit + y) * kJp^2 + i * kJp + j].  A thread owns a 4 x 4 block; entry
+// (i, j) and (j, i) take the same products in the same order, so the sum is symmetric.
 __global__ void __launch_bounds__(kSvdThreads)
-jacobi_round_kernel(double* __restrict__ X, double* __restrict__ W, int k, int64_t ld, int np,
-                    int round, double tol, int* __restrict__ flag) {
-    __shared__ double sh[3][kSvdThreads / 64];
+pair_gram_kernel(const double* __restrict__ X, int k, int64_t ld, int nb, int np, int round,
+                 int nsplit, double* __restrict__ part) {
+    constexpr int kPitch = kJp + 2;   // rows of the tile, 16-byte aligned
+    __shared__ __align__(16) double xs[kJrows * kPitch];
     int a, b;
     circle_pair(np, round, static_cast<int>(blockIdx.x), a, b);
-    if (a >= k || b >= k) return;   // the dummy player of an odd k (uniform per workgroup)
-    if (a > b) {
-        const int t = a;
-        a = b;
-        b = t;
+    const int ti = static_cast<int>(threadIdx.x) >> 4, tj = static_cast<int>(threadIdx.x) & 15;
+    double acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    for (int tile = 0; tile < kGramTiles; ++tile) {
+        const int r0 = (static_cast<int>(blockIdx.y) * kGramTiles + tile) * kJrows;
+        if (tile > 0) __syncthreads();
+        stage_pair_tile<1, kPitch>(X, k, ld, a, b, nb, r0, xs);
+        __syncthreads();
+#pragma unroll 4
+        for (int r = 0; r < kJrows; ++r) {
+            const double2 u01 = *reinterpret_cast<const double2*>(xs + r * kPitch + 4 * ti);
+            const double2 u23 = *reinterpret_cast<const double2*>(xs + r * kPitch + 4 * ti + 2);
+            const double2 v01 = *reinterpret_cast<const double2*>(xs + r * kPitch + 4 * tj);
+            const double2 v23 = *reinterpret_cast<const double2*>(xs + r * kPitch + 4 * tj + 2);
+            const double u[4] = {u01.x, u01.y, u23.x, u23.y};
+            const double v[4] = {v01.x, v01.y, v23.x, v23.y};
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = fma(u[i], v[j], acc[i][j]);
+        }
     }
-    double* xa = X + static_cast<int64_t>(a) * ld;
-    double* xb = X + static_cast<int64_t>(b) * ld;
-    double* wa = W + static_cast<int64_t>(a) * ld;
-    double* wb = W + static_cast<int64_t>(b) * ld;
-    if (k <= kRegK * kSvdThreads) {
-        // the pair's columns of X and W are read once, into registers, before the decision,
-        // so that the rotation needs no second trip to memory
-        double u[kRegK], v[kRegK], p[kRegK], q[kRegK];
-        double al = 0.0, be = 0.0, ga = 0.0;
+    double* out = part + (static_cast<int64_t>(blockIdx.x) * nsplit + blockIdx.y) * (kJp * kJp);
 #pragma unroll
-        for (int e = 0; e < kRegK; ++e) {
-            const int i = threadIdx.x + e * kSvdThreads;
-            const bool in = i < k;
-            u[e] = in ? xa[i] : 0.0;
-            v[e] = in ? xb[i] : 0.0;
-            p[e] = in ? wa[i] : 0.0;
-            q[e] = in ? wb[i] : 0.0;
-        }
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int e = 0; e < kRegK; ++e) {
-            al += u[e] * u[e];
-            be += v[e] * v[e];
-            ga += u[e] * v[e];
-        }
-        block_sum3(al, be, ga, sh);
-        if (!(ga != 0.0) || !(fabs(ga) > tol * sqrt(al) * sqrt(be))) return;
-        const double zeta = (be - al) / (2.0 * ga);
-        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double c = 1.0 / sqrt(1.0 + t * t);
-        const double s = c * t;
+        for (int j = 0; j < 4; ++j) out[(4 * ti + i) * kJp + 4 * tj + j] = acc[i][j];
+}
+
+// G[pair] = sum of the pair's partial Gram matrices in split order; a thread per entry, its
+// loads issued eight splits at a time.  Grid: (pairs, kJp^2 / 256).
+__global__ void __launch_bounds__(kSvdThreads)
+pair_reduce_kernel(const double* __restrict__ part, int nsplit, double* __restrict__ G) {
+    const int e = static_cast<int>(blockIdx.y) * kSvdThreads + static_cast<int>(threadIdx.x);
+    const double* src = part + static_cast<int64_t>(blockIdx.x) * nsplit * (kJp * kJp) + e;
+    double acc = 0.0;
+    for (int y0 = 0; y0 < nsplit; y0 += 8) {
+        double v[8];
 #pragma unroll
-        for (int e = 0; e < kRegK; ++e) {
-            const int i = threadIdx.x + e * kSvdThreads;
-            if (i < k) {
-                xa[i] = c * u[e] - s * v[e];
-                xb[i] = s * u[e] + c * v[e];
-                wa[i] = c * p[e] - s * q[e];
-                wb[i] = s * p[e] + c * q[e];
-            }
+        for (int q = 0; q < 8; ++q)
+            v[q] = y0 + q < nsplit ? src[static_cast<int64_t>(y0 + q) * (kJp * kJp)] : 0.0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (y0 + q < nsplit) acc += v[q];
+    }
+    G[static_cast<int64_t>(blockIdx.x) * (kJp * kJp) + e] = acc;
+}
+
+// One workgroup per pair of blocks: G = the pair's Gram matrix, then up to `inner` sweeps of cyclic two-sided Jacobi on G (circle ordering over the kJp
+// columns, kJp/2 disjoint rotations per round), accumulating V = product of the rotations.
+// Columns p, q rotate when |g_pq| > tol_r sqrt(g_pp g_qq), with the angle of one-sided
+// Jacobi: zeta = (g_qq - g_pp) / (2 g_pq), t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)),
+// c = 1 / sqrt(1 + t^2), s = c t, x_p <- c x_p - s x_q, x_q <- s x_p + c x_q; on G that is
+// G <- J^T G J, with g_pp - t g_pq, g_qq + t g_pq and a zero g_pq set directly.  skip[pair] is
+// 1 when nothing rotated (the apply kernel then leaves the pair), and flag is set when some
+// |g_pq| exceeded tol_c sqrt(g_pp g_qq) (the sweep is not the last).
+__global__ void __launch_bounds__(kSvdThreads)
+pair_eig_kernel(const double* __restrict__ gram, int inner, double tol_r, double tol_c,
+                double* __restrict__ Vout, int* __restrict__ skip, int* __restrict__ flag) {
+    __shared__ double G[kJp][kJp + 1];
+    __shared__ double V[kJp][kJp + 1];
+    __shared__ double rc[kJp / 2], rs[kJp / 2];
+    __shared__ int rp[kJp / 2], rq[kJp / 2];
+    __shared__ int rot, big;
+    const int tid = static_cast<int>(threadIdx.x);
+    const double* src = gram + static_cast<int64_t>(blockIdx.x) * (kJp * kJp);
+    double gv[kJp * kJp / kSvdThreads];
+#pragma unroll
+    for (int q = 0; q < kJp * kJp / kSvdThreads; ++q) gv[q] = src[tid + q * kSvdThreads];
+#pragma unroll
+    for (int q = 0; q < kJp * kJp / kSvdThreads; ++q) {
+        const int e = tid + q * kSvdThreads;
+        G[e / kJp][e % kJp] = gv[q];
+        V[e / kJp][e % kJp] = (e / kJp == e % kJp) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    // the upper-triangle 2 x 2 blocks (P, Q), P <= Q, this thread owns in every round
+    constexpr int kH = kJp / 2;
+    constexpr int kUp = kH * (kH + 1) / 2;
+    constexpr int kPer = (kUp + kSvdThreads - 1) / kSvdThreads;
+    int P[kPer], Q[kPer];
+    bool own[kPer];
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+        const int e = tid + i * kSvdThreads;
+        own[i] = e < kUp;
+        int pr = 0, rem = own[i] ? e : 0;
+        while (rem >= kH - pr) {
+            rem -= kH - pr;
+            ++pr;
         }
-        if (threadIdx.x == 0) flag[0] = 1;
+        P[i] = pr;
+        Q[i] = pr + rem;
+    }
+    if (tid == 0) big = 0;
+    bool any = false;
+    // a pair whose Gram matrix is already diagonal to tol_r rotates nothing in a sweep:
+    // leave it at once (every thread tests its own 16 entries)
+    bool open = false;
+#pragma unroll
+    for (int q = 0; q < kJp * kJp / kSvdThreads; ++q) {
+        const int e = tid + q * kSvdThreads;
+        const int i = e / kJp, j = e % kJp;
+        const double gij = gv[q];
+        open = open || (i != j && gij != 0.0 && gij * gij > tol_r * tol_r * G[i][i] * G[j][j]);
+    }
+    if (!__syncthreads_or(open)) {
+        if (tid == 0) skip[blockIdx.x] = 1;
         return;
     }
-    double al = 0.0, be = 0.0, ga = 0.0;
-    for (int i = threadIdx.x; i < k; i += kSvdThreads) {
-        const double u = xa[i], v = xb[i];
-        al += u * u;
-        be += v * v;
-        ga += u * v;
+    for (int sw = 0; sw < inner; ++sw) {
+        if (tid == 0) rot = 0;
+        __syncthreads();
+        for (int r = 0; r < kJp - 1; ++r) {
+            if (tid < kJp / 2) {
+                int pp, qq;
+                circle_pair(kJp, r, tid, pp, qq);
+                if (pp > qq) {
+                    const int t = pp;
+                    pp = qq;
+                    qq = t;
+                }
+                const double al = G[pp][pp], be = G[qq][qq], ga = G[pp][qq];
+                const double g2 = ga * ga, ab = al * be;
+                double c = 1.0, s = 0.0;
+                if (ga != 0.0 && g2 > tol_r * tol_r * ab) {
+                    // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)) written as
+                    // sign(d) 2 g_pq / (|d| + sqrt(d^2 + 4 g_pq^2)), d = g_qq - g_pp.  The
+                    // angle needs no last-bit accuracy (it only sets how far the pair
+                    // turns; one Newton step on each hardware estimate gives about 46
+                    // bits), c^2 + s^2 = 1 does: c comes from a fully refined 1 / sqrt.
+                    const double d = be - al, g2x = 2.0 * ga;
+                    const double hx = fma(d, d, g2x * g2x);
+                    const double y = __builtin_amdgcn_rsq(hx);
+                    double h = hx * y;                                  // sqrt(hx), ~23 bits
+                    h = fma(fma(-h, h, hx), 0.5 * y, h);                // one Newton step
+                    const double den = fabs(d) + h;
+                    double ri = __builtin_amdgcn_rcp(den);
+                    ri = fma(ri, fma(-den, ri, 1.0), ri);               // one Newton step
+                    double t = g2x * ri;
+                    if (d < 0.0) t = -t;
+                    double unused;
+                    sqrt_and_rsqrt(fma(t, t, 1.0), unused, c);
+                    s = c * t;
+                    rot = 1;
+                    if (g2 > tol_c * tol_c * ab) big = 1;
+                }
+                rc[tid] = c;
+                rs[tid] = s;
+                rp[tid] = pp;
+                rq[tid] = qq;
+            }
+            __syncthreads();
+            // G <- J^T G J by 2 x 2 blocks (rows of pair P, columns of pair Q) with P <= Q
+            // (528 of them, about two per thread, one owner each); only the upper triangle
+            // of G is kept up to date, every entry is read and written at (min, max).  All
+            // reads come first.
+            {
+                double c1[kPer], s1[kPer], c2[kPer], s2[kPer], g[kPer][4];
+                int p1[kPer], q1[kPer], p2[kPer], q2[kPer];
+#pragma unroll
+                for (int i = 0; i < kPer; ++i) {
+                    c1[i] = rc[P[i]];
+                    s1[i] = rs[P[i]];
+                    p1[i] = rp[P[i]];
+                    q1[i] = rq[P[i]];
+                    c2[i] = rc[Q[i]];
+                    s2[i] = rs[Q[i]];
+                    p2[i] = rp[Q[i]];
+                    q2[i] = rq[Q[i]];
+                }
+#pragma unroll
+                for (int i = 0; i < kPer; ++i) {
+                    g[i][0] = G[min(p1[i], p2[i])][max(p1[i], p2[i])];
+                    g[i][1] = G[min(p1[i], q2[i])][max(p1[i], q2[i])];
+                    g[i][2] = G[min(q1[i], p2[i])][max(q1[i], p2[i])];
+                    g[i][3] = G[min(q1[i], q2[i])][max(q1[i], q2[i])];
+                }
+#pragma unroll
+                for (int i = 0; i < kPer; ++i) {
+                    if (!own[i]) continue;
+                    if (s1[i] == 0.0 && s2[i] == 0.0) continue;
+                    if (P[i] == Q[i]) {   // diagonal block: the rotation's closed form
+                        const double t = s1[i] / c1[i];
+                        G[p1[i]][p1[i]] = g[i][0] - t * g[i][1];
+                        G[q1[i]][q1[i]] = g[i][3] + t * g[i][1];
+                        G[p1[i]][q1[i]] = 0.0;
+                        continue;
+                    }
+                    const double h11 = c1[i] * g[i][0] - s1[i] * g[i][2];
+                    const double h12 = c1[i] * g[i][1] - s1[i] * g[i][3];
+                    const double h21 = s1[i] * g[i][0] + c1[i] * g[i][2];
+                    const double h22 = s1[i] * g[i][1] + c1[i] * g[i][3];
+                    const double n11 = c2[i] * h11 - s2[i] * h12, n12 = s2[i] * h11 + c2[i] * h12;
+                    const double n21 = c2[i] * h21 - s2[i] * h22, n22 = s2[i] * h21 + c2[i] * h22;
+                    G[min(p1[i], p2[i])][max(p1[i], p2[i])] = n11;
+                    G[min(p1[i], q2[i])][max(p1[i], q2[i])] = n12;
+                    G[min(q1[i], p2[i])][max(q1[i], p2[i])] = n21;
+                    G[min(q1[i], q2[i])][max(q1[i], q2[i])] = n22;
+                }
+            }
+            // V <- V J: thread t applies rotation t mod 32 to rows t / 32 + 8 j
+            {
+                const int Pv = tid & (kH - 1), i0 = tid / kH;
+                const double c = rc[Pv], s = rs[Pv];
+                if (s != 0.0) {
+                    const int pp = rp[Pv], qq = rq[Pv];
+                    double vp[8], vq[8];
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        vp[j] = V[i0 + 8 * j][pp];
+                        vq[j] = V[i0 + 8 * j][qq];
+                    }
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        V[i0 + 8 * j][pp] = c * vp[j] - s * vq[j];
+                        V[i0 + 8 * j][qq] = s * vp[j] + c * vq[j];
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        const bool rotated = rot != 0;   // uniform: read after the round's barrier
+        __syncthreads();
+        if (!rotated) break;
+        any = true;
     }
-    block_sum3(al, be, ga, sh);
-    if (!(ga != 0.0) || !(fabs(ga) > tol * sqrt(al) * sqrt(be))) return;
-    const double zeta = (be - al) / (2.0 * ga);
-    const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-    const double c = 1.0 / sqrt(1.0 + t * t);
-    const double s = c * t;
-    for (int i = threadIdx.x; i < k; i += kSvdThreads) {
-        const double u = xa[i], v = xb[i];
-        xa[i] = c * u - s * v;
-        xb[i] = s * u + c * v;
-        const double p = wa[i], q = wb[i];
-        wa[i] = c * p - s * q;
-        wb[i] = s * p + c * q;
+    if (tid == 0) {
+        skip[blockIdx.x] = any ? 0 : 1;
+        if (big) flag[0] = 1;
     }
-    if (threadIdx.x == 0) flag[0] = 1;
+    if (!any) return;
+    double* v = Vout + static_cast<int64_t>(blockIdx.x) * (kJp * kJp);
+    for (int e = tid; e < kJp * kJp; e += kSvdThreads) v[e] = V[e / kJp][e % kJp];
+}
+
+// [X_a X_b] <- [X_a X_b] V on rows [kJrows y, kJrows (y + 1)) (grid z = 0), and the same on
+// W (z = 1).  The tile is read whole into LDS before it is written back; a thread forms a
+// 4 x 4 block of the product (rows 4 (t mod 16) .., slots 4 (t / 16) ..).
+__global__ void __launch_bounds__(kSvdThreads)
+pair_apply_kernel(double* __restrict__ X, double* __restrict__ W, int k, int64_t ld, int nb, int np,
+                  int round, const double* __restrict__ Vp, const int* __restrict__ skip) {
+    if (skip[blockIdx.x] != 0) return;   // uniform per workgroup
+    constexpr int kPitch = kJrows + 2;   // slots of the tile, 16-byte aligned
+    __shared__ __align__(16) double vs[kJp * kJp];
+    __shared__ __align__(16) double xs[kJp * kPitch];
+    double* M = blockIdx.z == 0 ? X : W;
+    int a, b;
+    circle_pair(np, round, static_cast<int>(blockIdx.x), a, b);
+    const double* v = Vp + static_cast<int64_t>(blockIdx.x) * (kJp * kJp);
+    {
+        double t[kJp * kJp / kSvdThreads];
+#pragma unroll
+        for (int q = 0; q < kJp * kJp / kSvdThreads; ++q) t[q] = v[threadIdx.x + q * kSvdThreads];
+#pragma unroll
+        for (int q = 0; q < kJp * kJp / kSvdThreads; ++q) vs[threadIdx.x + q * kSvdThreads] = t[q];
+    }
+    const int r0 = static_cast<int>(blockIdx.y) * kJrows;
+    stage_pair_tile<kPitch, 1>(M, k, ld, a, b, nb, r0, xs);
+    __syncthreads();
+    const int tr = static_cast<int>(threadIdx.x) & 15, tc = static_cast<int>(threadIdx.x) >> 4;
+    double acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+#pragma unroll 4
+    for (int i = 0; i < kJp; ++i) {
+        const double2 x01 = *reinterpret_cast<const double2*>(xs + i * kPitch + 4 * tr);
+        const double2 x23 = *reinterpret_cast<const double2*>(xs + i * kPitch + 4 * tr + 2);
+        const double2 w01 = *reinterpret_cast<const double2*>(vs + i * kJp + 4 * tc);
+        const double2 w23 = *reinterpret_cast<const double2*>(vs + i * kJp + 4 * tc + 2);
+        const double x[4] = {x01.x, x01.y, x23.x, x23.y};
+        const double w[4] = {w01.x, w01.y, w23.x, w23.y};
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[p][q] = fma(x[p], w[q], acc[p][q]);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int c = pair_col(a, b, nb, 4 * tc + q, k);
+        if (c < 0) continue;
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const int row = r0 + 4 * tr + p;
+            if (row < k) M[static_cast<int64_t>(c) * ld + row] = acc[p][q];
+        }
+    }
 }
 
 // sig[j] = ||X(:, j)||_2 (workgroup per column).
@@ -212,13 +479,37 @@ __global__ void identity_kernel(double* __restrict__ W, int k, int64_t ld) {
     if (i < k) W[static_cast<int64_t>(j) * ld + i] = i == j ? 1.0 : 0.0;
 }
 
-int jacobi_players(int k) { return k + (k & 1); }
+int jacobi_blocks(int k) { return (k + kJb - 1) / kJb; }
+int jacobi_rounds(int k) {
+    const int nb = jacobi_blocks(k);
+    return nb + (nb & 1) - 1;
+}
+size_t jacobi_part_elems(int k) {
+    const int nb = jacobi_blocks(k);
+    const int64_t pairs = (nb + (nb & 1)) / 2;
+    return static_cast<size_t>(pairs * (cdiv(k, kGramTiles * kJrows) + 1) * kJp * kJp);   // partials, sums
+}
+size_t jacobi_rot_elems(int k) {
+    const int nb = jacobi_blocks(k);
+    return static_cast<size_t>((nb + (nb & 1)) / 2) * kJp * kJp;
+}
 
-hipError_t launch_jacobi_round(double* X, double* W, int k, int64_t ld, int round, double tol,
-                               int* flag, hipStream_t s) {
-    const int np = jacobi_players(k);
-    hipLaunchKernelGGL(jacobi_round_kernel, dim3(static_cast<unsigned>(np / 2)), dim3(kSvdThreads), 0,
-                       s, X, W, k, ld, np, round, tol, flag);
+hipError_t launch_jacobi_block_round(double* X, double* W, int k, int64_t ld, int round, double tol_r,
+                                     double tol_c, int inner, double* part, double* V, int* skip,
+                                     int* flag, hipStream_t s) {
+    const int nb = jacobi_blocks(k);
+    const int np = nb + (nb & 1);
+    const unsigned pairs = static_cast<unsigned>(np / 2);
+    const int nsplit = static_cast<int>(cdiv(k, kGramTiles * kJrows));
+    hipLaunchKernelGGL(pair_gram_kernel, dim3(pairs, static_cast<unsigned>(nsplit)), dim3(kSvdThreads), 0, s,
+                       X, k, ld, nb, np, round, nsplit, part);
+    double* gram = part + static_cast<int64_t>(pairs) * nsplit * (kJp * kJp);
+    hipLaunchKernelGGL(pair_reduce_kernel, dim3(pairs, (kJp * kJp) / kSvdThreads), dim3(kSvdThreads), 0, s,
+                       part, nsplit, gram);
+    hipLaunchKernelGGL(pair_eig_kernel, dim3(pairs), dim3(kSvdThreads), 0, s, gram, inner, tol_r, tol_c, V,
+                       skip, flag);
+    hipLaunchKernelGGL(pair_apply_kernel, dim3(pairs, static_cast<unsigned>(cdiv(k, kJrows)), 2), dim3(kSvdThreads),
+                       0, s, X, W, k, ld, nb, np, round, V, skip);
     return hipGetLastError();
 }
 
