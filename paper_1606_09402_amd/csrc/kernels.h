@@ -113,6 +113,8 @@ struct ScanState {
     int skip;            // stop || halt
     int blocks;          // blocks scanned
     int pad;
+    int64_t rk[8];       // k and E after block i at [i mod 8] (the host reads the last few
+    double re[8];        // with the state itself, in one copy)
 };
 // st = {E = *normA2, k = 0, rest 0}
 hipError_t launch_scan_init(const double* normA2, ScanState* st, hipStream_t s);

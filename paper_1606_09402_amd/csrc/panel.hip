@@ -613,6 +613,8 @@ scan_block_kernel(const double* __restrict__ rowsq, const double* __restrict__ R
         st->exhausted |= exh;
         khist[st->blocks] = st->k;
         ehist[st->blocks] = Et;
+        st->rk[st->blocks & 7] = st->k;
+        st->re[st->blocks & 7] = Et;
         st->blocks += 1;
     }
 }

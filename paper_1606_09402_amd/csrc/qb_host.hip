@@ -26,6 +26,7 @@ constexpr int64_t kGramSplitElems = 1 << 22;
 constexpr int kMaxPower = 16;               // largest power-scheme parameter P accepted
 constexpr int kPowerBlock = 128;            // column block of the power-scheme orth()
 constexpr int kLookahead = 4;               // blocks enqueued ahead of the stopping decision
+static_assert(kLookahead <= 8, "the scan state keeps the (k, E) of its last 8 blocks");
 constexpr int kMaxOversample = 128;         // trQRCP sketch rows beyond b
 constexpr uint32_t kSketchStream = 1;       // generator stream of trQRCP's sketch (randQB: 0)
 
@@ -44,6 +45,8 @@ struct Layout {
         rowsq_part, rowsq, info, flags, split, csc, plan_a, plan_t, omt, gqt, total;
     size_t split2;          // split-K partials of the products issued on the side stream
     size_t scan, khist, ehist;   // device stopping state and the (k, E) after each block
+    size_t ynext, w2;            // randQB_FP look-ahead: the next block's partial Y, second W buffer
+    bool ahead;                  // look-ahead regions present
     int64_t nhist;
     // trQRCP: sketch St (n x l), its Gaussian (m x l), ||A(:, j)||^2 and its partials, the
     // remaining sketch norms, active flags, reflector, block pivots, their ||A(:, p)||^2,
@@ -171,6 +174,12 @@ Layout make_layout(int algo, int sparse, int dtype, int64_t m, int64_t n, int64_
     L.ehist = take(sizeof(double) * L.nhist);
     L.split = take(sizeof(double) * L.split_elems);
     L.split2 = take(sizeof(double) * L.split2_elems);
+    // randQB_FP look-ahead (only with a side stream, so not in the allocation-free sizing):
+    // the next block's G_J' - Q W' over the columns of Q known before this block ends, and a
+    // second W buffer for that block's W'
+    L.ahead = algo == QB_ALGO_FP && split_cap < 0;
+    L.ynext = take(L.ahead ? sizeof(double) * m * b : 0);
+    L.w2 = take(L.ahead ? sizeof(double) * lmax * b : 0);
     L.csc = sparse ? take(csc_layout(m, n, nnz).total) : take(0);
     // segment plans of CSR(A) and CSR(A^T) for the balanced SpMM (widest product: l~ or b)
     L.plan_a = sparse ? take(spmm_plan_bytes(m, nnz, lt)) : take(0);
@@ -228,7 +237,7 @@ struct Op {
 // so a call creates no stream or event once the pool has grown to the call's phase count.
 struct DevRes {
     hipStream_t side = nullptr;
-    hipEvent_t ev_y = nullptr, ev_s = nullptr;
+    hipEvent_t ev_y = nullptr, ev_s = nullptr, ev_pre = nullptr;
     std::vector<hipEvent_t> pool;
 };
 
@@ -245,11 +254,13 @@ DevRes* dev_res() {
         // be made, the products run on the caller's stream.
         if (hipStreamCreateWithFlags(&r->side, hipStreamNonBlocking) != hipSuccess) r->side = nullptr;
         if (r->side != nullptr && (hipEventCreateWithFlags(&r->ev_y, hipEventDisableTiming) != hipSuccess ||
-                                   hipEventCreateWithFlags(&r->ev_s, hipEventDisableTiming) != hipSuccess)) {
+                                   hipEventCreateWithFlags(&r->ev_s, hipEventDisableTiming) != hipSuccess ||
+                                   hipEventCreateWithFlags(&r->ev_pre, hipEventDisableTiming) != hipSuccess)) {
             if (r->ev_y) (void)hipEventDestroy(r->ev_y);
+            if (r->ev_s) (void)hipEventDestroy(r->ev_s);
             (void)hipStreamDestroy(r->side);
             r->side = nullptr;
-            r->ev_y = r->ev_s = nullptr;
+            r->ev_y = r->ev_s = r->ev_pre = nullptr;
         }
         (void)hipGetLastError();
         res[dev] = r;
@@ -308,6 +319,7 @@ struct Ctx {
     hipStream_t side = nullptr;   // randQB_FP: stream of the D, S products (or none)
     hipEvent_t ev_y = nullptr, ev_s = nullptr;
     const int* gate = nullptr;    // device flag that skips the block products (stopped call)
+    hipEvent_t ev_pre = nullptr;  // randQB_FP look-ahead done on the side stream
     template <class T>
     T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
 };
@@ -417,14 +429,31 @@ int cholqr(const Ctx& x, const double* X, int bw, double* Qout, int64_t ldq, dou
 // the w buffer already, as trQRCP does with W = B(:, J)), form W = B Omega_J,
 // Y = G_J - Q W (kept in the y buffer), Q_i = qr(Y), Q_i = qr(Q_i - Q (Q^T Q_i)) and
 // R_i = R~ R.  use_hh selects Householder instead of CholeskyQR for both qr calls.
-int fp_block_ds(const Ctx& x, int64_t k, int bw, const double* HJ, int64_t ldhj);
+int fp_block_ds(const Ctx& x, int64_t k, int bw, const double* HJ, int64_t ldhj, const double* W);
+
+// Look-ahead of the randQB_FP block loop.  Block i + 1 (columns J' of the chunk) needs
+// W' = B Omega_J' and Y' = G_J' - Q W' over all k + bw rows of B and columns of Q, but the
+// first k of them are known when block i starts.  So beside block i's QR, the side stream
+// forms W'(0:k, :) = B(0:k, :) Omega_J' (into the W buffer block i does not use) and
+// Yp = G_J' - Q(:, 0:k) W'(0:k, :) (into the ynext buffer); block i + 1 then only adds
+// W'(k:k+bw, :) = B_i Omega_J' and Y' = Yp - Q_i W'(k:k+bw, :).  The sums regroup the
+// same products (Y' to rounding).  Not across a chunk end (the next chunk's sketch
+// replaces G and Omega), not after a block redone by Householder QR.
+struct Lookahead {
+    int cur = 0;            // W buffer of the current block: 0 the w region, 1 the w2 region
+    int64_t k = -1;         // start of the block the precomputed parts belong to (-1: none)
+    int64_t kp = 0;         // rows of W' (columns of Q) they cover
+    int bw = 0;             // that block's width
+    bool pending = false;   // enqueued on the side stream, ev_pre recorded after it
+    int64_t k_end = 0;      // end of the current chunk
+};
 
 int orth_block(const Ctx& x, int64_t k, int bw, const double* GJ, int64_t ldgj, const double* OmJ,
-               int64_t ldoj, bool use_hh, const double* HJ, int64_t ldhj) {
+               int64_t ldoj, bool use_hh, const double* HJ, int64_t ldhj, Lookahead* la = nullptr) {
     const int64_t m = x.A.m, n = x.A.n;
     double* Y = x.at<double>(x.L.y);
     double* X2 = x.at<double>(x.L.x2);
-    double* W = x.at<double>(x.L.w);
+    double* W = x.at<double>(la != nullptr && la->cur == 1 ? x.L.w2 : x.L.w);
     double* Z = x.at<double>(x.L.z);
     double* Qi = x.Q + k * x.ldq;
     double* R1 = x.at<double>(x.L.r1);
@@ -432,21 +461,60 @@ int orth_block(const Ctx& x, int64_t k, int bw, const double* GJ, int64_t ldgj, 
     double* Rt = x.at<double>(x.L.rt);
     double* Rti = x.at<double>(x.L.rti);
     double* tau = x.at<double>(x.L.tau);
-    // W = B(0:k, :) Omega_J   (k x bw, row-major ld bw)
-    if (k > 0 && OmJ != nullptr) {
-        GemmDesc d = gdesc(k, bw, n, View{x.B, x.ldb, 1}, View{OmJ, ldoj, 1}, 1.0, 0.0,
-                           View{nullptr, 0, 0}, MutView{W, bw, 1}, x);
-        QB_HIP(gemm_f64(d, x.s));
+    if (la != nullptr && la->pending) {   // the side stream's look-ahead writes W and ynext
+        QB_HIP(hipStreamWaitEvent(x.s, x.ev_pre, 0));
+        la->pending = false;
     }
-    // Y = G_J - Q W   (m x bw, column-major ld m)
-    {
+    const bool use_ahead = la != nullptr && la->k == k && la->bw == bw && !use_hh && OmJ != nullptr;
+    if (la != nullptr) la->k = -1;
+    if (use_ahead) {
+        const int64_t kp = la->kp;
+        // W(kp:k, :) = B(kp:k, :) Omega_J
+        GemmDesc d = gdesc(k - kp, bw, n, View{x.B + kp * x.ldb, x.ldb, 1}, View{OmJ, ldoj, 1}, 1.0, 0.0,
+                           View{nullptr, 0, 0}, MutView{W + kp * bw, bw, 1}, x);
+        QB_HIP(gemm_f64(d, x.s));
+        // Y = Yp - Q(:, kp:k) W(kp:k, :)
+        GemmDesc e = gdesc(m, bw, k - kp, View{x.Q + kp * x.ldq, 1, x.ldq}, View{W + kp * bw, bw, 1}, -1.0,
+                           1.0, View{x.at<double>(x.L.ynext), 1, m}, MutView{Y, 1, m}, x);
+        QB_HIP(gemm_f64(e, x.s));
+    } else {
+        // W = B(0:k, :) Omega_J   (k x bw, row-major ld bw)
+        if (k > 0 && OmJ != nullptr) {
+            GemmDesc d = gdesc(k, bw, n, View{x.B, x.ldb, 1}, View{OmJ, ldoj, 1}, 1.0, 0.0,
+                               View{nullptr, 0, 0}, MutView{W, bw, 1}, x);
+            QB_HIP(gemm_f64(d, x.s));
+        }
+        // Y = G_J - Q W   (m x bw, column-major ld m)
         GemmDesc d = gdesc(m, bw, k, View{x.Q, 1, x.ldq}, View{W, bw, 1}, -1.0, 1.0,
                            View{GJ, ldgj, 1}, MutView{Y, 1, m}, x);
         QB_HIP(gemm_f64(d, x.s));
     }
     // randQB_FP: the parts of eq. (23) that need only Y and W, beside the QR below
     if (HJ != nullptr) {
-        if (int st = fp_block_ds(x, k, bw, HJ, ldhj)) return st;
+        if (int st = fp_block_ds(x, k, bw, HJ, ldhj, W)) return st;
+        // then the look-ahead of the next block of the chunk on the same side stream
+        const int64_t k2 = k + bw;
+        if (la != nullptr && x.side != nullptr && x.L.ahead && k > 0 && k2 < la->k_end) {
+            const int bw2 = static_cast<int>(x.p->b < la->k_end - k2 ? x.p->b : la->k_end - k2);
+            const int nc = la->cur ^ 1;
+            double* W2 = x.at<double>(nc == 1 ? x.L.w2 : x.L.w);
+            GemmDesc d = gdesc(k, bw2, n, View{x.B, x.ldb, 1}, View{OmJ + bw, ldoj, 1}, 1.0, 0.0,
+                               View{nullptr, 0, 0}, MutView{W2, bw2, 1}, x);
+            d.ws = x.at<double>(x.L.split2);
+            d.ws_elems = x.L.split2_elems;
+            QB_HIP(gemm_f64(d, x.side));
+            GemmDesc e = gdesc(m, bw2, k, View{x.Q, 1, x.ldq}, View{W2, bw2, 1}, -1.0, 1.0,
+                               View{GJ + bw, ldgj, 1}, MutView{x.at<double>(x.L.ynext), 1, m}, x);
+            e.ws = x.at<double>(x.L.split2);
+            e.ws_elems = x.L.split2_elems;
+            QB_HIP(gemm_f64(e, x.side));
+            QB_HIP(hipEventRecord(x.ev_pre, x.side));
+            la->pending = true;
+            la->k = k2;
+            la->kp = k;
+            la->bw = bw2;
+            la->cur = nc;
+        }
     }
     // first qr
     if (!use_hh) {
@@ -484,10 +552,9 @@ int orth_block(const Ctx& x, int64_t k, int bw, const double* GJ, int64_t ldgj, 
 // a side stream they run there, beside the panel QR of Y on the main stream (the two touch
 // disjoint buffers: Q(:, 0:k), Y, W, B and H are only read, D and S only written, and the
 // side products have their own split-K partials).
-int fp_block_ds(const Ctx& x, int64_t k, int bw, const double* HJ, int64_t ldhj) {
+int fp_block_ds(const Ctx& x, int64_t k, int bw, const double* HJ, int64_t ldhj, const double* W) {
     const int64_t m = x.A.m, n = x.A.n;
     double* Y = x.at<double>(x.L.y);
-    double* W = x.at<double>(x.L.w);
     double* D = x.at<double>(x.L.d);
     double* S = x.at<double>(x.L.s);
     hipStream_t st = x.s;
@@ -785,7 +852,8 @@ int run(int algo, Op& A, const qb_params* p, double* Q, int64_t ldq, double* B, 
     }
     ScanState* scan = reinterpret_cast<ScanState*>(wsb + L.scan);
     const Ctx x{A, p, Q, ldq, B, ldb, wsb, L, s, inf, &tm, host, side_ok ? res->side : nullptr,
-                side_ok ? res->ev_y : nullptr, side_ok ? res->ev_s : nullptr, &scan->skip};
+                side_ok ? res->ev_y : nullptr, side_ok ? res->ev_s : nullptr, &scan->skip,
+                side_ok ? res->ev_pre : nullptr};
     QB_HIP(hipMemcpyAsync(host, scal, sizeof(double), hipMemcpyDeviceToHost, s));
     QB_HIP(hipStreamSynchronize(s));
     const double normA2 = host[0];
@@ -815,6 +883,7 @@ int run(int algo, Op& A, const qb_params* p, double* Q, int64_t ldq, double* B, 
         double* gnorm2 = x.at<double>(L.gnorm2);
         bool stop = false;
         bool redo_hh = false;     // the block at row k broke down in CholeskyQR: redo it by Householder
+        Lookahead la;             // randQB_FP: the next block's W and Y parts formed beside this block
         double dec = 0.0;         // the indicator's drop per block over the last run of blocks
         double ratio = 0.0;       // and its ratio per block (geometric mean)
         while (k < lmax && !stop) {
@@ -824,6 +893,8 @@ int run(int algo, Op& A, const qb_params* p, double* Q, int64_t ldq, double* B, 
                                              eps2);
                 chunk_lo = k;
                 chunk_hi = k + w;
+                la.k_end = chunk_hi;
+                la.k = -1;
                 k_half = chunk_lo + b * (cdiv(w, b) / 2);
                 e_half = E;
                 tm.mark(1);
@@ -896,7 +967,8 @@ int run(int algo, Op& A, const qb_params* p, double* Q, int64_t ldq, double* B, 
                 }
                 const bool use_hh = t == 0 && redo_hh;
                 if (use_hh) QB_HIP(launch_scan_resume(scan, x.at<int>(L.flags), s));
-                if (int e = orth_block(x, ks, bwi, GJ, ldj, OmJ, ldj, use_hh, algo == QB_ALGO_FP ? HJ : nullptr, ldj))
+                if (int e = orth_block(x, ks, bwi, GJ, ldj, OmJ, ldj, use_hh, algo == QB_ALGO_FP ? HJ : nullptr, ldj,
+                                       algo == QB_ALGO_FP ? &la : nullptr))
                     return inf->status = e;
                 if (algo == QB_ALGO_FP) {
                     if (int e = fp_block_b(x, ks, bwi)) return inf->status = e;
@@ -919,15 +991,10 @@ int run(int algo, Op& A, const qb_params* p, double* Q, int64_t ldq, double* B, 
                 dec = (E - hs.E) / static_cast<double>(hs.blocks - first);
                 ratio = E > 0.0 && hs.E > 0.0 ? pow(hs.E / E, 1.0 / static_cast<double>(hs.blocks - first)) : 0.0;
                 if (algo == QB_ALGO_FP && k < k_half && hs.k >= k_half) {
-                    // the indicator at the end of the block that ends at k_half
-                    const int nb = hs.blocks - first;
-                    int64_t kh[2 * kLookahead];
-                    double eh[2 * kLookahead];
-                    QB_HIP(hipMemcpyAsync(kh, khist + first, sizeof(int64_t) * nb, hipMemcpyDeviceToHost, s));
-                    QB_HIP(hipMemcpyAsync(eh, ehist + first, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
-                    QB_HIP(hipStreamSynchronize(s));
-                    for (int i = 0; i < nb; ++i)
-                        if (kh[i] == k_half) e_half = eh[i];
+                    // the indicator at the end of the block that ends at k_half (a run holds
+                    // at most kLookahead blocks, so the state's ring of 8 still has them)
+                    for (int i = first; i < hs.blocks; ++i)
+                        if (hs.rk[i & 7] == k_half) e_half = hs.re[i & 7];
                 }
                 scanned = hs.blocks;
             }
@@ -938,6 +1005,8 @@ int run(int algo, Op& A, const qb_params* p, double* Q, int64_t ldq, double* B, 
             redo_hh = hs.halt != 0;
             if (redo_hh) inf->fallbacks += 1;
         }
+        // a look-ahead for a block that did not run still uses the workspace: join it
+        if (la.pending) QB_HIP(hipStreamWaitEvent(s, x.ev_pre, 0));
         inf->blocks = scanned;
         if (algo == QB_ALGO_EI) {
             inf->passes = 2 * scanned;
@@ -1363,7 +1432,7 @@ int layout_check(int algo, int sparse, int dtype, int64_t m, int64_t n, int64_t 
     std::vector<size_t> offs = {L.red, L.scal, L.om, L.g, L.h, L.gpart, L.gnorm2, L.y, L.x2, L.s, L.w,
                                 L.z, L.d, L.gram, L.r1, L.r1i, L.rt, L.rti, L.ri, L.rii, L.tau,
                                 L.rowsq_part, L.rowsq, L.info, L.flags, L.scan, L.khist, L.ehist,
-                                L.split, L.split2, L.csc,
+                                L.split, L.split2, L.ynext, L.w2, L.csc,
                                 L.plan_a, L.plan_t, L.omt, L.gqt, L.omt8, L.total};
     if (ell > 0) offs.insert(offs.end(), {L.sk, L.skom, L.cola, L.colpart, L.qn, L.act, L.hh, L.bpiv,
                                           L.g2p, L.rs, L.mm});
@@ -1419,6 +1488,10 @@ int layout_check(int algo, int sparse, int dtype, int64_t m, int64_t n, int64_t 
     // being at most cdiv(l_max, b)
     need(L.khist, 8.0 * (2 * cdiv(lmax, b) + 1));
     need(L.ehist, D * (2 * cdiv(lmax, b) + 1));
+    if (L.ahead) {
+        need(L.ynext, D * m * b);
+        need(L.w2, D * lmax * b);
+    }
     if (sparse) {
         need(L.csc, static_cast<double>(csc_layout(m, n, nnz).total));
         need(L.plan_a, static_cast<double>(spmm_plan_bytes(m, nnz, lt)));
