@@ -37,6 +37,7 @@ import json
 
 import numpy as np
 import os
+import re
 import statistics
 import sys
 import time
@@ -712,8 +713,8 @@ def measure_counters(l_tilde, timeout=300):
     # the sketch GEMMs: gemm_f64_kernel<128, 128, ...> with A layout 0 (G = A Omega) or
     # 1 (H = A^T G); the measured call's launches are the last half of each
     def launches(rows, counter, al):
-        tag = f"gemm_f64_kernel<128, 128, 32, 4, 2, {al}, 0"
-        vals = [v for _, k, c, v in rows if c == counter and tag in k]
+        tag = re.compile(rf"gemm_f64_kernel<128, 128, \d+, 4, 2, {al}, 0,")
+        vals = [v for _, k, c, v in rows if c == counter and tag.search(k)]
         return vals[len(vals) // 2:]
 
     def first(rows, counter, kname):

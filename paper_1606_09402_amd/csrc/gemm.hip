@@ -100,13 +100,13 @@ struct GemmCfg {
     static constexpr int FM = TM / 16, FN = TN / 16;
     // layout 0 tiles are [BM][BK] (k contiguous), layout 1 tiles are [BK][BM]; the
     // pitches make a 32-lane pass of MFMA operand reads hit 64 distinct banks
-    static constexpr int A_PITCH = AL == 0 ? ((BK + 31) / 32) * 32 + 2 : ((BM + 31) / 32) * 32 + 16;
+    static constexpr int A_PITCH = AL == 0 ? BK + 2 : ((BM + 31) / 32) * 32 + 16;
     static constexpr int A_ROWS = AL == 0 ? BM : BK;
     static constexpr int A_INNER = AL == 0 ? BK : BM;
-    static constexpr int B_PITCH = BL == 0 ? ((BN + 31) / 32) * 32 + 16 : ((BK + 31) / 32) * 32 + 2;
+    static constexpr int B_PITCH = BL == 0 ? ((BN + 31) / 32) * 32 + 16 : BK + 2;
     static constexpr int B_ROWS = BL == 0 ? BK : BN;
     static constexpr int B_INNER = BL == 0 ? BN : BK;
-    static_assert(TM % 16 == 0 && TN % 16 == 0 && BK % 4 == 0, "bad tile");
+    static_assert(TM % 16 == 0 && TN % 16 == 0 && (BK == 16 || BK == 32), "bad tile");
 };
 
 template <int BM, int BN, int BK, int WM, int WN, int AL, int BL, int OCC, int STAGES>
@@ -438,6 +438,15 @@ static hipError_t run_cfg(const GemmDesc& d, hipStream_t s) {
         if (d.max_split > 0 && want > d.max_split) want = d.max_split;
         while (want > 1 && want * d.M * d.N > d.ws_elems) --want;
         if (want > 1) nsplit = static_cast<int>(want);
+    } else if (d.ws != nullptr && BK == 16) {
+        // the two-per-CU sketch tile: split K in 2, 4 or 6 until there are at least 2400
+        // workgroups (measured on the 20000 x 15000 sketch products: G and H of 512 and
+        // 1024 columns ran fastest with 4-6 splits; odd counts were slower)
+        for (int ns = 2; ns <= 6; ns += 2) {
+            if (tiles * (nsplit > 1 ? nsplit : 1) >= 2400) break;
+            if (ktiles < 16 * ns || ns * d.M * d.N > d.ws_elems) break;
+            nsplit = ns;
+        }
     } else if (d.ws != nullptr) {
         // pick 1..4 K splits to shrink the idle tail of the last round of workgroups
         // (the split partials cost one extra pass over M x N); the resident workgroups
@@ -503,7 +512,7 @@ static hipError_t dispatch_shape(const GemmDesc& d, hipStream_t s) {
     switch (shape_class(d.M, d.N, d.K)) {
         case 0: return run_cfg<128, 64, 32, 4, 1, AL, BL, 2, 1>(d, s);
         case 1: return run_cfg<64, 64, 32, 2, 2, AL, BL, 2, 1>(d, s);
-        default: return run_cfg<128, 128, 32, 4, 2, AL, BL, 2, 2>(d, s);
+        default: return run_cfg<128, 128, 16, 4, 2, AL, BL, 2, 2>(d, s);
     }
 }
 
