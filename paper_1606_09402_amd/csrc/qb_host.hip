@@ -833,9 +833,19 @@ int run(int algo, Op& A, const qb_params* p, double* Q, int64_t ldq, double* B, 
     double* scal = reinterpret_cast<double*>(wsb + L.scal);
     double* red = reinterpret_cast<double*>(wsb + L.red);
 
-    // ||A||_F^2 (Algorithm 4 step 9)
+    // ||A||_F^2 (Algorithm 4 step 9).  Dense binary64 randQB_FP without the power scheme sums
+    // it on the side stream, beside the first chunk's Omega and G = A Omega on this stream
+    // (the chunk's width does not depend on it), and reads it back from the side stream once
+    // G is enqueued.
     tm.mark(0);
-    if (A.dtype == QB_BF16) {
+    const bool early_g = side_ok && algo == QB_ALGO_FP && !A.sparse && A.dtype == QB_F64 && p->power == 0;
+    int64_t w_early = 0;
+    if (early_g) {
+        QB_HIP(hipEventRecord(res->ev_pre, s));
+        QB_HIP(hipStreamWaitEvent(res->side, res->ev_pre, 0));
+        QB_HIP(launch_sumsq_dense(A.a, m, n, A.lda, red, scal, res->side));
+        w_early = next_chunk(p, L.lt, 0, 0, 0, 0.0, 0.0, 0.0);
+    } else if (A.dtype == QB_BF16) {
         QB_HIP(launch_sumsq_bf16(A.aq, m, n, A.lda, red, scal, s));
     } else if (A.dtype == QB_FP8E4M3) {
         QB_HIP(launch_sumsq_fp8(A.a8, A.row_exp, m, n, A.lda, red, scal, s));
@@ -854,12 +864,31 @@ int run(int algo, Op& A, const qb_params* p, double* Q, int64_t ldq, double* B, 
     const Ctx x{A, p, Q, ldq, B, ldb, wsb, L, s, inf, &tm, host, side_ok ? res->side : nullptr,
                 side_ok ? res->ev_y : nullptr, side_ok ? res->ev_s : nullptr, &scan->skip,
                 side_ok ? res->ev_pre : nullptr};
-    QB_HIP(hipMemcpyAsync(host, scal, sizeof(double), hipMemcpyDeviceToHost, s));
-    QB_HIP(hipStreamSynchronize(s));
+    if (early_g) {
+        // the first chunk's Omega and G (ungated: the stopping state is not set up yet)
+        Ctx xg = x;
+        xg.gate = nullptr;
+        tm.mark(1);
+        QB_HIP(launch_gauss_fill(p->seed, 0, 0, 0, 0, n, w_early, x.at<double>(L.om), w_early, s));
+        tm.mark(2);
+        if (int e = apply_A(xg, x.at<double>(L.om), w_early, x.at<double>(L.g), w_early, w_early,
+                            x.at<double>(L.gnorm2)))
+            return inf->status = e;
+        // the read-back to pageable memory holds the host until the sum is done; G is queued
+        QB_HIP(hipMemcpyAsync(host, scal, sizeof(double), hipMemcpyDeviceToHost, res->side));
+        QB_HIP(hipStreamSynchronize(res->side));
+        // later work on this stream (the scan state set-up reads the sum) follows the sum
+        QB_HIP(hipEventRecord(res->ev_pre, res->side));
+        QB_HIP(hipStreamWaitEvent(s, res->ev_pre, 0));
+    } else {
+        QB_HIP(hipMemcpyAsync(host, scal, sizeof(double), hipMemcpyDeviceToHost, s));
+        QB_HIP(hipStreamSynchronize(s));
+    }
     const double normA2 = host[0];
     inf->normA2 = normA2;
     if (!isfinite(normA2)) {
         tm.mark(-1);
+        if (early_g) QB_HIP(hipStreamSynchronize(s));
         return inf->status = QB_ERR_NONFINITE;
     }
     const double eps2 = p->tol_rel * p->tol_rel * normA2;
@@ -897,8 +926,9 @@ int run(int algo, Op& A, const qb_params* p, double* Q, int64_t ldq, double* B, 
                 la.k = -1;
                 k_half = chunk_lo + b * (cdiv(w, b) / 2);
                 e_half = E;
-                tm.mark(1);
-                QB_HIP(launch_gauss_fill(p->seed, 0, 0, 0, chunk_lo, n, w, Om, w, s));
+                const bool g_done = early_g && chunk_lo == 0 && w == w_early;   // Omega, G enqueued
+                tm.mark(g_done ? 3 : 1);
+                if (!g_done) QB_HIP(launch_gauss_fill(p->seed, 0, 0, 0, chunk_lo, n, w, Om, w, s));
                 if (p->power > 0) {
                     tm.mark(6);
                     if (int e = power_rounds(x, k, w, Om, H, G, gnorm2)) return inf->status = e;
@@ -907,9 +937,11 @@ int run(int algo, Op& A, const qb_params* p, double* Q, int64_t ldq, double* B, 
                 if (A.dtype == QB_BF16 || A.dtype == QB_FP8E4M3) {
                     if (int e = sketch_bf16(x, Om, G, H, w, gnorm2, true)) return inf->status = e;
                 } else {
-                    tm.mark(2);
-                    if (int e = apply_A(x, Om, w, G, w, w, gnorm2)) return inf->status = e;
-                    tm.mark(3);
+                    if (!g_done) {
+                        tm.mark(2);
+                        if (int e = apply_A(x, Om, w, G, w, w, gnorm2)) return inf->status = e;
+                        tm.mark(3);
+                    }
                     if (int e = apply_At(x, G, w, H, w, w)) return inf->status = e;
                 }
                 tm.mark(4);
