@@ -534,8 +534,13 @@ hipError_t gemm_f64(const GemmDesc& d, hipStream_t s) {
     // reductions of 100000 and more.  Shorter reductions and wider outputs stay on the
     // LDS-tiled kernel below.
     if (d.colsq == nullptr && d.N <= 64 && d.K > 128) {
-        if (d.A.si == 1 && d.K <= 16384 && ts_panel_dma_fits(d)) return ts_panel_dma(d, 2, 4, 4, 1, s, 1);
-        if (d.A.sj == 1 && d.B.si == 1 && d.K >= 100000 && ts_red_fits(d)) {
+        if (d.A.si == 1 && d.K <= 32768 && ts_panel_dma_fits(d)) return ts_panel_dma(d, 2, 4, 4, 1, s, 1);
+        // k-contiguous A with a long reduction: k-contiguous B (Q^T Y, Q^T Q_i, Y^T Y), or a
+        // row-major B under at least 4096 output rows (A Omega_i of randQB_EI: 703 against
+        // 887 us at 20000 x 64 x 15000; W = B Omega_J of the sparse workload: 3.53 against
+        // 4.03 ms at 7000 x 50 x 200000; at 1152 rows the tiled kernel was as fast)
+        const bool red_b = d.B.si == 1 ? d.K >= 100000 : d.B.sj == 1 && d.M >= 4096 && d.K >= 8192;
+        if (d.A.sj == 1 && red_b && ts_red_fits(d)) {
             // about 1024 workgroups (one per CU resident at a time), within the split buffer
             const int64_t tiles = cdiv(d.M, 64);
             int64_t ns = cdiv(1024, tiles);

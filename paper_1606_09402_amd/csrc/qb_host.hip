@@ -126,7 +126,7 @@ Layout make_layout(int algo, int sparse, int dtype, int64_t m, int64_t n, int64_
         L.split2_elems = 0;
     }
     // row-tile partials of the G column norms: dense GEMM tiles are >= 64 rows
-    L.gpart_groups = sparse ? colsq_groups(m) : cdiv(m, 64);
+    L.gpart_groups = sparse ? colsq_groups(m) : std::max<int64_t>(cdiv(m, 64), colsq_groups(m));
     // per-block row sums of squares of B_i: partials from a GEMM epilogue over n rows
     // (tiles of >= 64 rows) or from the column reduction (CSR EI)
     int64_t nb_part = cdiv(n, 64);
@@ -344,9 +344,17 @@ int apply_A(const Ctx& x, const double* X, int64_t ldx, double* G, int64_t ldg, 
     if (!A.sparse) {
         GemmDesc d = gdesc(A.m, w, A.n, View{A.a, A.lda, 1}, View{X, ldx, 1}, 1.0, 0.0,
                            View{nullptr, 0, 0}, MutView{G, ldg, 1}, x);
-        d.colsq = gpart;
-        d.colsq_groups = &groups;
-        QB_HIP(gemm_f64(d, x.s));
+        if (w <= 64 && A.m >= 4096) {
+            // a block of randQB_EI: the product on the narrow reduction-form kernel, the
+            // column norms in a pass of their own over the m x w result
+            QB_HIP(gemm_f64(d, x.s));
+            QB_HIP(launch_colsq_rowmajor(G, A.m, w, ldg, gpart, x.s));
+            groups = static_cast<int>(colsq_groups(A.m));
+        } else {
+            d.colsq = gpart;
+            d.colsq_groups = &groups;
+            QB_HIP(gemm_f64(d, x.s));
+        }
     } else {
         QB_HIP(launch_spmm_plan(A.plan_a, A.rowptr, A.colind, A.val, X, ldx, G, ldg, w, x.s));
         QB_HIP(launch_colsq_rowmajor(G, A.m, w, ldg, gpart, x.s));
@@ -1491,7 +1499,8 @@ int layout_check(int algo, int sparse, int dtype, int64_t m, int64_t n, int64_t 
     // column sums of squares of G (every chunk width w <= lt; EI: w = b)
     for (int64_t w = 1; w <= lt; ++w) {
         const int64_t groups = sparse ? colsq_groups(m) : lowp ? bf16_gemm_row_groups(m, w)
-                                                               : gemm_f64_colsq_groups(m, w);
+                                                               : std::max(gemm_f64_colsq_groups(m, w),
+                                                                          w <= 64 ? colsq_groups(m) : 0);
         need(L.gpart, D * groups * w);
     }
     need(L.gnorm2, D * lt);
