@@ -67,6 +67,11 @@ struct BGemm {
     int tiles_n;
     int64_t kchunk;   // K range of one split (blockIdx.y); several splits write partials to P
     T* P;             // [split][batch][M][N] partial sums (gridDim.y > 1)
+    // a second reduction segment (bgemm2_kernel only): k in [K1, K) reads A2(i, k - K1) and
+    // B2(k - K1, j), so C = alpha [A A2] [B; B2] + beta C0 in one pass over C
+    int64_t K1;
+    const T* A2; int64_t a2_si, a2_sk, a2_sz;
+    const T* B2; int64_t b2_sk, b2_sj, b2_sz;
 };
 
 template <typename T, int BM, int BN, int BK>
@@ -203,8 +208,10 @@ __global__ void __launch_bounds__(64 * WM * WN) bgemm2_kernel(const BGemm<T> g, 
     const int64_t z = blockIdx.z;
     const int tile_m = blockIdx.x / g.tiles_n, tile_n = blockIdx.x % g.tiles_n;
     const int64_t m0 = static_cast<int64_t>(tile_m) * BM, n0 = static_cast<int64_t>(tile_n) * BN;
-    const T* A = g.A + z * g.a_sz;
-    const T* B = g.B + z * g.b_sz;
+    const T* A1 = g.A + z * g.a_sz;
+    const T* B1 = g.B + z * g.b_sz;
+    const T* A2 = g.A2 != nullptr ? g.A2 + z * g.a2_sz : nullptr;
+    const T* B2 = g.B2 != nullptr ? g.B2 + z * g.b2_sz : nullptr;
     const bool full = m0 + BM <= g.M && n0 + BN <= g.N;
     const bool va = vec_a && full, vb = vec_b && full;
 
@@ -217,14 +224,23 @@ __global__ void __launch_bounds__(64 * WM * WN) bgemm2_kernel(const BGemm<T> g, 
         if (BKF) { kk = e % BK; jj = e / BK; } else { kk = e / BN; jj = e % BN; }
     };
     T ra[LA], rb[LB];
-    auto load = [&](int64_t k0, int64_t ke) {
-        const bool kin = k0 + BK <= ke;
+    auto load = [&](int64_t kg0, int64_t ke) {
+        const bool kin = kg0 + BK <= ke;
+        // the segment of this K tile (a tile never straddles K1: K1 and the split chunks are
+        // multiples of BK when there are two segments)
+        const bool seg2 = kg0 >= g.K1;
+        const T* A = seg2 ? A2 : A1;
+        const T* B = seg2 ? B2 : B1;
+        const int64_t a_si = seg2 ? g.a2_si : g.a_si, a_sk = seg2 ? g.a2_sk : g.a_sk;
+        const int64_t b_sk = seg2 ? g.b2_sk : g.b_sk, b_sj = seg2 ? g.b2_sj : g.b_sj;
+        const int64_t k0 = seg2 ? kg0 - g.K1 : kg0;
+        const int64_t kend = seg2 ? ke - g.K1 : (ke < g.K1 ? ke : g.K1);
 #pragma unroll
         for (int p = 0; p < LA / VE; ++p) {
             int kk, ii;
             a_of((tid + p * NT) * VE, kk, ii);
             if (va && kin) {
-                const V x = *reinterpret_cast<const V*>(A + (m0 + ii) * g.a_si + (k0 + kk) * g.a_sk);
+                const V x = *reinterpret_cast<const V*>(A + (m0 + ii) * a_si + (k0 + kk) * a_sk);
                 const T* xs = reinterpret_cast<const T*>(&x);
 #pragma unroll
                 for (int q = 0; q < VE; ++q) ra[p * VE + q] = xs[q];
@@ -232,7 +248,7 @@ __global__ void __launch_bounds__(64 * WM * WN) bgemm2_kernel(const BGemm<T> g, 
 #pragma unroll
                 for (int q = 0; q < VE; ++q) {
                     const int64_t i = m0 + ii + (AKF ? 0 : q), k = k0 + kk + (AKF ? q : 0);
-                    ra[p * VE + q] = (i < g.M && k < ke) ? A[i * g.a_si + k * g.a_sk] : T(0);
+                    ra[p * VE + q] = (i < g.M && k < kend) ? A[i * a_si + k * a_sk] : T(0);
                 }
             }
         }
@@ -241,7 +257,7 @@ __global__ void __launch_bounds__(64 * WM * WN) bgemm2_kernel(const BGemm<T> g, 
             int kk, jj;
             b_of((tid + p * NT) * VE, kk, jj);
             if (vb && kin) {
-                const V x = *reinterpret_cast<const V*>(B + (k0 + kk) * g.b_sk + (n0 + jj) * g.b_sj);
+                const V x = *reinterpret_cast<const V*>(B + (k0 + kk) * b_sk + (n0 + jj) * b_sj);
                 const T* xs = reinterpret_cast<const T*>(&x);
 #pragma unroll
                 for (int q = 0; q < VE; ++q) rb[p * VE + q] = xs[q];
@@ -249,7 +265,7 @@ __global__ void __launch_bounds__(64 * WM * WN) bgemm2_kernel(const BGemm<T> g, 
 #pragma unroll
                 for (int q = 0; q < VE; ++q) {
                     const int64_t j = n0 + jj + (BKF ? 0 : q), k = k0 + kk + (BKF ? q : 0);
-                    rb[p * VE + q] = (j < g.N && k < ke) ? B[k * g.b_sk + j * g.b_sj] : T(0);
+                    rb[p * VE + q] = (j < g.N && k < kend) ? B[k * b_sk + j * b_sj] : T(0);
                 }
             }
         }
@@ -396,6 +412,7 @@ hipError_t bgemm(int64_t batch, int64_t M, int64_t N, int64_t K, BV<T> a, BV<T> 
     g.alpha = alpha; g.beta = beta;
     g.C0 = c0.p; g.c0_si = c0.si; g.c0_sj = c0.sj; g.c0_sz = c0.sz;
     g.C = c.p; g.c_si = c.si; g.c_sj = c.sj; g.c_sz = c.sz;
+    g.K1 = K;   // one reduction segment
     if (batch > 65535) return hipErrorInvalidValue;
     // 128 x 128 tiles (two LDS stages) for outputs of at least 128 x 128 with a reduction
     // of at least 128; else 64 x 64 tiles, 128 x 64 for tall outputs with few tiles per matrix
@@ -440,6 +457,47 @@ hipError_t bgemm(int64_t batch, int64_t M, int64_t N, int64_t K, BV<T> a, BV<T> 
                            sw.p, static_cast<int>(nsplit), batch, M, N, alpha, beta, c0.p, c0.si, c0.sj, c0.sz,
                            c.p, c.si, c.sj, c.sz);
     }
+    return hipGetLastError();
+}
+
+// C = alpha [A1 A2] [B1; B2] + beta C0 over the reductions K1 then K2 (each a multiple of
+// 32), on the 128 x 128 two-stage kernel without K splits, so C is written once.  Both A
+// segments must share their layout (k-contiguous or not), both B segments likewise;
+// hipErrorNotSupported when the shape or the layouts do not fit.
+template <typename T>
+hipError_t bgemm_2seg(int64_t batch, int64_t M, int64_t N, int64_t K1, BV<T> a1, BV<T> b1, int64_t K2,
+                      BV<T> a2, BV<T> b2, T alpha, T beta, BV<T> c0, BMV<T> c, hipStream_t s) {
+    if (batch <= 0 || batch > 65535 || M < 128 || N < 128 || K1 <= 0 || K2 <= 0 || K1 % 32 != 0 ||
+        K2 % 32 != 0)
+        return hipErrorNotSupported;
+    const bool akf = a1.sj == 1, bkf = b1.si == 1 && b1.sj != 1;
+    if ((a2.sj == 1) != akf || (b2.si == 1 && b2.sj != 1) != bkf) return hipErrorNotSupported;
+    BGemm<T> g{};
+    g.M = M; g.N = N; g.K = K1 + K2; g.K1 = K1;
+    g.A = a1.p; g.a_si = a1.si; g.a_sk = a1.sj; g.a_sz = a1.sz;
+    g.B = b1.p; g.b_sk = b1.si; g.b_sj = b1.sj; g.b_sz = b1.sz;
+    g.A2 = a2.p; g.a2_si = a2.si; g.a2_sk = a2.sj; g.a2_sz = a2.sz;
+    g.B2 = b2.p; g.b2_sk = b2.si; g.b2_sj = b2.sj; g.b2_sz = b2.sz;
+    g.alpha = alpha; g.beta = beta;
+    g.C0 = c0.p; g.c0_si = c0.si; g.c0_sj = c0.sj; g.c0_sz = c0.sz;
+    g.C = c.p; g.c_si = c.si; g.c_sj = c.sj; g.c_sz = c.sz;
+    g.tiles_n = static_cast<int>(cdiv(N, 128));
+    g.kchunk = g.K;
+    g.P = nullptr;
+    constexpr int64_t VE = 16 / sizeof(T);
+    auto aligned = [&](const T* p, int64_t s1, int64_t sz) {
+        return reinterpret_cast<uintptr_t>(p) % 16 == 0 && s1 % VE == 0 && sz % VE == 0;
+    };
+    // 16-byte loads only when every matrix of both segments allows them
+    const int va = akf ? aligned(a1.p, a1.si, a1.sz) && aligned(a2.p, a2.si, a2.sz)
+                       : a1.si == 1 && a2.si == 1 && aligned(a1.p, a1.sj, a1.sz) && aligned(a2.p, a2.sj, a2.sz);
+    const int vb = bkf ? aligned(b1.p, b1.sj, b1.sz) && aligned(b2.p, b2.sj, b2.sz)
+                       : b1.sj == 1 && b2.sj == 1 && aligned(b1.p, b1.si, b1.sz) && aligned(b2.p, b2.si, b2.sz);
+    const dim3 grid(static_cast<unsigned>(cdiv(M, 128) * g.tiles_n), 1u, static_cast<unsigned>(batch));
+    if (akf && bkf) hipLaunchKernelGGL((bgemm2_kernel<T, 128, 128, 32, 4, 2, true, true>), grid, dim3(512), 0, s, g, va, vb);
+    else if (akf) hipLaunchKernelGGL((bgemm2_kernel<T, 128, 128, 32, 4, 2, true, false>), grid, dim3(512), 0, s, g, va, vb);
+    else if (bkf) hipLaunchKernelGGL((bgemm2_kernel<T, 128, 128, 32, 4, 2, false, true>), grid, dim3(512), 0, s, g, va, vb);
+    else hipLaunchKernelGGL((bgemm2_kernel<T, 128, 128, 32, 4, 2, false, false>), grid, dim3(512), 0, s, g, va, vb);
     return hipGetLastError();
 }
 
@@ -589,7 +647,7 @@ constexpr int kMaxDiffK = 256;
 
 struct DiffLayout {
     size_t om64, om, g, h, y, x, w, z, d, s, gram, r1, r1i, rt, rti, ri, rii, flag,
-        r, rinv, qt, mm, cs, yb, split, total;
+        r, rinv, qt, mm, cs, yb, omt, split, total;
     int64_t split_elems;
 };
 
@@ -638,6 +696,7 @@ DiffLayout diff_layout(int64_t batch, int64_t m, int64_t n, int64_t k, int64_t b
     L.mm = take(E * batch * k * k);
     L.cs = take(E * batch * k * k);
     L.yb = take(E * batch * m * k);
+    L.omt = take(E * k * n);   // Omega^T, rows of n (the backward's last product)
     L.split_elems = split_elems(batch, k, b);
     L.split = take(E * L.split_elems);
     L.total = off + 256;
@@ -813,12 +872,22 @@ int fixed_bwd(const qb_batch* Ab, int64_t k, uint64_t seed, const T* Q, int64_t 
                      BV<T>{Qt, k, 1, m * k}, BMV<T>{Qt, k, 1, m * k}, s, SW));
     QB_DHIP(bgemm<T>(bt, m, k, k, BV<T>{Qt, k, 1, m * k}, BV<T>{Rinv, 1, k, kk}, T(1), T(0), none,
                      BMV<T>{Yb, k, 1, m * k}, s, SW));
-    // dA = Q dB + Y-bar Omega^T
+    // dA = Q dB + Y-bar Omega^T.  Omega^T is copied with rows of n (0.5 MB at n = 1024, k = 128)
+    // so that both products read their right operand the same way; then, when the shape
+    // allows, one pass [Q Y-bar] [dB; Omega^T] writes dA once instead of writing it and
+    // reading it back for the second product.
+    T* OmT = P(L.omt);
+    QB_DHIP(bgemm<T>(1, k, n, 0, none, none, T(0), T(1), BV<T>{Om, 1, k, 0}, BMV<T>{OmT, n, 1, 0}, s, SW));
     if (has_db) {
+        const hipError_t e = bgemm_2seg<T>(bt, m, n, k, BV<T>{Q, ldq, 1, sq}, BV<T>{dB, lddb, 1, sdb}, k,
+                                           BV<T>{Yb, k, 1, m * k}, BV<T>{OmT, n, 1, 0}, T(1), T(0), none,
+                                           BMV<T>{dA, ldda, 1, sda}, s);
+        if (e == hipSuccess) return QB_OK;
+        if (e != hipErrorNotSupported) return QB_ERR_HIP;
         QB_DHIP(bgemm<T>(bt, m, n, k, BV<T>{Q, ldq, 1, sq}, BV<T>{dB, lddb, 1, sdb}, T(1), T(0), none,
                          BMV<T>{dA, ldda, 1, sda}, s, SW));
     }
-    QB_DHIP(bgemm<T>(bt, m, n, k, BV<T>{Yb, k, 1, m * k}, BV<T>{Om, 1, k, 0}, T(1),
+    QB_DHIP(bgemm<T>(bt, m, n, k, BV<T>{Yb, k, 1, m * k}, BV<T>{OmT, n, 1, 0}, T(1),
                      has_db ? T(1) : T(0), has_db ? BV<T>{dA, ldda, 1, sda} : none,
                      BMV<T>{dA, ldda, 1, sda}, s, SW));
     return QB_OK;
