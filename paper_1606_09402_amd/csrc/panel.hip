@@ -169,7 +169,7 @@ chol_blocked_kernel(const double* __restrict__ gram, int b, double tau, double* 
                     double* __restrict__ Rinv, int* __restrict__ flag) {
     constexpr int ld = BMAX + 1;
     constexpr int NBMAX = BMAX / kCb;
-    constexpr int CH = 8;   // elements per thread in flight when moving the matrix
+    constexpr int CH = 16;   // elements per thread in flight when moving the matrix
     __shared__ double S[BMAX * ld];
     __shared__ double U[(NBMAX > 1 ? NBMAX - 1 : 1) * kCb * kCb];
     __shared__ double rd[BMAX];
@@ -177,7 +177,9 @@ chol_blocked_kernel(const double* __restrict__ gram, int b, double tau, double* 
     __shared__ int bad;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nblk = (b + kCb - 1) / kCb, bp = nblk * kCb;
-    // load: all of a thread's global reads of a round are issued before its LDS writes
+    // load: all of a thread's global reads of a round are issued before its LDS writes; the
+    // largest diagonal entry comes from the same reads
+    double d = 0.0;
     for (int e0 = 0; e0 < bp * bp; e0 += 256 * CH) {
         double v[CH];
 #pragma unroll
@@ -191,9 +193,9 @@ chol_blocked_kernel(const double* __restrict__ gram, int b, double tau, double* 
             const int e = e0 + tid + 256 * u;
             const int i = e / bp, c = e - i * bp;
             if (e < bp * bp && c >= i) S[i * ld + c] = v[u];
+            if (e < bp * bp && c == i && i < b) d = fmax(d, v[u]);
         }
     }
-    double d = tid < b ? gram[tid * b + tid] : 0.0;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) d = fmax(d, __shfl_xor(d, off, 64));
     if (lane == 0) wmax[wave] = d;
