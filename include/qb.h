@@ -393,8 +393,10 @@ QB_API int qb_fixed_rank_bwd(const qb_batch* A, int64_t k, int32_t b, uint64_t s
  * j columns of U = Q U~ and V = V~ with the leading j values of s approximate the rank-j SVD
  * of A.  B^T is first reduced by a thin QR, B^T = P T (the block orthonormalisation of the
  * power scheme: 128-column blocks, CholeskyQR twice, Householder on breakdown), then the k x k
- * factor T^T is diagonalised by one-sided Jacobi rotations (circle ordering, a pair is
- * rotated while its cosine exceeds sqrt(k) 2^-53), and V = P W.
+ * factor T^T is diagonalised by block one-sided Jacobi (blocks of 32 columns in circle
+ * ordering; each pair of blocks rotated by the product of one cyclic Jacobi sweep over its
+ * Gram matrix; a column pair is rotated while its cosine exceeds 16 sqrt(k) 2^-53), and
+ * V = P W.
  *   Q  m x k, column-major (ldq >= m), orthonormal columns (as qb_fp_* return it)
  *   B  k x n, row-major (ldb >= n)
  *   U  out, m x k column-major (ldu >= m); s out, k values in descending order;
@@ -403,8 +405,8 @@ QB_API int qb_fixed_rank_bwd(const qb_batch* A, int64_t k, int32_t b, uint64_t s
  *      of U flips with it.  A zero singular value leaves its column of U zero.
  *   1 <= k <= min(m, n).  All pointers are device pointers; the workspace (256-byte
  *   aligned, qb_svd_workspace_bytes) holds every temporary.  The call synchronises the
- *   stream (one flag per Jacobi sweep).  *sweeps (may be NULL) receives the Jacobi sweeps
- *   taken.  Returns QB_OK, QB_NOT_CONVERGED if 40 sweeps did not converge (outputs still
+ *   stream (one flag per Jacobi sweep).  *sweeps (may be NULL) receives the sweeps over all
+ *   pairs of blocks taken.  Returns QB_OK, QB_NOT_CONVERGED if 40 sweeps did not converge (outputs still
  *   written), QB_ERR_ARG, QB_ERR_WORKSPACE or QB_ERR_HIP. */
 QB_API size_t qb_svd_workspace_bytes(int64_t m, int64_t n, int64_t k);
 QB_API int qb_svd_from_qb(int64_t m, int64_t n, int64_t k, const double* Q, int64_t ldq,
