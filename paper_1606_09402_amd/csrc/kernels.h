@@ -180,7 +180,8 @@ hipError_t launch_gather_cols(const double* X, int64_t ldx, int64_t rows, const 
                               double* Y, int64_t ldy, hipStream_t s);
 
 // svd.hip -- block one-sided Jacobi SVD of a k x k factor (circle ordering over blocks of
-// 32 columns) and its outputs
+// 32 columns) and its outputs.  Round -1 of a sweep turns every column pair of neighbouring
+// blocks 2p, 2p+1; rounds 0 .. jacobi_rounds(k)-1 turn the pairs across two blocks.
 int jacobi_rounds(int k);
 size_t jacobi_part_elems(int k);
 size_t jacobi_rot_elems(int k);

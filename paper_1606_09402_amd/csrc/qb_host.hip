@@ -1343,7 +1343,7 @@ int svd_from_qb(int64_t m, int64_t n, int64_t k, const double* Q, int64_t ldq, c
     int* hflag = reinterpret_cast<int*>(host + 3 * kMaxB);
     while (sweeps < kMaxSweeps) {
         QB_HIP(launch_fill_int(flags + 1, 1, 0, s));
-        for (int r = 0; r < rounds; ++r)
+        for (int r = -1; r < rounds; ++r)   // the within-block step, then the circle rounds
             QB_HIP(launch_jacobi_block_round(T, W, ki, k, r, tol_r, tol_c, kJacobiInner, jpart, jrot, jskip,
                                              flags + 1, s));
         ++sweeps;

@@ -61,6 +61,18 @@ constexpr int kJp = 2 * kJb;       // columns per pair of blocks
 constexpr int kJrows = 64;         // rows per LDS tile (Gram and apply)
 constexpr int kGramTiles = 2;      // tiles per Gram split
 
+// The pair of blocks that workgroup p of a round works on: round r >= 0 of the circle
+// ordering over np players, or, for round -1 (the within-block step of a sweep), the
+// neighbours 2 p and 2 p + 1.
+QB_DEV void round_pair(int np, int round, int p, int& a, int& b) {
+    if (round < 0) {
+        a = 2 * p;
+        b = 2 * p + 1;
+        return;
+    }
+    circle_pair(np, round, p, a, b);
+}
+
 // Column of X that slot j (0 .. kJp-1) of the pair of blocks (a, b) holds, or -1.
 QB_DEV int pair_col(int a, int b, int nb, int j, int k) {
     const int blk = j < kJb ? a : b;
@@ -99,7 +111,7 @@ pair_gram_kernel(const double* __restrict__ X, int k, int64_t ld, int nb, int np
     constexpr int kPitch = kJp + 2;   // rows of the tile, 16-byte aligned
     __shared__ __align__(16) double xs[kJrows * kPitch];
     int a, b;
-    circle_pair(np, round, static_cast<int>(blockIdx.x), a, b);
+    round_pair(np, round, static_cast<int>(blockIdx.x), a, b);
     const int ti = static_cast<int>(threadIdx.x) >> 4, tj = static_cast<int>(threadIdx.x) & 15;
     double acc[4][4];
 #pragma unroll
@@ -151,8 +163,13 @@ pair_reduce_kernel(const double* __restrict__ part, int nsplit, double* __restri
     G[static_cast<int64_t>(blockIdx.x) * (kJp * kJp) + e] = acc;
 }
 
-// One workgroup per pair of blocks: G = the pair's Gram matrix, then up to `inner` sweeps of cyclic two-sided Jacobi on G (circle ordering over the kJp
-// columns, kJp/2 disjoint rotations per round), accumulating V = product of the rotations.
+// One workgroup per pair of blocks: G = the pair's Gram matrix, then up to `inner` sweeps
+// of cyclic two-sided Jacobi on G, accumulating V = product of the rotations.  With cross
+// set a sweep turns only the column pairs that straddle the two blocks (kJb rounds of kJb
+// disjoint pairs: column i of block a with column i + r mod kJb of block b), else every pair
+// (circle ordering over the kJp columns, kJp - 1 rounds of kJp / 2 pairs).  A sweep of the
+// whole matrix is one step without cross over neighbouring blocks and one circle round with
+// cross per pair of blocks, so every column pair turns at least once per sweep.
 // Columns p, q rotate when |g_pq| > tol_r sqrt(g_pp g_qq), with the angle of one-sided
 // Jacobi: zeta = (g_qq - g_pp) / (2 g_pq), t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)),
 // c = 1 / sqrt(1 + t^2), s = c t, x_p <- c x_p - s x_q, x_q <- s x_p + c x_q; on G that is
@@ -160,7 +177,7 @@ pair_reduce_kernel(const double* __restrict__ part, int nsplit, double* __restri
 // 1 when nothing rotated (the apply kernel then leaves the pair), and flag is set when some
 // |g_pq| exceeded tol_c sqrt(g_pp g_qq) (the sweep is not the last).
 __global__ void __launch_bounds__(kSvdThreads)
-pair_eig_kernel(const double* __restrict__ gram, int inner, double tol_r, double tol_c,
+pair_eig_kernel(const double* __restrict__ gram, int inner, int cross, double tol_r, double tol_c,
                 double* __restrict__ Vout, int* __restrict__ skip, int* __restrict__ flag) {
     __shared__ double G[kJp][kJp + 1];
     __shared__ double V[kJp][kJp + 1];
@@ -207,7 +224,8 @@ pair_eig_kernel(const double* __restrict__ gram, int inner, double tol_r, double
         const int e = tid + q * kSvdThreads;
         const int i = e / kJp, j = e % kJp;
         const double gij = gv[q];
-        open = open || (i != j && gij != 0.0 && gij * gij > tol_r * tol_r * G[i][i] * G[j][j]);
+        const bool tested = cross ? (i < kJb) != (j < kJb) : i != j;
+        open = open || (tested && gij != 0.0 && gij * gij > tol_r * tol_r * G[i][i] * G[j][j]);
     }
     if (!__syncthreads_or(open)) {
         if (tid == 0) skip[blockIdx.x] = 1;
@@ -216,14 +234,19 @@ pair_eig_kernel(const double* __restrict__ gram, int inner, double tol_r, double
     for (int sw = 0; sw < inner; ++sw) {
         if (tid == 0) rot = 0;
         __syncthreads();
-        for (int r = 0; r < kJp - 1; ++r) {
+        for (int r = 0; r < (cross ? kJb : kJp - 1); ++r) {
             if (tid < kJp / 2) {
                 int pp, qq;
-                circle_pair(kJp, r, tid, pp, qq);
-                if (pp > qq) {
-                    const int t = pp;
-                    pp = qq;
-                    qq = t;
+                if (cross) {
+                    pp = tid;
+                    qq = kJb + ((tid + r) & (kJb - 1));
+                } else {
+                    circle_pair(kJp, r, tid, pp, qq);
+                    if (pp > qq) {
+                        const int t = pp;
+                        pp = qq;
+                        qq = t;
+                    }
                 }
                 const double al = G[pp][pp], be = G[qq][qq], ga = G[pp][qq];
                 const double g2 = ga * ga, ab = al * be;
@@ -351,7 +374,7 @@ pair_apply_kernel(double* __restrict__ X, double* __restrict__ W, int k, int64_t
     __shared__ __align__(16) double xs[kJp * kPitch];
     double* M = blockIdx.z == 0 ? X : W;
     int a, b;
-    circle_pair(np, round, static_cast<int>(blockIdx.x), a, b);
+    round_pair(np, round, static_cast<int>(blockIdx.x), a, b);
     const double* v = Vp + static_cast<int64_t>(blockIdx.x) * (kJp * kJp);
     {
         double t[kJp * kJp / kSvdThreads];
@@ -506,8 +529,8 @@ hipError_t launch_jacobi_block_round(double* X, double* W, int k, int64_t ld, in
     double* gram = part + static_cast<int64_t>(pairs) * nsplit * (kJp * kJp);
     hipLaunchKernelGGL(pair_reduce_kernel, dim3(pairs, (kJp * kJp) / kSvdThreads), dim3(kSvdThreads), 0, s,
                        part, nsplit, gram);
-    hipLaunchKernelGGL(pair_eig_kernel, dim3(pairs), dim3(kSvdThreads), 0, s, gram, inner, tol_r, tol_c, V,
-                       skip, flag);
+    hipLaunchKernelGGL(pair_eig_kernel, dim3(pairs), dim3(kSvdThreads), 0, s, gram, inner, round >= 0 ? 1 : 0,
+                       tol_r, tol_c, V, skip, flag);
     hipLaunchKernelGGL(pair_apply_kernel, dim3(pairs, static_cast<unsigned>(cdiv(k, kJrows)), 2), dim3(kSvdThreads),
                        0, s, X, W, k, ld, nb, np, round, V, skip);
     return hipGetLastError();
