@@ -163,13 +163,44 @@ pair_reduce_kernel(const double* __restrict__ part, int nsplit, double* __restri
     G[static_cast<int64_t>(blockIdx.x) * (kJp * kJp) + e] = acc;
 }
 
+// The rotation of columns p, q from their Gram entries al = g_pp, be = g_qq, ga = g_pq:
+// returns false (c = 1, s = t = 0) when |g_pq| <= tol_r sqrt(g_pp g_qq), and sets big when
+// |g_pq| > tol_c sqrt(g_pp g_qq).  t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)),
+// zeta = (g_qq - g_pp) / (2 g_pq), is evaluated as sign(d) 2 g_pq / (|d| + sqrt(d^2 + 4 g_pq^2)),
+// d = g_qq - g_pp.  The angle needs no last-bit accuracy (it only sets how far the pair
+// turns; one Newton step on each hardware estimate gives about 46 bits), c^2 + s^2 = 1 does:
+// c comes from a fully refined 1 / sqrt.
+QB_DEV bool pair_rotation(double al, double be, double ga, double tol_r, double tol_c, double& c,
+                          double& s, double& t, bool& big) {
+    const double g2 = ga * ga, ab = al * be;
+    c = 1.0;
+    s = 0.0;
+    t = 0.0;
+    big = false;
+    if (!(ga != 0.0 && g2 > tol_r * tol_r * ab)) return false;
+    const double d = be - al, g2x = 2.0 * ga;
+    const double hx = fma(d, d, g2x * g2x);
+    const double y = __builtin_amdgcn_rsq(hx);
+    double h = hx * y;                                  // sqrt(hx), ~23 bits
+    h = fma(fma(-h, h, hx), 0.5 * y, h);                // one Newton step
+    const double den = fabs(d) + h;
+    double ri = __builtin_amdgcn_rcp(den);
+    ri = fma(ri, fma(-den, ri, 1.0), ri);               // one Newton step
+    t = g2x * ri;
+    if (d < 0.0) t = -t;
+    double unused;
+    sqrt_and_rsqrt(fma(t, t, 1.0), unused, c);
+    s = c * t;
+    big = g2 > tol_c * tol_c * ab;
+    return true;
+}
+
 // One workgroup per pair of blocks: G = the pair's Gram matrix, then up to `inner` sweeps
-// of cyclic two-sided Jacobi on G, accumulating V = product of the rotations.  With cross
-// set a sweep turns only the column pairs that straddle the two blocks (kJb rounds of kJb
-// disjoint pairs: column i of block a with column i + r mod kJb of block b), else every pair
-// (circle ordering over the kJp columns, kJp - 1 rounds of kJp / 2 pairs).  A sweep of the
-// whole matrix is one step without cross over neighbouring blocks and one circle round with
-// cross per pair of blocks, so every column pair turns at least once per sweep.
+// of cyclic two-sided Jacobi on G (circle ordering over the kJp columns, kJp - 1 rounds of
+// kJp / 2 disjoint pairs), accumulating V = product of the rotations.  This is the
+// within-block step of a sweep (neighbouring blocks 2p, 2p + 1); the circle rounds over the
+// blocks that follow turn only the column pairs across their two blocks
+// (pair_eig_cross_kernel), so every column pair turns at least once per sweep.
 // Columns p, q rotate when |g_pq| > tol_r sqrt(g_pp g_qq), with the angle of one-sided
 // Jacobi: zeta = (g_qq - g_pp) / (2 g_pq), t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)),
 // c = 1 / sqrt(1 + t^2), s = c t, x_p <- c x_p - s x_q, x_q <- s x_p + c x_q; on G that is
@@ -177,11 +208,11 @@ pair_reduce_kernel(const double* __restrict__ part, int nsplit, double* __restri
 // 1 when nothing rotated (the apply kernel then leaves the pair), and flag is set when some
 // |g_pq| exceeded tol_c sqrt(g_pp g_qq) (the sweep is not the last).
 __global__ void __launch_bounds__(kSvdThreads)
-pair_eig_kernel(const double* __restrict__ gram, int inner, int cross, double tol_r, double tol_c,
+pair_eig_kernel(const double* __restrict__ gram, int inner, double tol_r, double tol_c,
                 double* __restrict__ Vout, int* __restrict__ skip, int* __restrict__ flag) {
     __shared__ double G[kJp][kJp + 1];
     __shared__ double V[kJp][kJp + 1];
-    __shared__ double rc[kJp / 2], rs[kJp / 2];
+    __shared__ double rc[kJp / 2], rs[kJp / 2], rt[kJp / 2];
     __shared__ int rp[kJp / 2], rq[kJp / 2];
     __shared__ int rot, big;
     const int tid = static_cast<int>(threadIdx.x);
@@ -224,8 +255,7 @@ pair_eig_kernel(const double* __restrict__ gram, int inner, int cross, double to
         const int e = tid + q * kSvdThreads;
         const int i = e / kJp, j = e % kJp;
         const double gij = gv[q];
-        const bool tested = cross ? (i < kJb) != (j < kJb) : i != j;
-        open = open || (tested && gij != 0.0 && gij * gij > tol_r * tol_r * G[i][i] * G[j][j]);
+        open = open || (i != j && gij != 0.0 && gij * gij > tol_r * tol_r * G[i][i] * G[j][j]);
     }
     if (!__syncthreads_or(open)) {
         if (tid == 0) skip[blockIdx.x] = 1;
@@ -234,46 +264,23 @@ pair_eig_kernel(const double* __restrict__ gram, int inner, int cross, double to
     for (int sw = 0; sw < inner; ++sw) {
         if (tid == 0) rot = 0;
         __syncthreads();
-        for (int r = 0; r < (cross ? kJb : kJp - 1); ++r) {
+        for (int r = 0; r < kJp - 1; ++r) {
             if (tid < kJp / 2) {
                 int pp, qq;
-                if (cross) {
-                    pp = tid;
-                    qq = kJb + ((tid + r) & (kJb - 1));
-                } else {
-                    circle_pair(kJp, r, tid, pp, qq);
-                    if (pp > qq) {
-                        const int t = pp;
-                        pp = qq;
-                        qq = t;
-                    }
+                circle_pair(kJp, r, tid, pp, qq);
+                if (pp > qq) {
+                    const int t = pp;
+                    pp = qq;
+                    qq = t;
                 }
-                const double al = G[pp][pp], be = G[qq][qq], ga = G[pp][qq];
-                const double g2 = ga * ga, ab = al * be;
-                double c = 1.0, s = 0.0;
-                if (ga != 0.0 && g2 > tol_r * tol_r * ab) {
-                    // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)) written as
-                    // sign(d) 2 g_pq / (|d| + sqrt(d^2 + 4 g_pq^2)), d = g_qq - g_pp.  The
-                    // angle needs no last-bit accuracy (it only sets how far the pair
-                    // turns; one Newton step on each hardware estimate gives about 46
-                    // bits), c^2 + s^2 = 1 does: c comes from a fully refined 1 / sqrt.
-                    const double d = be - al, g2x = 2.0 * ga;
-                    const double hx = fma(d, d, g2x * g2x);
-                    const double y = __builtin_amdgcn_rsq(hx);
-                    double h = hx * y;                                  // sqrt(hx), ~23 bits
-                    h = fma(fma(-h, h, hx), 0.5 * y, h);                // one Newton step
-                    const double den = fabs(d) + h;
-                    double ri = __builtin_amdgcn_rcp(den);
-                    ri = fma(ri, fma(-den, ri, 1.0), ri);               // one Newton step
-                    double t = g2x * ri;
-                    if (d < 0.0) t = -t;
-                    double unused;
-                    sqrt_and_rsqrt(fma(t, t, 1.0), unused, c);
-                    s = c * t;
+                double c, s, t;
+                bool bg;
+                if (pair_rotation(G[pp][pp], G[qq][qq], G[pp][qq], tol_r, tol_c, c, s, t, bg)) {
                     rot = 1;
-                    if (g2 > tol_c * tol_c * ab) big = 1;
+                    if (bg) big = 1;
                 }
                 rc[tid] = c;
+                rt[tid] = t;
                 rs[tid] = s;
                 rp[tid] = pp;
                 rq[tid] = qq;
@@ -309,7 +316,7 @@ pair_eig_kernel(const double* __restrict__ gram, int inner, int cross, double to
                     if (!own[i]) continue;
                     if (s1[i] == 0.0 && s2[i] == 0.0) continue;
                     if (P[i] == Q[i]) {   // diagonal block: the rotation's closed form
-                        const double t = s1[i] / c1[i];
+                        const double t = rt[P[i]];
                         G[p1[i]][p1[i]] = g[i][0] - t * g[i][1];
                         G[q1[i]][q1[i]] = g[i][3] + t * g[i][1];
                         G[p1[i]][q1[i]] = 0.0;
@@ -360,6 +367,140 @@ pair_eig_kernel(const double* __restrict__ gram, int inner, int cross, double to
     if (!any) return;
     double* v = Vout + static_cast<int64_t>(blockIdx.x) * (kJp * kJp);
     for (int e = tid; e < kJp * kJp; e += kSvdThreads) v[e] = V[e / kJp][e % kJp];
+}
+
+// The cross sweep of pair_eig_kernel (column i of block a against column i + r mod kJb of
+// block b in round r) with G and V held in registers.  Slot i of block b holds column
+// i + r mod kJb of b in round r, so the round's pairs are (i, i) and G splits into 2 x 2
+// blocks M_ij = [[A_ij, C_ij], [C_ji, D_ij]] (A = G_aa, C = G_ab, D = G_bb in slot order)
+// that each take J_i^T M_ij J_j with no data from other blocks.  Thread (i, h) -- lane
+// i = t mod 32 of half-wave h = t / 32 -- keeps the blocks of columns j = h + 8 q, q < 4, and
+// rows h + 8 u, u < 8, of V's columns (a_i, b_i); it computes the rotation of pair i and
+// takes those of pairs j from lane j.  Between rounds the slots of b move down by one:
+// C and D pass through LDS (ping-pong buffers, one barrier per round; C_ji is re-read from
+// the copy of C_ij its owner wrote, so the two copies of an entry never drift apart) and V's
+// b columns through a lane shuffle.  After kJb rounds the slots are back in column order.
+__global__ void __launch_bounds__(kSvdThreads)
+pair_eig_cross_kernel(const double* __restrict__ gram, int inner, double tol_r, double tol_c,
+                      double* __restrict__ Vout, int* __restrict__ skip, int* __restrict__ flag) {
+    static_assert(kJb == 32 && kSvdThreads == 256, "thread (lane, half-wave) layout");
+    constexpr int kQ = 4, kU = 8;
+    __shared__ double Cs[2][kJb][kJb + 1], Ds[2][kJb][kJb + 1], Ad[2][kJb];
+    __shared__ int rot, big;
+    const int tid = static_cast<int>(threadIdx.x);
+    const int i = tid & (kJb - 1), h = tid >> 5;
+    const double* g = gram + static_cast<int64_t>(blockIdx.x) * (kJp * kJp);
+    double A[kQ], C1[kQ], C2[kQ], D[kQ], Djj[kQ];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+        const int j = h + 8 * q;
+        A[q] = g[i * kJp + j];
+        C1[q] = g[i * kJp + kJb + j];
+        C2[q] = g[j * kJp + kJb + i];
+        D[q] = g[(kJb + i) * kJp + kJb + j];
+        Djj[q] = g[(kJb + j) * (kJp + 1)];
+    }
+    double aii = g[i * (kJp + 1)], cii = g[i * kJp + kJb + i], dii = g[(kJb + i) * (kJp + 1)];
+    if (tid == 0) {
+        rot = 0;
+        big = 0;
+    }
+    // a pair whose cross entries already pass the test rotates nothing: leave at once
+    bool open = false;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q)
+        open = open || (C1[q] != 0.0 && C1[q] * C1[q] > tol_r * tol_r * aii * Djj[q]);
+    if (!__syncthreads_or(open)) {
+        if (tid == 0) skip[blockIdx.x] = 1;
+        return;
+    }
+    double va[kU], vb[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+        const int l = h + 8 * u;
+        va[u] = l == i ? 1.0 : 0.0;
+        vb[u] = l == kJb + i ? 1.0 : 0.0;
+    }
+    bool any = false;
+    for (int sw = 0; sw < inner; ++sw) {
+        for (int r = 0; r < kJb; ++r) {
+            const int buf = r & 1;
+            double ci, si, ti;
+            bool bg;
+            if (pair_rotation(aii, dii, cii, tol_r, tol_c, ci, si, ti, bg) && h == 0) {
+                rot = 1;
+                if (bg) big = 1;
+            }
+            double cj[kQ], sj[kQ];
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) {
+                cj[q] = __shfl(ci, h + 8 * q, kJb);
+                sj[q] = __shfl(si, h + 8 * q, kJb);
+            }
+            // V first (it needs only this lane's rotation, so it covers the shuffles' latency),
+            // then b's slots of V move down by one.  No branches: c = 1, s = 0 leave every
+            // value exactly as it was.
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const double x = va[u], y = vb[u];
+                va[u] = ci * x - si * y;
+                vb[u] = si * x + ci * y;
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) vb[u] = __shfl(vb[u], (i + 1) & (kJb - 1), kJb);
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) {
+                // H = M J_j, then J_i^T H; the diagonal block of a turned pair takes the
+                // rotation's closed form (its cross entry becomes an exact zero)
+                const double h00 = cj[q] * A[q] - sj[q] * C1[q], h01 = sj[q] * A[q] + cj[q] * C1[q];
+                const double h10 = cj[q] * C2[q] - sj[q] * D[q], h11 = sj[q] * C2[q] + cj[q] * D[q];
+                const bool dg = h + 8 * q == i && si != 0.0;
+                const double a2 = dg ? A[q] - ti * C1[q] : ci * h00 - si * h10;
+                const double d2 = dg ? D[q] + ti * C1[q] : si * h01 + ci * h11;
+                C1[q] = dg ? 0.0 : ci * h01 - si * h11;
+                A[q] = a2;
+                D[q] = d2;
+            }
+            // publish C, D and diag(A); after the barrier take the next round's slots
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) {
+                const int j = h + 8 * q;
+                Cs[buf][i][j] = C1[q];
+                Ds[buf][i][j] = D[q];
+                if (j == i) Ad[buf][i] = A[q];
+            }
+            __syncthreads();
+            const int i1 = (i + 1) & (kJb - 1);
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) {
+                const int j = h + 8 * q, j1 = (j + 1) & (kJb - 1);
+                C1[q] = Cs[buf][i][j1];
+                C2[q] = Cs[buf][j][i1];
+                D[q] = Ds[buf][i1][j1];
+            }
+            aii = Ad[buf][i];
+            cii = Cs[buf][i][i1];
+            dii = Ds[buf][i1][i1];
+        }
+        __syncthreads();
+        const bool rotated = rot != 0;   // uniform: read after the sweep's last barrier
+        __syncthreads();
+        if (!rotated) break;
+        any = true;
+        if (tid == 0) rot = 0;   // rot is written by wave 0 only (h == 0), in program order after this
+    }
+    if (tid == 0) {
+        skip[blockIdx.x] = any ? 0 : 1;
+        if (big) flag[0] = 1;
+    }
+    if (!any) return;
+    double* v = Vout + static_cast<int64_t>(blockIdx.x) * (kJp * kJp);
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+        const int l = h + 8 * u;
+        v[l * kJp + i] = va[u];
+        v[l * kJp + kJb + i] = vb[u];
+    }
 }
 
 // [X_a X_b] <- [X_a X_b] V on rows [kJrows y, kJrows (y + 1)) (grid z = 0), and the same on
@@ -529,8 +670,12 @@ hipError_t launch_jacobi_block_round(double* X, double* W, int k, int64_t ld, in
     double* gram = part + static_cast<int64_t>(pairs) * nsplit * (kJp * kJp);
     hipLaunchKernelGGL(pair_reduce_kernel, dim3(pairs, (kJp * kJp) / kSvdThreads), dim3(kSvdThreads), 0, s,
                        part, nsplit, gram);
-    hipLaunchKernelGGL(pair_eig_kernel, dim3(pairs), dim3(kSvdThreads), 0, s, gram, inner, round >= 0 ? 1 : 0,
-                       tol_r, tol_c, V, skip, flag);
+    if (round >= 0)
+        hipLaunchKernelGGL(pair_eig_cross_kernel, dim3(pairs), dim3(kSvdThreads), 0, s, gram, inner, tol_r, tol_c,
+                           V, skip, flag);
+    else
+        hipLaunchKernelGGL(pair_eig_kernel, dim3(pairs), dim3(kSvdThreads), 0, s, gram, inner, tol_r, tol_c, V,
+                           skip, flag);
     hipLaunchKernelGGL(pair_apply_kernel, dim3(pairs, static_cast<unsigned>(cdiv(k, kJrows)), 2), dim3(kSvdThreads),
                        0, s, X, W, k, ld, nb, np, round, V, skip);
     return hipGetLastError();
