@@ -50,16 +50,16 @@ QB_DEV void circle_pair(int np, int r, int p, int& a, int& b) {
 // count gets an empty dummy block), and the circle ordering runs over the blocks: a round
 // pairs them into disjoint pairs of 2 kJb columns.  For each pair the round forms the Gram
 // matrix of its columns (pair_gram_kernel, split over the rows, partial sums added in split
-// order), finds the rotations that diagonalise it by cyclic two-sided Jacobi in LDS
-// (pair_eig_kernel: the rotation of columns p, q is the one the column pair itself would
-// get, read off the Gram entries), and applies their product V to the pair's columns of X
-// and of W (pair_apply_kernel).  The Gram matrix is formed afresh from X in every round, so
+// order, on the matrix cores), finds the rotations that diagonalise it by cyclic two-sided
+// Jacobi (pair_eig_kernel, pair_eig_cross_kernel: the rotation of columns p, q is the one
+// the column pair itself would get, read off the Gram entries), and applies their product
+// V to the pair's columns of X and of W (pair_apply_kernel, on the matrix cores).  The Gram matrix is formed afresh from X in every round, so
 // its rounding does not accumulate; the pair test of the next sweep measures the cosine of
 // each column pair from fresh dot products, as the scalar method does.
 constexpr int kJb = 32;            // columns per block
 constexpr int kJp = 2 * kJb;       // columns per pair of blocks
-constexpr int kJrows = 64;         // rows per LDS tile (Gram and apply)
-constexpr int kGramTiles = 2;      // tiles per Gram split
+constexpr int kJrows = 64;         // rows per apply workgroup (16 per wave)
+constexpr int kGramRows = 128;     // rows per Gram workgroup (32 per wave)
 
 // The pair of blocks that workgroup p of a round works on: round r >= 0 of the circle
 // ordering over np players, or, for round -1 (the within-block step of a sweep), the
@@ -81,67 +81,77 @@ QB_DEV int pair_col(int a, int b, int nb, int j, int k) {
     return c < k ? c : -1;
 }
 
-// The pair's tile of rows [r0, r0 + kJrows): element (row r, slot j) of X, zero outside X
-// or for an empty slot, stored at xs[j * SJ + r * SR] in LDS.  Thread t holds row
-// r0 + (t mod 64) of slots t / 64 + 4 q; its 16 loads are all issued before the first
-// LDS store.
-template <int SJ, int SR>
-QB_DEV void stage_pair_tile(const double* __restrict__ X, int k, int64_t ld, int a, int b, int nb, int r0,
-                            double* xs) {
-    constexpr int kPer = kJp * kJrows / kSvdThreads;
-    const int r = static_cast<int>(threadIdx.x) & (kJrows - 1);
-    const int j0 = static_cast<int>(threadIdx.x) / kJrows;
-    const int row = r0 + r;
-    double v[kPer];
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-        const int c = pair_col(a, b, nb, j0 + q * (kSvdThreads / kJrows), k);
-        v[q] = (c >= 0 && row < k) ? X[static_cast<int64_t>(c) * ld + row] : 0.0;
-    }
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) xs[(j0 + q * (kSvdThreads / kJrows)) * SJ + r * SR] = v[q];
-}
+// v_mfma_f64_16x16x4f64 takes A(i, r) from lane 16 r + i and B(r, j) from lane 16 r + j, and
+// leaves C(4 q + l / 16, l mod 16) in slot q of lane l.
+using svd_v4d = double __attribute__((ext_vector_type(4)));
+QB_DEV svd_v4d svd_mfma(double a, double b, svd_v4d c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
 
-// Partial Gram matrix of rows [R y, R (y + 1)), R = kGramTiles kJrows, of the pair's columns:
-// part[(pair * nsplit + y) * kJp^2 + i * kJp + j].  A thread owns a 4 x 4 block; entry
-// (i, j) and (j, i) take the same products in the same order, so the sum is symmetric.
+// Partial Gram matrix of rows [128 y, 128 (y + 1)) of the pair's columns on the matrix cores:
+// wave w takes 32 of the rows, lane (r, i) = (l / 16, l mod 16) supplying row
+// 16 h + 4 t + r at reduction step (h, t) of slot 16 g + i (a column of the same rows for
+// both operands, so C = sum over the rows of x_p x_q).  Only the 10 tiles of 16 x 16 on and
+// above the diagonal are formed; the waves' sums are added in wave order through LDS, and
+// each entry on or above the diagonal is written to both of its places (the result is
+// exactly symmetric).  part[(pair * nsplit + y) * kJp^2 + i * kJp + j].
 __global__ void __launch_bounds__(kSvdThreads)
 pair_gram_kernel(const double* __restrict__ X, int k, int64_t ld, int nb, int np, int round,
                  int nsplit, double* __restrict__ part) {
-    constexpr int kPitch = kJp + 2;   // rows of the tile, 16-byte aligned
-    __shared__ __align__(16) double xs[kJrows * kPitch];
+    constexpr int kTiles = 10;
+    __shared__ svd_v4d red[kSvdThreads / 64 - 1][kTiles][64];
     int a, b;
     round_pair(np, round, static_cast<int>(blockIdx.x), a, b);
-    const int ti = static_cast<int>(threadIdx.x) >> 4, tj = static_cast<int>(threadIdx.x) & 15;
-    double acc[4][4];
+    const int lane = static_cast<int>(threadIdx.x) & 63, w = static_cast<int>(threadIdx.x) >> 6;
+    const int rr = lane >> 4, ii = lane & 15;
+    static_assert(kGramRows == 32 * (kSvdThreads / 64), "32 rows per wave");
+    const int r0 = (static_cast<int>(blockIdx.y) * (kSvdThreads / 64) + w) * 32;
+    double v[4][2][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int g = 0; g < 4; ++g) {
+        const int c = pair_col(a, b, nb, 16 * g + ii, k);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-    for (int tile = 0; tile < kGramTiles; ++tile) {
-        const int r0 = (static_cast<int>(blockIdx.y) * kGramTiles + tile) * kJrows;
-        if (tile > 0) __syncthreads();
-        stage_pair_tile<1, kPitch>(X, k, ld, a, b, nb, r0, xs);
-        __syncthreads();
-#pragma unroll 4
-        for (int r = 0; r < kJrows; ++r) {
-            const double2 u01 = *reinterpret_cast<const double2*>(xs + r * kPitch + 4 * ti);
-            const double2 u23 = *reinterpret_cast<const double2*>(xs + r * kPitch + 4 * ti + 2);
-            const double2 v01 = *reinterpret_cast<const double2*>(xs + r * kPitch + 4 * tj);
-            const double2 v23 = *reinterpret_cast<const double2*>(xs + r * kPitch + 4 * tj + 2);
-            const double u[4] = {u01.x, u01.y, u23.x, u23.y};
-            const double v[4] = {v01.x, v01.y, v23.x, v23.y};
+        for (int h = 0; h < 2; ++h)
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = fma(u[i], v[j], acc[i][j]);
-        }
+            for (int t = 0; t < 4; ++t) {
+                const int row = r0 + 16 * h + 4 * t + rr;
+                v[g][h][t] = (c >= 0 && row < k) ? X[static_cast<int64_t>(c) * ld + row] : 0.0;
+            }
     }
+    svd_v4d acc[kTiles];
+#pragma unroll
+    for (int T = 0; T < kTiles; ++T) acc[T] = svd_v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            int T = 0;
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int n = m; n < 4; ++n, ++T) acc[T] = svd_mfma(v[m][h][t], v[n][h][t], acc[T]);
+        }
+    if (w > 0) {
+#pragma unroll
+        for (int T = 0; T < kTiles; ++T) red[w - 1][T][lane] = acc[T];
+    }
+    __syncthreads();
+    if (w != 0) return;
     double* out = part + (static_cast<int64_t>(blockIdx.x) * nsplit + blockIdx.y) * (kJp * kJp);
+    int T = 0;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int m = 0; m < 4; ++m)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) out[(4 * ti + i) * kJp + 4 * tj + j] = acc[i][j];
+        for (int n = m; n < 4; ++n, ++T) {
+            svd_v4d sum = acc[T];
+#pragma unroll
+            for (int u = 0; u < kSvdThreads / 64 - 1; ++u) sum += red[u][T][lane];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = 16 * m + 4 * q + rr, j = 16 * n + ii;
+                if (m == n && i > j) continue;
+                out[i * kJp + j] = sum[q];
+                out[j * kJp + i] = sum[q];
+            }
+        }
 }
 
 // G[pair] = sum of the pair's partial Gram matrices in split order; a thread per entry, its
@@ -504,15 +514,16 @@ pair_eig_cross_kernel(const double* __restrict__ gram, int inner, double tol_r, 
 }
 
 // [X_a X_b] <- [X_a X_b] V on rows [kJrows y, kJrows (y + 1)) (grid z = 0), and the same on
-// W (z = 1).  The tile is read whole into LDS before it is written back; a thread forms a
-// 4 x 4 block of the product (rows 4 (t mod 16) .., slots 4 (t / 16) ..).
+// W (z = 1), on the matrix cores as (X V)^T = V^T X^T: wave w takes 16 rows, lane (r, i)
+// supplying row i of slot 4 s + r at reduction step s, and V^T from LDS.  A wave reads all
+// of its rows before it writes them, and no other wave touches them, so the update is in
+// place; lane l writes rows of one column, 16 lanes to a column.
 __global__ void __launch_bounds__(kSvdThreads)
 pair_apply_kernel(double* __restrict__ X, double* __restrict__ W, int k, int64_t ld, int nb, int np,
                   int round, const double* __restrict__ Vp, const int* __restrict__ skip) {
     if (skip[blockIdx.x] != 0) return;   // uniform per workgroup
-    constexpr int kPitch = kJrows + 2;   // slots of the tile, 16-byte aligned
-    __shared__ __align__(16) double vs[kJp * kJp];
-    __shared__ __align__(16) double xs[kJp * kPitch];
+    static_assert(kJrows == 16 * (kSvdThreads / 64), "a wave per 16 rows");
+    __shared__ double vs[kJp * kJp];
     double* M = blockIdx.z == 0 ? X : W;
     int a, b;
     round_pair(np, round, static_cast<int>(blockIdx.x), a, b);
@@ -524,38 +535,31 @@ pair_apply_kernel(double* __restrict__ X, double* __restrict__ W, int k, int64_t
 #pragma unroll
         for (int q = 0; q < kJp * kJp / kSvdThreads; ++q) vs[threadIdx.x + q * kSvdThreads] = t[q];
     }
-    const int r0 = static_cast<int>(blockIdx.y) * kJrows;
-    stage_pair_tile<kPitch, 1>(M, k, ld, a, b, nb, r0, xs);
+    const int lane = static_cast<int>(threadIdx.x) & 63, w = static_cast<int>(threadIdx.x) >> 6;
+    const int rr = lane >> 4, ii = lane & 15;
+    const int row = static_cast<int>(blockIdx.y) * kJrows + 16 * w + ii;
+    double x[kJp / 4];
+#pragma unroll
+    for (int st = 0; st < kJp / 4; ++st) {
+        const int c = pair_col(a, b, nb, 4 * st + rr, k);
+        x[st] = (c >= 0 && row < k) ? M[static_cast<int64_t>(c) * ld + row] : 0.0;
+    }
     __syncthreads();
-    const int tr = static_cast<int>(threadIdx.x) & 15, tc = static_cast<int>(threadIdx.x) >> 4;
-    double acc[4][4];
+    svd_v4d acc[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int m = 0; m < 4; ++m) acc[m] = svd_v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-#pragma unroll 4
-    for (int i = 0; i < kJp; ++i) {
-        const double2 x01 = *reinterpret_cast<const double2*>(xs + i * kPitch + 4 * tr);
-        const double2 x23 = *reinterpret_cast<const double2*>(xs + i * kPitch + 4 * tr + 2);
-        const double2 w01 = *reinterpret_cast<const double2*>(vs + i * kJp + 4 * tc);
-        const double2 w23 = *reinterpret_cast<const double2*>(vs + i * kJp + 4 * tc + 2);
-        const double x[4] = {x01.x, x01.y, x23.x, x23.y};
-        const double w[4] = {w01.x, w01.y, w23.x, w23.y};
+    for (int st = 0; st < kJp / 4; ++st)
 #pragma unroll
-        for (int p = 0; p < 4; ++p)
+        for (int m = 0; m < 4; ++m) acc[m] = svd_mfma(vs[(4 * st + rr) * kJp + 16 * m + ii], x[st], acc[m]);
+    if (row >= k) return;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) acc[p][q] = fma(x[p], w[q], acc[p][q]);
-    }
+    for (int m = 0; m < 4; ++m)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int c = pair_col(a, b, nb, 4 * tc + q, k);
-        if (c < 0) continue;
-#pragma unroll
-        for (int p = 0; p < 4; ++p) {
-            const int row = r0 + 4 * tr + p;
-            if (row < k) M[static_cast<int64_t>(c) * ld + row] = acc[p][q];
+        for (int q = 0; q < 4; ++q) {
+            const int c = pair_col(a, b, nb, 16 * m + 4 * q + rr, k);
+            if (c >= 0) M[static_cast<int64_t>(c) * ld + row] = acc[m][q];
         }
-    }
 }
 
 // sig[j] = ||X(:, j)||_2 (workgroup per column).
@@ -651,7 +655,7 @@ int jacobi_rounds(int k) {
 size_t jacobi_part_elems(int k) {
     const int nb = jacobi_blocks(k);
     const int64_t pairs = (nb + (nb & 1)) / 2;
-    return static_cast<size_t>(pairs * (cdiv(k, kGramTiles * kJrows) + 1) * kJp * kJp);   // partials, sums
+    return static_cast<size_t>(pairs * (cdiv(k, kGramRows) + 1) * kJp * kJp);   // partials, sums
 }
 size_t jacobi_rot_elems(int k) {
     const int nb = jacobi_blocks(k);
@@ -664,7 +668,7 @@ hipError_t launch_jacobi_block_round(double* X, double* W, int k, int64_t ld, in
     const int nb = jacobi_blocks(k);
     const int np = nb + (nb & 1);
     const unsigned pairs = static_cast<unsigned>(np / 2);
-    const int nsplit = static_cast<int>(cdiv(k, kGramTiles * kJrows));
+    const int nsplit = static_cast<int>(cdiv(k, kGramRows));
     hipLaunchKernelGGL(pair_gram_kernel, dim3(pairs, static_cast<unsigned>(nsplit)), dim3(kSvdThreads), 0, s,
                        X, k, ld, nb, np, round, nsplit, part);
     double* gram = part + static_cast<int64_t>(pairs) * nsplit * (kJp * kJp);
