@@ -388,14 +388,14 @@ pair_eig_kernel(const double* __restrict__ gram, int inner, double tol_r, double
 // rows h + 8 u, u < 8, of V's columns (a_i, b_i); it computes the rotation of pair i and
 // takes those of pairs j from lane j.  Between rounds the slots of b move down by one:
 // C and D pass through LDS (ping-pong buffers, one barrier per round; C_ji is re-read from
-// the copy of C_ij its owner wrote, so the two copies of an entry never drift apart) and V's
-// b columns through a lane shuffle.  After kJb rounds the slots are back in column order.
+// the copy of C_ij its owner wrote, so the two copies of an entry never drift apart), V's
+// b columns and the diagonal of D through lane shuffles.  After kJb rounds the slots are back in column order.
 __global__ void __launch_bounds__(kSvdThreads)
 pair_eig_cross_kernel(const double* __restrict__ gram, int inner, double tol_r, double tol_c,
                       double* __restrict__ Vout, int* __restrict__ skip, int* __restrict__ flag) {
     static_assert(kJb == 32 && kSvdThreads == 256, "thread (lane, half-wave) layout");
     constexpr int kQ = 4, kU = 8;
-    __shared__ double Cs[2][kJb][kJb + 1], Ds[2][kJb][kJb + 1], Ad[2][kJb];
+    __shared__ double Cs[2][kJb][kJb + 1], Ds[2][kJb][kJb + 1];
     __shared__ int rot, big;
     const int tid = static_cast<int>(threadIdx.x);
     const int i = tid & (kJb - 1), h = tid >> 5;
@@ -458,29 +458,37 @@ pair_eig_cross_kernel(const double* __restrict__ gram, int inner, double tol_r, 
             }
 #pragma unroll
             for (int u = 0; u < kU; ++u) vb[u] = __shfl(vb[u], (i + 1) & (kJb - 1), kJb);
+            // pair i's diagonal entries after its rotation (closed form); every thread of lane
+            // i holds them, and the owner of the diagonal block takes the same values
+            const bool turned = si != 0.0;
+            const double aii2 = turned ? aii - ti * cii : aii;
+            const double dii2 = turned ? dii + ti * cii : dii;
 #pragma unroll
             for (int q = 0; q < kQ; ++q) {
                 // H = M J_j, then J_i^T H; the diagonal block of a turned pair takes the
-                // rotation's closed form (its cross entry becomes an exact zero)
+                // closed form (its cross entry becomes an exact zero)
                 const double h00 = cj[q] * A[q] - sj[q] * C1[q], h01 = sj[q] * A[q] + cj[q] * C1[q];
                 const double h10 = cj[q] * C2[q] - sj[q] * D[q], h11 = sj[q] * C2[q] + cj[q] * D[q];
-                const bool dg = h + 8 * q == i && si != 0.0;
-                const double a2 = dg ? A[q] - ti * C1[q] : ci * h00 - si * h10;
-                const double d2 = dg ? D[q] + ti * C1[q] : si * h01 + ci * h11;
-                C1[q] = dg ? 0.0 : ci * h01 - si * h11;
+                const bool dg = h + 8 * q == i;
+                const double a2 = dg ? aii2 : ci * h00 - si * h10;
+                const double d2 = dg ? dii2 : si * h01 + ci * h11;
+                C1[q] = dg && turned ? 0.0 : ci * h01 - si * h11;
                 A[q] = a2;
                 D[q] = d2;
             }
-            // publish C, D and diag(A); after the barrier take the next round's slots
+            // publish C and D; the next round's slots move down by one.  A stays, the diagonal
+            // of D moves across lanes, the rest through LDS after the barrier.
 #pragma unroll
             for (int q = 0; q < kQ; ++q) {
                 const int j = h + 8 * q;
                 Cs[buf][i][j] = C1[q];
                 Ds[buf][i][j] = D[q];
-                if (j == i) Ad[buf][i] = A[q];
             }
-            __syncthreads();
             const int i1 = (i + 1) & (kJb - 1);
+            aii = aii2;
+            dii = __shfl(dii2, i1, kJb);
+            __syncthreads();
+            cii = Cs[buf][i][i1];
 #pragma unroll
             for (int q = 0; q < kQ; ++q) {
                 const int j = h + 8 * q, j1 = (j + 1) & (kJb - 1);
@@ -488,9 +496,6 @@ pair_eig_cross_kernel(const double* __restrict__ gram, int inner, double tol_r, 
                 C2[q] = Cs[buf][j][i1];
                 D[q] = Ds[buf][i1][j1];
             }
-            aii = Ad[buf][i];
-            cii = Cs[buf][i][i1];
-            dii = Ds[buf][i1][i1];
         }
         __syncthreads();
         const bool rotated = rot != 0;   // uniform: read after the sweep's last barrier
