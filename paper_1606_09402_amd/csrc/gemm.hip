@@ -534,7 +534,10 @@ hipError_t gemm_f64(const GemmDesc& d, hipStream_t s) {
     // reductions of 100000 and more.  Shorter reductions and wider outputs stay on the
     // LDS-tiled kernel below.
     if (d.colsq == nullptr && d.N <= 64 && d.K > 128) {
-        if (d.A.si == 1 && d.K <= 32768 && ts_panel_dma_fits(d)) return ts_panel_dma(d, 2, 4, 4, 1, s, 1);
+        // (the panel form splits only the rows: under 8192 of them a long reduction runs on
+        // too few workgroups -- 315 us at 1216 x 64 x 15000 against 40 us split-K below)
+        if (d.A.si == 1 && d.K <= 32768 && (d.M >= 8192 || d.K <= 4096) && ts_panel_dma_fits(d))
+            return ts_panel_dma(d, 2, 4, 4, 1, s, 1);
         // k-contiguous A with a long reduction: k-contiguous B (Q^T Y, Q^T Q_i, Y^T Y), or a
         // row-major B under at least 4096 output rows (A Omega_i of randQB_EI: 703 against
         // 887 us at 20000 x 64 x 15000; W = B Omega_J of the sparse workload: 3.53 against

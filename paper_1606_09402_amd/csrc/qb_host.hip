@@ -664,15 +664,16 @@ int project_out(const Ctx& x, int64_t rows, int bw, View src, MutView dst, View 
 }
 
 // orth() of Algorithm 4 steps 4-5 on the rows x w row-major panel X (ld ldx), in place:
-// block Gram-Schmidt over kPowerBlock-column blocks (the widest the CholeskyQR kernel
-// takes, so that the projections are wide GEMMs), each projected twice against Q(:, 0:kq)
+// block Gram-Schmidt over b-column blocks (b <= kPowerBlock, the widest the CholeskyQR
+// kernel takes; the power rounds use that width, so that the projections are wide GEMMs,
+// the SVD's thin QR of B^T 64, where the shorter Cholesky chain of the narrower blocks
+// outweighs the narrower products), each projected twice against Q(:, 0:kq)
 // and the blocks already done, and orthonormalised after each projection by CholeskyQR
 // (or, with use_hh, by Householder QR).  Block j of the result depends only on blocks
 // 0..j of X and has diag(R) > 0, as the Q factor of a Householder QR of [Q, X] would.
 // A CholeskyQR breakdown sets the flag; the caller then redoes the panel with use_hh.
 int orth_panel(const Ctx& x, double* X, int64_t rows, int64_t w, int64_t ldx, int64_t kq,
-               bool use_hh) {
-    const int b = kPowerBlock;
+               bool use_hh, int b = kPowerBlock) {
     double* Y = x.at<double>(x.L.y);     // rows x kPowerBlock, column-major
     double* X2 = x.at<double>(x.L.x2);   // rows x kPowerBlock, column-major
     double* tau = x.at<double>(x.L.tau);
@@ -1316,7 +1317,7 @@ int svd_from_qb(int64_t m, int64_t n, int64_t k, const double* Q, int64_t ldq, c
         GemmDesc c = gdesc(n, k, 0, View{nullptr, 0, 0}, View{nullptr, 0, 0}, 0.0, 1.0,
                            View{B, 1, ldb}, MutView{P, k, 1}, x);
         QB_HIP(gemm_f64(c, s));
-        if (int e = orth_panel(x, P, n, k, k, 0, attempt == 1)) return e;
+        if (int e = orth_panel(x, P, n, k, k, 0, attempt == 1, 64)) return e;
         bool broken = false;
         if (int e = read_flag(x, &broken)) return e;
         if (!broken) break;
