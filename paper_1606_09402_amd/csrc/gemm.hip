@@ -535,7 +535,8 @@ hipError_t gemm_f64(const GemmDesc& d, hipStream_t s) {
     // LDS-tiled kernel below.
     if (d.colsq == nullptr && d.N <= 64 && d.K > 128) {
         // (the panel form splits only the rows: under 8192 of them a long reduction runs on
-        // too few workgroups -- 315 us at 1216 x 64 x 15000 against 40 us split-K below)
+        // too few workgroups: 315 us at up to 1216 x 64 x 15000, where the split-K kernel
+        // below takes a tenth of that)
         if (d.A.si == 1 && d.K <= 32768 && (d.M >= 8192 || d.K <= 4096) && ts_panel_dma_fits(d))
             return ts_panel_dma(d, 2, 4, 4, 1, s, 1);
         // k-contiguous A with a long reduction: k-contiguous B (Q^T Y, Q^T Q_i, Y^T Y), or a
