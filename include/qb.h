@@ -392,11 +392,12 @@ QB_API int qb_fixed_rank_bwd(const qb_batch* A, int64_t k, int32_t b, uint64_t s
  * small factor, B = U~ diag(s) V~^T, turns A ~ QB into A ~ (Q U~) diag(s) V~^T; the leading
  * j columns of U = Q U~ and V = V~ with the leading j values of s approximate the rank-j SVD
  * of A.  B^T is first reduced by a thin QR, B^T = P T (the block orthonormalisation of the
- * power scheme: 128-column blocks, CholeskyQR twice, Householder on breakdown), then the k x k
- * factor T^T is diagonalised by block one-sided Jacobi (blocks of 32 columns in circle
- * ordering; each pair of blocks rotated by the product of one cyclic Jacobi sweep over its
- * Gram matrix; a column pair is rotated while its cosine exceeds 16 sqrt(k) 2^-53), and
- * V = P W.
+ * power scheme in 64-column blocks: CholeskyQR twice, Householder on breakdown), then the
+ * k x k factor T^T is diagonalised by block one-sided Jacobi (blocks of 32 columns; a sweep
+ * turns every column pair of neighbouring blocks, then runs the circle ordering over the
+ * blocks, turning the column pairs across each pair of blocks; each pair of blocks is
+ * rotated by the product of one cyclic Jacobi sweep over its Gram matrix; a column pair is
+ * rotated while its cosine exceeds 16 sqrt(k) 2^-53), and V = P W.
  *   Q  m x k, column-major (ldq >= m), orthonormal columns (as qb_fp_* return it)
  *   B  k x n, row-major (ldb >= n)
  *   U  out, m x k column-major (ldu >= m); s out, k values in descending order;
