@@ -52,6 +52,7 @@ struct Layout {
     // remaining sketch norms, active flags, reflector, block pivots, their ||A(:, p)||^2,
     // R~_11 and R~_11 R_i^{-1}
     size_t sk, skom, cola, colpart, qn, act, hh, bpiv, g2p, rs, mm;
+    size_t qcv, qci, beta;   // per-workgroup best columns of the one-launch pivot steps, diag(R~)
     int64_t lt, split_elems, split2_elems, gpart_groups;
     int64_t ldm16, ldn16;   // row strides (elements) of the bfloat16 copies: m, n rounded to 8
     size_t omt8;            // e4m3 form: e4m3(2^5 Omega)^T bytes (l~ x ldn8)
@@ -204,6 +205,9 @@ Layout make_layout(int algo, int sparse, int dtype, int64_t m, int64_t n, int64_
         L.g2p = take(sizeof(double) * b);
         L.rs = take(sizeof(double) * b * b);
         L.mm = take(sizeof(double) * b * b);
+        L.qcv = take(sizeof(double) * 2 * qrcp_cand_slots(n));
+        L.qci = take(sizeof(int) * 2 * qrcp_cand_slots(n));
+        L.beta = take(sizeof(double) * b);
     }
     L.total = off + 256;
     return L;
@@ -1171,6 +1175,9 @@ int qrcp_run(const qb_dense* Ad, const qb_params* p, int oversample, double* Q, 
         double* M = x.at<double>(L.mm);
         double* Y = x.at<double>(L.g);
         double* Wb = x.at<double>(L.w);
+        double* qcv = x.at<double>(L.qcv);
+        int* qci = x.at<int>(L.qci);
+        double* betas = x.at<double>(L.beta);
         QB_HIP(launch_fill_int(x.at<int>(L.flags), 8, 0, s));
         // ||A(:, j)||^2, the reference of the exhaustion guard
         QB_HIP(launch_colsq_rowmajor(A.a, m, n, A.lda, x.at<double>(L.colpart), s));
@@ -1184,11 +1191,12 @@ int qrcp_run(const qb_dense* Ad, const qb_params* p, int oversample, double* Q, 
         tm.mark(4);
         QB_HIP(launch_fill_int(act, static_cast<int>(n), 1, s));
         QB_HIP(launch_qrcp_norms(St, n, ell, act, qn, s));
+        QB_HIP(launch_qrcp_cands(qn, n, ell, qcv, qci, s));
         bool stop = false;
         while (k < lmax && !stop) {
             const int bwi = static_cast<int>(b < lmax - k ? b : lmax - k);
             for (int t = 0; t < bwi; ++t)
-                QB_HIP(launch_qrcp_step(St, n, ell, t, qn, act, bpiv, colA, g2p, hh, s));
+                QB_HIP(launch_qrcp_step(St, n, ell, t, qn, act, bpiv, colA, g2p, hh, betas, qcv, qci, s));
             QB_HIP(launch_gather_cols(A.a, A.lda, m, bpiv, bwi, Y, bwi, s));
             if (k > 0) QB_HIP(launch_gather_cols(B, ldb, k, bpiv, bwi, Wb, bwi, s));
             bool breakdown = false;
@@ -1218,7 +1226,7 @@ int qrcp_run(const qb_dense* Ad, const qb_params* p, int oversample, double* Q, 
             if (exh) exhausted = true;
             if (!stop && k < lmax) {
                 // sample update in the rotated basis: St(:, 0:bw) -= B_i^T (R~_11 R_i^{-1})^T
-                QB_HIP(launch_qrcp_rs(St, ell, bpiv, bwi, Rs, s));
+                QB_HIP(launch_qrcp_rs(St, ell, bpiv, betas, bwi, Rs, s));
                 GemmDesc d = gdesc(bwi, bwi, bwi, View{Rs, bwi, 1}, View{x.at<double>(L.rii), bwi, 1}, 1.0,
                                    0.0, View{nullptr, 0, 0}, MutView{M, bwi, 1}, x);
                 QB_HIP(gemm_f64(d, s));
@@ -1226,6 +1234,7 @@ int qrcp_run(const qb_dense* Ad, const qb_params* p, int oversample, double* Q, 
                                    View{St, ell, 1}, MutView{St, ell, 1}, x);
                 QB_HIP(gemm_f64(u, s));
                 QB_HIP(launch_qrcp_norms(St, n, ell, act, qn, s));
+                QB_HIP(launch_qrcp_cands(qn, n, ell, qcv, qci, s));
             }
         }
     }
