@@ -153,7 +153,27 @@ qrcp_step_kernel(double* __restrict__ St, int64_t n, int l, int t, double* __res
     __shared__ double vsh[kStepRows];
     __shared__ double cval[kStepCols];
     __shared__ int cidx[kStepCols];
+    __shared__ double s_alpha;
     const int tid = static_cast<int>(threadIdx.x), lane = tid & 63, wave = tid >> 6;
+    // the workgroup's columns (16 lanes each, lane r mod 16 holding rows r, r + 16, ...) are
+    // read first: they do not depend on the pivot
+    constexpr int kPasses = kStepCols / (kStepThreads / 16);
+    constexpr int kU = kStepRows / 16;
+    const int grp = tid >> 4, gl = tid & 15;
+    const int64_t c0 = static_cast<int64_t>(blockIdx.x) * kStepCols;
+    double xr[kPasses][kU];
+    bool act[kPasses];
+#pragma unroll
+    for (int pass = 0; pass < kPasses; ++pass) {
+        const int64_t j = c0 + pass * (kStepThreads / 16) + grp;
+        act[pass] = j < n && active[j] != 0;
+        const double* y = St + j * l;
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int r = gl + 16 * u;
+            xr[pass][u] = (act[pass] && r >= t && r < l) ? y[r] : 0.0;
+        }
+    }
     // the pivot: best of the candidates (a total order, so every lane ends with the same one)
     double best = -1.0;
     int bi = -1;
@@ -188,7 +208,6 @@ qrcp_step_kernel(double* __restrict__ St, int64_t n, int l, int t, double* __res
             bi = wi[w];
         }
     const int p = bi;
-    const int64_t c0 = static_cast<int64_t>(blockIdx.x) * kStepCols;
     if (p < 0) {   // no active column left: nothing to apply, no candidates
         if (blockIdx.x == 0 && tid == 0) {
             piv[t] = -1;
@@ -207,11 +226,12 @@ qrcp_step_kernel(double* __restrict__ St, int64_t n, int l, int t, double* __res
     double part = (tid > t && tid < l) ? xv * xv : 0.0;
     part = wave_allsum(part);
     if (lane == 0) red[wave] = part;
+    if (tid == t) s_alpha = xv;
     __syncthreads();
     double sigma = 0.0;
 #pragma unroll
     for (int w = 0; w < kStepThreads / 64; ++w) sigma += red[w];
-    const double a = x[t];
+    const double a = s_alpha;
     double tau = 0.0, beta = a, scale = 0.0;
     if (sigma != 0.0) {
         const double nrm = sqrt(a * a + sigma);
@@ -226,28 +246,19 @@ qrcp_step_kernel(double* __restrict__ St, int64_t n, int l, int t, double* __res
         betas[t] = beta;
     }
     __syncthreads();
-    // the workgroup's columns: 16 lanes each, lane r mod 16 holding rows r, r + 16, ...
-    const int grp = tid >> 4, gl = tid & 15;
-    constexpr int kU = kStepRows / 16;
 #pragma unroll
-    for (int pass = 0; pass < kStepCols / (kStepThreads / 16); ++pass) {
+    for (int pass = 0; pass < kPasses; ++pass) {
         const int slot = pass * (kStepThreads / 16) + grp;
         const int64_t j = c0 + slot;
         double nv = -1.0;
-        const bool live = j < n && j != p && active[j] != 0;   // uniform over the 16 lanes
+        const bool live = act[pass] && j != p;   // uniform over the 16 lanes
         if (live) {
             double* y = St + j * l;
-            double xr[kU];
             double d = 0.0;
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
                 const int r = gl + 16 * u;
-                xr[u] = (r >= t && r < l) ? y[r] : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < kU; ++u) {
-                const int r = gl + 16 * u;
-                if (r >= t && r < l) d += vsh[r] * xr[u];
+                if (r >= t && r < l) d += vsh[r] * xr[pass][u];
             }
 #pragma unroll
             for (int off = 8; off > 0; off >>= 1) d += __shfl_xor(d, off, 16);
@@ -257,7 +268,7 @@ qrcp_step_kernel(double* __restrict__ St, int64_t n, int l, int t, double* __res
             for (int u = 0; u < kU; ++u) {
                 const int r = gl + 16 * u;
                 if (r >= t && r < l) {
-                    const double v = xr[u] - f * vsh[r];
+                    const double v = xr[pass][u] - f * vsh[r];
                     y[r] = v;
                     if (r > t) sq += v * v;
                 }
