@@ -173,15 +173,14 @@ void coo_counts(int64_t m, int64_t n, int64_t nnz, char* ws, const int64_t** nru
 int qrcp_max_rows();
 hipError_t launch_qrcp_norms(const double* St, int64_t n, int l, const int* active, double* norm2,
                              hipStream_t s);
-// One pivot step (one launch for l <= 256, else two).  betas[t] receives the pivot's diagonal
+// One pivot step, one launch (l <= qrcp_max_rows()).  betas[t] receives the pivot's diagonal
 // entry of the sketch's triangular factor; cv / ci hold 2 x qrcp_cand_slots(n) per-workgroup
 // best columns (alternating between steps; launch_qrcp_cands fills them before a block's
 // first step, after the norms).
 hipError_t launch_qrcp_step(double* St, int64_t n, int l, int t, double* norm2, int* active, int* piv,
-                            const double* colA, double* g2, double* hh, double* betas, double* cv, int* ci,
-                            hipStream_t s);
+                            const double* colA, double* g2, double* betas, double* cv, int* ci, hipStream_t s);
 int64_t qrcp_cand_slots(int64_t n);
-hipError_t launch_qrcp_cands(const double* norm2, int64_t n, int l, double* cv, int* ci, hipStream_t s);
+hipError_t launch_qrcp_cands(const double* norm2, int64_t n, double* cv, int* ci, hipStream_t s);
 hipError_t launch_qrcp_rs(const double* St, int l, const int* piv, const double* betas, int bw, double* Rs,
                           hipStream_t s);
 hipError_t launch_gather_cols(const double* X, int64_t ldx, int64_t rows, const int* piv, int bw,

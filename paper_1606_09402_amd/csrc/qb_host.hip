@@ -49,9 +49,9 @@ struct Layout {
     bool ahead;                  // look-ahead regions present
     int64_t nhist;
     // trQRCP: sketch St (n x l), its Gaussian (m x l), ||A(:, j)||^2 and its partials, the
-    // remaining sketch norms, active flags, reflector, block pivots, their ||A(:, p)||^2,
-    // R~_11 and R~_11 R_i^{-1}
-    size_t sk, skom, cola, colpart, qn, act, hh, bpiv, g2p, rs, mm;
+    // remaining sketch norms, active flags, block pivots, their ||A(:, p)||^2, R~_11 and
+    // R~_11 R_i^{-1}
+    size_t sk, skom, cola, colpart, qn, act, bpiv, g2p, rs, mm;
     size_t qcv, qci, beta;   // per-workgroup best columns of the one-launch pivot steps, diag(R~)
     int64_t lt, split_elems, split2_elems, gpart_groups;
     int64_t ldm16, ldn16;   // row strides (elements) of the bfloat16 copies: m, n rounded to 8
@@ -200,7 +200,6 @@ Layout make_layout(int algo, int sparse, int dtype, int64_t m, int64_t n, int64_
         L.colpart = take(sizeof(double) * colsq_groups(m) * n);
         L.qn = take(sizeof(double) * n);
         L.act = take(sizeof(int) * n);
-        L.hh = take(sizeof(double) * (ell + 1));
         L.bpiv = take(sizeof(int) * b);
         L.g2p = take(sizeof(double) * b);
         L.rs = take(sizeof(double) * b * b);
@@ -1168,7 +1167,6 @@ int qrcp_run(const qb_dense* Ad, const qb_params* p, int oversample, double* Q, 
         double* colA = x.at<double>(L.cola);
         double* qn = x.at<double>(L.qn);
         int* act = x.at<int>(L.act);
-        double* hh = x.at<double>(L.hh);
         int* bpiv = x.at<int>(L.bpiv);
         double* g2p = x.at<double>(L.g2p);
         double* Rs = x.at<double>(L.rs);
@@ -1191,12 +1189,12 @@ int qrcp_run(const qb_dense* Ad, const qb_params* p, int oversample, double* Q, 
         tm.mark(4);
         QB_HIP(launch_fill_int(act, static_cast<int>(n), 1, s));
         QB_HIP(launch_qrcp_norms(St, n, ell, act, qn, s));
-        QB_HIP(launch_qrcp_cands(qn, n, ell, qcv, qci, s));
+        QB_HIP(launch_qrcp_cands(qn, n, qcv, qci, s));
         bool stop = false;
         while (k < lmax && !stop) {
             const int bwi = static_cast<int>(b < lmax - k ? b : lmax - k);
             for (int t = 0; t < bwi; ++t)
-                QB_HIP(launch_qrcp_step(St, n, ell, t, qn, act, bpiv, colA, g2p, hh, betas, qcv, qci, s));
+                QB_HIP(launch_qrcp_step(St, n, ell, t, qn, act, bpiv, colA, g2p, betas, qcv, qci, s));
             QB_HIP(launch_gather_cols(A.a, A.lda, m, bpiv, bwi, Y, bwi, s));
             if (k > 0) QB_HIP(launch_gather_cols(B, ldb, k, bpiv, bwi, Wb, bwi, s));
             bool breakdown = false;
@@ -1234,7 +1232,7 @@ int qrcp_run(const qb_dense* Ad, const qb_params* p, int oversample, double* Q, 
                                    View{St, ell, 1}, MutView{St, ell, 1}, x);
                 QB_HIP(gemm_f64(u, s));
                 QB_HIP(launch_qrcp_norms(St, n, ell, act, qn, s));
-                QB_HIP(launch_qrcp_cands(qn, n, ell, qcv, qci, s));
+                QB_HIP(launch_qrcp_cands(qn, n, qcv, qci, s));
             }
         }
     }
@@ -1484,8 +1482,8 @@ int layout_check(int algo, int sparse, int dtype, int64_t m, int64_t n, int64_t 
                                 L.rowsq_part, L.rowsq, L.info, L.flags, L.scan, L.khist, L.ehist,
                                 L.split, L.split2, L.ynext, L.w2, L.csc,
                                 L.plan_a, L.plan_t, L.omt, L.gqt, L.omt8, L.total};
-    if (ell > 0) offs.insert(offs.end(), {L.sk, L.skom, L.cola, L.colpart, L.qn, L.act, L.hh, L.bpiv,
-                                          L.g2p, L.rs, L.mm});
+    if (ell > 0) offs.insert(offs.end(), {L.sk, L.skom, L.cola, L.colpart, L.qn, L.act, L.bpiv,
+                                          L.g2p, L.rs, L.mm, L.qcv, L.qci, L.beta});
     auto extent = [&](size_t off) {
         size_t next = L.total;
         for (size_t o : offs)
@@ -1560,11 +1558,14 @@ int layout_check(int algo, int sparse, int dtype, int64_t m, int64_t n, int64_t 
         need(L.colpart, D * colsq_groups(m) * n);
         need(L.qn, D * n);
         need(L.act, sizeof(int) * n);
-        need(L.hh, D * (ell + 1));
         need(L.bpiv, sizeof(int) * b);
         need(L.g2p, D * b);
         need(L.rs, D * b * b);
         need(L.mm, D * b * b);
+        // the pivot steps' per-workgroup best columns (two step parities) and diag(R~_11)
+        need(L.qcv, D * 2 * qrcp_cand_slots(n));
+        need(L.qci, sizeof(int) * 2.0 * qrcp_cand_slots(n));
+        need(L.beta, D * b);
     }
     return ok ? QB_OK : QB_ERR_WORKSPACE;
 }

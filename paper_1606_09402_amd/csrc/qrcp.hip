@@ -3,17 +3,13 @@
 // stored transposed (St, n x l row-major: column j of S is row j of St, l contiguous
 // values).  A pivot step picks the active column of largest remaining norm, forms its
 // Householder reflector, applies it to every other active column and recomputes each
-// column's remaining norm exactly (no downdating).  For sketches of up to 256 rows a step is
-// one launch (qrcp_step_kernel): every workgroup finds the pivot itself from the per-
-// workgroup best columns the previous step left, forms the reflector from the pivot column
-// and updates its own 32 columns, 16 lanes to a column; otherwise a step is two launches
-// (one workgroup picks, then a wave per column applies).  Every sum has a fixed order, so
-// the pivots are reproducible.
+// column's remaining norm exactly (no downdating).  A step is one launch (qrcp_step_kernel):
+// every workgroup finds the pivot itself from the per-workgroup best columns the previous
+// step left, forms the reflector from the pivot column and updates its own 32 columns, 16
+// lanes to a column.  Every sum has a fixed order, so the pivots are reproducible.
 #include "kernels.h"
 
 namespace qb {
-
-constexpr int kPickThreads = 1024;   // also the largest sketch height l
 
 // Butterfly sum over the wave; every lane ends with the same total (each level adds a
 // pair of equal partial sums in either order, and IEEE addition is commutative).
@@ -40,100 +36,19 @@ __global__ void qrcp_norms_kernel(const double* __restrict__ St, int64_t n, int 
     if (lane == 0) norm2[j] = s;
 }
 
-// Step t of the sketch's pivoted QR.  Pivot: the active column of largest norm2 (smallest
-// index among equal values).  Its reflector of rows t..l-1 in LAPACK's convention
-// (v(t) = 1, beta = -sign(alpha) ||x||, tau = (beta - alpha) / beta, tau = 0 when rows
-// t+1.. are zero) goes to hh (v in hh[0..l), tau in hh[l]); the pivot column becomes
-// (rows < t unchanged, beta, zeros), a column of the sketch's triangular factor.  The pivot
-// is recorded in piv[t], deactivated, and ||A(:, p)||^2 copied to g2[t].  With no active
-// column left (the caller never asks for more pivots than there are columns) it records -1
-// and an identity reflector.
-__global__ void __launch_bounds__(kPickThreads)
-qrcp_pick_kernel(double* __restrict__ St, int64_t n, int l, int t, double* __restrict__ norm2,
-                 int* __restrict__ active, int* __restrict__ piv, const double* __restrict__ colA,
-                 double* __restrict__ g2, double* __restrict__ hh, double* __restrict__ betas) {
-    __shared__ double sv[kPickThreads];
-    __shared__ int64_t si[kPickThreads];
-    __shared__ double red[kPickThreads / 64];
-    __shared__ double s_alpha;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    double best = -1.0;   // inactive entries hold -1 and never win
-    int64_t bi = -1;
-    for (int64_t j = tid; j < n; j += kPickThreads) {
-        const double v = norm2[j];
-        if (v > best) {   // increasing j: the first of equal values stays
-            best = v;
-            bi = j;
-        }
-    }
-    sv[tid] = best;
-    si[tid] = bi;
-    __syncthreads();
-    for (int off = kPickThreads / 2; off > 0; off >>= 1) {
-        if (tid < off) {
-            const double o = sv[tid + off];
-            const int64_t oi = si[tid + off];
-            if (o > sv[tid] || (o == sv[tid] && oi >= 0 && (si[tid] < 0 || oi < si[tid]))) {
-                sv[tid] = o;
-                si[tid] = oi;
-            }
-        }
-        __syncthreads();
-    }
-    const int64_t p = si[0];
-    if (p < 0) {
-        if (tid < l) hh[tid] = 0.0;
-        if (tid == 0) {
-            hh[l] = 0.0;
-            piv[t] = -1;
-            g2[t] = 0.0;
-            betas[t] = 0.0;
-        }
-        return;
-    }
-    double* x = St + p * l;
-    const double xv = tid < l ? x[tid] : 0.0;
-    double part = (tid > t && tid < l) ? xv * xv : 0.0;
-    part = wave_allsum(part);
-    if (lane == 0) red[wave] = part;
-    __syncthreads();
-    double sigma = 0.0;
-#pragma unroll
-    for (int w = 0; w < kPickThreads / 64; ++w) sigma += red[w];
-    if (tid == t) s_alpha = xv;
-    __syncthreads();
-    const double a = s_alpha;
-    double tau = 0.0, beta = a, scale = 0.0;
-    if (sigma != 0.0) {
-        const double nrm = sqrt(a * a + sigma);
-        beta = a >= 0.0 ? -nrm : nrm;
-        tau = (beta - a) / beta;
-        scale = 1.0 / (a - beta);
-    }
-    if (tid < l) {
-        hh[tid] = tid < t ? 0.0 : (tid == t ? 1.0 : xv * scale);
-        x[tid] = tid < t ? xv : (tid == t ? beta : 0.0);
-    }
-    if (tid == 0) {
-        hh[l] = tau;
-        piv[t] = static_cast<int>(p);
-        active[p] = 0;
-        norm2[p] = -1.0;
-        g2[t] = colA[p];
-        betas[t] = beta;
-    }
-}
-
-// One-launch pivot step for sketches of up to kStepRows rows.  Workgroup g owns columns
+// Pivot step t for sketches of up to kStepRows rows.  Workgroup g owns columns
 // [kStepCols g, kStepCols (g + 1)); cv_in / ci_in hold each workgroup's best active column
 // (largest norm2, smallest index among equal values; -1 / -1 for none) before the step, and
 // cv_out / ci_out receive them after it.  Every workgroup reduces the candidates to the
-// pivot p (the same column the one-workgroup scan picks), forms the reflector from St(p, :)
-// exactly as qrcp_pick_kernel does (the sums over the four waves in wave order), applies it
-// to its active columns other than p and recomputes their norms.  The pivot column itself is
+// pivot p (the column a scan of all norms in index order picks), forms its reflector of rows
+// t..l-1 in LAPACK's convention (v(t) = 1, beta = -sign(alpha) ||x||, tau = (beta - alpha) /
+// beta, tau = 0 when rows t+1.. are zero; the sum of squares over the four waves in wave
+// order), applies it to its active columns other than p and recomputes their norms.  The pivot column itself is
 // read by every workgroup and written by none: its diagonal entry beta goes to betas[t] (the
 // entries below it are zeros of the triangular factor, never read), and its owner only
-// deactivates it.  piv[t], g2[t] and betas[t] are written by workgroup 0.
+// deactivates it.  piv[t], g2[t] = ||A(:, p)||^2 and betas[t] are written by workgroup 0; with
+// no active column left (the caller never asks for more pivots than there are columns) piv[t]
+// is -1 and nothing changes.
 constexpr int kStepThreads = 256;
 constexpr int kStepRows = 256;
 constexpr int kStepCols = 32;   // columns per workgroup: 16 lanes per column, two passes
@@ -321,30 +236,6 @@ __global__ void qrcp_cand_kernel(const double* __restrict__ norm2, int64_t n, in
     ci[g] = bi;
 }
 
-// Applies the reflector of step t to rows t..l-1 of every active column (one wave each) and
-// sets norm2 to the column's sum of squares over rows t+1..l-1.
-__global__ void qrcp_apply_kernel(double* __restrict__ St, int64_t n, int l, int t,
-                                  const double* __restrict__ hh, const int* __restrict__ active,
-                                  double* __restrict__ norm2) {
-    const int64_t j = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
-    const int lane = threadIdx.x & 63;
-    if (j >= n || !active[j]) return;   // uniform per wave
-    double* x = St + j * l;
-    const double tau = hh[l];
-    double d = 0.0;
-    for (int r = t + lane; r < l; r += 64) d += hh[r] * x[r];
-    d = wave_allsum(d);
-    const double f = tau * d;
-    double s = 0.0;
-    for (int r = t + lane; r < l; r += 64) {
-        const double y = x[r] - f * hh[r];
-        x[r] = y;
-        if (r > t) s += y * y;
-    }
-    s = wave_allsum(s);
-    if (lane == 0) norm2[j] = s;
-}
-
 // Rs(i, c) = St(piv[c], i) for i < c, betas[c] for i = c, 0 below (bw x bw row-major): the
 // sketch's triangular factor R~_11 in pivot order.  Grid: (column blocks, bw rows).
 __global__ void qrcp_rs_kernel(const double* __restrict__ St, int l, const int* __restrict__ piv,
@@ -371,11 +262,10 @@ __global__ void gather_cols_kernel(const double* __restrict__ X, int64_t ldx, in
     Y[i * ldy + c] = pc >= 0 ? X[i * ldx + pc] : 0.0;
 }
 
-int qrcp_max_rows() { return kPickThreads; }
+int qrcp_max_rows() { return kStepRows; }
 int64_t qrcp_cand_slots(int64_t n) { return cdiv(n, kStepCols); }
 
-hipError_t launch_qrcp_cands(const double* norm2, int64_t n, int l, double* cv, int* ci, hipStream_t s) {
-    if (l > kStepRows) return hipSuccess;   // the two-launch steps keep no candidates
+hipError_t launch_qrcp_cands(const double* norm2, int64_t n, double* cv, int* ci, hipStream_t s) {
     const int ncand = static_cast<int>(qrcp_cand_slots(n));
     hipLaunchKernelGGL(qrcp_cand_kernel, dim3(static_cast<unsigned>(cdiv(ncand, 256))), dim3(256), 0, s, norm2,
                        n, ncand, cv, ci);
@@ -390,21 +280,13 @@ hipError_t launch_qrcp_norms(const double* St, int64_t n, int l, const int* acti
 }
 
 hipError_t launch_qrcp_step(double* St, int64_t n, int l, int t, double* norm2, int* active, int* piv,
-                            const double* colA, double* g2, double* hh, double* betas, double* cv, int* ci,
-                            hipStream_t s) {
-    if (l > kPickThreads || t < 0 || t >= l) return hipErrorInvalidValue;
-    if (l <= kStepRows) {
-        const int64_t ncand = qrcp_cand_slots(n);
-        const int in = t & 1, out = in ^ 1;
-        hipLaunchKernelGGL(qrcp_step_kernel, dim3(static_cast<unsigned>(ncand)), dim3(kStepThreads), 0, s, St, n,
-                           l, t, norm2, active, piv, colA, g2, betas, static_cast<int>(ncand), cv + in * ncand,
-                           ci + in * ncand, cv + out * ncand, ci + out * ncand);
-        return hipGetLastError();
-    }
-    hipLaunchKernelGGL(qrcp_pick_kernel, dim3(1), dim3(kPickThreads), 0, s, St, n, l, t, norm2, active,
-                       piv, colA, g2, hh, betas);
-    hipLaunchKernelGGL(qrcp_apply_kernel, dim3(static_cast<unsigned>(cdiv(n, 4))), dim3(256), 0, s, St, n,
-                       l, t, hh, active, norm2);
+                            const double* colA, double* g2, double* betas, double* cv, int* ci, hipStream_t s) {
+    if (l > kStepRows || t < 0 || t >= l) return hipErrorInvalidValue;
+    const int64_t ncand = qrcp_cand_slots(n);
+    const int in = t & 1, out = in ^ 1;
+    hipLaunchKernelGGL(qrcp_step_kernel, dim3(static_cast<unsigned>(ncand)), dim3(kStepThreads), 0, s, St, n, l, t,
+                       norm2, active, piv, colA, g2, betas, static_cast<int>(ncand), cv + in * ncand, ci + in * ncand,
+                       cv + out * ncand, ci + out * ncand);
     return hipGetLastError();
 }
 
