@@ -53,12 +53,14 @@ QB_DEV void circle_pair(int np, int r, int p, int& a, int& b) {
 // order, on the matrix cores), finds the rotations that diagonalise it by cyclic two-sided
 // Jacobi (pair_eig_kernel, pair_eig_cross_kernel: the rotation of columns p, q is the one
 // the column pair itself would get, read off the Gram entries), and applies their product
-// V to the pair's columns of X and of W (pair_apply_kernel, on the matrix cores).  The Gram matrix is formed afresh from X in every round, so
-// its rounding does not accumulate; the pair test of the next sweep measures the cosine of
-// each column pair from fresh dot products, as the scalar method does.
+// V to the pair's columns of X and of W (pair_apply_kernel, on the matrix cores).  The Gram
+// matrix is formed afresh from X in every round, so its rounding does not accumulate; the
+// pair test of the next sweep measures the cosine of each column pair from fresh dot
+// products, as the scalar method does.
 constexpr int kJb = 32;            // columns per block
 constexpr int kJp = 2 * kJb;       // columns per pair of blocks
-constexpr int kJrows = 64;         // rows per apply workgroup (16 per wave)
+constexpr int kApplyTiles = 2;     // 16-row tiles per wave in the apply kernel
+constexpr int kJrows = 16 * kApplyTiles * 4;   // rows per apply workgroup (four waves)
 constexpr int kGramRows = 128;     // rows per Gram workgroup (32 per wave)
 
 // The pair of blocks that workgroup p of a round works on: round r >= 0 of the circle
@@ -519,15 +521,16 @@ pair_eig_cross_kernel(const double* __restrict__ gram, int inner, double tol_r, 
 }
 
 // [X_a X_b] <- [X_a X_b] V on rows [kJrows y, kJrows (y + 1)) (grid z = 0), and the same on
-// W (z = 1), on the matrix cores as (X V)^T = V^T X^T: wave w takes 16 rows, lane (r, i)
-// supplying row i of slot 4 s + r at reduction step s, and V^T from LDS.  A wave reads all
+// W (z = 1), on the matrix cores as (X V)^T = V^T X^T: wave w takes kApplyTiles tiles of 16
+// rows, lane (r, i) supplying row i of a tile's slot 4 s + r at reduction step s, and V^T
+// from LDS (one read serves the wave's tiles).  A wave reads all
 // of its rows before it writes them, and no other wave touches them, so the update is in
 // place; lane l writes rows of one column, 16 lanes to a column.
 __global__ void __launch_bounds__(kSvdThreads)
 pair_apply_kernel(double* __restrict__ X, double* __restrict__ W, int k, int64_t ld, int nb, int np,
                   int round, const double* __restrict__ Vp, const int* __restrict__ skip) {
     if (skip[blockIdx.x] != 0) return;   // uniform per workgroup
-    static_assert(kJrows == 16 * (kSvdThreads / 64), "a wave per 16 rows");
+    static_assert(kJrows == 16 * kApplyTiles * (kSvdThreads / 64), "kApplyTiles 16-row tiles per wave");
     __shared__ double vs[kJp * kJp];
     double* M = blockIdx.z == 0 ? X : W;
     int a, b;
@@ -542,28 +545,42 @@ pair_apply_kernel(double* __restrict__ X, double* __restrict__ W, int k, int64_t
     }
     const int lane = static_cast<int>(threadIdx.x) & 63, w = static_cast<int>(threadIdx.x) >> 6;
     const int rr = lane >> 4, ii = lane & 15;
-    const int row = static_cast<int>(blockIdx.y) * kJrows + 16 * w + ii;
-    double x[kJp / 4];
+    const int row0 = static_cast<int>(blockIdx.y) * kJrows + 16 * kApplyTiles * w + ii;
+    double x[kApplyTiles][kJp / 4];
 #pragma unroll
     for (int st = 0; st < kJp / 4; ++st) {
         const int c = pair_col(a, b, nb, 4 * st + rr, k);
-        x[st] = (c >= 0 && row < k) ? M[static_cast<int64_t>(c) * ld + row] : 0.0;
+#pragma unroll
+        for (int h = 0; h < kApplyTiles; ++h) {
+            const int row = row0 + 16 * h;
+            x[h][st] = (c >= 0 && row < k) ? M[static_cast<int64_t>(c) * ld + row] : 0.0;
+        }
     }
     __syncthreads();
-    svd_v4d acc[4];
+    svd_v4d acc[kApplyTiles][4];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) acc[m] = svd_v4d{0.0, 0.0, 0.0, 0.0};
+    for (int h = 0; h < kApplyTiles; ++h)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) acc[h][m] = svd_v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int st = 0; st < kJp / 4; ++st)
 #pragma unroll
-        for (int m = 0; m < 4; ++m) acc[m] = svd_mfma(vs[(4 * st + rr) * kJp + 16 * m + ii], x[st], acc[m]);
-    if (row >= k) return;
+        for (int m = 0; m < 4; ++m) {
+            const double vt = vs[(4 * st + rr) * kJp + 16 * m + ii];
+#pragma unroll
+            for (int h = 0; h < kApplyTiles; ++h) acc[h][m] = svd_mfma(vt, x[h][st], acc[h][m]);
+        }
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int c = pair_col(a, b, nb, 16 * m + 4 * q + rr, k);
-            if (c >= 0) M[static_cast<int64_t>(c) * ld + row] = acc[m][q];
+            if (c < 0) continue;
+#pragma unroll
+            for (int h = 0; h < kApplyTiles; ++h) {
+                const int row = row0 + 16 * h;
+                if (row < k) M[static_cast<int64_t>(c) * ld + row] = acc[h][m][q];
+            }
         }
 }
 
