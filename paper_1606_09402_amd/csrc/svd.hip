@@ -61,7 +61,8 @@ constexpr int kJb = 32;            // columns per block
 constexpr int kJp = 2 * kJb;       // columns per pair of blocks
 constexpr int kApplyTiles = 2;     // 16-row tiles per wave in the apply kernel
 constexpr int kJrows = 16 * kApplyTiles * 4;   // rows per apply workgroup (four waves)
-constexpr int kGramRows = 128;     // rows per Gram workgroup (32 per wave)
+constexpr int kGramH = 2;          // 16-row steps per wave in the Gram kernel
+constexpr int kGramRows = 16 * kGramH * 4;   // rows per Gram workgroup (four waves)
 
 // The pair of blocks that workgroup p of a round works on: round r >= 0 of the circle
 // ordering over np players, or, for round -1 (the within-block step of a sweep), the
@@ -88,8 +89,9 @@ QB_DEV int pair_col(int a, int b, int nb, int j, int k) {
 using svd_v4d = double __attribute__((ext_vector_type(4)));
 QB_DEV svd_v4d svd_mfma(double a, double b, svd_v4d c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
 
-// Partial Gram matrix of rows [128 y, 128 (y + 1)) of the pair's columns on the matrix cores:
-// wave w takes 32 of the rows, lane (r, i) = (l / 16, l mod 16) supplying row
+// Partial Gram matrix of rows [R y, R (y + 1)), R = kGramRows, of the pair's columns on the
+// matrix cores: wave w takes 16 kGramH of the rows (16 of them, 64 rows a workgroup, was
+// slower: 11.0 against 9.7 us a launch at k = 1250), lane (r, i) = (l / 16, l mod 16) supplying row
 // 16 h + 4 t + r at reduction step (h, t) of slot 16 g + i (a column of the same rows for
 // both operands, so C = sum over the rows of x_p x_q).  Only the 10 tiles of 16 x 16 on and
 // above the diagonal are formed; the waves' sums are added in wave order through LDS, and
@@ -104,14 +106,14 @@ pair_gram_kernel(const double* __restrict__ X, int k, int64_t ld, int nb, int np
     round_pair(np, round, static_cast<int>(blockIdx.x), a, b);
     const int lane = static_cast<int>(threadIdx.x) & 63, w = static_cast<int>(threadIdx.x) >> 6;
     const int rr = lane >> 4, ii = lane & 15;
-    static_assert(kGramRows == 32 * (kSvdThreads / 64), "32 rows per wave");
-    const int r0 = (static_cast<int>(blockIdx.y) * (kSvdThreads / 64) + w) * 32;
-    double v[4][2][4];
+    static_assert(kGramRows == 16 * kGramH * (kSvdThreads / 64), "16 kGramH rows per wave");
+    const int r0 = (static_cast<int>(blockIdx.y) * (kSvdThreads / 64) + w) * 16 * kGramH;
+    double v[4][kGramH][4];
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
         const int c = pair_col(a, b, nb, 16 * g + ii, k);
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
+        for (int h = 0; h < kGramH; ++h)
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 const int row = r0 + 16 * h + 4 * t + rr;
@@ -122,7 +124,7 @@ pair_gram_kernel(const double* __restrict__ X, int k, int64_t ld, int nb, int np
 #pragma unroll
     for (int T = 0; T < kTiles; ++T) acc[T] = svd_v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
+    for (int h = 0; h < kGramH; ++h)
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             int T = 0;
