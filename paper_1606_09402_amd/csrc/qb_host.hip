@@ -668,9 +668,10 @@ int project_out(const Ctx& x, int64_t rows, int bw, View src, MutView dst, View 
 
 // orth() of Algorithm 4 steps 4-5 on the rows x w row-major panel X (ld ldx), in place:
 // block Gram-Schmidt over b-column blocks (b <= kPowerBlock, the widest the CholeskyQR
-// kernel takes; the power rounds use that width, so that the projections are wide GEMMs,
-// the SVD's thin QR of B^T 64, where the shorter Cholesky chain of the narrower blocks
-// outweighs the narrower products), each projected twice against Q(:, 0:kq)
+// kernel takes; the power rounds and the SVD's thin QR of B^T use 64, where the shorter
+// Cholesky chain of the narrower blocks outweighs the narrower products: the 128-column
+// one-workgroup Cholesky takes about 190 us, the 64-column one 55 us), each projected twice
+// against Q(:, 0:kq)
 // and the blocks already done, and orthonormalised after each projection by CholeskyQR
 // (or, with use_hh, by Householder QR).  Block j of the result depends only on blocks
 // 0..j of X and has diag(R) > 0, as the Q factor of a Householder QR of [Q, X] would.
@@ -741,10 +742,10 @@ int power_rounds(const Ctx& x, int64_t k, int64_t w, double*& Om, double*& H, do
                 }
                 if (side == 0) {   // G = orth((I - Q Q^T) A Omega)
                     if (int e = apply_A(x, Om, w, G, w, w, gnorm2)) return e;
-                    if (int e = orth_panel(x, G, m, w, w, k, use_hh)) return e;
+                    if (int e = orth_panel(x, G, m, w, w, k, use_hh, 64)) return e;
                 } else {           // Omega = orth(A^T G)
                     if (int e = apply_At(x, G, w, H, w, w)) return e;
-                    if (int e = orth_panel(x, H, n, w, w, 0, use_hh)) return e;
+                    if (int e = orth_panel(x, H, n, w, w, 0, use_hh, 64)) return e;
                 }
                 bool broken = false;
                 if (int e = read_flag(x, &broken)) return e;
