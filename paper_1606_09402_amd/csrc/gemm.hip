@@ -509,7 +509,8 @@ int64_t gemm_f64_colsq_groups(int64_t M, int64_t N) {
 
 // Class 0 (tall outputs of at most 64 columns, e.g. the n x 64 B_i = (A^T Q_i)^T of randQB_EI
 // and trQRCP) takes the 16-deep two-stage ring, two workgroups per CU: 54.9 against 49.6
-// TFLOP/s on the 15000 x 64 x 20000 products with the 32-deep single-stage tile.
+// TFLOP/s on the 15000 x 64 x 20000 products with the 32-deep single-stage tile.  Class 1
+// (the block loop's k x 64 split-K products) measured the same either way and keeps its tile.
 template <int AL, int BL>
 static hipError_t dispatch_shape(const GemmDesc& d, hipStream_t s) {
     switch (shape_class(d.M, d.N, d.K)) {
