@@ -668,9 +668,9 @@ int project_out(const Ctx& x, int64_t rows, int bw, View src, MutView dst, View 
 
 // orth() of Algorithm 4 steps 4-5 on the rows x w row-major panel X (ld ldx), in place:
 // block Gram-Schmidt over b-column blocks (b <= kPowerBlock, the widest the CholeskyQR
-// kernel takes; the power rounds and the SVD's thin QR of B^T use 64, where the shorter
-// Cholesky chain of the narrower blocks outweighs the narrower products: the 128-column
-// one-workgroup Cholesky takes about 190 us, the 64-column one 55 us), each projected twice
+// kernel takes; the callers pick b by orth_block_cols: on panels of up to 65536 rows the
+// shorter Cholesky chain of 64-column blocks outweighs their narrower products, the
+// 128-column one-workgroup Cholesky taking about 190 us against 55 us), each projected twice
 // against Q(:, 0:kq)
 // and the blocks already done, and orthonormalised after each projection by CholeskyQR
 // (or, with use_hh, by Householder QR).  Block j of the result depends only on blocks
@@ -715,6 +715,12 @@ int orth_panel(const Ctx& x, double* X, int64_t rows, int64_t w, int64_t ldx, in
     return QB_OK;
 }
 
+// Block width of orth_panel for panels of `rows` rows: 64 up to 65536 rows (the shorter
+// Cholesky chain wins: the P = 1 call on 20000 x 15000 took 72.6 against 75.2 ms), 128
+// above (the wider projections win: the P = 1 call on the 500000 x 200000 CSR matrix took
+// 4.92 s with 64 against 4.55 s with 128).
+int orth_block_cols(int64_t rows) { return rows <= 65536 ? 64 : kPowerBlock; }
+
 // Whether some CholeskyQR since the last reset broke down (waits for the stream).
 int read_flag(const Ctx& x, bool* broken) {
     int* hflag = reinterpret_cast<int*>(x.host_info + 3 * kMaxB);
@@ -742,10 +748,10 @@ int power_rounds(const Ctx& x, int64_t k, int64_t w, double*& Om, double*& H, do
                 }
                 if (side == 0) {   // G = orth((I - Q Q^T) A Omega)
                     if (int e = apply_A(x, Om, w, G, w, w, gnorm2)) return e;
-                    if (int e = orth_panel(x, G, m, w, w, k, use_hh, 64)) return e;
+                    if (int e = orth_panel(x, G, m, w, w, k, use_hh, orth_block_cols(m))) return e;
                 } else {           // Omega = orth(A^T G)
                     if (int e = apply_At(x, G, w, H, w, w)) return e;
-                    if (int e = orth_panel(x, H, n, w, w, 0, use_hh, 64)) return e;
+                    if (int e = orth_panel(x, H, n, w, w, 0, use_hh, orth_block_cols(n))) return e;
                 }
                 bool broken = false;
                 if (int e = read_flag(x, &broken)) return e;
@@ -1325,7 +1331,7 @@ int svd_from_qb(int64_t m, int64_t n, int64_t k, const double* Q, int64_t ldq, c
         GemmDesc c = gdesc(n, k, 0, View{nullptr, 0, 0}, View{nullptr, 0, 0}, 0.0, 1.0,
                            View{B, 1, ldb}, MutView{P, k, 1}, x);
         QB_HIP(gemm_f64(c, s));
-        if (int e = orth_panel(x, P, n, k, k, 0, attempt == 1, 64)) return e;
+        if (int e = orth_panel(x, P, n, k, k, 0, attempt == 1, orth_block_cols(n))) return e;
         bool broken = false;
         if (int e = read_flag(x, &broken)) return e;
         if (!broken) break;
