@@ -507,14 +507,19 @@ int64_t gemm_f64_colsq_groups(int64_t M, int64_t N) {
     return cdiv(M, N <= 64 || M <= 2048 ? 64 : 128);   // the most any K gives
 }
 
-// Class 0 (tall outputs of at most 64 columns, e.g. the n x 64 B_i = (A^T Q_i)^T of randQB_EI
-// and trQRCP) takes the 16-deep two-stage ring, two workgroups per CU: 54.9 against 49.6
-// TFLOP/s on the 15000 x 64 x 20000 products with the 32-deep single-stage tile.  Class 1
-// (the block loop's k x 64 split-K products) measured the same either way and keeps its tile.
+// Class 0 (tall outputs of at most 64 columns) with a long reduction, e.g. the n x 64
+// B_i = (A^T Q_i)^T of randQB_EI and trQRCP, takes the 16-deep two-stage ring, two workgroups
+// per CU: 54.9 against 49.6 TFLOP/s on the 15000 x 64 x 20000 products with the 32-deep
+// single-stage tile.  With a short one (the sparse workload's Q_i = Y R^-1 and
+// B_i^T = S^T R_i^-1, 500000 x 50 x 50) the 32-deep tile stays faster (902 against 961 us).
+// Class 1 (the block loop's k x 64 split-K products) measured the same either way and keeps
+// its tile.
 template <int AL, int BL>
 static hipError_t dispatch_shape(const GemmDesc& d, hipStream_t s) {
     switch (shape_class(d.M, d.N, d.K)) {
-        case 0: return run_cfg<128, 64, 16, 4, 1, AL, BL, 2, 2>(d, s);
+        case 0:
+            return d.K >= 4096 ? run_cfg<128, 64, 16, 4, 1, AL, BL, 2, 2>(d, s)
+                               : run_cfg<128, 64, 32, 4, 1, AL, BL, 2, 1>(d, s);
         case 1: return run_cfg<64, 64, 32, 2, 2, AL, BL, 2, 1>(d, s);
         default: return run_cfg<128, 128, 16, 4, 2, AL, BL, 2, 2>(d, s);
     }
