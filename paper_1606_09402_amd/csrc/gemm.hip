@@ -511,7 +511,8 @@ int64_t gemm_f64_colsq_groups(int64_t M, int64_t N) {
 // B_i = (A^T Q_i)^T of randQB_EI and trQRCP, takes the 16-deep two-stage ring, two workgroups
 // per CU: 54.9 against 49.6 TFLOP/s on the 15000 x 64 x 20000 products with the 32-deep
 // single-stage tile.  With a short one (the sparse workload's Q_i = Y R^-1 and
-// B_i^T = S^T R_i^-1, 500000 x 50 x 50) the 32-deep tile stays faster (902 against 961 us).
+// B_i^T = S^T R_i^-1, 500000 x 50 x 50) the 32-deep tile measured no slower (902-944 against
+// 961 us in traced runs).
 // Class 1 (the block loop's k x 64 split-K products) measured the same either way and keeps
 // its tile.
 template <int AL, int BL>
