@@ -393,7 +393,8 @@ pair_eig_kernel(const double* __restrict__ gram, int inner, double tol_r, double
 // takes those of pairs j from lane j.  Between rounds the slots of b move down by one:
 // C and D pass through LDS (ping-pong buffers, one barrier per round; C_ji is re-read from
 // the copy of C_ij its owner wrote, so the two copies of an entry never drift apart), V's
-// b columns and the diagonal of D through lane shuffles.  After kJb rounds the slots are back in column order.
+// b columns and the diagonal of D through lane shuffles.  After kJb rounds the slots are
+// back in column order.  Same tests, skip flag and flag as pair_eig_kernel.
 __global__ void __launch_bounds__(kSvdThreads)
 pair_eig_cross_kernel(const double* __restrict__ gram, int inner, double tol_r, double tol_c,
                       double* __restrict__ Vout, int* __restrict__ skip, int* __restrict__ flag) {
