@@ -5,14 +5,14 @@
  * rank k adaptively so that ||A - QB||_F < tol ||A||_F, following Yu, Gu, Li,
  * "Efficient randomized algorithms for the fixed-precision low-rank matrix
  * approximation" (arXiv 1606.09402):
- *   - randQB_FP: Algorithm 4 (Algorithm 3 plus the re-orthogonalised steps 9a-9c,
+ *   - randQB_FP: Algorithm 4 (Algorithm 3 plus the re-orthogonalised blocks,
  *     eq. (23)); one sweep G = A Omega, H = A^T G per chunk of Omega columns, then a
  *     block loop that touches only G, H, Omega, Q, B.  With power parameter P > 0
  *     (binary64 A only) each chunk first runs P rounds G = orth(A Omega),
- *     Omega = orth(A^T G) (steps 3-6), on the residual A - QB after the first chunk.
+ *     Omega = orth(A^T G) (the power scheme), on the residual A - QB after the first chunk.
  *   - randQB_EI: Algorithm 2, two passes over A per block.
  *   - both stop with the Frobenius error indicator of Theorem 1 / Algorithm 1,
- *     decremented row by row (Section 3.1, steps 7a-8e) unless row_by_row == 0.
+ *     decremented row by row (Section 3.1) unless row_by_row == 0.
  *   - A may be dense (binary64, or bfloat16 / e4m3 for randQB_FP's precision form), CSR,
  *     or COO (turned into CSR on the device); a batched fixed-rank form with its adjoint
  *     serves differentiation; qb_svd_from_qb turns a QB factorisation into an approximate
@@ -138,7 +138,7 @@ typedef struct {
                             factors and triangular inverses of every block are formed in one
                             workgroup's registers and LDS, which bounds b; Section 5 uses
                             b = 10 to 50.                                                   */
-    int32_t power;       /* power-scheme parameter P of Algorithm 4 (steps 3-6), 0 <= P <= 16.
+    int32_t power;       /* power-scheme parameter P of Algorithm 4, 0 <= P <= 16.
                             P > 0 is accepted by randQB_FP on binary64 A (dense or CSR) and
                             returns QB_ERR_UNSUPPORTED elsewhere.  Each chunk's Gaussian
                             Omega is replaced by the result of P rounds
@@ -156,7 +156,7 @@ typedef struct {
                             eps^2, plus b, rounded up to a multiple of b, within
                             [b, 4 x previous]), never wider than min(50 b, l_max).           */
     uint64_t seed;       /* Philox key of Omega                                              */
-    int32_t row_by_row;  /* 1: steps 7a-8e (rank any integer); 0: whole-block stopping      */
+    int32_t row_by_row;  /* 1: Section 3.1 row by row (rank any integer); 0: whole-block stop */
     int32_t reserved;
 } qb_params;
 
@@ -191,7 +191,7 @@ QB_API size_t qb_dense_workspace_bytes(int algo, const qb_dense* A, const qb_par
 
 /* randQB_FP (Algorithm 4) on dense row-major A of dtype QB_F64, QB_BF16 or QB_FP8E4M3
  * (A->row_exp then gives the per-row power-of-two scales).  p->power > 0 (the power scheme
- * of Algorithm 4 steps 3-6) is accepted for QB_F64 only.  ws must hold at least
+ * of Algorithm 4) is accepted for QB_F64 only.  ws must hold at least
  * qb_dense_workspace_bytes(QB_ALGO_FP, A, p) bytes of device memory (256-byte aligned).  For
  * the low-precision element types the relative tolerance is taken against ||A_q||_F. */
 QB_API int qb_fp_dense(const qb_dense* A, const qb_params* p, double* Q, int64_t ldq, double* B,
@@ -291,13 +291,13 @@ QB_API int qb_gaussian_fill(uint64_t seed, uint32_t stream_id, uint32_t batch, i
                      int64_t col0, int64_t rows, int64_t cols, double* out, int64_t ld,
                      hipStream_t stream);
 
-/* ||A||_F^2 (Theorem 1 / Algorithm 1 step 2) of dense row-major A (QB_F64 or
+/* ||A||_F^2 (Theorem 1 / Algorithm 1) of dense row-major A (QB_F64 or
  * QB_BF16), as a deterministic FP64 tree sum of squares; *out_host receives the value.
  * ws needs qb_sumsq_workspace_bytes() bytes.  Synchronises the stream. */
 QB_API size_t qb_sumsq_workspace_bytes(void);
 QB_API int qb_sumsq_dense(const qb_dense* A, double* out_host, void* ws, hipStream_t stream);
 
-/* One sketch sweep of randQB_FP (Algorithm 4 steps 2, 7, 8 with P = 0):
+/* One sketch sweep of randQB_FP (Algorithm 4 with P = 0: Omega, G and H):
  * Omega(:, col0:col0+l) drawn as in qb_gaussian_fill (stream 0, batch 0) into om
  * (n x l, row-major, ld l), G = A Omega into g (m x l row-major, ld l), H = A^T G into
  * h (n x l row-major, ld l).  Enqueued on stream; does not synchronise. */
@@ -343,7 +343,7 @@ QB_API int qb_sketch_csr(const qb_csr* A, uint64_t seed, int64_t col0, int64_t l
  * For each matrix A (m x n) of the batch and the fixed Gaussian Omega (n x k, drawn as in
  * qb_gaussian_fill with stream 0, batch 0, columns 0..k-1, rounded to the element type),
  * the forward runs randQB_FP without stopping for t = k / b blocks (Algorithm 3 with the
- * re-orthogonalised steps 9a-9c / eq. (23); G = A Omega and H = A^T G once).  In exact
+ * re-orthogonalised blocks and eq. (23); G = A Omega and H = A^T G once).  In exact
  * arithmetic the result is Q = qf(A Omega) with diag(R) > 0 and B = Q^T A, a
  * differentiable function of A; the backward computes dL/dA from dL/dQ and dL/dB by the
  * adjoints of B = Q^T A, of the thin QR (R-bar = 0) and of the triangular solve with R,

@@ -1,6 +1,6 @@
 """Reference for the differentiation form (test infrastructure only).
 
-The fixed-rank randQB_FP of Algorithm 3 with steps 9a-9c (Algorithm 4, P = 0, no
+The fixed-rank randQB_FP of Algorithm 3 with the re-orthogonalisation of Algorithm 4 (P = 0, no
 stopping) computes, in exact arithmetic, Q = qf(A Omega) with diag(R) > 0 and B = Q^T A
 for the fixed Gaussian Omega (the remark after eq. (23): all block variants give the same
 Q and B).  This module writes that map in plain float64 torch on the CPU, so that

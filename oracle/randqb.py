@@ -5,12 +5,12 @@ Written from Yu, Gu, Li, arXiv 1606.09402:
 * Theorem 1 / eq. (5): for orthonormal Q and B = Q^T A,
   ||A - QB||_F^2 = ||A||_F^2 - ||B||_F^2, so E = ||A||^2 - sum ||B_i||^2 tracks the
   squared error without forming the residual (Algorithm 1, Theorem 2).
-* Section 3.1, steps 7a-8e: the indicator may be decremented row by row; at the
+* Section 3.1, the row-by-row rule: the indicator may be decremented row by row; at the
   first row j where E < eps^2 the rows after j of B_i (columns of Q_i) are dropped.
 * Algorithm 2 (randQB_EI): Q_i = orth(A Omega_i - Q (B Omega_i)), re-orthogonalise
   Q_i = orth(Q_i - Q (Q^T Q_i)), B_i = Q_i^T A.
-* Algorithm 3 with steps 9a-9c, i.e. Algorithm 4 with power parameter P = 0
-  (randQB_FP): G = A Omega, H = A^T G once; per block
+* Algorithm 3 with the re-orthogonalisation of Algorithm 4, i.e. Algorithm 4 with power
+  parameter P = 0 (randQB_FP): G = A Omega, H = A^T G once; per block
   Y_i = G_J - Q (B Omega_J); [Q_i, R_i] = qr(Y_i);
   [Q_i, R~_i] = qr(Q_i - Q (Q^T Q_i)); R_i = R~_i R_i;
   B_i = R_i^{-T} (H_J^T - Y_i^T Q B - Omega_J^T B^T B)   (eq. (23)).
@@ -38,12 +38,12 @@ design notes of the repository):
   2^-40 ||G_J(:,j)||_2, otherwise the method stops before row j (the numerical
   rank of A has been reached and R_i^{-T} would divide by round-off);
 * A = 0 returns rank 0; E < eps^2 before the first block (tol > 1) returns rank 0.
-* power scheme (Algorithm 4 steps 3-6, P >= 1): in the first chunk (Q empty) the P
+* power scheme (Algorithm 4, P >= 1): in the first chunk (Q empty) the P
   rounds G = orth(A Omega), Omega = orth(A^T G) run as written.  When a later chunk
   redraws Omega (the restart after Algorithm 4), the rounds act on the current residual
   A - Q B instead of A, i.e. G = orth(A Omega - Q (B Omega)) and
   Omega = orth(A^T G - B^T (Q^T G)); on A itself they would steer the new columns back
-  into the range that Q already holds.  G = A Omega and H = A^T G of steps 7-8 then
+  into the range that Q already holds.  The sketch G = A Omega and H = A^T G then
   take the full A as written (the block loop deflates).  Each chunk costs 2 P + 2
   passes.
 """
@@ -182,8 +182,8 @@ def _check(A, tol_rel, b, l_max):
 
 
 def _scan_rows(Bi, R, gnorm, E, eps2, row_by_row):
-    """Steps 7a-8e (or Algorithm 1 steps 7-8 when row_by_row is False) plus the
-    exhaustion guard.  Returns (rows kept, new E, stop flag, exhausted flag)."""
+    """The row-by-row stopping rule of Section 3.1 (or Algorithm 1's whole-block test when
+    row_by_row is False) plus the exhaustion guard.  Returns (rows kept, new E, stop flag, exhausted flag)."""
     bw = Bi.shape[0]
     r = row_sumsq(Bi)
     if row_by_row:
@@ -234,7 +234,7 @@ def _chunk_width(adaptive: bool, cap: int, b: int, left: int, w_prev: int, span:
 
 
 def power_omega(A, Om: np.ndarray, power: int, Q=None, B=None) -> np.ndarray:
-    """Steps 3-6 of Algorithm 4 on the residual A - Q B (Q, B empty in the first chunk):
+    """The power scheme of Algorithm 4 on the residual A - Q B (Q, B empty in the first chunk):
     power times G = orth((A - QB) Omega), then Omega = orth((A - QB)^T G)."""
     deflate = Q is not None and Q.shape[1] > 0
     for _ in range(power):
@@ -308,7 +308,7 @@ def randqb_fp(A, tol_rel: float, b: int, seed: int, l_max=None, l_tilde: int = 0
             k_half = chunk_lo + b * ((-(-w // b)) // 2)
             e_half = E
             Om = omega(seed, n, chunk_lo, chunk_hi - chunk_lo)
-            if power > 0:                           # steps 3-6
+            if power > 0:                           # the power scheme
                 Om = power_omega(A, Om, power, st.Q, st.B)
                 passes += 2 * power
             if keep_omega:
@@ -346,7 +346,7 @@ def randqb_fp(A, tol_rel: float, b: int, seed: int, l_max=None, l_tilde: int = 0
 
 def randqb_ei(A, tol_rel: float, b: int, seed: int, l_max=None,
               row_by_row: bool = True) -> QBResult:
-    """randQB_EI (Algorithm 2) with the row-by-row indicator of steps 7a-8e."""
+    """randQB_EI (Algorithm 2) with the row-by-row indicator of Section 3.1."""
     m, n, l_max = _check(A, tol_rel, b, l_max)
     normA2 = sumsq(A)
     if not np.isfinite(normA2):
@@ -389,8 +389,8 @@ def randqb_fixed(A, Om: np.ndarray):
 
 
 def randqb_fp_fixed(A, Om: np.ndarray, b: int, reorth: bool = True):
-    """Fixed-rank randQB_FP: Algorithm 3, with steps 9a-9c when reorth is True.
-    The rank is Om.shape[1]; the last block may be narrower than b."""
+    """Fixed-rank randQB_FP: Algorithm 3, with the re-orthogonalisation of Algorithm 4 when
+    reorth is True.  The rank is Om.shape[1]; the last block may be narrower than b."""
     A = np.asarray(A)
     m, n = A.shape
     G = A @ Om

@@ -1,8 +1,9 @@
 // Differentiation form: fixed-rank randQB_FP on a batch of matrices and the adjoint of
 // A -> (Q, B) for a fixed Omega.
 //
-// Forward, per matrix (Algorithm 3 with steps 9a-9c, i.e. Algorithm 4 with P = 0 and no
-// stopping; rank k = t b): G = A Omega, H = A^T G once, then per block J
+// Forward, per matrix (Algorithm 3 with the re-orthogonalisation of Algorithm 4, i.e.
+// Algorithm 4 with P = 0 and no stopping; rank k = t b): G = A Omega, H = A^T G once, then
+// per block J
 //   W = B Omega_J, Y = G_J - Q W, [Q_i, R] = qr(Y), [Q_i, R~] = qr(Q_i - Q (Q^T Q_i)),
 //   R_i = R~ R, B_i = R_i^{-T} (H_J^T - (Y^T Q) B - W^T B)     (eq. (23)).
 // In exact arithmetic this is Q = qf(A Omega) (diag(R) > 0) and B = Q^T A, so the map has

@@ -1,7 +1,7 @@
 // FP64 GEMM on CDNA4 matrix cores (v_mfma_f64_16x16x4_f64) for every product of the
-// QB method: the sketch sweep G = A Omega, H = A^T G (Algorithm 4 steps 7-8), EI's
-// A Omega_i and A^T Q_i (Algorithm 2 steps 5, 7), and the tall-skinny block products
-// B Omega_i, G_i - Q W, Q^T Q_i, Y^T Q, H_i^T - D B of steps 11-15.
+// QB method: the sketch sweep G = A Omega, H = A^T G (Algorithm 4), EI's
+// A Omega_i and A^T Q_i (Algorithm 2), and the tall-skinny block products
+// B Omega_i, G_i - Q W, Q^T Q_i, Y^T Q, H_i^T - D B of Algorithm 4's block loop (eq. (23)).
 //
 //   out(i, j) = alpha * sum_k Aop(i, k) Bop(k, j) + beta * C0(i, j)
 //

@@ -2,9 +2,9 @@
 //  * Cholesky of a b x b Gram matrix X^T X = R^T R with the inverse of R (CholeskyQR:
 //    Q = X R^{-1}), reporting breakdown so the host can switch to Householder;
 //  * the Householder thin QR of an m x b panel with diag(R) >= 0 (the fallback, and
-//    the definition of qr used by the paper's steps 12-13);
-//  * R_i = R~_i R_i (Algorithm 4 step 14);
-//  * R_i^{-1}, from which the GEMM B_i^T = S^T R_i^{-1} solves R_i^T B_i = S (step 15,
+//    the definition of qr used by the paper's two qr calls per block);
+//  * R_i = R~_i R_i (Algorithm 4);
+//  * R_i^{-1}, from which the GEMM B_i^T = S^T R_i^{-1} solves R_i^T B_i = S (eq. (23),
 //    the "\" of Section 4.1);
 //  * gathering the per-block values the host needs for the stopping test.
 #include "kernels.h"
@@ -560,8 +560,8 @@ __global__ void scan_resume_kernel(ScanState* __restrict__ st, int* __restrict__
     }
 }
 
-// Steps 7a-8e of Section 3.1 (or the whole-block test of Algorithms 1, 2 and 4) on the
-// device, the same arithmetic in the same order as the host rule it replaces.  One wave:
+// The row-by-row stopping rule of Section 3.1 (or the whole-block test of Algorithms 1, 2
+// and 4) on the device, the same arithmetic in the same order as the host rule it replaces.  One wave:
 // lane j loads row j's (and row j + 64's) values and evaluates its guard; lane 0 then runs
 // the sequential decrements with the values taken from the other lanes' registers.
 __global__ void __launch_bounds__(64)

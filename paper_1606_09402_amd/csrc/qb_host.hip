@@ -1,6 +1,6 @@
 // Host orchestration and C ABI of the QB library.
 //
-// randQB_FP (Algorithm 4 with P = 0, steps 9a-9c / eq. (23)) and randQB_EI
+// randQB_FP (Algorithm 4 with P = 0: the re-orthogonalised blocks and eq. (23)) and randQB_EI
 // (Algorithm 2), both with the row-by-row error indicator of Section 3.1.  Every
 // arithmetic step runs in the HIP kernels of this library; the host only carves the
 // caller's workspace, enqueues kernels on the caller's stream, and after each block
@@ -435,7 +435,7 @@ int cholqr(const Ctx& x, const double* X, int bw, double* Qout, int64_t ldq, dou
     return cholqr_v(x, m, View{X, 1, m}, bw, MutView{Qout, 1, ldq}, R, Rinv);
 }
 
-// Steps 11-14 of Algorithm 4 (steps 5-6 of Algorithm 2): given G_J (m x bw, row-major,
+// A block of Algorithm 4 up to R_i (as Algorithm 2's block QR): given G_J (m x bw, row-major,
 // ld ldgj) and Omega_J (n x bw, row-major, ld ldoj; nullptr when the caller has put W in
 // the w buffer already, as trQRCP does with W = B(:, J)), form W = B Omega_J,
 // Y = G_J - Q W (kept in the y buffer), Q_i = qr(Y), Q_i = qr(Q_i - Q (Q^T Q_i)) and
@@ -552,12 +552,12 @@ int orth_block(const Ctx& x, int64_t k, int bw, const double* GJ, int64_t ldgj, 
         QB_HIP(launch_tri_inv(R1, bw, R1i, x.s));
         QB_HIP(launch_tri_inv(Rt, bw, Rti, x.s));
     }
-    // R_i = R~ R (step 14) and its inverse R^{-1} R~^{-1}
+    // R_i = R~ R (Algorithm 4) and its inverse R^{-1} R~^{-1}
     QB_HIP(launch_upper_mul2(Rt, R1, R1i, Rti, bw, x.at<double>(x.L.ri), x.at<double>(x.L.rii), x.s));
     return QB_OK;
 }
 
-// Step 15 of Algorithm 4 (eq. (23)):
+// Algorithm 4's B_i by eq. (23):
 //   B_i = R_i^{-T} (H_J^T - (Y^T Q) B - W^T B) = R_i^{-T} (H_J^T - D^T B),  D = Q^T Y + W.
 // fp_block_ds forms D and S = H_J^T - D^T B; they need only Y and W, so when the context has
 // a side stream they run there, beside the panel QR of Y on the main stream (the two touch
@@ -613,7 +613,7 @@ int fp_block_b(const Ctx& x, int64_t k, int bw) {
     return QB_OK;
 }
 
-// Step 7 of Algorithm 2: B_i = Q_i^T A, computed as (A^T Q_i)^T into rows k..k+bw of B,
+// Algorithm 2's B_i = Q_i^T A, computed as (A^T Q_i)^T into rows k..k+bw of B,
 // with the row sums of squares into the rowsq buffer.
 int ei_block_b(const Ctx& x, int64_t k, int bw) {
     const Op& A = x.A;
@@ -666,7 +666,7 @@ int project_out(const Ctx& x, int64_t rows, int bw, View src, MutView dst, View 
     return QB_OK;
 }
 
-// orth() of Algorithm 4 steps 4-5 on the rows x w row-major panel X (ld ldx), in place:
+// orth() of Algorithm 4's power scheme on the rows x w row-major panel X (ld ldx), in place:
 // block Gram-Schmidt over b-column blocks (b <= kPowerBlock, the widest the CholeskyQR
 // kernel takes; the callers pick b by orth_block_cols: on panels of up to 65536 rows the
 // shorter Cholesky chain of 64-column blocks outweighs their narrower products, the
@@ -730,7 +730,7 @@ int read_flag(const Ctx& x, bool* broken) {
     return QB_OK;
 }
 
-// Steps 3-6 of Algorithm 4 for one chunk of w columns: P rounds of
+// The power scheme of Algorithm 4 for one chunk of w columns: P rounds of
 // G = orth(A Omega) and Omega = orth(A^T G).  After the first chunk (k > 0) the rounds act
 // on the residual A - Q B: G is also made orthogonal to Q(:, 0:k), and then
 // (A - QB)^T G = A^T G because B = Q^T A.  Omega and H are swapped in every round (the
@@ -777,7 +777,8 @@ int fetch_block(const Ctx& x, int bw, const double* gnorm2_j, bool* breakdown) {
     return QB_OK;
 }
 
-// Steps 7a-8e (or Algorithm 1 steps 7-8) with the exhaustion guard.
+// The row-by-row stopping rule of Section 3.1 (or Algorithm 1's whole-block test) with the
+// exhaustion guard.
 void scan_rows(const double* hinfo, int bw, bool row_by_row, double eps2, double* E, int* keep,
                bool* stop, bool* exhausted) {
     const double* rowsq = hinfo;
@@ -852,7 +853,7 @@ int run(int algo, Op& A, const qb_params* p, double* Q, int64_t ldq, double* B, 
     double* scal = reinterpret_cast<double*>(wsb + L.scal);
     double* red = reinterpret_cast<double*>(wsb + L.red);
 
-    // ||A||_F^2 (Algorithm 4 step 9).  Dense binary64 randQB_FP without the power scheme sums
+    // ||A||_F^2 (Algorithm 4).  Dense binary64 randQB_FP without the power scheme sums
     // it on the side stream, beside the first chunk's Omega and G = A Omega on this stream
     // (the chunk's width does not depend on it), and reads it back from the side stream once
     // G is enqueued.

@@ -1,4 +1,4 @@
-// Deterministic FP64 reductions: ||A||_F^2 as a sum of squares (Algorithm 1 step 2,
+// Deterministic FP64 reductions: ||A||_F^2 as a sum of squares (Algorithm 1,
 // Section 3.3 asks for the squares to be summed directly), and small fixed-order
 // finalisations of per-workgroup partial sums.  No floating-point atomics are used,
 // so repeated runs give identical bits.

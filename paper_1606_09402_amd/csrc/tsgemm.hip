@@ -1,9 +1,9 @@
 // Narrow FP64 products of the block loop (at most 64 output columns) on CDNA4 matrix cores,
 // with the MFMA operands loaded from global memory straight into registers: no LDS staging
 // and no barrier in the main loop, so every wave streams its operand independently and keeps
-// several k-steps of loads in flight.  These products (Algorithm 4 steps 11-15: B Omega_J,
-// G_J - Q W, the Gram matrices of CholeskyQR, Q^T Q_i, Q_i - Q Z, Q^T Y, H_J - B^T D) each read
-// an m x k or k x n panel once and sit at the ridge of the FP64 roofline (2 b flops per 8 bytes
+// several k-steps of loads in flight.  These products (the block loop of Algorithm 4 and
+// eq. (23): B Omega_J, G_J - Q W, the Gram matrices of CholeskyQR, Q^T Q_i, Q_i - Q Z,
+// Q^T Y, H_J - B^T D) each read an m x k or k x n panel once and sit at the ridge of the FP64 roofline (2 b flops per 8 bytes
 // of the panel), so the panel has to stream at the rate the matrix cores consume it.
 //
 // v_mfma_f64_16x16x4f64 takes A(i, k) from lane 16 k + i and B(k, j) from lane 16 k + j, and

@@ -1,4 +1,4 @@
-"""GPU parity of the power scheme (Algorithm 4 steps 3-6, P >= 1): the HIP path through
+"""GPU parity of the power scheme (Algorithm 4, P >= 1): the HIP path through
 the C ABI against the binary64 oracle on the same seeded inputs, with the tolerances of
 the P = 0 path (same rank, status, passes, blocks and chunks; E within 1e-10 ||A||^2; Q
 and B within 1e-10 plus the method's forward-error scale; Q^T Q = I to 1e-12; E equal to

@@ -1,4 +1,4 @@
-"""Pins of the oracle's power scheme (Algorithm 4 steps 3-6, P >= 1) against what the
+"""Pins of the oracle's power scheme (Algorithm 4, P >= 1) against what the
 paper and the mathematics fix.  CPU only.
 
 * Closed form: orth(X) is the Q factor of a thin QR with diag(R) > 0, and that factor
