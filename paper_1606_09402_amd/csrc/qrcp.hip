@@ -51,7 +51,7 @@ __global__ void qrcp_norms_kernel(const double* __restrict__ St, int64_t n, int 
 // is -1 and nothing changes.
 constexpr int kStepThreads = 256;
 constexpr int kStepRows = 256;
-constexpr int kStepCols = 32;   // columns per workgroup: 16 lanes per column, two passes
+constexpr int kStepCols = 32;   // columns per workgroup: 16 lanes per column, two passes (64: 41.0 against 37.1 ms a call)
 
 QB_DEV bool qrcp_better(double v, int i, double bv, int bi) {
     return v > bv || (v == bv && i >= 0 && (bi < 0 || i < bi));
