@@ -5,7 +5,7 @@
 // Householder reflector, applies it to every other active column and recomputes each
 // column's remaining norm exactly (no downdating).  A step is one launch (qrcp_step_kernel):
 // every workgroup finds the pivot itself from the per-workgroup best columns the previous
-// step left, forms the reflector from the pivot column and updates its own 32 columns, 16
+// step left, forms the reflector from the pivot column and updates its own 16 columns, 16
 // lanes to a column.  Every sum has a fixed order, so the pivots are reproducible.
 #include "kernels.h"
 
@@ -51,7 +51,9 @@ __global__ void qrcp_norms_kernel(const double* __restrict__ St, int64_t n, int 
 // is -1 and nothing changes.
 constexpr int kStepThreads = 256;
 constexpr int kStepRows = 256;
-constexpr int kStepCols = 32;   // columns per workgroup: 16 lanes per column, two passes (64: 41.0 against 37.1 ms a call)
+constexpr int kStepCols = 16;   // columns per workgroup, 16 lanes per column (32 and 64
+                                // columns per workgroup, in two and four passes, took 37.1
+                                // and 41.0 ms a trQRCP call against 36.2 ms)
 
 QB_DEV bool qrcp_better(double v, int i, double bv, int bi) {
     return v > bv || (v == bv && i >= 0 && (bi < 0 || i < bi));
