@@ -75,6 +75,7 @@ CASES = [
     (60, 40, 1, 4, 1e-3, "exp7", None),        # b = 1: one pivot per block
     (500, 300, 16, 8, 1e-9, "poly2", 40),      # capped: not converged at l_max
     (256, 900, 32, 16, 1e-3, "sshape", None),  # wide
+    (600, 400, 128, 128, 1e-3, "poly1.5", None),   # the tallest sketch: b + oversample = 256 rows
 ]
 
 
