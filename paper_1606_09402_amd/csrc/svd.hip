@@ -599,16 +599,26 @@ column_norm_kernel(const double* __restrict__ X, int k, int64_t ld, double* __re
 }
 
 // pos[j] = place of column j in descending order of sig (equal values keep index order).
-__global__ void svd_order_kernel(const double* __restrict__ sig, int k, int* __restrict__ pos) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= k) return;
-    const double v = sig[j];
+// sig is read through LDS, 256 values at a time (every value is compared by every thread).
+// Launch: 256 threads per workgroup.
+__global__ void __launch_bounds__(256)
+svd_order_kernel(const double* __restrict__ sig, int k, int* __restrict__ pos) {
+    __shared__ double sh[256];
+    const int t = static_cast<int>(threadIdx.x);
+    const int j = static_cast<int>(blockIdx.x) * 256 + t;
+    const double v = j < k ? sig[j] : 0.0;
     int p = 0;
-    for (int i = 0; i < k; ++i) {
-        const double u = sig[i];
-        p += (u > v || (u == v && i < j)) ? 1 : 0;
+    for (int i0 = 0; i0 < k; i0 += 256) {
+        __syncthreads();
+        if (i0 + t < k) sh[t] = sig[i0 + t];
+        __syncthreads();
+        const int n = k - i0 < 256 ? k - i0 : 256;
+        for (int q = 0; q < n; ++q) {
+            const double u = sh[q];
+            p += (u > v || (u == v && i0 + q < j)) ? 1 : 0;
+        }
     }
-    pos[j] = p;
+    if (j < k) pos[j] = p;
 }
 
 // Sorted outputs: s[pos[j]] = sig[j], Ut(:, pos[j]) = X(:, j) / sig[j] (zero for a zero
